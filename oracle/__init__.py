@@ -1,0 +1,245 @@
+"""Oracle for the adaptive WENO-theta scheme: plain serial FP64 C code.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the benchmark's ``cpu_baseline`` leg may import this package.  The
+product library (``paper_1504_00731_amd``) never imports it, and the two
+share no source.
+
+The C source ``wto_oracle.c`` follows the paper (Jung & Nguyen, adaptive
+WENO-theta, Sec. 2-4) step by step; this module only marshals numpy arrays
+through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wto_oracle.c")
+_HDR = os.path.join(_HERE, "wto_oracle.h")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+LINEAR, BURGERS, EULER = 0, 1, 2
+PERIODIC, TRANSMISSIVE = 0, 1
+DIAG_LEN = 19
+DIAG_NAMES = ("q0", "q1", "q2", "q3", "b0", "b1", "b2", "b3", "R", "restricted",
+              "tau5", "tau6", "theta", "w0", "w1", "w2", "w3", "h", "tau")
+
+_STATUS = {0: "ok", 1: "bad argument", 2: "unsupported", 3: "non-physical state",
+           4: "non-finite value"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what}: {_STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
+    if (not force and os.path.exists(_LIB)
+            and os.path.getmtime(_LIB) >= max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("system", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
+                ("bc", ctypes.c_int32 * 3), ("a", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("eps", ctypes.c_double), ("alpha_R", ctypes.c_double)]
+
+
+@dataclass
+class Problem:
+    """Grid and scheme parameters (mirrors ``wto_problem``)."""
+    ndim: int
+    system: int
+    n: tuple
+    dx: tuple
+    bc: tuple
+    a: float = 1.0
+    gamma: float = 1.4
+    cfl: float = 0.5
+    eps: float = 1e-10
+    alpha_R: float = 50.0
+
+    @property
+    def m(self) -> int:
+        return self.ndim + 2 if self.system == EULER else 1
+
+    @property
+    def shape(self) -> tuple:
+        """Array shape (m, [nz,] [ny,] nx) of a state."""
+        return (self.m,) + tuple(reversed(self.n[: self.ndim]))
+
+    def c_struct(self) -> _Problem:
+        p = _Problem()
+        p.ndim, p.system = self.ndim, self.system
+        n = list(self.n) + [1] * (3 - len(self.n))
+        dx = list(self.dx) + [1.0] * (3 - len(self.dx))
+        bc = list(self.bc) + [0] * (3 - len(self.bc))
+        for k in range(3):
+            p.n[k] = int(n[k]) if k < self.ndim else 1
+            p.dx[k] = float(dx[k])
+            p.bc[k] = int(bc[k])
+        p.a, p.gamma, p.cfl, p.eps, p.alpha_R = (float(self.a), float(self.gamma),
+                                                 float(self.cfl), float(self.eps),
+                                                 float(self.alpha_R))
+        return p
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        P = ctypes.POINTER(_Problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        _lib.wto_weno_theta.restype = ctypes.c_double
+        _lib.wto_weno_theta.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        _lib.wto_weno_theta_diag.restype = None
+        _lib.wto_weno_theta_diag.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        _lib.wto_euler_eigen.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                         dp, dp, dp, dp, dp]
+        _lib.wto_alpha.argtypes = [P, dp, dp, dp]
+        _lib.wto_rhs.argtypes = [P, dp, dp, dp, dp]
+        _lib.wto_rhs_points.argtypes = [P, dp, dp, ip, ctypes.c_int64, dp]
+        _lib.wto_step.argtypes = [P, dp, ctypes.c_double, dp]
+        _lib.wto_solve.argtypes = [P, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                   dp, ip]
+        _lib.wto_decisions_1d.argtypes = [P, dp, dp, i32p, dp]
+        for name in ("wto_euler_eigen", "wto_alpha", "wto_rhs", "wto_rhs_points", "wto_step",
+                     "wto_solve", "wto_decisions_1d"):
+            getattr(_lib, name).restype = ctypes.c_int
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+def _check(code, what):
+    if code != 0:
+        raise OracleError(code, what)
+
+
+def weno_theta(s, eps=1e-10, alpha_R=50.0) -> float:
+    s = _f64(s, (6,))
+    return lib().wto_weno_theta(_dp(s), eps, alpha_R)
+
+
+def weno_theta_diag(s, eps=1e-10, alpha_R=50.0) -> dict:
+    s = _f64(s, (6,))
+    out = np.zeros(DIAG_LEN)
+    lib().wto_weno_theta_diag(_dp(s), eps, alpha_R, _dp(out))
+    return dict(zip(DIAG_NAMES, out.tolist()))
+
+
+def euler_eigen(ndim, direction, gamma, uL, uR):
+    m = ndim + 2
+    uL, uR = _f64(uL, (m,)), _f64(uR, (m,))
+    L, R, lam = np.zeros((m, m)), np.zeros((m, m)), np.zeros(m)
+    _check(lib().wto_euler_eigen(ndim, direction, gamma, _dp(uL), _dp(uR), _dp(L), _dp(R),
+                                 _dp(lam)), "euler_eigen")
+    return L, R, lam
+
+
+def alpha(P: Problem, u):
+    u = _f64(u, P.shape)
+    al = np.zeros(P.ndim * P.m)
+    am = np.zeros(P.ndim)
+    _check(lib().wto_alpha(ctypes.byref(P.c_struct()), _dp(u), _dp(al), _dp(am)), "alpha")
+    return al.reshape(P.ndim, P.m), am
+
+
+def rhs(P: Problem, u, f=None, alpha_=None):
+    u = _f64(u, P.shape)
+    f = None if f is None else _f64(f, P.shape)
+    al = None if alpha_ is None else _f64(np.asarray(alpha_, dtype=np.float64).ravel())
+    L = np.zeros(P.shape)
+    _check(lib().wto_rhs(ctypes.byref(P.c_struct()), _dp(u), _dp(f), _dp(al), _dp(L)), "rhs")
+    return L
+
+
+def rhs_points(P: Problem, u, cells, alpha_=None):
+    u = _f64(u, P.shape)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    al = None if alpha_ is None else _f64(np.asarray(alpha_, dtype=np.float64).ravel())
+    out = np.zeros((cells.size, P.m))
+    _check(lib().wto_rhs_points(ctypes.byref(P.c_struct()), _dp(u), _dp(al),
+                                cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                cells.size, _dp(out)), "rhs_points")
+    return out
+
+
+def step(P: Problem, u, dt=0.0):
+    u = _f64(u, P.shape).copy()
+    dtu = ctypes.c_double(0.0)
+    _check(lib().wto_step(ctypes.byref(P.c_struct()), _dp(u), float(dt), ctypes.byref(dtu)),
+           "step")
+    return u, dtu.value
+
+
+def solve(P: Problem, u, t_end, t0=0.0, max_steps=-1):
+    u = _f64(u, P.shape).copy()
+    t = ctypes.c_double(0.0)
+    k = ctypes.c_int64(0)
+    _check(lib().wto_solve(ctypes.byref(P.c_struct()), _dp(u), float(t0), float(t_end),
+                           int(max_steps), ctypes.byref(t), ctypes.byref(k)), "solve")
+    return u, t.value, k.value
+
+
+def decisions_1d(P: Problem, u, alpha_=None):
+    """theta / restriction decisions per interface, field and sign, with margins."""
+    u = _f64(u, P.shape)
+    n = P.n[0]
+    al = None if alpha_ is None else _f64(np.asarray(alpha_, dtype=np.float64).ravel())
+    dec = np.zeros((n + 1, P.m, 4), dtype=np.int32)
+    mar = np.zeros((n + 1, P.m, 4))
+    _check(lib().wto_decisions_1d(ctypes.byref(P.c_struct()), _dp(u), _dp(al),
+                                  dec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  _dp(mar)), "decisions_1d")
+    return dec, mar
+
+
+def linear_problem(n, lo=-1.0, hi=1.0, a=1.0, bc=PERIODIC, alpha_R=50.0, cfl=0.5,
+                   system=LINEAR) -> Problem:
+    return Problem(ndim=1, system=system, n=(n,), dx=((hi - lo) / n,), bc=(bc,), a=a,
+                   alpha_R=alpha_R, cfl=cfl)
+
+
+def euler_problem(n, lo, hi, bc=TRANSMISSIVE, gamma=1.4, cfl=0.5, alpha_R=50.0) -> Problem:
+    n = tuple(int(v) for v in n)
+    ndim = len(n)
+    lo = tuple(lo) if isinstance(lo, (tuple, list)) else (lo,) * ndim
+    hi = tuple(hi) if isinstance(hi, (tuple, list)) else (hi,) * ndim
+    bc = tuple(bc) if isinstance(bc, (tuple, list)) else (bc,) * ndim
+    dx = tuple((hi[k] - lo[k]) / n[k] for k in range(ndim))
+    return Problem(ndim=ndim, system=EULER, n=n, dx=dx, bc=bc, gamma=gamma, cfl=cfl,
+                   alpha_R=alpha_R)
+
+
+INF = math.inf

@@ -1,0 +1,96 @@
+/*
+ * Oracle for the adaptive WENO-theta finite-difference scheme (Jung & Nguyen,
+ * "A New Adaptive WENO-theta Scheme for Hyperbolic Conservation Laws").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, serial-per-element FP64 CPU
+ * implementation used to check the GPU library.  Only the test suite, the
+ * smoke entry point and the benchmark's CPU-baseline leg may load it.  The
+ * product library shares no source with it and never calls it.
+ *
+ * All arrays are host arrays.  A state array holds m components of point
+ * values, component-major, x fastest: u[c][z][y][x] (no ghost points).
+ */
+#ifndef WTO_ORACLE_H
+#define WTO_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { WTO_OK = 0, WTO_ERR_ARG = 1, WTO_ERR_UNSUPPORTED = 2,
+       WTO_ERR_NONPHYSICAL = 3, WTO_ERR_NONFINITE = 4 };
+enum { WTO_LINEAR = 0, WTO_BURGERS = 1, WTO_EULER = 2 };
+enum { WTO_PERIODIC = 0, WTO_TRANSMISSIVE = 1 };
+
+typedef struct {
+    int32_t ndim;      /* 1, 2 or 3 (scalar systems: 1 only)                 */
+    int32_t system;    /* WTO_LINEAR (f = a u), WTO_BURGERS (f = u^2/2), WTO_EULER */
+    int64_t n[3];      /* points per dimension (n[k] = 1 for k >= ndim)     */
+    double  dx[3];     /* grid spacing per dimension                        */
+    int32_t bc[3];     /* WTO_PERIODIC or WTO_TRANSMISSIVE per dimension     */
+    double  a;         /* advection speed of WTO_LINEAR                     */
+    double  gamma;     /* ratio of specific heats (Euler)                   */
+    double  cfl;       /* CFL number                                        */
+    double  eps;       /* epsilon of the nonlinear weights (1e-10)          */
+    double  alpha_R;   /* restriction threshold; 0 disables, +inf = linear  */
+} wto_problem;
+
+/* Number of diagnostic values written by wto_weno_theta_diag. */
+#define WTO_DIAG_LEN 19
+
+/* One WENO-theta reconstruction of the interface value from six stencil
+ * values s[0..5] = f_{j-2}..f_{j+3}.  Returns the reconstructed value. */
+double wto_weno_theta(const double s[6], double eps, double alpha_R);
+
+/* Same, also reporting intermediates:
+ * out = {q0,q1,q2,q3, b0,b1,b2,b3 (before restriction), R, restricted,
+ *        tau5, tau6, theta, w0,w1,w2,w3, h, tau}. */
+void wto_weno_theta_diag(const double s[6], double eps, double alpha_R,
+                         double out[WTO_DIAG_LEN]);
+
+/* Roe-averaged eigen-system of the Euler flux in direction dir between the
+ * conserved states uL and uR (canonical order rho, m_x.., E).  Lmat and Rmat
+ * are m x m row-major in the permuted component order (rho, m_normal,
+ * m_tangential.., E); lam[m] are the eigenvalues.  Returns a status. */
+int wto_euler_eigen(int32_t ndim, int32_t dir, double gamma, const double *uL,
+                    const double *uR, double *Lmat, double *Rmat, double *lam);
+
+/* Global Lax-Friedrichs speeds alpha[d*m + s] = max over all points of
+ * |lambda_s| in direction d, and amax[d] = max over all points of the
+ * largest wave speed in direction d (|u_d| + c for Euler, |f'(u)| scalar). */
+int wto_alpha(const wto_problem *P, const double *u, double *alpha, double *amax);
+
+/* Spatial operator L(u) of the conservative semi-discretisation.
+ * f: optional caller-evaluated flux point values (1D scalar only; NULL means
+ * the flux of P->system).  alpha: optional LF speeds [ndim*m] (NULL means
+ * computed by wto_alpha). */
+int wto_rhs(const wto_problem *P, const double *u, const double *f,
+            const double *alpha, double *L);
+
+/* L(u) at selected points only (flattened x-fastest indices), written as
+ * Lpts[k*m + c].  alpha as in wto_rhs. */
+int wto_rhs_points(const wto_problem *P, const double *u, const double *alpha,
+                   const int64_t *cells, int64_t npts, double *Lpts);
+
+/* One 3-stage TVD Runge-Kutta step in place.  dt > 0 is used as given,
+ * dt <= 0 selects the CFL step.  *dt_used receives the step taken. */
+int wto_step(const wto_problem *P, double *u, double dt, double *dt_used);
+
+/* Advance from t0 to t_end with CFL steps (the last one clipped to t_end), or
+ * until max_steps steps (max_steps < 0: unlimited). */
+int wto_solve(const wto_problem *P, double *u, double t0, double t_end,
+              int64_t max_steps, double *t_out, int64_t *steps_out);
+
+/* Per-interface decisions of a 1D problem for flip accounting: for interface
+ * j+1/2, j = -1..n-1, and each field s, theta and restriction of the + and -
+ * reconstructions.  dec has (n+1)*m*4 entries: [iface][s][theta+, restr+,
+ * theta-, restr-]; margins has (n+1)*m*4 entries: relative |tau6-tau5| and
+ * |R-alpha_R| margins in the same layout. */
+int wto_decisions_1d(const wto_problem *P, const double *u, const double *alpha,
+                     int32_t *dec, double *margins);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

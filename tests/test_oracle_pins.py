@@ -1,0 +1,535 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Every test here checks the oracle against something other than itself: printed
+values (Table 1), closed forms printed in the paper (the 5th- and 6th-order
+linear fluxes, Taylor expansions of the indicators), exact solutions,
+invariants (conservation, free-stream, mirror and diagonal symmetry), Roe's
+property of the mean matrix, and an independent exact Riemann solver.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_00731_amd import workloads as W
+from tests.exact_riemann import sample, star_state
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Reconstruction: closed forms
+# ---------------------------------------------------------------------------
+
+def f5(s):
+    """5th-order upwind linear flux printed in Sec. 2.2 (coefficients 2,-13,47,27,-3 over 60)."""
+    return (2 * s[0] - 13 * s[1] + 47 * s[2] + 27 * s[3] - 3 * s[4]) / 60.0
+
+
+def f6(s):
+    """6th-order central linear flux printed in Sec. 2.3 (1,-8,37,37,-8,1 over 60)."""
+    return (s[0] - 8 * s[1] + 37 * s[2] + 37 * s[3] - 8 * s[4] + s[5]) / 60.0
+
+
+def test_linear_limits_match_printed_5th_and_6th_order_fluxes():
+    """With the restriction always active (alpha_R = inf) the weights are linear, and the
+    interface value is f^5 for theta = 1 and f^6 for theta = 0 (Sec. 3)."""
+    rng = np.random.default_rng(1)
+    seen = set()
+    for _ in range(4000):
+        s = rng.normal(size=6) * rng.choice([1e-3, 1.0, 1e3])
+        d = oracle.weno_theta_diag(s, 1e-10, math.inf)
+        th = d["theta"]
+        seen.add(th)
+        ref = f5(s) if th == 1.0 else f6(s)
+        scale = np.abs(s).max()
+        assert abs(d["h"] - ref) <= 2e-15 * scale * 10, (s, d, ref)
+        # theta follows tau6 < tau5
+        assert (th == 0.0) == (d["tau6"] < d["tau5"])
+    assert seen == {0.0, 1.0}
+
+
+def test_restricted_weights_are_the_linear_weights():
+    rng = np.random.default_rng(2)
+    for _ in range(500):
+        s = rng.normal(size=6)
+        d = oracle.weno_theta_diag(s, 1e-10, math.inf)
+        th = d["theta"]
+        gam = [(1 + th) / 20, 3 * (3 + th) / 20, 3 * (3 - th) / 20, (1 - th) / 20]
+        assert d["restricted"] == 1.0
+        for k in range(4):
+            assert abs(d["w%d" % k] - gam[k]) <= 4e-16
+
+
+def test_constant_stencil():
+    d = oracle.weno_theta_diag(np.full(6, 3.25), 1e-10, 50.0)
+    assert d["h"] == 3.25 or abs(d["h"] - 3.25) <= 4.5e-16
+    assert d["b0"] == d["b1"] == d["b2"] == d["b3"] == 0.0
+    assert d["tau5"] == d["tau6"] == 0.0 and d["theta"] == 1.0   # tie -> theta = 1
+
+
+def test_candidate_fluxes_are_3rd_order():
+    """Each q_k approximates h(x_{j+1/2}) to O(dx^3) (Sec. 2.2); with f the sliding
+    average of h = cos, h(x_{j+1/2}) is known in closed form."""
+    errs = []
+    for dx in (0.02, 0.01):
+        x = (np.arange(6) - 2) * dx + 0.3
+        # f(x) = (1/dx) int_{x-dx/2}^{x+dx/2} cos = (sin(x+dx/2) - sin(x-dx/2)) / dx
+        f = (np.sin(x + dx / 2) - np.sin(x - dx / 2)) / dx
+        d = oracle.weno_theta_diag(f, 1e-10, 50.0)
+        h = np.cos(0.3 + dx / 2)
+        errs.append([abs(d["q%d" % k] - h) for k in range(4)])
+    ratio = np.array(errs[0]) / np.array(errs[1])
+    assert np.all(ratio > 7.0), ratio     # 2^3 = 8
+
+
+# ---------------------------------------------------------------------------
+# Taylor expansions printed in Sec. 3.1
+# ---------------------------------------------------------------------------
+
+def _derivs(x, ph):
+    """f = sin(x + ph): derivatives f^(0..6) at x."""
+    s, c = math.sin(x + ph), math.cos(x + ph)
+    return [s, c, -s, -c, s, c, -s]
+
+
+@pytest.mark.parametrize("x0,ph", [(0.1, 0.3), (0.7, 1.9), (-0.4, 4.0)])
+def test_beta_tilde_taylor_expansions(x0, ph):
+    """beta~_k = f'^2 dx^2 + f'f'' dx^3 + c_k dx^4 + O(dx^5), with
+    c_0 = c_3 = 4/3 f''^2 - 5/3 f'f''' and c_1 = c_2 = 4/3 f''^2 + 1/3 f'f'''."""
+    D = _derivs(x0, ph)
+    c4 = {0: 4 / 3 * D[2] ** 2 - 5 / 3 * D[1] * D[3],
+          1: 4 / 3 * D[2] ** 2 + 1 / 3 * D[1] * D[3]}
+    c4[2], c4[3] = c4[1], c4[0]
+    prev = None
+    for dx in (4e-3, 2e-3):
+        s = np.sin(x0 + ph + (np.arange(6) - 2) * dx)
+        d = oracle.weno_theta_diag(s, 1e-10, 0.0)
+        errs = []
+        for k in range(4):
+            r = (d["b%d" % k] - D[1] ** 2 * dx ** 2 - D[1] * D[2] * dx ** 3) / dx ** 4
+            errs.append(abs(r - c4[k]))
+        errs = np.array(errs)
+        assert np.all(errs < 10 * dx), (k, errs)
+        if prev is not None:
+            assert np.all(errs < 0.7 * prev + 1e-3)
+        prev = errs
+
+
+@pytest.mark.parametrize("x0,ph", [(0.1, 0.3), (0.7, 1.9)])
+def test_tau_taylor_expansions(x0, ph):
+    """tau_5 = f'''^2 dx^6 + f'''f'''' dx^7 + (f'''f^(5)/2 + 4/3 f''''^2) dx^8 + ...
+    tau_6 = f''''^2 dx^8 + f''''f^(5) dx^9 + ... (Sec. 3.1)."""
+    D = _derivs(x0, ph)
+    for dx in (2e-2, 1e-2):
+        s = np.sin(x0 + ph + (np.arange(6) - 2) * dx)
+        d = oracle.weno_theta_diag(s, 1e-10, 0.0)
+        r5 = (d["tau5"] - D[3] ** 2 * dx ** 6 - D[3] * D[4] * dx ** 7) / dx ** 8
+        assert abs(r5 - (0.5 * D[3] * D[5] + 4 / 3 * D[4] ** 2)) < 40 * dx
+        r6 = (d["tau6"] - D[4] ** 2 * dx ** 8) / dx ** 9
+        assert abs(r6 - D[4] * D[5]) < 40 * dx
+
+
+# ---------------------------------------------------------------------------
+# Scheme-level pins on the scalar equation
+# ---------------------------------------------------------------------------
+
+def _table1():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "table1_weno_theta6.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        kind, n, l1, linf = line.split()
+        rows.append((kind, int(n), float(l1), float(linf)))
+    return rows
+
+
+def _u0_table1(x, kind):
+    if kind == "sin":
+        return np.sin(np.pi * x)
+    k = 2 if kind == "k2" else 3
+    return (x + 0.5) ** k * np.exp(-100.0 * (x + 0.5) ** 2)
+
+
+def _table1_errors(kind, N, alpha_R=50.0):
+    P = oracle.linear_problem(N, alpha_R=alpha_R)
+    x = -1.0 + np.arange(N) * (2.0 / N)
+    u = _u0_table1(x, kind)[None]
+    dt = (2.0 / N) ** 2
+    for _ in range(N * N // 4):          # t = 1 with dt = dx^2
+        u, _ = oracle.step(P, u, dt)
+    y = (x - 1.0 + 1.0) % 2.0 - 1.0
+    e = np.abs(u[0] - _u0_table1(y, kind))
+    # Reading: errors over the N+1 grid points x_0..x_N of Sec. 2 (x_N is the
+    # periodic image of x_0), L1 = dx * sum |e_j|.
+    l1 = (2.0 / N) * (e.sum() + e[0])
+    return l1, e.max()
+
+
+@pytest.mark.parametrize("row", [r for r in _table1() if r[1] <= 160],
+                         ids=lambda r: f"{r[0]}-{r[1]}")
+def test_table1_reproduced(row):
+    """Table 1 (Sec. 3.2), WENO-theta6 with alpha_R = 50: the smooth sine rows agree to
+    the printed two digits; the rows with vanishing derivatives agree within 6%."""
+    kind, N, l1_ref, linf_ref = row
+    l1, linf = _table1_errors(kind, N)
+    if kind == "sin":
+        assert float("%.1e" % l1) == l1_ref and float("%.1e" % linf) == linf_ref, (l1, linf)
+    else:
+        assert abs(l1 / l1_ref - 1) < 0.06 and abs(linf / linf_ref - 1) < 0.06, (l1, linf)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind", ["sin", "k2", "k3"])
+def test_table1_finest_grid(kind):
+    """N = 320: the k = 2, 3 rows agree within 6%.  The sine row is printed as 4.1e-13,
+    below what FP64 reaches here: the error grows when dt is reduced, i.e. it is
+    round-off accumulated over 25600 steps, so only a bound is checked."""
+    ref = {r[0]: r for r in _table1() if r[1] == 320}[kind]
+    l1, linf = _table1_errors(kind, 320)
+    if kind == "sin":
+        assert l1 < 5e-12 and linf < 5e-12
+    else:
+        assert abs(l1 / ref[2] - 1) < 0.06 and abs(linf / ref[3] - 1) < 0.06
+
+
+def test_alpha_R_reading_distinguished():
+    """Without the restriction (alpha_R = 0) the k = 2 row at N = 40 is off by > 25%:
+    Table 1 was computed with the restriction active (alpha_R = 50)."""
+    l1, _ = _table1_errors("k2", 40, alpha_R=0.0)
+    assert l1 / 3.7e-4 > 1.25
+
+
+def test_polynomial_exactness():
+    """With linear weights the scheme differentiates polynomials of degree <= 4 exactly:
+    L(u)_j = -p'(x_j) away from the boundary (f^5 and f^6 both reproduce them)."""
+    N = 40
+    P = oracle.linear_problem(N, lo=0.0, hi=1.0, bc=oracle.TRANSMISSIVE, alpha_R=math.inf)
+    x = (np.arange(N) + 0.5) / N
+    rng = np.random.default_rng(3)
+    for deg in range(5):
+        c = rng.normal(size=deg + 1)
+        u = np.polyval(c, x)
+        L = oracle.rhs(P, u[None])[0]
+        dp = np.polyval(np.polyder(c), x) if deg > 0 else np.zeros_like(x)
+        interior = slice(4, N - 4)
+        assert np.max(np.abs(L[interior] + dp[interior])) < 1e-10 * (1 + np.abs(c).sum())
+
+
+def test_ideal_weights_recovered_on_smooth_data():
+    """Without restriction, omega_k - gamma_k^theta = O(dx^4) at least (Sec. 2.3 remark);
+    measured over interfaces of sin data away from f' = 0."""
+    res = []
+    for N in (50, 100, 200):
+        x = np.arange(N) * (2.0 / N) - 1.0
+        f = np.sin(np.pi * x + 0.3)
+        worst = 0.0
+        for j in range(N):
+            if abs(np.cos(np.pi * x[j] + 0.3)) < 0.3:
+                continue
+            s = f[(j + np.arange(-2, 4)) % N]
+            d = oracle.weno_theta_diag(s, 1e-10, 0.0)
+            th = d["theta"]
+            gam = [(1 + th) / 20, 3 * (3 + th) / 20, 3 * (3 - th) / 20, (1 - th) / 20]
+            worst = max(worst, max(abs(d["w%d" % k] - gam[k]) for k in range(4)))
+        res.append(worst)
+    assert res[0] / res[1] > 2 ** 3.8 and res[1] / res[2] > 2 ** 3.8, res
+
+
+def test_seeded_modes_converge_at_6th_order():
+    """Seeded 3-mode advection (the 1D scalar workload) against the exact translation,
+    dt = dx^2, t = 0.5: observed order >= 5.5."""
+    case = W.scalar_modes(seed=0, n=40)
+    errs = []
+    for N in (40, 80):
+        c = W.scalar_modes(seed=0, n=N)
+        P = oracle.linear_problem(N)
+        u = c.u
+        dt = (2.0 / N) ** 2
+        for _ in range(int(round(0.5 / dt))):
+            u, _ = oracle.step(P, u, dt)
+        errs.append(np.abs(u[0] - W.scalar_exact_modes(c, 0.5)).max())
+    assert case.u.shape == (1, 40)
+    assert math.log2(errs[0] / errs[1]) > 5.5, errs
+
+
+def test_cfl_solve_translates_modes():
+    c = W.scalar_modes(seed=4, n=200)
+    P = oracle.linear_problem(200)
+    u, t, k = oracle.solve(P, c.u, 2.0)
+    assert t == 2.0 and k == 400                  # dt = 0.5 * 0.01 / 1
+    assert np.abs(u[0] - c.u[0]).max() < 5e-4
+
+
+def test_mirror_rule_of_negative_flux():
+    """F^- is the mirror of F^+ (Remark on flux splitting): advection with speed -1 of
+    mirrored data is the mirror of advection with speed +1, bitwise."""
+    N = 64
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=N)
+    Pp = oracle.linear_problem(N, a=1.0)
+    Pm = oracle.linear_problem(N, a=-1.0)
+    Lp = oracle.rhs(Pp, u[None])[0]
+    # mirror about the interface between points N-1 and 0: u'_j = u_{N-1-j}
+    Lm = oracle.rhs(Pm, u[::-1][None])[0]
+    assert np.array_equal(Lm[::-1], Lp)      # v(x,t) = u(-x,t) solves v_t - v_x = 0
+
+
+def test_flux_values_given_by_caller():
+    N = 48
+    rng = np.random.default_rng(6)
+    u = rng.normal(size=(1, N))
+    P = oracle.linear_problem(N, system=oracle.BURGERS)
+    al, _ = oracle.alpha(P, u)
+    f = 0.5 * u * u
+    assert np.array_equal(oracle.rhs(P, u), oracle.rhs(P, u, f=f, alpha_=al))
+
+
+def test_burgers_shock_stays_bounded():
+    """Burgers with u0 = 1/2 + sin(pi x) to t = 0.55 (Sec. 4.1, TEST 2): total variation
+    does not grow beyond the initial one by more than a few percent, and the mean is kept."""
+    N = 200
+    P = oracle.linear_problem(N, system=oracle.BURGERS)
+    x = -1.0 + np.arange(N) * (2.0 / N)
+    u0 = 0.5 + np.sin(np.pi * x)
+    u, t, _ = oracle.solve(P, u0[None], 0.55)
+    tv0 = np.abs(np.diff(np.r_[u0, u0[0]])).sum()
+    tv = np.abs(np.diff(np.r_[u[0], u[0, 0]])).sum()
+    assert tv <= tv0 * 1.02
+    assert abs(u[0].sum() - u0.sum()) <= 1e-12 * np.abs(u0).sum()
+
+
+# ---------------------------------------------------------------------------
+# Euler: eigen-system, invariants, exact Riemann solutions
+# ---------------------------------------------------------------------------
+
+def _flux_perm(u, d, gamma):
+    """Independent Euler flux in direction d in permuted order (rho, m_d, m_t.., E)."""
+    ndim = len(u) - 2
+    rho, E = u[0], u[-1]
+    vel = [u[1 + k] / rho for k in range(ndim)]
+    p = (gamma - 1) * (E - 0.5 * rho * sum(v * v for v in vel))
+    perm = [0, 1 + d] + [1 + k for k in range(ndim) if k != d] + [ndim + 1]
+    up = np.array([u[k] for k in perm])
+    un = vel[d]
+    f = up * un
+    f[1] += p
+    f[-1] += p * un
+    return f, up
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_roe_eigensystem(ndim):
+    """L R = I, A R = R Lambda at the Roe state, and Roe's property
+    A(u~)(u_R - u_L) = f(u_R) - f(u_L) (Sec. 4.2, Roe mean matrix)."""
+    rng = np.random.default_rng(7 + ndim)
+    g = 1.4
+    for _ in range(20):
+        sts = []
+        for _ in range(2):
+            rho = rng.uniform(0.2, 3)
+            vel = rng.uniform(-2, 2, ndim)
+            p = rng.uniform(0.2, 5)
+            sts.append(W.conserved(np.array(rho), list(vel), np.array(p), g).astype(float))
+        uL, uR = sts
+        for d in range(ndim):
+            L, R, lam = oracle.euler_eigen(ndim, d, g, uL, uR)
+            m = ndim + 2
+            assert np.allclose(L @ R, np.eye(m), atol=1e-13)
+            fL, pL = _flux_perm(uL, d, g)
+            fR, pR = _flux_perm(uR, d, g)
+            A = R @ np.diag(lam) @ L
+            assert np.allclose(A @ (pR - pL), fR - fL, rtol=1e-12, atol=1e-12)
+            # A is the flux Jacobian at the Roe-averaged state
+            sl, sr = np.sqrt(uL[0]), np.sqrt(uR[0])
+            vt = [(sl * uL[1 + k] / uL[0] + sr * uR[1 + k] / uR[0]) / (sl + sr) for k in range(ndim)]
+            HL = (uL[-1] + (g - 1) * (uL[-1] - 0.5 * sum(uL[1 + k] ** 2 for k in range(ndim)) / uL[0])) / uL[0]
+            HR = (uR[-1] + (g - 1) * (uR[-1] - 0.5 * sum(uR[1 + k] ** 2 for k in range(ndim)) / uR[0])) / uR[0]
+            H = (sl * HL + sr * HR) / (sl + sr)
+            rho_t = sl * sr
+            p_t = (g - 1) / g * rho_t * (H - 0.5 * sum(v * v for v in vt))
+            ut = W.conserved(np.array(rho_t), vt, np.array(p_t), g).astype(float)
+            J = np.zeros((m, m))
+            _, up = _flux_perm(ut, d, g)
+            perm = [0, 1 + d] + [1 + k for k in range(ndim) if k != d] + [ndim + 1]
+            for c in range(m):
+                h = 1e-6 * max(1.0, abs(up[c]))
+                e = np.zeros(m)
+                e[perm[c]] = h
+                J[:, c] = (_flux_perm(ut + e, d, g)[0] - _flux_perm(ut - e, d, g)[0]) / (2 * h)
+            assert np.allclose(J, A, rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_free_stream_is_exactly_preserved(ndim):
+    n = {1: (40,), 2: (16, 12), 3: (8, 7, 6)}[ndim]
+    vel = [0.3, -0.7, 0.2][:ndim]
+    rho = np.full(tuple(reversed(n)), 1.3)
+    u = W.conserved(rho, vel, 2.1)
+    for bc in (oracle.PERIODIC, oracle.TRANSMISSIVE):
+        P = oracle.euler_problem(n, 0.0, 1.0, bc=bc)
+        L = oracle.rhs(P, u)
+        assert np.all(L == 0.0)
+        # the printed convex-combination form of the stages (3/4 u + 1/4 u) may move a
+        # constant by an ulp; nothing else may change it
+        u1, _ = oracle.step(P, u)
+        assert np.all(np.abs(u1 - u) <= 2 * np.spacing(np.abs(u)))
+
+
+@pytest.mark.parametrize("ndim", [1, 2])
+def test_periodic_conservation(ndim):
+    case = W.euler1d_smooth_periodic(1, 128) if ndim == 1 else W.euler2d_smooth_periodic(2, 32)
+    P = oracle.euler_problem(case.n, case.lo, case.hi, bc=oracle.PERIODIC)
+    u = case.u
+    s0 = u.reshape(u.shape[0], -1).sum(axis=1)
+    for _ in range(10):
+        u, _ = oracle.step(P, u)
+    s1 = u.reshape(u.shape[0], -1).sum(axis=1)
+    scale = np.abs(case.u).reshape(u.shape[0], -1).sum(axis=1)
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s1 - s0) / scale
+
+
+def test_mirror_symmetry_123_bitwise():
+    """The 123 problem is mirror symmetric about x = 0 (rho, p even, u odd, Sec. 4.2):
+    the computed solution stays mirror symmetric bit for bit."""
+    case = W.problem_123(200)
+    P = oracle.euler_problem(case.n, case.lo, case.hi)
+    u, t, k = oracle.solve(P, case.u, 0.3)
+    assert k > 5
+    assert np.array_equal(u[0], u[0][::-1])
+    assert np.array_equal(u[1], -u[1][::-1])
+    assert np.array_equal(u[2], u[2][::-1])
+
+
+def test_mirror_symmetry_seeded_bitwise():
+    rng = np.random.default_rng(8)
+    n = 128
+    half = n // 2
+    seg = np.repeat(np.arange(8), half // 8)       # 8 constant segments per half
+    rho = rng.uniform(0.5, 2.0, 8)[seg]
+    vel = rng.uniform(-1, 1, 8)[seg]
+    p = rng.uniform(0.5, 2.0, 8)[seg]
+    rho = np.r_[rho[::-1], rho]
+    vel = np.r_[-vel[::-1], vel]
+    p = np.r_[p[::-1], p]
+    u = W.conserved(rho, [vel], p)
+    P = oracle.euler_problem((n,), -1.0, 1.0)
+    for _ in range(5):
+        u, _ = oracle.step(P, u)
+    assert np.array_equal(u[0], u[0][::-1]) and np.array_equal(u[1], -u[1][::-1])
+
+
+def test_diagonal_symmetry_2d_bitwise():
+    """TEST 8's quadrant data (Sec. 4.3) are symmetric about x = y (quadrants 2 and 4
+    exchange u and v): rho(x,y) = rho(y,x), m_x <-> m_y, bit for bit after several steps."""
+    case = W.test8_quadrants(40)
+    P = oracle.euler_problem(case.n, case.lo, case.hi)
+    u = case.u
+    for _ in range(4):
+        u, _ = oracle.step(P, u)
+    assert np.array_equal(u[0], u[0].T)
+    assert np.array_equal(u[1], u[2].T)
+    assert np.array_equal(u[3], u[3].T)
+
+
+def test_diagonal_symmetry_3d():
+    rng = np.random.default_rng(9)
+    n = 10
+    a = rng.uniform(0.5, 1.5, (n, n, n))
+    rho = a + a.transpose(0, 2, 1)
+    vx = rng.uniform(-0.5, 0.5, (n, n, n))
+    vy = vx.transpose(0, 2, 1).copy()
+    vz = rng.uniform(-0.5, 0.5, (n, n, n))
+    vz = vz + vz.transpose(0, 2, 1)
+    p = rho * 1.1
+    u = W.conserved(rho, [vx, vy, vz], p)
+    P = oracle.euler_problem((n, n, n), 0.0, 1.0, bc=oracle.PERIODIC)
+    for _ in range(2):
+        u, _ = oracle.step(P, u)
+    # In 3D the z-sweep sums its two tangential components in axis order (x then y), so
+    # exchanging x and y reorders two terms of a sum: symmetry holds to rounding only.
+    sw = lambda A: A.transpose(0, 2, 1)
+    tol = lambda A: 1e-13 * np.abs(A).max()
+    assert np.abs(u[0] - sw(u[0])).max() <= tol(u[0])
+    assert np.abs(u[1] - sw(u[2])).max() <= tol(u[1])
+    assert np.abs(u[3] - sw(u[3])).max() <= tol(u[3])
+    assert np.abs(u[4] - sw(u[4])).max() <= tol(u[4])
+
+
+def test_exact_riemann_solver_star_states():
+    """Independent check of the test's exact solver: known star states of Sod and 123."""
+    p, u = star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert abs(p - 0.30313) < 1e-5 and abs(u - 0.92745) < 1e-5
+    p, u = star_state((1.0, -2.0, 0.4), (1.0, 2.0, 0.4))
+    assert abs(p - 0.00189) < 1e-5 and abs(u) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["sod", "lax", "123"])
+def test_riemann_l1_converges_to_exact(name):
+    """Shock tubes of Sec. 4.2 (TEST 3) against the exact solution at a shortened final
+    time: L1(rho) decreases monotonically with N at an observed order in [0.5, 1.2]
+    (discontinuous solutions)."""
+    make = {"sod": W.sod, "lax": W.lax, "123": W.problem_123}[name]
+    t_end = {"sod": 1.0, "lax": 0.6, "123": 0.5}[name]
+    errs = []
+    for N in (100, 200, 400):
+        c = make(N)
+        P = oracle.euler_problem(c.n, c.lo, c.hi, alpha_R=c.alpha_R)
+        u, t, _ = oracle.solve(P, c.u, t_end)
+        x = -5.0 + (np.arange(N) + 0.5) * (10.0 / N)
+        rho, _, _ = sample(c.extra["left"], c.extra["right"], x / t_end)
+        errs.append((10.0 / N) * np.abs(u[0] - rho).sum())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert np.all(orders > 0.5) and np.all(orders < 1.2), (errs, orders)
+
+
+def test_shu_osher_runs_positive():
+    c = W.shu_osher(200)
+    P = oracle.euler_problem(c.n, c.lo, c.hi)
+    u, t, k = oracle.solve(P, c.u, 0.5)
+    assert t == 0.5 and np.all(u[0] > 0)
+
+
+# ---------------------------------------------------------------------------
+# Oracle API behaviour
+# ---------------------------------------------------------------------------
+
+def test_rhs_points_match_full_rhs():
+    case = W.euler2d_seeded(seed=3, n=24)
+    P = oracle.euler_problem(case.n, case.lo, case.hi)
+    L = oracle.rhs(P, case.u)
+    cells = np.array([0, 5, 23, 24, 300, 24 * 24 - 1])
+    Lp = oracle.rhs_points(P, case.u, cells)
+    for k, c in enumerate(cells):
+        assert np.array_equal(Lp[k], L[:, c // 24, c % 24])
+
+
+def test_errors_reported():
+    P = oracle.euler_problem((16,), 0.0, 1.0)
+    u = W.conserved(np.ones(16), [np.zeros(16)], np.ones(16))
+    bad = u.copy()
+    bad[0, 3] = -1.0
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.rhs(P, bad)
+    assert e.value.code == 3
+    bad = u.copy()
+    bad[2, 5] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.rhs(P, bad)
+    assert e.value.code == 4
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.rhs(oracle.euler_problem((5,), 0.0, 1.0), u[:, :5])
+    assert e.value.code == 1
+
+
+def test_resume_is_bitwise_identical():
+    c = W.sod(100)
+    P = oracle.euler_problem(c.n, c.lo, c.hi)
+    ua, ta, ka = oracle.solve(P, c.u, 0.4)
+    ub, tb, kb = oracle.solve(P, c.u, 0.4, max_steps=7)
+    ub, tb, kb2 = oracle.solve(P, ub, 0.4, t0=tb)
+    assert ta == tb and ka == kb + kb2 and np.array_equal(ua, ub)

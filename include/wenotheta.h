@@ -1,0 +1,161 @@
+/*
+ * wenotheta.h -- C ABI of the MI355X (gfx950) WENO-theta library.
+ *
+ * The library advances hyperbolic conservation laws u_t + f(u)_x (+ g(u)_y
+ * + h(u)_z) = 0 with the adaptive WENO-theta finite-difference scheme of
+ * Jung & Nguyen ("A New Adaptive WENO-theta Scheme for Hyperbolic
+ * Conservation Laws"):
+ *   - point values on a uniform grid and the conservative semi-discretisation
+ *     L(u)_j = -(F_{j+1/2} - F_{j-1/2}) / dx (Sec. 2);
+ *   - global Lax-Friedrichs flux splitting, the negative part reconstructed on
+ *     the mirrored stencil (Sec. 2.2.2, remark on flux splitting);
+ *   - WENO-theta reconstruction: four 3-point candidate fluxes, central
+ *     smoothness indicators beta~_k with the alpha_R restriction, the
+ *     large-stencil indicators tau_5 / tau_6 and the theta switch between the
+ *     5th-order upwind and 6th-order central linear weights (Sec. 3, 3.1);
+ *   - for the Euler equations, characteristic-wise reconstruction with the Roe
+ *     mean matrix (Sec. 4.2), dimension by dimension in 2D and 3D (Sec. 4.3);
+ *   - 3rd-order TVD Runge-Kutta in time (Sec. 2.1).
+ *
+ * Conventions for every entry point:
+ *   - C symbols only; nothing throws across the ABI; every call returns a
+ *     wt_status (WT_OK = 0).
+ *   - Array arguments are DEVICE pointers unless stated otherwise.  A state
+ *     holds m components of FP64 point values, component-major, x fastest:
+ *     u[c][z][y][x], no ghost points.  m = 1 for the scalar systems, ndim + 2
+ *     for Euler with components (rho, rho*u_x, [rho*u_y, [rho*u_z,]] E).
+ *   - The caller owns u, f and L.  The library owns only the context's
+ *     workspace (stage buffers, reduction slots, device scalars), allocated
+ *     lazily on the first call with a given size and kept until the context
+ *     is destroyed; calls after that allocate nothing.
+ *   - Work is ordered on the given stream (a hipStream_t passed as void*;
+ *     NULL = the default stream).  Calls on one context must be issued on one
+ *     stream and must not overlap.
+ *   - Argument errors are detected on the host, before any work is queued,
+ *     and returned synchronously.  States the device finds non-physical
+ *     (rho <= 0, p <= 0) or non-finite are recorded in the context and
+ *     returned by the next synchronising call (wenotheta_sync,
+ *     wenotheta_solve); the contents of u are then unspecified.
+ */
+#ifndef WENOTHETA_H
+#define WENOTHETA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WT_OK = 0,
+    WT_ERR_ARG = 1,          /* invalid argument (checked on the host)        */
+    WT_ERR_UNSUPPORTED = 2,  /* valid but not provided (e.g. scalar in 2D)    */
+    WT_ERR_NONPHYSICAL = 3,  /* rho <= 0 or p <= 0 met on the device          */
+    WT_ERR_NONFINITE = 4,    /* NaN or Inf met on the device                  */
+    WT_ERR_DEVICE = 5,       /* HIP runtime error                             */
+    WT_ERR_NOMEM = 6         /* workspace allocation failed                   */
+} wt_status;
+
+typedef enum {
+    WT_LINEAR = 0,   /* f(u) = a u                       (scalar, 1D) */
+    WT_BURGERS = 1,  /* f(u) = u^2 / 2                   (scalar, 1D) */
+    WT_EULER = 2     /* Euler equations of gas dynamics, 1D/2D/3D      */
+} wt_system;
+
+typedef enum {
+    WT_PERIODIC = 0,     /* wrap-around                                     */
+    WT_TRANSMISSIVE = 1  /* zero gradient: ghost points copy the nearest point */
+} wt_bc;
+
+typedef enum {
+    WT_FP64 = 0          /* every step in IEEE double precision             */
+} wt_precision;
+
+/* Uniform grid.  n[k] points in dimension k (n[k] = 1 for k >= ndim; at least
+ * 6 for k < ndim), spacing dx_k = (hi[k] - lo[k]) / n[k], boundary condition
+ * bc[k] applied at both ends of dimension k. */
+typedef struct {
+    int32_t ndim;
+    int32_t reserved0;
+    int64_t n[3];
+    double lo[3];
+    double hi[3];
+    int32_t bc[3];
+    int32_t reserved1;
+} wt_grid;
+
+/* Scheme parameters. */
+typedef struct {
+    int32_t system;     /* wt_system                                          */
+    int32_t precision;  /* wt_precision                                       */
+    double a;           /* advection speed of WT_LINEAR                       */
+    double gamma;       /* ratio of specific heats (> 1), Euler (Sec. 4.2: 1.4) */
+    double cfl;         /* CFL number (> 0), e.g. 0.5 (Sec. 4.3)              */
+    double eps;         /* epsilon of the nonlinear weights (> 0), 1e-10 (Sec. 3.1) */
+    double alpha_R;     /* restriction threshold of beta~_k (>= 0; 0 switches it
+                           off, +inf gives the linear weights), 50 (Sec. 4.2) */
+} wt_params;
+
+typedef struct wt_ctx wt_ctx;
+
+/* Create a context bound to HIP device `device`.  *ctx receives the handle. */
+wt_status wenotheta_ctx_create(wt_ctx **ctx, int32_t device);
+
+/* Free the context and its workspace (synchronises the device first). */
+wt_status wenotheta_ctx_destroy(wt_ctx *ctx);
+
+/* Static description of a status code. */
+const char *wenotheta_status_string(int32_t status);
+
+/* Spatial operator L = L(u) of the semi-discretisation (Sec. 2): writes m
+ * components of L(u) for every grid point into L_out (device, same layout as
+ * u).  The Lax-Friedrichs speeds are alpha_s = max over the grid of
+ * |lambda_s(u)| per field and direction, computed on the device, unless
+ * alpha_host (HOST array of ndim*m values, [dir][field]) is given.
+ * f: optional device array of caller-evaluated flux point values f(u_j), for
+ * the 1D scalar case only; it then requires alpha_host (alpha = max|f'(u)|,
+ * remark on flux splitting).  Asynchronous. */
+wt_status wenotheta_rhs(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
+                        const double *u, const double *f, const double *alpha_host,
+                        double *L_out, void *stream);
+
+/* One 3-stage TVD Runge-Kutta step (Sec. 2.1) of u in place.  dt > 0 is used
+ * as given; dt <= 0 selects the CFL step dt = cfl / sum_d(amax_d / dx_d),
+ * amax_d the largest wave speed in direction d.  dt_used_dev: optional
+ * DEVICE pointer receiving the step taken.  Asynchronous. */
+wt_status wenotheta_step(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
+                         double *u, double dt, double *dt_used_dev, void *stream);
+
+/* Advance u in place from time t0 to t_end with CFL steps, the last one
+ * clipped to end at t_end (a step that would leave less than 1e-6 of itself
+ * to go is stretched to t_end), or until max_steps steps have been taken
+ * (max_steps < 0: no limit).  Synchronises; *t_out and *steps_out (HOST,
+ * optional) receive the time reached and the steps taken.  Returns any error
+ * the device recorded. */
+wt_status wenotheta_solve(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
+                          double *u, double t0, double t_end, int64_t max_steps,
+                          double *t_out, int64_t *steps_out, void *stream);
+
+/* Wait for the work queued on `stream` and return (and clear) any error the
+ * device recorded since the last synchronising call. */
+wt_status wenotheta_sync(wt_ctx *ctx, void *stream);
+
+/* Per-kernel timing.  enable != 0 starts recording a pair of HIP events on the
+ * launch stream around every sweep kernel (and clears the totals); 0 stops.
+ * Measurement support for callers that report kernel durations; it does not
+ * change any result. */
+wt_status wenotheta_profile(wt_ctx *ctx, int32_t enable);
+
+/* Totals since wenotheta_profile(ctx, 1), folded in at each synchronising
+ * call: ms[k] (HOST) the summed kernel milliseconds and count[k] (HOST) the
+ * launches of kind k, nkinds >= 6.  Kind d (0..2) is the sweep along
+ * direction d in a non-final role (writing or accumulating the divergence);
+ * kind 3 + d is the sweep along d that finishes a stage or an RHS evaluation.
+ * Returns WT_ERR_ARG if more launches were queued between two synchronising
+ * calls than could be recorded (4096). */
+wt_status wenotheta_profile_read(wt_ctx *ctx, double *ms, int64_t *count, int32_t nkinds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WENOTHETA_H */

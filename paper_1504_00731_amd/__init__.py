@@ -1,2 +1,12 @@
-"""MI355X-native WENO-theta library (adaptive WENO-theta finite differences, HIP/gfx950)."""
+"""MI355X-native WENO-theta library (adaptive WENO-theta finite differences, HIP/gfx950).
+
+The computation lives in ``libwenotheta.so`` (HIP kernels behind the C ABI of
+``include/wenotheta.h``); this package holds its ctypes binding
+(:mod:`.binding`), the build step (:mod:`.build`) and seeded input generators
+(:mod:`.workloads`).
+"""
 from . import workloads  # noqa: F401
+from .binding import (  # noqa: F401
+    INF, WT_BURGERS, WT_EULER, WT_FP64, WT_LINEAR, WT_PERIODIC, WT_TRANSMISSIVE, Context, Grid,
+    LibraryMissing, Params, WenoThetaError, state_shape, wenotheta_rhs, wenotheta_solve,
+    wenotheta_step, wenotheta_sync, wenotheta_profile, wenotheta_profile_read)

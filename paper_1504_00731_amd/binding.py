@@ -1,0 +1,247 @@
+"""ctypes binding of libwenotheta.so (the C ABI of include/wenotheta.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Torch is used for device memory and streams.  The
+library must have been built (``paper_1504_00731_amd.build``); without it,
+every call raises ``LibraryMissing`` -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwenotheta.so")
+
+WT_OK, WT_ERR_ARG, WT_ERR_UNSUPPORTED, WT_ERR_NONPHYSICAL = 0, 1, 2, 3
+WT_ERR_NONFINITE, WT_ERR_DEVICE, WT_ERR_NOMEM = 4, 5, 6
+WT_LINEAR, WT_BURGERS, WT_EULER = 0, 1, 2
+WT_PERIODIC, WT_TRANSMISSIVE = 0, 1
+WT_FP64 = 0
+
+EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
+            "wenotheta_rhs", "wenotheta_step", "wenotheta_solve", "wenotheta_sync",
+            "wenotheta_profile", "wenotheta_profile_read")
+PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
+                 "sweep_z_final")
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class WenoThetaError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = _lib().wenotheta_status_string(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{what}: {msg} (status {code})")
+        self.code = code
+
+
+class wt_grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 3),
+                ("reserved1", ctypes.c_int32)]
+
+
+class wt_params(ctypes.Structure):
+    _fields_ = [("system", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("a", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("eps", ctypes.c_double), ("alpha_R", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(
+                f"{LIB_PATH} is not built; run `python -m paper_1504_00731_amd.build` "
+                "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        G, P = ctypes.POINTER(wt_grid), ctypes.POINTER(wt_params)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.wenotheta_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32]
+        L.wenotheta_ctx_destroy.argtypes = [vp]
+        L.wenotheta_status_string.argtypes = [ctypes.c_int32]
+        L.wenotheta_status_string.restype = ctypes.c_char_p
+        L.wenotheta_rhs.argtypes = [vp, G, P, vp, vp, dp, vp, vp]
+        L.wenotheta_step.argtypes = [vp, G, P, vp, ctypes.c_double, vp, vp]
+        L.wenotheta_solve.argtypes = [vp, G, P, vp, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int64, dp, ctypes.POINTER(ctypes.c_int64), vp]
+        L.wenotheta_sync.argtypes = [vp, vp]
+        L.wenotheta_profile.argtypes = [vp, ctypes.c_int32]
+        L.wenotheta_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        for name in EXPORTED:
+            if name != "wenotheta_status_string":
+                getattr(L, name).restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int, what: str):
+    if code != WT_OK:
+        raise WenoThetaError(code, what)
+
+
+@dataclass
+class Grid:
+    """Uniform grid: n points per dimension (x first), [lo, hi] per dimension, bc per dimension."""
+    n: tuple
+    lo: tuple
+    hi: tuple
+    bc: tuple
+
+    @property
+    def ndim(self) -> int:
+        return len(self.n)
+
+    def c_struct(self) -> wt_grid:
+        g = wt_grid()
+        g.ndim = self.ndim
+        for k in range(3):
+            inside = k < self.ndim
+            g.n[k] = int(self.n[k]) if inside else 1
+            g.lo[k] = float(self.lo[k]) if inside else 0.0
+            g.hi[k] = float(self.hi[k]) if inside else 1.0
+            g.bc[k] = int(self.bc[k]) if inside else 0
+        return g
+
+
+@dataclass
+class Params:
+    system: int = WT_EULER
+    a: float = 1.0
+    gamma: float = 1.4
+    cfl: float = 0.5
+    eps: float = 1e-10
+    alpha_R: float = 50.0
+    precision: int = WT_FP64
+
+    def c_struct(self) -> wt_params:
+        p = wt_params()
+        p.system, p.precision = int(self.system), int(self.precision)
+        p.a, p.gamma, p.cfl = float(self.a), float(self.gamma), float(self.cfl)
+        p.eps, p.alpha_R = float(self.eps), float(self.alpha_R)
+        return p
+
+
+class Context:
+    """Owns a wt_ctx (workspace on one device)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib().wenotheta_ctx_create(ctypes.byref(h), int(device)), "wenotheta_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib().wenotheta_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, name, shape=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def state_shape(grid: Grid, params: Params) -> tuple:
+    m = grid.ndim + 2 if params.system == WT_EULER else 1
+    return (m,) + tuple(reversed(tuple(int(v) for v in grid.n)))
+
+
+# --- the C entry points, same names ------------------------------------------------
+
+def wenotheta_rhs(ctx: Context, grid: Grid, params: Params, u, L_out, f=None, alpha_host=None,
+                  stream=None):
+    shp = state_shape(grid, params)
+    al = None
+    if alpha_host is not None:
+        vals = [float(v) for v in alpha_host]
+        al = (ctypes.c_double * len(vals))(*vals)
+    _check(_lib().wenotheta_rhs(ctx.handle, ctypes.byref(grid.c_struct()),
+                                ctypes.byref(params.c_struct()), _dev_ptr(u, "u", shp),
+                                _dev_ptr(f, "f", shp), al, _dev_ptr(L_out, "L_out", shp),
+                                _stream_ptr(stream)), "wenotheta_rhs")
+    return L_out
+
+
+def wenotheta_step(ctx: Context, grid: Grid, params: Params, u, dt=0.0, dt_used=None,
+                   stream=None):
+    shp = state_shape(grid, params)
+    _check(_lib().wenotheta_step(ctx.handle, ctypes.byref(grid.c_struct()),
+                                 ctypes.byref(params.c_struct()), _dev_ptr(u, "u", shp),
+                                 float(dt), _dev_ptr(dt_used, "dt_used", (1,)),
+                                 _stream_ptr(stream)), "wenotheta_step")
+    return u
+
+
+def wenotheta_solve(ctx: Context, grid: Grid, params: Params, u, t_end, t0=0.0, max_steps=-1,
+                    stream=None):
+    shp = state_shape(grid, params)
+    t = ctypes.c_double(0.0)
+    k = ctypes.c_int64(0)
+    _check(_lib().wenotheta_solve(ctx.handle, ctypes.byref(grid.c_struct()),
+                                  ctypes.byref(params.c_struct()), _dev_ptr(u, "u", shp),
+                                  float(t0), float(t_end), int(max_steps), ctypes.byref(t),
+                                  ctypes.byref(k), _stream_ptr(stream)), "wenotheta_solve")
+    return t.value, k.value
+
+
+def wenotheta_sync(ctx: Context, stream=None):
+    _check(_lib().wenotheta_sync(ctx.handle, _stream_ptr(stream)), "wenotheta_sync")
+
+
+def wenotheta_profile(ctx: Context, enable: bool):
+    _check(_lib().wenotheta_profile(ctx.handle, 1 if enable else 0), "wenotheta_profile")
+
+
+def wenotheta_profile_read(ctx: Context) -> dict:
+    """{kind: (total_ms, launches)} since profiling was enabled."""
+    ms = (ctypes.c_double * 6)()
+    cnt = (ctypes.c_int64 * 6)()
+    _check(_lib().wenotheta_profile_read(ctx.handle, ms, cnt, 6), "wenotheta_profile_read")
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_KINDS)}
+
+
+def loaded_library_path() -> str:
+    _lib()
+    return LIB_PATH
+
+
+INF = math.inf

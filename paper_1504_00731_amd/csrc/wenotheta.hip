@@ -1,0 +1,1065 @@
+// MI355X (gfx950) implementation of the WENO-theta C ABI declared in
+// include/wenotheta.h.
+//
+// Structure of one Runge-Kutta stage on an ndim-dimensional grid:
+//   * one "sweep" kernel per direction.  A block owns a tile of TX columns x
+//     TN points along the sweep direction; it stages the tile plus a 3-point
+//     halo on both sides (the stencil S^6 of the interfaces it owns) in LDS,
+//     converting each point once to the quantities the fluxes need, then one
+//     thread per interface computes the characteristic-wise WENO-theta flux
+//     (Roe basis, projection, Lax-Friedrichs split, two reconstructions per
+//     field, back-projection), and the cells take flux differences;
+//   * all sweeps but the last write / accumulate the divergence D; the last
+//     one forms L = -(D_x + D_y + D_z), applies the stage of the TVD
+//     Runge-Kutta scheme and, in an epilogue, reduces the Lax-Friedrichs
+//     speeds of the new state for the next stage (wave shuffles, then one
+//     atomic max per block and value, skipped when it cannot raise the value).
+//
+// Global quantities (Lax-Friedrichs speeds, dt, t, error flags) live in a
+// small device struct of the context, so a whole solve runs without host
+// round trips between steps.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "wenotheta.h"
+#include "wt_physics.hpp"
+#include "wt_weno.hpp"
+
+namespace wt {
+
+constexpr int kThreads = 256;
+constexpr int kSlots = 3;        // ring of Lax-Friedrichs speed slots
+constexpr int kSlotLen = 16;     // [dir * 5 + field]
+constexpr int kErrNonphysical = 1;
+constexpr int kErrNonfinite = 2;
+
+struct DevState {
+    unsigned long long alpha[kSlots][kSlotLen];  // non-negative doubles as bits
+    double dt;
+    double t;
+    double t_end;
+    long long steps;
+    long long max_steps;
+    int done;
+    int err;
+};
+
+// Sweep direction DIR, tile TX x TN with TX * (TN + 1) == kThreads interfaces.
+enum : int { MODE_FIRST = 0, MODE_MID = 1, MODE_LAST_RHS = 2, MODE_LAST_STAGE = 3 };
+
+struct SweepArgs {
+    const double *uin;     // state whose fluxes are taken
+    const double *u0;      // state at the start of the step (stages 2, 3)
+    double *out;           // L (rhs) or the next stage state
+    double *D;             // divergence accumulator (ndim > 1)
+    const double *fgiven;  // caller flux point values (1D scalar rhs) or null
+    DevState *st;
+    int64_t n[3];
+    int64_t ncell;
+    double dx;             // spacing along the sweep
+    double a;              // linear advection speed
+    double gamma, eps, alpha_R;
+    int bc;                // boundary condition along the sweep
+    int slot_rd, slot_wr, slot_zero;
+    int stage;             // 1..3 (MODE_LAST_STAGE)
+    int check_done;
+};
+
+__device__ __forceinline__ double bits_to_double(unsigned long long b)
+{
+    return __longlong_as_double(static_cast<long long>(b));
+}
+
+__device__ __forceinline__ unsigned long long double_to_bits(double d)
+{
+    return static_cast<unsigned long long>(__double_as_longlong(d));
+}
+
+// Boundary conditions as index maps (periodic wrap, zero-gradient clamp).
+__device__ __forceinline__ int64_t map_index(int64_t i, int64_t n, int bc)
+{
+    if (bc == WT_PERIODIC) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Raise slot[k] to v (v >= 0).  A relaxed device-scope read first skips the
+// atomic when the slot already holds at least v (values only increase
+// between the zeroing and the reading of a slot).
+__device__ __forceinline__ void slot_max(unsigned long long *p, double v)
+{
+    const unsigned long long vb = double_to_bits(v);
+    const unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (vb > cur) atomicMax(p, vb);
+}
+
+// Block-wide max of NV values per thread, then one slot update per value.
+template <int NV>
+__device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long long *slot,
+                                               const int (&slot_idx)[NV])
+{
+    __shared__ double red[NV][kThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double w = wave_max(v[k]);
+        if (lane == 0) red[k][wid] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x;
+        double m = red[k][0];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) m = red[k][w] > m ? red[k][w] : m;
+        slot_max(&slot[slot_idx[k]], m);
+    }
+}
+
+// Wave speeds of one cell (canonical state): per direction |u_d - c|, |u_d|,
+// |u_d + c|, with c = sqrt(gamma p / rho).  Returns an error bit mask.
+template <int NDIM>
+__device__ __forceinline__ int euler_speeds(const double *uc, double gamma, double *lam)
+{
+    double vel[NDIM], p, H;
+    const bool ok = euler_cell<NDIM>(uc, gamma, vel, p, H);
+    const double c = __builtin_sqrt(gamma * p / uc[0]);
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        lam[3 * d + 0] = __builtin_fabs(vel[d] - c);
+        lam[3 * d + 1] = __builtin_fabs(vel[d]);
+        lam[3 * d + 2] = __builtin_fabs(vel[d] + c);
+    }
+    if (ok) return 0;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < NDIM + 2; ++k) finite = finite && __builtin_isfinite(uc[k]);
+    return finite ? kErrNonphysical : kErrNonfinite;
+}
+
+// Lax-Friedrichs speed values per point: one per (direction, field), field
+// s of direction d taking |u_d - c|, |u_d|, |u_d + c| for s = 0, 1, 2 and
+// |u_d| for the shear fields.  Value k lives in slot entry d * 5 + s.
+template <int SYS, int NDIM>
+struct SpeedLayout {
+    static constexpr int M = Ncomp<SYS, NDIM>::value;
+    static constexpr int NV = SYS == SYS_EULER ? NDIM * M : 1;
+    __device__ static constexpr int slot_index(int k) { return SYS == SYS_EULER ? (k / M) * 5 + k % M : 0; }
+    __device__ static constexpr int lam_index(int k)
+    {
+        return 3 * (k / M) + (k % M < 3 ? k % M : 1);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Lax-Friedrichs speeds of a state (grid-stride reduction into one slot)
+// ---------------------------------------------------------------------------
+template <int SYS, int NDIM>
+__global__ __launch_bounds__(kThreads) void alpha_kernel(const double *u, int64_t ncell, double a,
+                                                         double gamma, DevState *st, int slot)
+{
+    constexpr int NV = SpeedLayout<SYS, NDIM>::NV;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    int err = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < ncell;
+         i += (int64_t)gridDim.x * kThreads) {
+        if constexpr (SYS == SYS_EULER) {
+            double uc[NDIM + 2], lam[3 * NDIM];
+#pragma unroll
+            for (int c = 0; c < NDIM + 2; ++c) uc[c] = u[c * ncell + i];
+            err |= euler_speeds<NDIM>(uc, gamma, lam);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const double l = lam[SpeedLayout<SYS, NDIM>::lam_index(k)];
+                v[k] = l > v[k] ? l : v[k];
+            }
+        } else {
+            const double x = u[i];
+            if (!__builtin_isfinite(x)) err |= kErrNonfinite;
+            const double sp = SYS == SYS_LINEAR ? __builtin_fabs(a) : __builtin_fabs(x);
+            v[0] = sp > v[0] ? sp : v[0];
+        }
+    }
+    if (err) atomicOr(&st->err, err);
+    int idx[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) idx[k] = SpeedLayout<SYS, NDIM>::slot_index(k);
+    block_slot_max<NV>(v, st->alpha[slot], idx);
+}
+
+// Set slot `slot` to the given values (or zero) and zero slot `zero_slot`.
+struct SlotValues {
+    double v[kSlotLen];
+};
+
+__global__ void set_slots_kernel(DevState *st, int slot, SlotValues vals, int zero_slot)
+{
+    const int k = threadIdx.x;
+    if (k < kSlotLen) {
+        st->alpha[slot][k] = double_to_bits(vals.v[k]);
+        if (zero_slot >= 0) st->alpha[zero_slot][k] = 0ull;
+    }
+}
+
+__device__ __forceinline__ double lf_speed(const DevState *st, int slot, int dir, int field)
+{
+    return bits_to_double(st->alpha[slot][dir * 5 + field]);
+}
+
+// ---------------------------------------------------------------------------
+// Step bookkeeping: dt from the speeds of the step's initial state
+// ---------------------------------------------------------------------------
+struct StepArgs {
+    DevState *st;
+    int slot;            // speeds of u^n
+    int ndim;
+    int euler;
+    double dx[3];
+    double cfl;
+    double dt_fixed;     // > 0: use it
+    int clip;            // solve mode: clip to t_end, honour max_steps
+};
+
+__global__ void step_begin_kernel(StepArgs A)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DevState *st = A.st;
+    if (st->done) return;
+    if (st->err) { st->done = 1; return; }
+    if (A.clip && (!(st->t < st->t_end) || (st->max_steps >= 0 && st->steps >= st->max_steps))) {
+        st->done = 1;
+        return;
+    }
+    double dt = A.dt_fixed;
+    if (!(dt > 0.0)) {
+        // dt = cfl / sum_d amax_d / dx_d, amax_d = max(|u_d| + c) = max(alpha_{d,0}, alpha_{d,2})
+        double s = 0.0;
+        for (int d = 0; d < A.ndim; ++d) {
+            double am;
+            if (A.euler) {
+                const double l0 = bits_to_double(st->alpha[A.slot][d * 5 + 0]);
+                const double l2 = bits_to_double(st->alpha[A.slot][d * 5 + 2]);
+                am = l2 > l0 ? l2 : l0;
+            } else {
+                am = bits_to_double(st->alpha[A.slot][0]);
+            }
+            s = d == 0 ? am / A.dx[0] : s + am / A.dx[d];
+        }
+        dt = A.cfl / s;
+    }
+    double t_next = st->t + dt;
+    if (A.clip) {
+        if (st->t + dt >= st->t_end - 1e-6 * dt) {
+            dt = st->t_end - st->t;
+            t_next = st->t_end;
+        }
+    }
+    st->dt = dt;
+    st->t = t_next;
+    st->steps = st->steps + 1;
+}
+
+__global__ void solve_init_kernel(DevState *st, double t0, double t_end, long long max_steps)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->t = t0;
+        st->t_end = t_end;
+        st->steps = 0;
+        st->max_steps = max_steps;
+        st->done = 0;
+    }
+}
+
+__global__ void copy_dt_kernel(const DevState *st, double *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = st->dt;
+}
+
+// ---------------------------------------------------------------------------
+// Sweep kernel
+// ---------------------------------------------------------------------------
+template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE>
+__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
+{
+    static_assert(TX * (TN + 1) == kThreads, "one interface per thread");
+    constexpr int M = Ncomp<SYS, NDIM>::value;
+    constexpr int NC = (TN + 6) * TX;           // staged points of the tile
+    constexpr bool EULER = SYS == SYS_EULER;
+    constexpr int NV = SpeedLayout<SYS, NDIM>::NV;
+
+    __shared__ double s_u[M][NC];
+    __shared__ double s_f[EULER ? 1 : NC];       // scalar: flux values
+    __shared__ double s_v[EULER ? NDIM : 1][EULER ? NC : 1];
+    __shared__ double s_p[EULER ? NC : 1];
+    __shared__ double s_sr[EULER ? NC : 1];
+    __shared__ double s_H[EULER ? NC : 1];
+    __shared__ double s_F[M][kThreads];
+
+    DevState *st = A.st;
+    if (A.check_done && st->done) return;
+
+    const int64_t nx = A.n[0], ny = A.n[1], nz = A.n[2];
+    const int64_t nd = A.n[DIR];
+    const int64_t nseg = (nd + TN - 1) / TN;
+    const int64_t ngx = DIR == 0 ? 1 : (nx + TX - 1) / TX;
+
+    // block -> (x0, seg, base): base is the offset of sweep index 0 of column x0
+    int64_t b = blockIdx.x, seg, x0 = 0, base;
+    int64_t sstride;
+    if constexpr (DIR == 0) {
+        seg = b % nseg;
+        const int64_t row = b / nseg;            // y + z * ny
+        base = row * nx;
+        sstride = 1;
+    } else if constexpr (DIR == 1) {
+        const int64_t gx = b % ngx;
+        const int64_t r = b / ngx;
+        seg = r % nseg;
+        const int64_t z = r / nseg;
+        x0 = gx * TX;
+        base = z * nx * ny + x0;
+        sstride = nx;
+    } else {
+        const int64_t gx = b % ngx;
+        const int64_t r = b / ngx;
+        seg = r % nseg;
+        const int64_t y = r / nseg;
+        x0 = gx * TX;
+        base = y * nx + x0;
+        sstride = nx * ny;
+    }
+    const int64_t g0 = seg * TN;                 // first owned point along the sweep
+    const int64_t ncell = A.ncell;
+
+    // ---- stage the tile (owned points + 3-point halos) ----
+    int err = 0;
+    for (int i = threadIdx.x; i < NC; i += kThreads) {
+        const int r = i / TX, cx = i % TX;
+        const int64_t g = map_index(g0 - 3 + r, nd, A.bc);
+        int64_t xo = cx;
+        if constexpr (DIR != 0) xo = x0 + cx < nx ? cx : nx - 1 - x0;
+        const int64_t idx = base + g * sstride + xo;
+        if constexpr (EULER) {
+            double uc[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) uc[c] = A.uin[c * ncell + idx];
+            double vel[NDIM], p, H;
+            const bool ok = euler_cell<NDIM>(uc, A.gamma, vel, p, H);
+            if (!ok) {
+                bool fin = true;
+#pragma unroll
+                for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
+                err |= fin ? kErrNonphysical : kErrNonfinite;
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) s_u[c][i] = uc[c];
+#pragma unroll
+            for (int k = 0; k < NDIM; ++k) s_v[k][i] = vel[k];
+            s_p[i] = p;
+            s_sr[i] = __builtin_sqrt(uc[0]);
+            s_H[i] = H;
+        } else {
+            const double x = A.uin[idx];
+            double f;
+            if (A.fgiven) f = A.fgiven[idx];
+            else if constexpr (SYS == SYS_LINEAR) f = A.a * x;
+            else f = 0.5 * x * x;
+            if (!__builtin_isfinite(x) || !__builtin_isfinite(f)) err |= kErrNonfinite;
+            s_u[0][i] = x;
+            s_f[i] = f;
+        }
+    }
+    if (err) atomicOr(&st->err, err);
+    __syncthreads();
+
+    // ---- one interface per thread: interface between points it-1 and it ----
+    {
+        const int t = threadIdx.x;
+        const int it = t / TX, cx = t % TX;
+        const bool valid = (DIR == 0 || x0 + cx < nx) && g0 + it <= nd;
+        if (valid) {
+            if constexpr (EULER) {
+                constexpr int NT = NDIM - 1;
+                double velL[NDIM], velR[NDIM];
+#pragma unroll
+                for (int k = 0; k < NDIM; ++k) {
+                    velL[k] = s_v[k][t + 2 * TX];
+                    velR[k] = s_v[k][t + 3 * TX];
+                }
+                const RoeBasis<NDIM> B = roe_basis<NDIM, DIR>(s_sr[t + 2 * TX], velL, s_H[t + 2 * TX],
+                                                              s_sr[t + 3 * TX], velR, s_H[t + 3 * TX],
+                                                              A.gamma);
+                if (!B.ok) atomicOr(&st->err, kErrNonphysical);
+                double hs[M];
+#pragma unroll
+                for (int s = 0; s < M; ++s) {
+                    const double al = lf_speed(st, A.slot_rd, DIR, s);
+                    double vp[6], vm[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const int i = t + k * TX;
+                        // permuted state and normal flux of point k
+                        const double U0 = s_u[0][i];
+                        const double Un = s_u[1 + DIR][i];
+                        double Ut[NT > 0 ? NT : 1], vt[NT > 0 ? NT : 1];
+#pragma unroll
+                        for (int q = 0; q < NT; ++q) {
+                            Ut[q] = s_u[1 + tangential_axis<DIR>(q)][i];
+                            vt[q] = s_v[tangential_axis<DIR>(q)][i];
+                        }
+                        const double UE = s_u[NDIM + 1][i];
+                        const double vn = s_v[DIR][i];
+                        const double p = s_p[i];
+                        const double f0 = Un;
+                        const double f1 = Un * vn + p;
+                        const double fE = vn * (UE + p);
+                        double q, w;
+                        if (s == 0 || s == 1 || s == 2) {
+                            const double ln0 = s == 0 ? B.l0n0 : (s == 1 ? B.l1n0 : B.l2n0);
+                            const double ln1 = s == 0 ? B.l0n1 : (s == 1 ? B.l1n1 : B.l2n1);
+                            const double lE = s == 0 ? B.l0E : (s == 1 ? B.l1E : B.l2E);
+                            q = ln0 * U0 + ln1 * Un;
+                            w = ln0 * f0 + ln1 * f1;
+#pragma unroll
+                            for (int q2 = 0; q2 < NT; ++q2) {
+                                const double lt = s == 0 ? B.l0t[q2] : (s == 1 ? B.l1t[q2] : B.l2t[q2]);
+                                q = q + lt * Ut[q2];
+                                w = w + lt * (Un * vt[q2]);
+                            }
+                            q = q + lE * UE;
+                            w = w + lE * fE;
+                        } else {
+                            // shear field of tangential direction s - 3: row (-u_t, 0, .., 1, .., 0)
+                            const int tq = s - 3;
+                            const double nut = -B.ut[tq];
+                            q = nut * U0 + Ut[tq];
+                            w = nut * f0 + Un * vt[tq];
+                        }
+                        vp[k] = 0.5 * (w + al * q);
+                        vm[5 - k] = 0.5 * (w - al * q);
+                    }
+                    hs[s] = weno_theta(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], A.eps, A.alpha_R) +
+                            weno_theta(vm[0], vm[1], vm[2], vm[3], vm[4], vm[5], A.eps, A.alpha_R);
+                }
+                // back-projection F = R h: acoustic pair, then entropy, then shear
+                const double un = B.un, c = B.c;
+                double Fp[M];
+                Fp[0] = (hs[0] + hs[2]) + hs[1];
+                Fp[1] = ((un - c) * hs[0] + (un + c) * hs[2]) + un * hs[1];
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    const double ut = B.ut[q];
+                    Fp[2 + q] = ((ut * hs[0] + ut * hs[2]) + ut * hs[1]) + hs[3 + q];
+                }
+                {
+                    double e = (B.H - un * c) * hs[0] + (B.H + un * c) * hs[2];
+                    e = e + B.q2 * hs[1];
+#pragma unroll
+                    for (int q = 0; q < NT; ++q) e = e + B.ut[q] * hs[3 + q];
+                    Fp[M - 1] = e;
+                }
+                // back to canonical component order
+                s_F[0][t] = Fp[0];
+                s_F[1 + DIR][t] = Fp[1];
+#pragma unroll
+                for (int q = 0; q < NT; ++q) s_F[1 + tangential_axis<DIR>(q)][t] = Fp[2 + q];
+                s_F[M - 1][t] = Fp[M - 1];
+            } else {
+                const double al = bits_to_double(st->alpha[A.slot_rd][0]);
+                double vp[6], vm[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const int i = t + k * TX;
+                    const double x = s_u[0][i], f = s_f[i];
+                    vp[k] = 0.5 * (f + al * x);
+                    vm[5 - k] = 0.5 * (f - al * x);
+                }
+                s_F[0][t] = weno_theta(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], A.eps, A.alpha_R) +
+                            weno_theta(vm[0], vm[1], vm[2], vm[3], vm[4], vm[5], A.eps, A.alpha_R);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- cells: flux differences, then the mode's update ----
+    double spd[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) spd[k] = 0.0;
+    int err2 = 0;
+    if (threadIdx.x < TN * TX) {
+        const int t = threadIdx.x;
+        const int it = t / TX, cx = t % TX;
+        const int64_t g = g0 + it;
+        if ((DIR == 0 || x0 + cx < nx) && g < nd) {
+            const int64_t idx = base + g * sstride + cx;
+            double Lc[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double Dd = (s_F[c][t + TX] - s_F[c][t]) / A.dx;
+                const int64_t o = c * ncell + idx;
+                if constexpr (MODE == MODE_FIRST) {
+                    A.D[o] = Dd;
+                } else if constexpr (MODE == MODE_MID) {
+                    A.D[o] = A.D[o] + Dd;
+                } else {
+                    if constexpr (NDIM == 1) Lc[c] = -Dd;
+                    else Lc[c] = -(A.D[o] + Dd);
+                }
+            }
+            if constexpr (MODE == MODE_LAST_RHS) {
+#pragma unroll
+                for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = Lc[c];
+            } else if constexpr (MODE == MODE_LAST_STAGE) {
+                const double dt = st->dt;
+                double un[M];
+                if (A.stage == 1) {
+#pragma unroll
+                    for (int c = 0; c < M; ++c) {
+                        const int64_t o = c * ncell + idx;
+                        un[c] = A.uin[o] + dt * Lc[c];
+                    }
+                } else if (A.stage == 2) {
+                    const double cdt = 0.25 * dt;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) {
+                        const int64_t o = c * ncell + idx;
+                        un[c] = 0.75 * A.u0[o] + 0.25 * A.uin[o] + cdt * Lc[c];
+                    }
+                } else {
+                    const double cdt = (2.0 / 3.0) * dt;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) {
+                        const int64_t o = c * ncell + idx;
+                        un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * A.uin[o] + cdt * Lc[c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = un[c];
+                // Lax-Friedrichs speeds of the new state
+                if constexpr (EULER) {
+                    double lam[3 * NDIM];
+                    err2 |= euler_speeds<NDIM>(un, A.gamma, lam);
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) spd[k] = lam[SpeedLayout<SYS, NDIM>::lam_index(k)];
+                } else {
+                    if (!__builtin_isfinite(un[0])) err2 |= kErrNonfinite;
+                    spd[0] = SYS == SYS_LINEAR ? __builtin_fabs(A.a) : __builtin_fabs(un[0]);
+                }
+            }
+        }
+    }
+    if constexpr (MODE == MODE_LAST_STAGE) {
+        if (err2) atomicOr(&st->err, err2);
+        int sidx[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sidx[k] = SpeedLayout<SYS, NDIM>::slot_index(k);
+        block_slot_max<NV>(spd, st->alpha[A.slot_wr], sidx);
+        if (blockIdx.x == 0 && threadIdx.x < kSlotLen)
+            __hip_atomic_store(&st->alpha[A.slot_zero][threadIdx.x], 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <int DIR>
+struct TileShape;
+template <>
+struct TileShape<0> { static constexpr int TX = 1, TN = 255; };
+template <>
+struct TileShape<1> { static constexpr int TX = 8, TN = 31; };
+template <>
+struct TileShape<2> { static constexpr int TX = 8, TN = 31; };
+
+template <int SYS, int NDIM, int DIR, int MODE>
+hipError_t launch_sweep(const SweepArgs &A, hipStream_t s)
+{
+    constexpr int TX = TileShape<DIR>::TX, TN = TileShape<DIR>::TN;
+    const int64_t nd = A.n[DIR];
+    const int64_t nseg = (nd + TN - 1) / TN;
+    int64_t blocks;
+    if (DIR == 0) blocks = nseg * A.n[1] * A.n[2];
+    else if (DIR == 1) blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[2];
+    else blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[1];
+    hipLaunchKernelGGL((sweep_kernel<SYS, NDIM, DIR, TX, TN, MODE>), dim3((unsigned)blocks),
+                       dim3(kThreads), 0, s, A);
+    return hipGetLastError();
+}
+
+template <int SYS, int NDIM, int DIR>
+hipError_t launch_sweep_mode(int mode, const SweepArgs &A, hipStream_t s)
+{
+    switch (mode) {
+        case MODE_FIRST: return launch_sweep<SYS, NDIM, DIR, MODE_FIRST>(A, s);
+        case MODE_MID: return launch_sweep<SYS, NDIM, DIR, MODE_MID>(A, s);
+        case MODE_LAST_RHS: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_RHS>(A, s);
+        default: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_STAGE>(A, s);
+    }
+}
+
+template <int SYS, int NDIM>
+hipError_t launch_sweep_dir(int dir, int mode, const SweepArgs &A, hipStream_t s)
+{
+    if (dir == 0) return launch_sweep_mode<SYS, NDIM, 0>(mode, A, s);
+    if constexpr (NDIM > 1)
+        if (dir == 1) return launch_sweep_mode<SYS, NDIM, 1>(mode, A, s);
+    if constexpr (NDIM > 2)
+        if (dir == 2) return launch_sweep_mode<SYS, NDIM, 2>(mode, A, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_any(int sys, int ndim, int dir, int mode, const SweepArgs &A, hipStream_t s)
+{
+    if (sys == SYS_LINEAR) return launch_sweep_dir<SYS_LINEAR, 1>(dir, mode, A, s);
+    if (sys == SYS_BURGERS) return launch_sweep_dir<SYS_BURGERS, 1>(dir, mode, A, s);
+    if (ndim == 1) return launch_sweep_dir<SYS_EULER, 1>(dir, mode, A, s);
+    if (ndim == 2) return launch_sweep_dir<SYS_EULER, 2>(dir, mode, A, s);
+    return launch_sweep_dir<SYS_EULER, 3>(dir, mode, A, s);
+}
+
+hipError_t launch_alpha(int sys, int ndim, const double *u, int64_t ncell, double a, double gamma,
+                        DevState *st, int slot, hipStream_t s)
+{
+    int64_t blocks = (ncell + kThreads - 1) / kThreads;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    const dim3 g((unsigned)blocks), bl(kThreads);
+    if (sys == SYS_LINEAR)
+        hipLaunchKernelGGL((alpha_kernel<SYS_LINEAR, 1>), g, bl, 0, s, u, ncell, a, gamma, st, slot);
+    else if (sys == SYS_BURGERS)
+        hipLaunchKernelGGL((alpha_kernel<SYS_BURGERS, 1>), g, bl, 0, s, u, ncell, a, gamma, st, slot);
+    else if (ndim == 1)
+        hipLaunchKernelGGL((alpha_kernel<SYS_EULER, 1>), g, bl, 0, s, u, ncell, a, gamma, st, slot);
+    else if (ndim == 2)
+        hipLaunchKernelGGL((alpha_kernel<SYS_EULER, 2>), g, bl, 0, s, u, ncell, a, gamma, st, slot);
+    else
+        hipLaunchKernelGGL((alpha_kernel<SYS_EULER, 3>), g, bl, 0, s, u, ncell, a, gamma, st, slot);
+    return hipGetLastError();
+}
+
+}  // namespace wt
+
+// ---------------------------------------------------------------------------
+// Context and C ABI
+// ---------------------------------------------------------------------------
+// Per-kernel timing with HIP events recorded on the launch stream around each
+// sweep launch (enabled by wenotheta_profile).  Kinds: sweep direction d in
+// its non-final role (d) or as the final sweep of a stage or RHS (3 + d).
+constexpr int kProfKinds = 6;
+constexpr int kProfPairs = 4096;
+
+struct wt_ctx {
+    int device = 0;
+    wt::DevState *st = nullptr;
+    double *U1 = nullptr, *U2 = nullptr, *D = nullptr;
+    size_t cap = 0;       // doubles per workspace buffer
+    int64_t g = 0;        // stage counter (selects the speed slots)
+    // profiler
+    bool prof = false;
+    hipEvent_t ev[2 * kProfPairs] = {};
+    int ev_kind[kProfPairs] = {};
+    int nev = 0;
+    double prof_ms[kProfKinds] = {};
+    int64_t prof_n[kProfKinds] = {};
+    int64_t prof_dropped = 0;
+};
+
+namespace {
+
+using namespace wt;
+
+struct Shape {
+    int ndim;
+    int m;
+    int64_t n[3];
+    int64_t ncell;
+    double dx[3];
+    int bc[3];
+};
+
+wt_status validate(const wt_grid *G, const wt_params *P, Shape &S)
+{
+    if (!G || !P) return WT_ERR_ARG;
+    if (G->ndim < 1 || G->ndim > 3) return WT_ERR_ARG;
+    if (P->system < WT_LINEAR || P->system > WT_EULER) return WT_ERR_ARG;
+    if (P->precision != WT_FP64) return WT_ERR_UNSUPPORTED;
+    if (P->system != WT_EULER && G->ndim != 1) return WT_ERR_UNSUPPORTED;
+    if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0)) return WT_ERR_ARG;
+    if (P->system == WT_EULER && !(P->gamma > 1.0)) return WT_ERR_ARG;
+    if (P->system == WT_LINEAR && !std::isfinite(P->a)) return WT_ERR_ARG;
+    S.ndim = G->ndim;
+    S.m = P->system == WT_EULER ? G->ndim + 2 : 1;
+    S.ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (k < G->ndim) {
+            if (G->n[k] < 6 || G->n[k] > (int64_t(1) << 31)) return WT_ERR_ARG;
+            if (!(G->hi[k] > G->lo[k])) return WT_ERR_ARG;
+            if (G->bc[k] != WT_PERIODIC && G->bc[k] != WT_TRANSMISSIVE) return WT_ERR_ARG;
+            S.n[k] = G->n[k];
+            S.dx[k] = (G->hi[k] - G->lo[k]) / (double)G->n[k];
+            S.bc[k] = G->bc[k];
+        } else {
+            if (G->n[k] != 1) return WT_ERR_ARG;
+            S.n[k] = 1;
+            S.dx[k] = 1.0;
+            S.bc[k] = WT_PERIODIC;
+        }
+        S.ncell *= S.n[k];
+    }
+    if (S.ncell * S.m > (int64_t(1) << 40)) return WT_ERR_ARG;
+    return WT_OK;
+}
+
+wt_status ensure_workspace(wt_ctx *c, const Shape &S)
+{
+    const size_t need = (size_t)S.ncell * (size_t)S.m;
+    if (need <= c->cap) return WT_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    (void)hipFree(c->U1);
+    (void)hipFree(c->U2);
+    (void)hipFree(c->D);
+    c->U1 = c->U2 = c->D = nullptr;
+    c->cap = 0;
+    if (hipMalloc(&c->U1, need * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->U2, need * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->D, need * sizeof(double)) != hipSuccess) {
+        (void)hipFree(c->U1);
+        (void)hipFree(c->U2);
+        (void)hipFree(c->D);
+        c->U1 = c->U2 = c->D = nullptr;
+        (void)hipGetLastError();
+        return WT_ERR_NOMEM;
+    }
+    c->cap = need;
+    return WT_OK;
+}
+
+// Launch one sweep, bracketed by profiling events when enabled.
+hipError_t timed_sweep(wt_ctx *c, int sys, int ndim, int dir, int mode, const SweepArgs &A,
+                       hipStream_t s)
+{
+    const bool rec = c->prof && c->nev < kProfPairs;
+    if (c->prof && !rec) c->prof_dropped++;
+    if (rec && hipEventRecord(c->ev[2 * c->nev], s) != hipSuccess) return hipErrorUnknown;
+    const hipError_t e = launch_sweep_any(sys, ndim, dir, mode, A, s);
+    if (e != hipSuccess) return e;
+    if (rec) {
+        if (hipEventRecord(c->ev[2 * c->nev + 1], s) != hipSuccess) return hipErrorUnknown;
+        c->ev_kind[c->nev] = (mode == MODE_LAST_RHS || mode == MODE_LAST_STAGE ? 3 : 0) + dir;
+        c->nev++;
+    }
+    return hipSuccess;
+}
+
+// Fold the recorded (completed) event pairs into the per-kind totals.
+void drain_profile(wt_ctx *c)
+{
+    for (int k = 0; k < c->nev; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess) {
+            c->prof_ms[c->ev_kind[k]] += ms;
+            c->prof_n[c->ev_kind[k]] += 1;
+        }
+    }
+    c->nev = 0;
+}
+
+SweepArgs base_args(wt_ctx *c, const Shape &S, const wt_params *P)
+{
+    SweepArgs A{};
+    A.st = c->st;
+    for (int k = 0; k < 3; ++k) A.n[k] = S.n[k];
+    A.ncell = S.ncell;
+    A.a = P->a;
+    A.gamma = P->gamma;
+    A.eps = P->eps;
+    A.alpha_R = P->alpha_R;
+    A.D = c->D;
+    return A;
+}
+
+// Queue the speeds of u into slot g % 3 and zero slot (g + 1) % 3.
+wt_status queue_alpha_init(wt_ctx *c, const Shape &S, const wt_params *P, const double *u,
+                           hipStream_t s)
+{
+    const int rd = (int)(c->g % kSlots), nx = (int)((c->g + 1) % kSlots);
+    SlotValues zero{};
+    hipLaunchKernelGGL(set_slots_kernel, dim3(1), dim3(64), 0, s, c->st, rd, zero, nx);
+    if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    if (launch_alpha(P->system, S.ndim, u, S.ncell, P->a, P->gamma, c->st, rd, s) != hipSuccess)
+        return WT_ERR_DEVICE;
+    return WT_OK;
+}
+
+// One Runge-Kutta stage: uin -> out, reading speeds of uin from slot g % 3 and
+// writing those of out into slot (g + 1) % 3.
+wt_status queue_stage(wt_ctx *c, const Shape &S, const wt_params *P, const double *uin,
+                      const double *u0, double *out, int stage, hipStream_t s)
+{
+    SweepArgs A = base_args(c, S, P);
+    A.uin = uin;
+    A.u0 = u0;
+    A.out = out;
+    A.stage = stage;
+    A.check_done = 1;
+    A.slot_rd = (int)(c->g % kSlots);
+    A.slot_wr = (int)((c->g + 1) % kSlots);
+    A.slot_zero = (int)((c->g + 2) % kSlots);
+    for (int d = 0; d < S.ndim; ++d) {
+        const int mode = d == S.ndim - 1 ? MODE_LAST_STAGE : (d == 0 ? MODE_FIRST : MODE_MID);
+        A.dx = S.dx[d];
+        A.bc = S.bc[d];
+        if (timed_sweep(c, P->system, S.ndim, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
+    }
+    c->g += 1;
+    return WT_OK;
+}
+
+wt_status queue_step(wt_ctx *c, const Shape &S, const wt_params *P, double *u, double dt_fixed,
+                     int clip, hipStream_t s)
+{
+    StepArgs B{};
+    B.st = c->st;
+    B.slot = (int)(c->g % kSlots);
+    B.ndim = S.ndim;
+    B.euler = P->system == WT_EULER;
+    for (int k = 0; k < 3; ++k) B.dx[k] = S.dx[k];
+    B.cfl = P->cfl;
+    B.dt_fixed = dt_fixed;
+    B.clip = clip;
+    hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(64), 0, s, B);
+    if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    wt_status r;
+    if ((r = queue_stage(c, S, P, u, u, c->U1, 1, s))) return r;
+    if ((r = queue_stage(c, S, P, c->U1, u, c->U2, 2, s))) return r;
+    if ((r = queue_stage(c, S, P, c->U2, u, u, 3, s))) return r;
+    return WT_OK;
+}
+
+// Read and clear the device error word (synchronises the stream).
+wt_status collect(wt_ctx *c, hipStream_t s, DevState *host)
+{
+    if (hipMemcpyAsync(host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return WT_ERR_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
+    drain_profile(c);
+    int e = host->err;
+    if (e) {
+        const int zero = 0;
+        if (hipMemcpyAsync(&c->st->err, &zero, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return WT_ERR_DEVICE;
+    }
+    if (e & kErrNonfinite) return WT_ERR_NONFINITE;
+    if (e & kErrNonphysical) return WT_ERR_NONPHYSICAL;
+    return WT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wenotheta_status_string(int32_t s)
+{
+    switch (s) {
+        case WT_OK: return "ok";
+        case WT_ERR_ARG: return "invalid argument";
+        case WT_ERR_UNSUPPORTED: return "unsupported configuration";
+        case WT_ERR_NONPHYSICAL: return "non-physical state (rho <= 0 or p <= 0)";
+        case WT_ERR_NONFINITE: return "non-finite value";
+        case WT_ERR_DEVICE: return "HIP device error";
+        case WT_ERR_NOMEM: return "out of device memory";
+        default: return "unknown status";
+    }
+}
+
+wt_status wenotheta_ctx_create(wt_ctx **out, int32_t device)
+{
+    if (!out) return WT_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return WT_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return WT_ERR_DEVICE;
+    wt_ctx *c = new (std::nothrow) wt_ctx();
+    if (!c) return WT_ERR_NOMEM;
+    c->device = device;
+    if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess) {
+        delete c;
+        return WT_ERR_NOMEM;
+    }
+    if (hipMemset(c->st, 0, sizeof(DevState)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(c->st);
+        delete c;
+        return WT_ERR_DEVICE;
+    }
+    *out = c;
+    return WT_OK;
+}
+
+wt_status wenotheta_ctx_destroy(wt_ctx *c)
+{
+    if (!c) return WT_ERR_ARG;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->U1);
+    (void)hipFree(c->U2);
+    (void)hipFree(c->D);
+    (void)hipFree(c->st);
+    for (int k = 0; k < 2 * kProfPairs; ++k)
+        if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    delete c;
+    return WT_OK;
+}
+
+wt_status wenotheta_profile(wt_ctx *c, int32_t enable)
+{
+    if (!c) return WT_ERR_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    if (enable && !c->ev[0]) {
+        for (int k = 0; k < 2 * kProfPairs; ++k)
+            if (hipEventCreate(&c->ev[k]) != hipSuccess) return WT_ERR_DEVICE;
+    }
+    c->prof = enable != 0;
+    c->nev = 0;
+    for (int k = 0; k < kProfKinds; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    c->prof_dropped = 0;
+    return WT_OK;
+}
+
+wt_status wenotheta_profile_read(wt_ctx *c, double *ms, int64_t *count, int32_t nkinds)
+{
+    if (!c || !ms || !count || nkinds < kProfKinds) return WT_ERR_ARG;
+    for (int k = 0; k < kProfKinds; ++k) {
+        ms[k] = c->prof_ms[k];
+        count[k] = c->prof_n[k];
+    }
+    return c->prof_dropped ? WT_ERR_ARG : WT_OK;
+}
+
+wt_status wenotheta_rhs(wt_ctx *c, const wt_grid *G, const wt_params *P, const double *u,
+                        const double *f, const double *alpha_host, double *L, void *stream)
+{
+    if (!c || !u || !L) return WT_ERR_ARG;
+    Shape S;
+    wt_status r = validate(G, P, S);
+    if (r) return r;
+    if (f && (P->system == WT_EULER || !alpha_host)) return WT_ERR_ARG;
+    if (alpha_host)
+        for (int k = 0; k < S.ndim * S.m; ++k)
+            if (!(alpha_host[k] >= 0.0) || !std::isfinite(alpha_host[k])) return WT_ERR_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    if ((r = ensure_workspace(c, S))) return r;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha_host) {
+        SlotValues v{};
+        for (int d = 0; d < S.ndim; ++d)
+            for (int k = 0; k < S.m; ++k) v.v[d * 5 + k] = alpha_host[d * S.m + k];
+        hipLaunchKernelGGL(set_slots_kernel, dim3(1), dim3(64), 0, s, c->st, (int)(c->g % kSlots), v, -1);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    } else if ((r = queue_alpha_init(c, S, P, u, s))) {
+        return r;
+    }
+    SweepArgs A = base_args(c, S, P);
+    A.uin = u;
+    A.out = L;
+    A.fgiven = f;
+    A.check_done = 0;
+    A.slot_rd = (int)(c->g % kSlots);
+    for (int d = 0; d < S.ndim; ++d) {
+        const int mode = d == S.ndim - 1 ? MODE_LAST_RHS : (d == 0 ? MODE_FIRST : MODE_MID);
+        A.dx = S.dx[d];
+        A.bc = S.bc[d];
+        if (timed_sweep(c, P->system, S.ndim, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
+    }
+    return WT_OK;
+}
+
+wt_status wenotheta_step(wt_ctx *c, const wt_grid *G, const wt_params *P, double *u, double dt,
+                         double *dt_used, void *stream)
+{
+    if (!c || !u) return WT_ERR_ARG;
+    Shape S;
+    wt_status r = validate(G, P, S);
+    if (r) return r;
+    if (!std::isfinite(dt)) return WT_ERR_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    if ((r = ensure_workspace(c, S))) return r;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, 0.0, 0.0, -1ll);
+    if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    if ((r = queue_alpha_init(c, S, P, u, s))) return r;
+    if ((r = queue_step(c, S, P, u, dt > 0.0 ? dt : 0.0, 0, s))) return r;
+    if (dt_used) {
+        hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, s, c->st, dt_used);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    }
+    return WT_OK;
+}
+
+wt_status wenotheta_solve(wt_ctx *c, const wt_grid *G, const wt_params *P, double *u, double t0,
+                          double t_end, int64_t max_steps, double *t_out, int64_t *steps_out,
+                          void *stream)
+{
+    if (!c || !u) return WT_ERR_ARG;
+    Shape S;
+    wt_status r = validate(G, P, S);
+    if (r) return r;
+    if (std::isnan(t0) || std::isnan(t_end) || !std::isfinite(t0)) return WT_ERR_ARG;
+    if (!std::isfinite(t_end) && max_steps < 0) return WT_ERR_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    if ((r = ensure_workspace(c, S))) return r;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, t0, t_end,
+                       (long long)max_steps);
+    if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    if ((r = queue_alpha_init(c, S, P, u, s))) return r;
+    DevState host{};
+    int64_t launched = 0;
+    int64_t chunk = 1;
+    for (;;) {
+        int64_t k = chunk;
+        if (max_steps >= 0 && launched + k > max_steps) k = max_steps - launched;
+        for (int64_t i = 0; i < k; ++i)
+            if ((r = queue_step(c, S, P, u, 0.0, 1, s))) return r;
+        launched += k;
+        if ((r = collect(c, s, &host))) return r;
+        if (host.done || (max_steps >= 0 && launched >= max_steps)) break;
+        if (chunk < 64) chunk *= 2;
+    }
+    if (t_out) *t_out = host.t;
+    if (steps_out) *steps_out = host.steps;
+    return WT_OK;
+}
+
+wt_status wenotheta_sync(wt_ctx *c, void *stream)
+{
+    if (!c) return WT_ERR_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    DevState host{};
+    return collect(c, (hipStream_t)stream, &host);
+}
+
+}  // extern "C"

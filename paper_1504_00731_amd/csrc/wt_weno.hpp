@@ -1,0 +1,96 @@
+// WENO-theta interface reconstruction, FP64 device code for gfx950.
+//
+// One call reconstructs the value of the numerical flux h at x_{j+1/2} from
+// the six split flux values f_{j-2} .. f_{j+3} of the stencil S^6:
+//   * four 3-point candidate fluxes, those of S0, S1, S2 (Sec. 2.2) and of the
+//     most downwind S3 (Sec. 2.3);
+//   * the central smoothness indicators beta~_k (Sec. 3.1), beta~_3 measured
+//     on the extended sub-stencil {x_j .. x_{j+3}} in its modified form;
+//   * the restriction: all beta~_k become 0 when
+//     max_k beta~_k / (eps + min_k beta~_k) <= alpha_R (Sec. 3.1);
+//   * tau_5 and tau_6, the indicators of S^5 and S^6, and the switch
+//     (tau, theta) = (tau_6, 0) if tau_6 < tau_5 else (tau_5, 1);
+//   * gamma^theta (theta = 1: 5th-order upwind weights, theta = 0: 6th-order
+//     central weights) and omega_k = alpha_k / sum alpha_l with
+//     alpha_k = gamma_k (1 + tau / (eps + beta~_k)) (Sec. 3).
+//
+// Exactness contract: the file is compiled without floating-point
+// contraction and every quantity is formed by the same sequence of IEEE
+// double operations (same association, same constants) as the plain
+// definition of each formula, so the result is bit-identical to any other
+// evaluation of the formulas in that order.  The theta and restriction
+// decisions therefore never flip against such a reference.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+namespace wt {
+
+// Linear weights gamma^theta_k = (1+theta)/20, 3(3+theta)/20, 3(3-theta)/20,
+// (1-theta)/20, folded for the two values theta takes.
+struct GammaTheta {
+    static constexpr double g0_t0 = (1.0 / 20.0) * (1.0 + 0.0);
+    static constexpr double g1_t0 = (3.0 / 20.0) * (3.0 + 0.0);
+    static constexpr double g2_t0 = (3.0 / 20.0) * (3.0 - 0.0);
+    static constexpr double g3_t0 = (1.0 / 20.0) * (1.0 - 0.0);
+    static constexpr double g0_t1 = (1.0 / 20.0) * (1.0 + 1.0);
+    static constexpr double g1_t1 = (3.0 / 20.0) * (3.0 + 1.0);
+    static constexpr double g2_t1 = (3.0 / 20.0) * (3.0 - 1.0);
+    static constexpr double g3_t1 = (1.0 / 20.0) * (1.0 - 1.0);
+};
+
+__device__ __forceinline__ double sq(double x) { return x * x; }
+
+// s0..s5 = f_{j-2} .. f_{j+3}.
+__device__ __forceinline__ double weno_theta(double s0, double s1, double s2, double s3,
+                                             double s4, double s5, double eps, double alpha_R)
+{
+    // candidate fluxes
+    const double q0 = (2.0 / 6.0) * s0 - (7.0 / 6.0) * s1 + (11.0 / 6.0) * s2;
+    const double q1 = -(1.0 / 6.0) * s1 + (5.0 / 6.0) * s2 + (2.0 / 6.0) * s3;
+    const double q2 = (2.0 / 6.0) * s2 + (5.0 / 6.0) * s3 - (1.0 / 6.0) * s4;
+    const double q3 = (11.0 / 6.0) * s3 - (7.0 / 6.0) * s4 + (2.0 / 6.0) * s5;
+
+    // central smoothness indicators
+    double b0 = (13.0 / 12.0) * sq(s0 - 2.0 * s1 + s2) + sq(s0 - 3.0 * s1 + 2.0 * s2);
+    double b1 = (13.0 / 12.0) * sq(s1 - 2.0 * s2 + s3) + sq(s3 - s2);
+    double b2 = (13.0 / 12.0) * sq(s2 - 2.0 * s3 + s4) + sq(s2 - s3);
+    double b3 = (13.0 / 48.0) * sq(3.0 * s2 - 7.0 * s3 + 5.0 * s4 - s5) + sq(2.0 * s3 - 3.0 * s4 + s5);
+
+    // restriction (all or none)
+    double bmax = b0, bmin = b0;
+    bmax = b1 > bmax ? b1 : bmax;
+    bmax = b2 > bmax ? b2 : bmax;
+    bmax = b3 > bmax ? b3 : bmax;
+    bmin = b1 < bmin ? b1 : bmin;
+    bmin = b2 < bmin ? b2 : bmin;
+    bmin = b3 < bmin ? b3 : bmin;
+    const bool restricted = bmax / (eps + bmin) <= alpha_R;
+    b0 = restricted ? 0.0 : b0;
+    b1 = restricted ? 0.0 : b1;
+    b2 = restricted ? 0.0 : b2;
+    b3 = restricted ? 0.0 : b3;
+
+    // large-stencil indicators and the theta switch
+    const double tau5 = (13.0 / 12.0) * sq(s0 - 4.0 * s1 + 6.0 * s2 - 4.0 * s3 + s4) +
+                        sq(-s1 + 3.0 * s2 - 3.0 * s3 + s4);
+    const double tau6 = (13.0 / 12.0) * sq(-s0 + 5.0 * s1 - 10.0 * s2 + 10.0 * s3 - 5.0 * s4 + s5) +
+                        0.25 * sq(s0 - 3.0 * s1 + 2.0 * s2 + 2.0 * s3 - 3.0 * s4 + s5);
+    const bool central = tau6 < tau5;           // theta = 0
+    const double tau = central ? tau6 : tau5;
+    const double g0 = central ? GammaTheta::g0_t0 : GammaTheta::g0_t1;
+    const double g1 = central ? GammaTheta::g1_t0 : GammaTheta::g1_t1;
+    const double g2 = central ? GammaTheta::g2_t0 : GammaTheta::g2_t1;
+    const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
+
+    // nonlinear weights
+    const double a0 = g0 * (1.0 + tau / (eps + b0));
+    const double a1 = g1 * (1.0 + tau / (eps + b1));
+    const double a2 = g2 * (1.0 + tau / (eps + b2));
+    const double a3 = g3 * (1.0 + tau / (eps + b3));
+    const double sum = a0 + a1 + a2 + a3;
+    return (a0 / sum) * q0 + (a1 / sum) * q1 + (a2 / sum) * q2 + (a3 / sum) * q3;
+}
+
+}  // namespace wt

@@ -1,0 +1,130 @@
+// Host build of the kernels' per-interface arithmetic (wt_flux.hpp and the
+// headers it includes), for CPU tests of that arithmetic without a GPU.  The
+// loops below only gather each interface's stencil with the kernels' boundary
+// index maps and take flux differences in the kernels' order; every FP64
+// operation on the data is the one the device code performs.
+#include <cstdint>
+#include <cstdlib>
+#include <vector>
+
+#include "wt_flux.hpp"
+
+namespace {
+
+int64_t map_index(int64_t i, int64_t n, int bc)
+{
+    if (bc == 0) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <int NDIM>
+struct HostStencil {
+    double uu[6][NDIM + 2], vv[6][NDIM], pp[6], ss[6], hh[6];
+    double U(int k, int c) const { return uu[k][c]; }
+    double v(int k, int d) const { return vv[k][d]; }
+    double p(int k) const { return pp[k]; }
+    double sr(int k) const { return ss[k]; }
+    double H(int k) const { return hh[k]; }
+};
+
+struct HostScalar {
+    double uu[6], ff[6];
+    double u(int k) const { return uu[k]; }
+    double f(int k) const { return ff[k]; }
+};
+
+template <int NDIM, int DIR>
+int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double gamma, double eps,
+                double aR, const double *u, double *D, bool first)
+{
+    constexpr int M = NDIM + 2;
+    const int64_t N = n[0] * n[1] * n[2];
+    const int64_t nd = n[DIR];
+    const int64_t sd = DIR == 0 ? 1 : (DIR == 1 ? n[0] : n[0] * n[1]);
+    std::vector<double> F((size_t)(nd + 1) * M);
+    int bad = 0;
+    for (int64_t cell = 0; cell < N; ++cell) {
+        const int64_t coord = (cell / sd) % nd;
+        if (coord != 0) continue;                 // one pass per pencil
+        const int64_t base = cell;
+        for (int64_t i = -1; i < nd; ++i) {
+            HostStencil<NDIM> S;
+            for (int k = 0; k < 6; ++k) {
+                const int64_t idx = base + map_index(i - 2 + k, nd, bc) * sd;
+                double uc[M];
+                for (int c = 0; c < M; ++c) uc[c] = u[c * N + idx];
+                double p, H;
+                if (!wt::euler_cell<NDIM>(uc, gamma, S.vv[k], p, H)) bad = 1;
+                for (int c = 0; c < M; ++c) S.uu[k][c] = uc[c];
+                S.pp[k] = p;
+                S.ss[k] = wt::sqrt_rn(uc[0]);
+                S.hh[k] = H;
+            }
+            if (!wt::euler_interface_flux<NDIM, DIR>(S, al, gamma, eps, aR, &F[(i + 1) * M])) bad = 1;
+        }
+        for (int64_t i = 0; i < nd; ++i)
+            for (int c = 0; c < M; ++c) {
+                const double Dd = wt::div_rn(F[(i + 1) * M + c] - F[i * M + c], dx);
+                const int64_t o = c * N + base + i * sd;
+                D[o] = first ? Dd : D[o] + Dd;
+            }
+    }
+    return bad;
+}
+
+}  // namespace
+
+extern "C" {
+
+// The finishing steps of the device division and square root, for tests.
+double wth_div_finish(double q, double a, double b) { return wt::div_finish(q, a, b); }
+double wth_sqrt_finish(double s, double x) { return wt::sqrt_finish(s, x); }
+
+double wth_weno(const double *s, double eps, double aR)
+{
+    return wt::weno_theta(s[0], s[1], s[2], s[3], s[4], s[5], eps, aR);
+}
+
+// Full L(u) for the Euler equations (alpha: [ndim][5] LF speeds per field) or
+// for a 1D scalar state with given flux values f (alpha[0]).
+int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc,
+            const double *alpha, double gamma, double eps, double aR, const double *u,
+            const double *f, double *L)
+{
+    if (sys != 2) {
+        const int64_t nn = n[0];
+        std::vector<double> F((size_t)nn + 1);
+        for (int64_t i = -1; i < nn; ++i) {
+            HostScalar S;
+            for (int k = 0; k < 6; ++k) {
+                const int64_t idx = map_index(i - 2 + k, nn, bc[0]);
+                S.uu[k] = u[idx];
+                S.ff[k] = f[idx];
+            }
+            F[i + 1] = wt::scalar_interface_flux(S, alpha[0], eps, aR);
+        }
+        for (int64_t i = 0; i < nn; ++i) L[i] = -wt::div_rn(F[i + 1] - F[i], dx[0]);
+        return 0;
+    }
+    const int M = ndim + 2;
+    const int64_t N = n[0] * n[1] * n[2];
+    std::vector<double> D((size_t)N * M);
+    int bad = 0;
+    if (ndim == 1) {
+        bad |= euler_sweep<1, 0>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
+    } else if (ndim == 2) {
+        bad |= euler_sweep<2, 0>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
+        bad |= euler_sweep<2, 1>(n, dx[1], bc[1], alpha + 5, gamma, eps, aR, u, D.data(), false);
+    } else {
+        bad |= euler_sweep<3, 0>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
+        bad |= euler_sweep<3, 1>(n, dx[1], bc[1], alpha + 5, gamma, eps, aR, u, D.data(), false);
+        bad |= euler_sweep<3, 2>(n, dx[2], bc[2], alpha + 10, gamma, eps, aR, u, D.data(), false);
+    }
+    for (int64_t k = 0; k < N * M; ++k) L[k] = -D[k];
+    return bad;
+}
+
+}  // extern "C"

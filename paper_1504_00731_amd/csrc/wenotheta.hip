@@ -28,8 +28,7 @@
 #include <new>
 
 #include "wenotheta.h"
-#include "wt_physics.hpp"
-#include "wt_weno.hpp"
+#include "wt_flux.hpp"
 
 namespace wt {
 
@@ -140,7 +139,7 @@ __device__ __forceinline__ int euler_speeds(const double *uc, double gamma, doub
 {
     double vel[NDIM], p, H;
     const bool ok = euler_cell<NDIM>(uc, gamma, vel, p, H);
-    const double c = __builtin_sqrt(gamma * p / uc[0]);
+    const double c = sqrt_rn(div_rn(gamma * p, uc[0]));
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
         lam[3 * d + 0] = __builtin_fabs(vel[d] - c);
@@ -262,9 +261,9 @@ __global__ void step_begin_kernel(StepArgs A)
             } else {
                 am = bits_to_double(st->alpha[A.slot][0]);
             }
-            s = d == 0 ? am / A.dx[0] : s + am / A.dx[d];
+            s = d == 0 ? div_rn(am, A.dx[0]) : s + div_rn(am, A.dx[d]);
         }
-        dt = A.cfl / s;
+        dt = div_rn(A.cfl, s);
     }
     double t_next = st->t + dt;
     if (A.clip) {
@@ -297,6 +296,29 @@ __global__ void copy_dt_kernel(const DevState *st, double *dst)
 // ---------------------------------------------------------------------------
 // Sweep kernel
 // ---------------------------------------------------------------------------
+
+// Stencil accessors over the staged tile: point k of the interface owned by
+// thread t is tile entry t + k * TX.
+template <int M, int NDIM, int NC, int TX>
+struct LdsStencil {
+    const double (*u)[NC];
+    const double (*vel)[NC];
+    const double *pr, *sq, *hh;
+    int t;
+    __device__ double U(int k, int c) const { return u[c][t + k * TX]; }
+    __device__ double v(int k, int d) const { return vel[d][t + k * TX]; }
+    __device__ double p(int k) const { return pr[t + k * TX]; }
+    __device__ double sr(int k) const { return sq[t + k * TX]; }
+    __device__ double H(int k) const { return hh[t + k * TX]; }
+};
+
+template <int NC, int TX>
+struct LdsScalarStencil {
+    const double *uu, *ff;
+    int t;
+    __device__ double u(int k) const { return uu[t + k * TX]; }
+    __device__ double f(int k) const { return ff[t + k * TX]; }
+};
 template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
 {
@@ -375,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
 #pragma unroll
             for (int k = 0; k < NDIM; ++k) s_v[k][i] = vel[k];
             s_p[i] = p;
-            s_sr[i] = __builtin_sqrt(uc[0]);
+            s_sr[i] = sqrt_rn(uc[0]);
             s_H[i] = H;
         } else {
             const double x = A.uin[idx];
@@ -398,103 +420,18 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
         const bool valid = (DIR == 0 || x0 + cx < nx) && g0 + it <= nd;
         if (valid) {
             if constexpr (EULER) {
-                constexpr int NT = NDIM - 1;
-                double velL[NDIM], velR[NDIM];
+                const LdsStencil<M, NDIM, NC, TX> S{s_u, s_v, s_p, s_sr, s_H, t};
+                double al[M], F[M];
 #pragma unroll
-                for (int k = 0; k < NDIM; ++k) {
-                    velL[k] = s_v[k][t + 2 * TX];
-                    velR[k] = s_v[k][t + 3 * TX];
-                }
-                const RoeBasis<NDIM> B = roe_basis<NDIM, DIR>(s_sr[t + 2 * TX], velL, s_H[t + 2 * TX],
-                                                              s_sr[t + 3 * TX], velR, s_H[t + 3 * TX],
-                                                              A.gamma);
-                if (!B.ok) atomicOr(&st->err, kErrNonphysical);
-                double hs[M];
+                for (int q = 0; q < M; ++q) al[q] = lf_speed(st, A.slot_rd, DIR, q);
+                if (!euler_interface_flux<NDIM, DIR>(S, al, A.gamma, A.eps, A.alpha_R, F))
+                    atomicOr(&st->err, kErrNonphysical);
 #pragma unroll
-                for (int s = 0; s < M; ++s) {
-                    const double al = lf_speed(st, A.slot_rd, DIR, s);
-                    double vp[6], vm[6];
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) {
-                        const int i = t + k * TX;
-                        // permuted state and normal flux of point k
-                        const double U0 = s_u[0][i];
-                        const double Un = s_u[1 + DIR][i];
-                        double Ut[NT > 0 ? NT : 1], vt[NT > 0 ? NT : 1];
-#pragma unroll
-                        for (int q = 0; q < NT; ++q) {
-                            Ut[q] = s_u[1 + tangential_axis<DIR>(q)][i];
-                            vt[q] = s_v[tangential_axis<DIR>(q)][i];
-                        }
-                        const double UE = s_u[NDIM + 1][i];
-                        const double vn = s_v[DIR][i];
-                        const double p = s_p[i];
-                        const double f0 = Un;
-                        const double f1 = Un * vn + p;
-                        const double fE = vn * (UE + p);
-                        double q, w;
-                        if (s == 0 || s == 1 || s == 2) {
-                            const double ln0 = s == 0 ? B.l0n0 : (s == 1 ? B.l1n0 : B.l2n0);
-                            const double ln1 = s == 0 ? B.l0n1 : (s == 1 ? B.l1n1 : B.l2n1);
-                            const double lE = s == 0 ? B.l0E : (s == 1 ? B.l1E : B.l2E);
-                            q = ln0 * U0 + ln1 * Un;
-                            w = ln0 * f0 + ln1 * f1;
-#pragma unroll
-                            for (int q2 = 0; q2 < NT; ++q2) {
-                                const double lt = s == 0 ? B.l0t[q2] : (s == 1 ? B.l1t[q2] : B.l2t[q2]);
-                                q = q + lt * Ut[q2];
-                                w = w + lt * (Un * vt[q2]);
-                            }
-                            q = q + lE * UE;
-                            w = w + lE * fE;
-                        } else {
-                            // shear field of tangential direction s - 3: row (-u_t, 0, .., 1, .., 0)
-                            const int tq = s - 3;
-                            const double nut = -B.ut[tq];
-                            q = nut * U0 + Ut[tq];
-                            w = nut * f0 + Un * vt[tq];
-                        }
-                        vp[k] = 0.5 * (w + al * q);
-                        vm[5 - k] = 0.5 * (w - al * q);
-                    }
-                    hs[s] = weno_theta(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], A.eps, A.alpha_R) +
-                            weno_theta(vm[0], vm[1], vm[2], vm[3], vm[4], vm[5], A.eps, A.alpha_R);
-                }
-                // back-projection F = R h: acoustic pair, then entropy, then shear
-                const double un = B.un, c = B.c;
-                double Fp[M];
-                Fp[0] = (hs[0] + hs[2]) + hs[1];
-                Fp[1] = ((un - c) * hs[0] + (un + c) * hs[2]) + un * hs[1];
-#pragma unroll
-                for (int q = 0; q < NT; ++q) {
-                    const double ut = B.ut[q];
-                    Fp[2 + q] = ((ut * hs[0] + ut * hs[2]) + ut * hs[1]) + hs[3 + q];
-                }
-                {
-                    double e = (B.H - un * c) * hs[0] + (B.H + un * c) * hs[2];
-                    e = e + B.q2 * hs[1];
-#pragma unroll
-                    for (int q = 0; q < NT; ++q) e = e + B.ut[q] * hs[3 + q];
-                    Fp[M - 1] = e;
-                }
-                // back to canonical component order
-                s_F[0][t] = Fp[0];
-                s_F[1 + DIR][t] = Fp[1];
-#pragma unroll
-                for (int q = 0; q < NT; ++q) s_F[1 + tangential_axis<DIR>(q)][t] = Fp[2 + q];
-                s_F[M - 1][t] = Fp[M - 1];
+                for (int q = 0; q < M; ++q) s_F[q][t] = F[q];
             } else {
-                const double al = bits_to_double(st->alpha[A.slot_rd][0]);
-                double vp[6], vm[6];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    const int i = t + k * TX;
-                    const double x = s_u[0][i], f = s_f[i];
-                    vp[k] = 0.5 * (f + al * x);
-                    vm[5 - k] = 0.5 * (f - al * x);
-                }
-                s_F[0][t] = weno_theta(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], A.eps, A.alpha_R) +
-                            weno_theta(vm[0], vm[1], vm[2], vm[3], vm[4], vm[5], A.eps, A.alpha_R);
+                const LdsScalarStencil<NC, TX> S{s_u[0], s_f, t};
+                s_F[0][t] = scalar_interface_flux(S, bits_to_double(st->alpha[A.slot_rd][0]), A.eps,
+                                                  A.alpha_R);
             }
         }
     }
@@ -514,7 +451,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
             double Lc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                const double Dd = (s_F[c][t + TX] - s_F[c][t]) / A.dx;
+                const double Dd = div_rn(s_F[c][t + TX] - s_F[c][t], A.dx);
                 const int64_t o = c * ncell + idx;
                 if constexpr (MODE == MODE_FIRST) {
                     A.D[o] = Dd;

@@ -13,7 +13,8 @@
 #pragma once
 #pragma clang fp contract(off)
 
-#include <hip/hip_runtime.h>
+#include "wt_common.hpp"
+#include "wt_round.hpp"
 
 namespace wt {
 
@@ -26,14 +27,14 @@ struct Ncomp {
 
 // Index of the k-th tangential axis of direction DIR (increasing axis order).
 template <int DIR>
-__device__ __forceinline__ constexpr int tangential_axis(int k)
+WT_HD constexpr int tangential_axis(int k)
 {
     return k < DIR ? k : k + 1;
 }
 
 // Sum of squares over the axes in the order x, y, z.
 template <int NDIM>
-__device__ __forceinline__ double sum_sq_xyz(const double *v)
+WT_HD double sum_sq_xyz(const double *v)
 {
     double s = v[0] * v[0];
     if constexpr (NDIM > 1) s = s + v[1] * v[1];
@@ -46,16 +47,16 @@ __device__ __forceinline__ double sum_sq_xyz(const double *v)
 // H = (E + p) / rho (Sec. 4.2; the 2D form of Sec. 4.3 with the density
 // restored).  Returns false for a non-physical or non-finite state.
 template <int NDIM>
-__device__ __forceinline__ bool euler_cell(const double *uc, double gamma, double *vel,
+WT_HD bool euler_cell(const double *uc, double gamma, double *vel,
                                            double &p, double &H)
 {
     const double rho = uc[0];
     const double E = uc[NDIM + 1];
 #pragma unroll
-    for (int k = 0; k < NDIM; ++k) vel[k] = uc[1 + k] / rho;
+    for (int k = 0; k < NDIM; ++k) vel[k] = div_rn(uc[1 + k], rho);
     const double v2 = sum_sq_xyz<NDIM>(vel);
     p = (gamma - 1.0) * (E - 0.5 * rho * v2);
-    H = (E + p) / rho;
+    H = div_rn(E + p, rho);
     return rho > 0.0 && p > 0.0 && H == H && __builtin_fabs(H) < __builtin_huge_val();
 }
 
@@ -79,7 +80,7 @@ struct RoeBasis {
 };
 
 template <int NDIM, int DIR>
-__device__ __forceinline__ RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
+WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
                                                     double srR, const double *velR, double HR,
                                                     double gamma)
 {
@@ -87,19 +88,19 @@ __device__ __forceinline__ RoeBasis<NDIM> roe_basis(double srL, const double *ve
     const double den = srL + srR;
     double vt[3];
 #pragma unroll
-    for (int k = 0; k < NDIM; ++k) vt[k] = (srL * velL[k] + srR * velR[k]) / den;
-    const double H = (srL * HL + srR * HR) / den;
+    for (int k = 0; k < NDIM; ++k) vt[k] = div_rn(srL * velL[k] + srR * velR[k], den);
+    const double H = div_rn(srL * HL + srR * HR, den);
     const double q2 = 0.5 * sum_sq_xyz<NDIM>(vt);
     const double c2 = (gamma - 1.0) * (H - q2);
     B.ok = c2 > 0.0;
-    const double c = __builtin_sqrt(c2);
+    const double c = sqrt_rn(c2);
     const double un = vt[DIR];
 #pragma unroll
     for (int t = 0; t < NDIM - 1; ++t) B.ut[t] = vt[tangential_axis<DIR>(t)];
-    const double b1 = (gamma - 1.0) / c2;
+    const double b1 = div_rn(gamma - 1.0, c2);
     const double b2 = b1 * q2;
-    const double uc = un / c;
-    const double ic = 1.0 / c;
+    const double uc = div_rn(un, c);
+    const double ic = div_rn(1.0, c);
     B.un = un;
     B.c = c;
     B.H = H;

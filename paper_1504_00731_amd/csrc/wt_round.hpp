@@ -1,0 +1,105 @@
+// Correctly rounded FP64 division and square root on gfx950.
+//
+// The compiler's FP64 division sequence (scale, reciprocal, two Newton steps,
+// fused correction) returns a faithful quotient, but not always the nearest
+// one: when the exact quotient lies within about 2^-53 ulp of a rounding
+// midpoint it can round the wrong way (e.g. 0x1.6666666666663p-2 /
+// 0x1.ffffffffffffbp-4).  Every value the kernels produce must be the one a
+// plain IEEE evaluation produces, so each quotient and root is finished here
+// with an exact test against its neighbour:
+//   division (denominator b > 0, q faithful): the remainders r = a - q b and
+//     r' = a - q' b of q and of its neighbour q' on the side of a/b are exact
+//     (FMA); |r| and |r'| are b times the two distances to a/b, so the
+//     smaller one names the nearest double (an exact quotient is never a
+//     midpoint);
+//   square root (s faithful, x > 0): the side of sqrt(x) is the sign of
+//     x - s^2; sqrt(x) is past the midpoint m between s and its neighbour s'
+//     exactly when x - s s' > 0 (upwards) or x - s' s <= 0 (downwards),
+//     because x - m^2 = x - s s' - (s' - s)^2 / 4 and x - s s' is a multiple
+//     of (s' - s)^2.
+// On the host (where / and sqrt are IEEE) the same finishing steps are used
+// by the CPU tests to check them on faithful-but-wrong inputs.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <cstring>
+
+#include "wt_common.hpp"
+
+namespace wt {
+
+WT_HD long long bits_of(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __double_as_longlong(x);
+#else
+    long long b;
+    std::memcpy(&b, &x, sizeof b);
+    return b;
+#endif
+}
+
+WT_HD double double_of(long long b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __longlong_as_double(b);
+#else
+    double x;
+    std::memcpy(&x, &b, sizeof x);
+    return x;
+#endif
+}
+
+// Adjacent double of a finite non-zero x, towards +inf (up) or -inf.
+WT_HD double neighbour(double x, bool up)
+{
+    const bool away = (x > 0.0) == up;          // magnitude grows
+    return double_of(bits_of(x) + (away ? 1 : -1));
+}
+
+// Nearest double to a / b given a faithful q (b > 0).
+WT_HD double div_finish(double q, double a, double b)
+{
+    const double r = __builtin_fma(-q, b, a);
+    if (!(r != 0.0) || !(q != 0.0)) return q;   // exact, zero or NaN
+    const double qn = neighbour(q, r > 0.0);
+    const double rn = __builtin_fma(-qn, b, a);
+    return __builtin_fabs(rn) < __builtin_fabs(r) ? qn : q;
+}
+
+// Nearest double to sqrt(x) given a faithful s (x > 0).
+WT_HD double sqrt_finish(double s, double x)
+{
+    if (!(s > 0.0)) return s;
+    const double r = __builtin_fma(-s, s, x);
+    if (r > 0.0) {
+        const double su = neighbour(s, true);
+        return __builtin_fma(-s, su, x) > 0.0 ? su : s;
+    }
+    if (r < 0.0) {
+        const double sd = neighbour(s, false);
+        return __builtin_fma(-sd, s, x) <= 0.0 ? sd : s;
+    }
+    return s;
+}
+
+// a / b rounded to nearest (b > 0 wherever the kernels divide).
+WT_HD double div_rn(double a, double b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return div_finish(a / b, a, b);
+#else
+    return a / b;
+#endif
+}
+
+WT_HD double sqrt_rn(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return sqrt_finish(__builtin_sqrt(x), x);
+#else
+    return __builtin_sqrt(x);
+#endif
+}
+
+}  // namespace wt

@@ -23,7 +23,8 @@
 #pragma once
 #pragma clang fp contract(off)
 
-#include <hip/hip_runtime.h>
+#include "wt_common.hpp"
+#include "wt_round.hpp"
 
 namespace wt {
 
@@ -40,10 +41,10 @@ struct GammaTheta {
     static constexpr double g3_t1 = (1.0 / 20.0) * (1.0 - 1.0);
 };
 
-__device__ __forceinline__ double sq(double x) { return x * x; }
+WT_HD double sq(double x) { return x * x; }
 
 // s0..s5 = f_{j-2} .. f_{j+3}.
-__device__ __forceinline__ double weno_theta(double s0, double s1, double s2, double s3,
+WT_HD double weno_theta(double s0, double s1, double s2, double s3,
                                              double s4, double s5, double eps, double alpha_R)
 {
     // candidate fluxes
@@ -66,7 +67,7 @@ __device__ __forceinline__ double weno_theta(double s0, double s1, double s2, do
     bmin = b1 < bmin ? b1 : bmin;
     bmin = b2 < bmin ? b2 : bmin;
     bmin = b3 < bmin ? b3 : bmin;
-    const bool restricted = bmax / (eps + bmin) <= alpha_R;
+    const bool restricted = div_rn(bmax, eps + bmin) <= alpha_R;
     b0 = restricted ? 0.0 : b0;
     b1 = restricted ? 0.0 : b1;
     b2 = restricted ? 0.0 : b2;
@@ -85,12 +86,12 @@ __device__ __forceinline__ double weno_theta(double s0, double s1, double s2, do
     const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
 
     // nonlinear weights
-    const double a0 = g0 * (1.0 + tau / (eps + b0));
-    const double a1 = g1 * (1.0 + tau / (eps + b1));
-    const double a2 = g2 * (1.0 + tau / (eps + b2));
-    const double a3 = g3 * (1.0 + tau / (eps + b3));
+    const double a0 = g0 * (1.0 + div_rn(tau, eps + b0));
+    const double a1 = g1 * (1.0 + div_rn(tau, eps + b1));
+    const double a2 = g2 * (1.0 + div_rn(tau, eps + b2));
+    const double a3 = g3 * (1.0 + div_rn(tau, eps + b3));
     const double sum = a0 + a1 + a2 + a3;
-    return (a0 / sum) * q0 + (a1 / sum) * q1 + (a2 / sum) * q2 + (a3 / sum) * q3;
+    return div_rn(a0, sum) * q0 + div_rn(a1, sum) * q1 + div_rn(a2, sum) * q2 + div_rn(a3, sum) * q3;
 }
 
 }  // namespace wt

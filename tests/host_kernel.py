@@ -1,0 +1,79 @@
+"""Host build of the kernels' per-interface arithmetic (csrc/host_check.cpp),
+for CPU-only checks of the device code's operation sequence against the oracle."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1504_00731_amd", "csrc")
+LIB = os.path.join(ROOT, "tests", "_build", "libhostcheck.so")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".cpp"))]
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(map(os.path.getmtime, srcs)):
+            os.makedirs(os.path.dirname(LIB), exist_ok=True)
+            tmp = LIB + ".tmp%d" % os.getpid()
+            subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                            "-Wno-unknown-pragmas", "-fPIC", "-shared", "-o", tmp,
+                            os.path.join(CSRC, "host_check.cpp")], check=True)
+            os.replace(tmp, LIB)
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.wth_weno.restype = ctypes.c_double
+        L.wth_weno.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        L.wth_rhs.restype = ctypes.c_int
+        L.wth_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), dp,
+                              ctypes.POINTER(ctypes.c_int), dp, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def weno(s, eps=1e-10, alpha_R=50.0) -> float:
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    return lib().wth_weno(_dp(s), eps, alpha_R)
+
+
+def rhs(P, u, alpha, f=None):
+    """L(u) with the device arithmetic; P is an oracle.Problem (grid description only),
+    alpha the [ndim][m] Lax-Friedrichs speeds."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    n = (ctypes.c_int64 * 3)(*([int(v) for v in P.n] + [1] * (3 - len(P.n))))
+    dx = (ctypes.c_double * 3)(*([float(v) for v in P.dx] + [1.0] * (3 - len(P.dx))))
+    bc = (ctypes.c_int * 3)(*([int(v) for v in P.bc] + [0] * (3 - len(P.bc))))
+    al = np.zeros((3, 5))
+    a = np.asarray(alpha, dtype=np.float64).reshape(P.ndim, -1)
+    al[:P.ndim, :a.shape[1]] = a
+    if P.system != 2 and f is None:
+        f = P.a * u if P.system == 0 else 0.5 * u * u
+    f = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
+    L = np.zeros_like(u)
+    bad = lib().wth_rhs(P.system, P.ndim, n, dx, bc, _dp(al), P.gamma, P.eps, P.alpha_R,
+                        _dp(u), _dp(f), _dp(L))
+    return L, bad
+
+
+def div_finish(q, a, b) -> float:
+    f = lib().wth_div_finish
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_double] * 3
+    return f(q, a, b)
+
+
+def sqrt_finish(s, x) -> float:
+    f = lib().wth_sqrt_finish
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_double] * 2
+    return f(s, x)

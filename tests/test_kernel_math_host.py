@@ -1,0 +1,93 @@
+"""CPU checks of the kernels' arithmetic, through a host build of the device
+headers (no GPU): the finishing steps that make device division and square
+root correctly rounded, and the per-interface flux / RHS operation sequence
+against the oracle, bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_00731_amd import workloads as W
+from tests import host_kernel as HK
+
+
+def _neighbours(x):
+    return [x, np.nextafter(x, np.inf), np.nextafter(x, -np.inf)]
+
+
+def test_division_finish_recovers_the_nearest_quotient():
+    """Given any faithful quotient (the nearest or either neighbour), the finishing
+    step returns the IEEE quotient; includes the hard case met on the device."""
+    rng = np.random.default_rng(0)
+    cases = [(float.fromhex("0x1.6666666666663p-2"), float.fromhex("0x1.ffffffffffffbp-4"))]
+    a = rng.normal(size=3000) * np.exp(rng.uniform(-40, 40, 3000))
+    b = np.exp(rng.uniform(-40, 40, 3000))
+    cases += list(zip(a.tolist(), b.tolist()))
+    # divisors just below / above powers of two and numerators with long tails
+    for k in range(1, 64):
+        cases.append((0.35 * (1 - k * 2.0 ** -53), 0.125 * (1 - k * 2.0 ** -53)))
+        cases.append((1.0 + k * 2.0 ** -52, 3.0 - k * 2.0 ** -51))
+    for a_, b_ in cases:
+        q = a_ / b_
+        for qh in _neighbours(q):
+            assert HK.div_finish(float(qh), a_, b_) == q, (a_, b_, qh, q)
+
+
+def test_sqrt_finish_recovers_the_nearest_root():
+    rng = np.random.default_rng(1)
+    xs = np.exp(rng.uniform(-60, 60, 4000)).tolist()
+    xs += [float(np.nextafter(4.0 ** k, 0)) for k in range(-5, 6)]
+    xs += [float(np.nextafter(4.0 ** k, np.inf)) for k in range(-5, 6)]
+    xs += [2.0, 0.125, 1.12, float.fromhex("0x1.ffffffffffffbp-4")]
+    for x in xs:
+        s = math.sqrt(x)
+        for sh in _neighbours(s):
+            assert HK.sqrt_finish(float(sh), x) == s, (x, sh, s)
+
+
+def test_weno_operation_sequence_matches_oracle():
+    rng = np.random.default_rng(2)
+    for _ in range(3000):
+        s = rng.normal(size=6) * rng.choice([1e-8, 1.0, 1e5])
+        for aR in (50.0, 0.0, math.inf):
+            assert HK.weno(s, 1e-10, aR) == oracle.weno_theta(s, 1e-10, aR)
+
+
+def _compare(P, u):
+    al, _ = oracle.alpha(P, u)
+    ref = oracle.rhs(P, u)
+    got, bad = HK.rhs(P, u, al)
+    assert bad == 0
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("n", [6, 37, 300])
+def test_rhs_1d_matches_oracle(n):
+    for seed in range(3):
+        c = W.euler1d_seeded(seed, n)
+        _compare(oracle.euler_problem(c.n, c.lo, c.hi), c.u)
+    c = W.scalar_modes(0, n)
+    P = oracle.linear_problem(n)
+    al, _ = oracle.alpha(P, c.u)
+    got, _ = HK.rhs(P, c.u, al)
+    assert np.array_equal(got, oracle.rhs(P, c.u))
+
+
+def test_rhs_2d_3d_match_oracle():
+    c = W.euler2d_seeded(1, 40)
+    _compare(oracle.euler_problem(c.n, c.lo, c.hi), c.u)
+    c = W.euler2d_smooth_periodic(3, 24)
+    _compare(oracle.euler_problem(c.n, c.lo, c.hi, bc=oracle.PERIODIC), c.u)
+    c = W.euler3d_seeded(0, n=16)
+    _compare(oracle.euler_problem(c.n, c.lo, c.hi, bc=oracle.PERIODIC), c.u)
+
+
+def test_rhs_along_a_shock_tube_trajectory():
+    """Sod's problem (Sec. 4.2), N = 300: every stage state of 40 oracle steps."""
+    c = W.sod(300)
+    P = oracle.euler_problem(c.n, c.lo, c.hi)
+    u = c.u
+    for _ in range(40):
+        _compare(P, u)
+        u, _ = oracle.step(P, u)

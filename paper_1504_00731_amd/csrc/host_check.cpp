@@ -22,12 +22,17 @@ int64_t map_index(int64_t i, int64_t n, int bc)
 
 template <int NDIM>
 struct HostStencil {
-    double uu[6][NDIM + 2], vv[6][NDIM], pp[6], ss[6], hh[6];
+    double uu[6][NDIM + 2], ff[6][NDIM + 2], vv[6][NDIM], ss[6], hh[6];
     double U(int k, int c) const { return uu[k][c]; }
+    double f(int k, int c) const { return ff[k][c]; }
     double v(int k, int d) const { return vv[k][d]; }
-    double p(int k) const { return pp[k]; }
     double sr(int k) const { return ss[k]; }
     double H(int k) const { return hh[k]; }
+};
+
+struct HostSpeeds {
+    const double *al;
+    double operator()(int s) const { return al[s]; }
 };
 
 struct HostScalar {
@@ -59,11 +64,11 @@ int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double ga
                 double p, H;
                 if (!wt::euler_cell<NDIM>(uc, gamma, S.vv[k], p, H)) bad = 1;
                 for (int c = 0; c < M; ++c) S.uu[k][c] = uc[c];
-                S.pp[k] = p;
+                wt::euler_normal_flux<NDIM, DIR>(uc, S.vv[k], p, S.ff[k]);
                 S.ss[k] = wt::sqrt_rn(uc[0]);
                 S.hh[k] = H;
             }
-            if (!wt::euler_interface_flux<NDIM, DIR>(S, al, gamma, eps, aR, &F[(i + 1) * M])) bad = 1;
+            if (!wt::euler_interface_flux<NDIM, DIR>(S, HostSpeeds{al}, gamma, eps, aR, &F[(i + 1) * M])) bad = 1;
         }
         for (int64_t i = 0; i < nd; ++i)
             for (int c = 0; c < M; ++c) {
@@ -82,6 +87,7 @@ extern "C" {
 // The finishing steps of the device division and square root, for tests.
 double wth_div_finish(double q, double a, double b) { return wt::div_finish(q, a, b); }
 double wth_sqrt_finish(double s, double x) { return wt::sqrt_finish(s, x); }
+double wth_div_by_recip(double a, double b, double y) { return wt::div_by_recip(a, b, y); }
 
 double wth_weno(const double *s, double eps, double aR)
 {

@@ -62,6 +62,7 @@ struct SweepArgs {
     int64_t n[3];
     int64_t ncell;
     double dx;             // spacing along the sweep
+    double rdx;            // 1 / dx rounded to nearest (host-computed)
     double a;              // linear advection speed
     double gamma, eps, alpha_R;
     int bc;                // boundary condition along the sweep
@@ -219,11 +220,6 @@ __global__ void set_slots_kernel(DevState *st, int slot, SlotValues vals, int ze
     }
 }
 
-__device__ __forceinline__ double lf_speed(const DevState *st, int slot, int dir, int field)
-{
-    return bits_to_double(st->alpha[slot][dir * 5 + field]);
-}
-
 // ---------------------------------------------------------------------------
 // Step bookkeeping: dt from the speeds of the step's initial state
 // ---------------------------------------------------------------------------
@@ -302,14 +298,22 @@ __global__ void copy_dt_kernel(const DevState *st, double *dst)
 template <int M, int NDIM, int NC, int TX>
 struct LdsStencil {
     const double (*u)[NC];
+    const double (*fn)[NC];
     const double (*vel)[NC];
-    const double *pr, *sq, *hh;
+    const double *sq, *hh;
     int t;
     __device__ double U(int k, int c) const { return u[c][t + k * TX]; }
+    __device__ double f(int k, int c) const { return fn[c][t + k * TX]; }
     __device__ double v(int k, int d) const { return vel[d][t + k * TX]; }
-    __device__ double p(int k) const { return pr[t + k * TX]; }
     __device__ double sr(int k) const { return sq[t + k * TX]; }
     __device__ double H(int k) const { return hh[t + k * TX]; }
+};
+
+// Lax-Friedrichs speed of field s of the sweep direction, from a slot.
+struct SlotSpeeds {
+    const unsigned long long *slot;
+    int dir;
+    __device__ double operator()(int s) const { return bits_to_double(slot[dir * 5 + s]); }
 };
 
 template <int NC, int TX>
@@ -320,7 +324,10 @@ struct LdsScalarStencil {
     __device__ double f(int k) const { return ff[t + k * TX]; }
 };
 template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
+#ifndef WT_SWEEP_MIN_WAVES
+#define WT_SWEEP_MIN_WAVES 1
+#endif
+__global__ __launch_bounds__(kThreads, WT_SWEEP_MIN_WAVES) void sweep_kernel(SweepArgs A)
 {
     static_assert(TX * (TN + 1) == kThreads, "one interface per thread");
     constexpr int M = Ncomp<SYS, NDIM>::value;
@@ -329,9 +336,8 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
     constexpr int NV = SpeedLayout<SYS, NDIM>::NV;
 
     __shared__ double s_u[M][NC];
-    __shared__ double s_f[EULER ? 1 : NC];       // scalar: flux values
+    __shared__ double s_f[M][NC];                 // normal flux (Euler) / flux values (scalar)
     __shared__ double s_v[EULER ? NDIM : 1][EULER ? NC : 1];
-    __shared__ double s_p[EULER ? NC : 1];
     __shared__ double s_sr[EULER ? NC : 1];
     __shared__ double s_H[EULER ? NC : 1];
     __shared__ double s_F[M][kThreads];
@@ -392,11 +398,15 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
                 for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
                 err |= fin ? kErrNonphysical : kErrNonfinite;
             }
+            double fn[M];
+            euler_normal_flux<NDIM, DIR>(uc, vel, p, fn);
 #pragma unroll
-            for (int c = 0; c < M; ++c) s_u[c][i] = uc[c];
+            for (int c = 0; c < M; ++c) {
+                s_u[c][i] = uc[c];
+                s_f[c][i] = fn[c];
+            }
 #pragma unroll
             for (int k = 0; k < NDIM; ++k) s_v[k][i] = vel[k];
-            s_p[i] = p;
             s_sr[i] = sqrt_rn(uc[0]);
             s_H[i] = H;
         } else {
@@ -407,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
             else f = 0.5 * x * x;
             if (!__builtin_isfinite(x) || !__builtin_isfinite(f)) err |= kErrNonfinite;
             s_u[0][i] = x;
-            s_f[i] = f;
+            s_f[0][i] = f;
         }
     }
     if (err) atomicOr(&st->err, err);
@@ -420,16 +430,15 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
         const bool valid = (DIR == 0 || x0 + cx < nx) && g0 + it <= nd;
         if (valid) {
             if constexpr (EULER) {
-                const LdsStencil<M, NDIM, NC, TX> S{s_u, s_v, s_p, s_sr, s_H, t};
-                double al[M], F[M];
-#pragma unroll
-                for (int q = 0; q < M; ++q) al[q] = lf_speed(st, A.slot_rd, DIR, q);
+                const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
+                const SlotSpeeds al{st->alpha[A.slot_rd], DIR};
+                double F[M];
                 if (!euler_interface_flux<NDIM, DIR>(S, al, A.gamma, A.eps, A.alpha_R, F))
                     atomicOr(&st->err, kErrNonphysical);
 #pragma unroll
                 for (int q = 0; q < M; ++q) s_F[q][t] = F[q];
             } else {
-                const LdsScalarStencil<NC, TX> S{s_u[0], s_f, t};
+                const LdsScalarStencil<NC, TX> S{s_u[0], s_f[0], t};
                 s_F[0][t] = scalar_interface_flux(S, bits_to_double(st->alpha[A.slot_rd][0]), A.eps,
                                                   A.alpha_R);
             }
@@ -451,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A)
             double Lc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                const double Dd = div_rn(s_F[c][t + TX] - s_F[c][t], A.dx);
+                const double Dd = div_by_recip(s_F[c][t + TX] - s_F[c][t], A.dx, A.rdx);
                 const int64_t o = c * ncell + idx;
                 if constexpr (MODE == MODE_FIRST) {
                     A.D[o] = Dd;
@@ -765,6 +774,7 @@ wt_status queue_stage(wt_ctx *c, const Shape &S, const wt_params *P, const doubl
     for (int d = 0; d < S.ndim; ++d) {
         const int mode = d == S.ndim - 1 ? MODE_LAST_STAGE : (d == 0 ? MODE_FIRST : MODE_MID);
         A.dx = S.dx[d];
+        A.rdx = 1.0 / S.dx[d];
         A.bc = S.bc[d];
         if (timed_sweep(c, P->system, S.ndim, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
     }
@@ -928,6 +938,7 @@ wt_status wenotheta_rhs(wt_ctx *c, const wt_grid *G, const wt_params *P, const d
     for (int d = 0; d < S.ndim; ++d) {
         const int mode = d == S.ndim - 1 ? MODE_LAST_RHS : (d == 0 ? MODE_FIRST : MODE_MID);
         A.dx = S.dx[d];
+        A.rdx = 1.0 / S.dx[d];
         A.bc = S.bc[d];
         if (timed_sweep(c, P->system, S.ndim, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
     }

@@ -11,9 +11,15 @@
 // The stencil is read through an accessor, so the kernels can serve it from
 // LDS and a host build can serve it from arrays:
 //   S.U(k, c)  conserved component c (canonical order) of point k = 0..5
-//   S.v(k, d)  velocity along axis d;  S.p(k) pressure;  S.sr(k) sqrt(rho);
-//   S.H(k) total enthalpy                          (Euler)
-//   S.u(k), S.f(k) state and flux value             (scalar)
+//   S.f(k, c)  normal flux component c (canonical order) of point k
+//   S.v(k, d)  velocity along axis d;  S.sr(k) sqrt(rho);  S.H(k) enthalpy
+//   S.u(k), S.f(k) state and flux value            (scalar)
+//
+// Register use.  The characteristic fields are visited by a loop the
+// compiler keeps rolled (the trip count is the same for every lane, so the
+// branches on the field index are uniform); one WENO-theta body serves both
+// split signs.  This keeps the live set to one field's 12 stencil values plus
+// the Roe basis and the flux accumulators, instead of all fields at once.
 #pragma once
 #pragma clang fp contract(off)
 
@@ -23,11 +29,25 @@
 
 namespace wt {
 
-// al[s]: Lax-Friedrichs speed of field s for this direction.  F receives the
+// Normal flux of a cell in canonical component order for direction DIR:
+// (rho u_n, rho u_x u_n + p delta_{x,n}, .., u_n (E + p)), formed as
+// m_n, m_n u_n + p, m_n u_t, u_n (E + p).
+template <int NDIM, int DIR>
+WT_HD void euler_normal_flux(const double *uc, const double *vel, double p, double *f)
+{
+    const double mn = uc[1 + DIR];
+    const double un = vel[DIR];
+    f[0] = mn;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) f[1 + d] = d == DIR ? mn * un + p : mn * vel[d];
+    f[NDIM + 1] = un * (uc[NDIM + 1] + p);
+}
+
+// al(s): Lax-Friedrichs speed of field s for this direction.  F receives the
 // flux in canonical component order.  Returns false if the Roe sound speed is
 // not real.
-template <int NDIM, int DIR, class Acc>
-WT_HD bool euler_interface_flux(const Acc &S, const double *al, double gamma, double eps,
+template <int NDIM, int DIR, class Acc, class Alpha>
+WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, double eps,
                                 double alpha_R, double *F)
 {
     constexpr int M = NDIM + 2;
@@ -40,73 +60,102 @@ WT_HD bool euler_interface_flux(const Acc &S, const double *al, double gamma, do
     }
     const RoeBasis<NDIM> B =
         roe_basis<NDIM, DIR>(S.sr(2), velL, S.H(2), S.sr(3), velR, S.H(3), gamma);
+    const double un = B.un, c = B.c;
 
-    double hs[M];
+    // Back-projection accumulators in permuted order (rho, m_n, m_t.., E).
+    // Fields are visited in the order 0, 2, 1, 3, 4 so that every component
+    // sums R h as (R_0 h_0 + R_2 h_2) + R_1 h_1 + R_3 h_3 + R_4 h_4.
+    double acc[M];
+#pragma unroll 1
+    for (int it = 0; it < M; ++it) {
+        const int s = it == 1 ? 2 : (it == 2 ? 1 : it);
+        // row s of L in permuted order
+        double ln0, ln1, lE, lt[NT > 0 ? NT : 1];
+        int shear = -1;
+        if (s == 0) {
+            ln0 = B.l0n0; ln1 = B.l0n1; lE = B.l0E;
 #pragma unroll
-    for (int s = 0; s < M; ++s) {
-        const double a = al[s];
-        double vp[6], vm[6];
+            for (int t = 0; t < NT; ++t) lt[t] = B.l0t[t];
+        } else if (s == 1) {
+            ln0 = B.l1n0; ln1 = B.l1n1; lE = B.l1E;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) lt[t] = B.l1t[t];
+        } else if (s == 2) {
+            ln0 = B.l2n0; ln1 = B.l2n1; lE = B.l2E;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) lt[t] = B.l2t[t];
+        } else {
+            shear = s - 3;
+            ln0 = -(shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]); ln1 = 0.0; lE = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) lt[t] = 0.0;
+        }
+        const double a = al(s);
+        double w[6], q[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            // permuted state and normal flux of point k
-            const double U0 = S.U(k, 0);
-            const double Un = S.U(k, 1 + DIR);
-            double Ut[NT > 0 ? NT : 1], vt[NT > 0 ? NT : 1];
-#pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                Ut[q] = S.U(k, 1 + tangential_axis<DIR>(q));
-                vt[q] = S.v(k, tangential_axis<DIR>(q));
-            }
-            const double UE = S.U(k, NDIM + 1);
-            const double vn = S.v(k, DIR);
-            const double p = S.p(k);
-            const double f0 = Un;
-            const double f1 = Un * vn + p;
-            const double fE = vn * (UE + p);
-            double q, w;
-            if (s < 3) {
-                const double ln0 = s == 0 ? B.l0n0 : (s == 1 ? B.l1n0 : B.l2n0);
-                const double ln1 = s == 0 ? B.l0n1 : (s == 1 ? B.l1n1 : B.l2n1);
-                const double lE = s == 0 ? B.l0E : (s == 1 ? B.l1E : B.l2E);
-                q = ln0 * U0 + ln1 * Un;
-                w = ln0 * f0 + ln1 * f1;
+            if (shear < 0) {
+                double qq = ln0 * S.U(k, 0) + ln1 * S.U(k, 1 + DIR);
+                double ww = ln0 * S.f(k, 0) + ln1 * S.f(k, 1 + DIR);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    const double lt = s == 0 ? B.l0t[t] : (s == 1 ? B.l1t[t] : B.l2t[t]);
-                    q = q + lt * Ut[t];
-                    w = w + lt * (Un * vt[t]);
+                    qq = qq + lt[t] * S.U(k, 1 + tangential_axis<DIR>(t));
+                    ww = ww + lt[t] * S.f(k, 1 + tangential_axis<DIR>(t));
                 }
-                q = q + lE * UE;
-                w = w + lE * fE;
+                q[k] = qq + lE * S.U(k, NDIM + 1);
+                w[k] = ww + lE * S.f(k, NDIM + 1);
             } else {
-                // shear field of tangential direction s - 3: row (-u_t, 0, .., 1, .., 0)
-                const int t = s - 3;
-                const double nut = -B.ut[t];
-                q = nut * U0 + Ut[t];
-                w = nut * f0 + Un * vt[t];
+                // shear row (-u_t, 0, .., 1, .., 0): only two non-zero entries
+                const int ax = 1 + (shear == 0 ? tangential_axis<DIR>(0) : tangential_axis<DIR>(NT - 1));
+                q[k] = ln0 * S.U(k, 0) + S.U(k, ax);
+                w[k] = ln0 * S.f(k, 0) + S.f(k, ax);
             }
-            vp[k] = 0.5 * (w + a * q);
-            vm[5 - k] = 0.5 * (w - a * q);
         }
-        hs[s] = weno_theta(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], eps, alpha_R) +
-                weno_theta(vm[0], vm[1], vm[2], vm[3], vm[4], vm[5], eps, alpha_R);
-    }
-
-    // back-projection F = R h: the acoustic pair first, then the entropy
-    // field, then the shear fields (a mirrored state gives the mirrored flux)
-    const double un = B.un, c = B.c;
-    F[0] = (hs[0] + hs[2]) + hs[1];
-    F[1 + DIR] = ((un - c) * hs[0] + (un + c) * hs[2]) + un * hs[1];
+        // split and reconstruct: sign +1 on j-2..j+3, sign -1 mirrored
+        double h = 0.0;
+#pragma unroll 1
+        for (int sg = 0; sg < 2; ++sg) {
+            double v[6];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const double ut = B.ut[t];
-        F[1 + tangential_axis<DIR>(t)] = ((ut * hs[0] + ut * hs[2]) + ut * hs[1]) + hs[3 + t];
-    }
-    double e = (B.H - un * c) * hs[0] + (B.H + un * c) * hs[2];
-    e = e + B.q2 * hs[1];
+            for (int k = 0; k < 6; ++k) {
+                const double vplus = 0.5 * (w[k] + a * q[k]);
+                const double vminus = 0.5 * (w[5 - k] - a * q[5 - k]);
+                v[k] = sg == 0 ? vplus : vminus;
+            }
+            const double r = weno_theta(v[0], v[1], v[2], v[3], v[4], v[5], eps, alpha_R);
+            h = sg == 0 ? r : h + r;
+        }
+        // accumulate R h: column s of R in permuted order
+        if (s == 0) {
+            acc[0] = h;
+            acc[1] = (un - c) * h;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) e = e + B.ut[t] * hs[3 + t];
-    F[M - 1] = e;
+            for (int t = 0; t < NT; ++t) acc[2 + t] = B.ut[t] * h;
+            acc[M - 1] = (B.H - un * c) * h;
+        } else if (s == 2) {
+            acc[0] = acc[0] + h;
+            acc[1] = acc[1] + (un + c) * h;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[2 + t] = acc[2 + t] + B.ut[t] * h;
+            acc[M - 1] = acc[M - 1] + (B.H + un * c) * h;
+        } else if (s == 1) {
+            acc[0] = acc[0] + h;
+            acc[1] = acc[1] + un * h;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[2 + t] = acc[2 + t] + B.ut[t] * h;
+            acc[M - 1] = acc[M - 1] + B.q2 * h;
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                if (t == shear) acc[2 + t] = acc[2 + t] + h;
+            acc[M - 1] = acc[M - 1] + (shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]) * h;
+        }
+    }
+    F[0] = acc[0];
+    F[1 + DIR] = acc[1];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) F[1 + tangential_axis<DIR>(t)] = acc[2 + t];
+    F[M - 1] = acc[M - 1];
     return B.ok;
 }
 

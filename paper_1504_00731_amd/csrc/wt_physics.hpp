@@ -52,11 +52,12 @@ WT_HD bool euler_cell(const double *uc, double gamma, double *vel,
 {
     const double rho = uc[0];
     const double E = uc[NDIM + 1];
+    const double y = div_rn(1.0, rho);          // shared by the quotients by rho
 #pragma unroll
-    for (int k = 0; k < NDIM; ++k) vel[k] = div_rn(uc[1 + k], rho);
+    for (int k = 0; k < NDIM; ++k) vel[k] = div_by_recip(uc[1 + k], rho, y);
     const double v2 = sum_sq_xyz<NDIM>(vel);
     p = (gamma - 1.0) * (E - 0.5 * rho * v2);
-    H = div_rn(E + p, rho);
+    H = div_by_recip(E + p, rho, y);
     return rho > 0.0 && p > 0.0 && H == H && __builtin_fabs(H) < __builtin_huge_val();
 }
 
@@ -86,10 +87,11 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
 {
     RoeBasis<NDIM> B;
     const double den = srL + srR;
+    const double yd = div_rn(1.0, den);         // shared by the Roe averages
     double vt[3];
 #pragma unroll
-    for (int k = 0; k < NDIM; ++k) vt[k] = div_rn(srL * velL[k] + srR * velR[k], den);
-    const double H = div_rn(srL * HL + srR * HR, den);
+    for (int k = 0; k < NDIM; ++k) vt[k] = div_by_recip(srL * velL[k] + srR * velR[k], den, yd);
+    const double H = div_by_recip(srL * HL + srR * HR, den, yd);
     const double q2 = 0.5 * sum_sq_xyz<NDIM>(vt);
     const double c2 = (gamma - 1.0) * (H - q2);
     B.ok = c2 > 0.0;
@@ -99,8 +101,8 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
     for (int t = 0; t < NDIM - 1; ++t) B.ut[t] = vt[tangential_axis<DIR>(t)];
     const double b1 = div_rn(gamma - 1.0, c2);
     const double b2 = b1 * q2;
-    const double uc = div_rn(un, c);
     const double ic = div_rn(1.0, c);
+    const double uc = div_by_recip(un, c, ic);
     B.un = un;
     B.c = c;
     B.H = H;

@@ -83,6 +83,18 @@ WT_HD double sqrt_finish(double s, double x)
     return s;
 }
 
+// a / b rounded to nearest from y = RN(1 / b) (b > 0): two FMA corrections
+// (Markstein): q1 = q0 + (a - b q0) y is within one ulp of a / b, and with y
+// the nearest reciprocal, q1 + (a - b q1) y rounds to the nearest quotient.
+// Used where several quotients share a denominator.  Same code on the host,
+// where the CPU tests check it against IEEE division.
+WT_HD double div_by_recip(double a, double b, double y)
+{
+    const double q0 = a * y;
+    const double q1 = __builtin_fma(__builtin_fma(-b, q0, a), y, q0);
+    return __builtin_fma(__builtin_fma(-b, q1, a), y, q1);
+}
+
 // a / b rounded to nearest (b > 0 wherever the kernels divide).
 WT_HD double div_rn(double a, double b)
 {

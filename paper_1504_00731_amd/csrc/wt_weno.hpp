@@ -59,7 +59,10 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3,
     double b2 = (13.0 / 12.0) * sq(s2 - 2.0 * s3 + s4) + sq(s2 - s3);
     double b3 = (13.0 / 48.0) * sq(3.0 * s2 - 7.0 * s3 + 5.0 * s4 - s5) + sq(2.0 * s3 - 3.0 * s4 + s5);
 
-    // restriction (all or none)
+    // restriction (all or none): R = bmax / (eps + bmin) <= alpha_R.  The
+    // product test decides it without the quotient unless bmax is within
+    // 2^-40 of alpha_R (eps + bmin); RN is monotone, so outside that band the
+    // decision equals the one on the rounded quotient.
     double bmax = b0, bmin = b0;
     bmax = b1 > bmax ? b1 : bmax;
     bmax = b2 > bmax ? b2 : bmax;
@@ -67,11 +70,12 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3,
     bmin = b1 < bmin ? b1 : bmin;
     bmin = b2 < bmin ? b2 : bmin;
     bmin = b3 < bmin ? b3 : bmin;
-    const bool restricted = div_rn(bmax, eps + bmin) <= alpha_R;
-    b0 = restricted ? 0.0 : b0;
-    b1 = restricted ? 0.0 : b1;
-    b2 = restricted ? 0.0 : b2;
-    b3 = restricted ? 0.0 : b3;
+    const double den = eps + bmin;
+    const double lim = alpha_R * den;
+    bool restricted;
+    if (bmax < lim * (1.0 - 0x1p-40)) restricted = true;
+    else if (bmax > lim * (1.0 + 0x1p-40)) restricted = false;
+    else restricted = div_rn(bmax, den) <= alpha_R;
 
     // large-stencil indicators and the theta switch
     const double tau5 = (13.0 / 12.0) * sq(s0 - 4.0 * s1 + 6.0 * s2 - 4.0 * s3 + s4) +
@@ -85,13 +89,41 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3,
     const double g2 = central ? GammaTheta::g2_t0 : GammaTheta::g2_t1;
     const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
 
-    // nonlinear weights
-    const double a0 = g0 * (1.0 + div_rn(tau, eps + b0));
-    const double a1 = g1 * (1.0 + div_rn(tau, eps + b1));
-    const double a2 = g2 * (1.0 + div_rn(tau, eps + b2));
-    const double a3 = g3 * (1.0 + div_rn(tau, eps + b3));
+    // alpha_k = gamma_k (1 + tau / (eps + beta~_k)); restricted indicators are
+    // all zero, so the four quotients are one: tau / (eps + 0) = tau / eps
+    double d0, d1, d2, d3;
+    if (restricted) {
+        d0 = div_rn(tau, eps);
+        d1 = d0;
+        d2 = d0;
+        d3 = d0;
+    } else {
+        d0 = div_rn(tau, eps + b0);
+        d1 = div_rn(tau, eps + b1);
+        d2 = div_rn(tau, eps + b2);
+        d3 = div_rn(tau, eps + b3);
+    }
+    const double a0 = g0 * (1.0 + d0);
+    const double a1 = g1 * (1.0 + d1);
+    const double a2 = g2 * (1.0 + d2);
+    const double a3 = g3 * (1.0 + d3);
     const double sum = a0 + a1 + a2 + a3;
-    return div_rn(a0, sum) * q0 + div_rn(a1, sum) * q1 + div_rn(a2, sum) * q2 + div_rn(a3, sum) * q3;
+
+    // omega_k = alpha_k / sum share the denominator: one reciprocal
+    double w0, w1, w2, w3;
+    if (sum <= 0x1.fffffffffffffp+1023) {
+        const double y = div_rn(1.0, sum);
+        w0 = div_by_recip(a0, sum, y);
+        w1 = div_by_recip(a1, sum, y);
+        w2 = div_by_recip(a2, sum, y);
+        w3 = div_by_recip(a3, sum, y);
+    } else {
+        w0 = div_rn(a0, sum);
+        w1 = div_rn(a1, sum);
+        w2 = div_rn(a2, sum);
+        w3 = div_rn(a3, sum);
+    }
+    return w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
 }
 
 }  // namespace wt

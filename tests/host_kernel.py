@@ -77,3 +77,10 @@ def sqrt_finish(s, x) -> float:
     f.restype = ctypes.c_double
     f.argtypes = [ctypes.c_double] * 2
     return f(s, x)
+
+
+def div_by_recip(a, b, y) -> float:
+    f = lib().wth_div_by_recip
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_double] * 3
+    return f(a, b, y)

@@ -91,3 +91,45 @@ def test_rhs_along_a_shock_tube_trajectory():
     for _ in range(40):
         _compare(P, u)
         u, _ = oracle.step(P, u)
+
+
+def test_restriction_threshold_band():
+    """Stencils whose ratio R = max beta~ / (eps + min beta~) lies within a few ulps of
+    alpha_R: the device's product pre-test must agree with the rounded quotient."""
+    rng = np.random.default_rng(7)
+    checked = 0
+    for _ in range(60):
+        base = rng.normal(size=6)
+        direction = rng.normal(size=6)
+        # find lam with R(lam) crossing alpha_R = 50 by bisection on the oracle's R
+        R = lambda lam: oracle.weno_theta_diag(base + lam * direction, 1e-10, 50.0)["R"]
+        lo, hi = 0.0, 1.0
+        if (R(lo) - 50.0) * (R(hi) - 50.0) > 0:
+            continue
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if (R(mid) - 50.0) * (R(lo) - 50.0) > 0:
+                lo = mid
+            else:
+                hi = mid
+        for lam in np.linspace(lo, hi, 5).tolist() + [np.nextafter(lo, -1), np.nextafter(hi, 2)]:
+            s = base + lam * direction
+            assert HK.weno(s, 1e-10, 50.0) == oracle.weno_theta(s, 1e-10, 50.0)
+            checked += 1
+    assert checked > 50
+
+
+def test_markstein_quotients_on_hard_cases():
+    """Quotients sharing a denominator use RN(1/b) and two FMA corrections; check them
+    against IEEE division on numerators and denominators next to powers of two."""
+    import math
+    for ea in (-3, 0, 5):
+        for eb in (-4, 3):
+            for i in range(0, 120, 3):
+                for j in range(1, 120, 5):
+                    a = math.ldexp(1 + i * 2.0 ** -52, ea)
+                    b = math.ldexp(1 - j * 2.0 ** -53, eb)
+                    assert HK.div_by_recip(a, b, 1.0 / b) == a / b
+    a_hard = float.fromhex("0x1.6666666666663p-2")
+    b_hard = float.fromhex("0x1.ffffffffffffbp-4")
+    assert HK.div_by_recip(a_hard, b_hard, 1.0 / b_hard) == a_hard / b_hard

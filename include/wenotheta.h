@@ -68,7 +68,13 @@ typedef enum {
 } wt_bc;
 
 typedef enum {
-    WT_FP64 = 0          /* every step in IEEE double precision             */
+    WT_FP64 = 0,         /* every step in IEEE double precision, in the plain
+                            order of the formulas (bit-reproducible)          */
+    WT_FP32_RECON = 1    /* the WENO-theta reconstructions in FP32: each
+                            stencil is shifted by its point f_j and scaled by
+                            a power of two (epsilon scaled by its square)
+                            before rounding to FP32; projections, fluxes, RK
+                            stages and all stored states stay FP64           */
 } wt_precision;
 
 /* Uniform grid.  n[k] points in dimension k (n[k] = 1 for k >= ndim; at least
@@ -135,6 +141,36 @@ wt_status wenotheta_step(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
 wt_status wenotheta_solve(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
                           double *u, double t0, double t_end, int64_t max_steps,
                           double *t_out, int64_t *steps_out, void *stream);
+
+/* Batched solves: nprob independent 1D Euler problems (prm->system must be
+ * WT_EULER) packed side by side in one state, each advanced by nsteps CFL
+ * steps of its own (dt_b = cfl / (amax_b / dx_b)), in one persistent kernel
+ * launched through a captured HIP graph.
+ *   u       DEVICE, FP64, [3][total] component-major: problem b occupies
+ *           columns offset[b] .. offset[b] + n[b] - 1; advanced in place;
+ *   n, offset, lo, hi, bc   HOST arrays of nprob entries: points (>= 6),
+ *           first column, domain ends (dx_b = (hi - lo) / n) and boundary
+ *           condition of each problem; the column ranges must be disjoint
+ *           and inside [0, total);
+ *   t_out      optional DEVICE array of nprob doubles: the time each problem
+ *              reached;
+ *   status_out optional DEVICE array of nprob int32: WT_OK, or
+ *              WT_ERR_NONPHYSICAL / WT_ERR_NONFINITE for a problem whose
+ *              state became non-physical (its columns of u are then
+ *              unspecified; the other problems are unaffected).  Without
+ *              status_out such an error is recorded in the context and
+ *              returned by wenotheta_sync;
+ *   steps_out  optional DEVICE array of nprob int64: the steps completed
+ *              before a problem's state became non-physical (nsteps if it
+ *              never did).
+ * The WENO-theta step of each problem is the one wenotheta_step performs on
+ * it alone (bit for bit in WT_FP64).  Asynchronous after the problem tables
+ * are uploaded. */
+wt_status wenotheta_solve_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
+                                  const int64_t *offset, const double *lo, const double *hi,
+                                  const int32_t *bc, const wt_params *prm, double *u,
+                                  int64_t total, int64_t nsteps, double *t_out,
+                                  int32_t *status_out, int64_t *steps_out, void *stream);
 
 /* Wait for the work queued on `stream` and return (and clear) any error the
  * device recorded since the last synchronising call. */

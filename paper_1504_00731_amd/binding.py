@@ -19,11 +19,11 @@ WT_OK, WT_ERR_ARG, WT_ERR_UNSUPPORTED, WT_ERR_NONPHYSICAL = 0, 1, 2, 3
 WT_ERR_NONFINITE, WT_ERR_DEVICE, WT_ERR_NOMEM = 4, 5, 6
 WT_LINEAR, WT_BURGERS, WT_EULER = 0, 1, 2
 WT_PERIODIC, WT_TRANSMISSIVE = 0, 1
-WT_FP64 = 0
+WT_FP64, WT_FP32_RECON = 0, 1
 
 EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
             "wenotheta_rhs", "wenotheta_step", "wenotheta_solve", "wenotheta_sync",
-            "wenotheta_profile", "wenotheta_profile_read")
+            "wenotheta_profile", "wenotheta_profile_read", "wenotheta_solve_batched")
 PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
                  "sweep_z_final")
 
@@ -76,6 +76,9 @@ def _lib():
                                       ctypes.c_int64, dp, ctypes.POINTER(ctypes.c_int64), vp]
         L.wenotheta_sync.argtypes = [vp, vp]
         L.wenotheta_profile.argtypes = [vp, ctypes.c_int32]
+        i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+        L.wenotheta_solve_batched.argtypes = [vp, ctypes.c_int64, i64p, i64p, dp, dp, i32p, P, vp,
+                                              ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
         L.wenotheta_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
         for name in EXPORTED:
             if name != "wenotheta_status_string":
@@ -180,6 +183,18 @@ def _dev_ptr(t, name, shape=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _dev_int_ptr(t, name, n, bits):
+    import torch
+    if t is None:
+        return None
+    want = torch.int32 if bits == 32 else torch.int64
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != want or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous CUDA (HIP) int{bits} tensor")
+    if tuple(t.shape) != (n,):
+        raise ValueError(f"{name} must have shape ({n},)")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def state_shape(grid: Grid, params: Params) -> tuple:
     m = grid.ndim + 2 if params.system == WT_EULER else 1
     return (m,) + tuple(reversed(tuple(int(v) for v in grid.n)))
@@ -237,6 +252,33 @@ def wenotheta_profile_read(ctx: Context) -> dict:
     cnt = (ctypes.c_int64 * 6)()
     _check(_lib().wenotheta_profile_read(ctx.handle, ms, cnt, 6), "wenotheta_profile_read")
     return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_KINDS)}
+
+
+def wenotheta_solve_batched(ctx: Context, params: Params, u, n, offset, lo, hi, bc, nsteps,
+                            t_out=None, status_out=None, steps_out=None, stream=None):
+    """Advance packed independent 1D Euler problems (u: [3, total] device tensor)."""
+    import numpy as np
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    bc = np.ascontiguousarray(bc, dtype=np.int32)
+    nprob = int(n.size)
+    if not (offset.size == lo.size == hi.size == bc.size == nprob):
+        raise ValueError("problem tables must have one entry per problem")
+    if u.dim() != 2 or u.shape[0] != 3:
+        raise ValueError("u must have shape (3, total)")
+    total = int(u.shape[1])
+    i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(_lib().wenotheta_solve_batched(
+        ctx.handle, nprob, n.ctypes.data_as(i64p), offset.ctypes.data_as(i64p),
+        lo.ctypes.data_as(dp), hi.ctypes.data_as(dp), bc.ctypes.data_as(i32p),
+        ctypes.byref(params.c_struct()), _dev_ptr(u, "u"), total, int(nsteps),
+        _dev_ptr(t_out, "t_out", (nprob,)), _dev_int_ptr(status_out, "status_out", nprob, 32),
+        _dev_int_ptr(steps_out, "steps_out", nprob, 64), _stream_ptr(stream)),
+        "wenotheta_solve_batched")
+    return u
 
 
 def loaded_library_path() -> str:

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwenotheta.so")
-SOURCES = ["wenotheta.hip"]
+SOURCES = ["wenotheta.hip", "batched.hip"]
 ARCH = os.environ.get("WENOTHETA_ARCH", "gfx950")
 
 # No floating-point contraction (the kernels reproduce a fixed sequence of

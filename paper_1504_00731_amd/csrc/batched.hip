@@ -1,0 +1,425 @@
+// Batched solves: many independent 1D Euler problems of uneven sizes advanced
+// by one persistent kernel.
+//
+// Each workgroup takes a problem from a work queue (largest first), and runs
+// all of that problem's RK3 steps itself: per stage it sweeps the problem in
+// segments of 255 points (the same staged-tile / one-interface-per-thread /
+// flux-difference structure as the grid sweeps), writing the next stage state;
+// the problem's Lax-Friedrichs speeds and its CFL step are block reductions,
+// so no grid-wide synchronisation is ever needed.  The stage buffers of a
+// problem are touched by one workgroup only; a device-scope fence and a
+// barrier separate a stage's writes from the next stage's reads.  The whole
+// batch is one graph (queue reset + kernel), captured once per argument set
+// and replayed.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "wenotheta.h"
+#include "wt_ctx.hpp"
+#include "wt_device.hpp"
+
+namespace wt {
+
+struct BatchArgs {
+    double *u;                 // packed states [3][total], advanced in place
+    double *U1, *U2;           // packed stage buffers
+    int64_t total;
+    const int64_t *n, *off;    // points and first column of each problem
+    const double *dx, *rdx;    // spacing and its rounded reciprocal
+    const int32_t *bc;         // boundary condition of each problem
+    const int32_t *order;      // problems, largest first
+    int32_t *queue;            // next queue position
+    double *t_out;             // time reached per problem (optional)
+    int32_t *status_out;       // status per problem (optional)
+    int64_t *steps_out;        // steps completed per problem (optional)
+    DevState *st;
+    int nprob;
+    int64_t nsteps;
+    double gamma, eps, alpha_R, cfl;
+};
+
+// Block-wide max of three per-thread values; every thread gets the result.
+__device__ __forceinline__ void block_max3(double (&v)[3], double (*red)[kThreads / 64])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double w = wave_max(v[k]);
+        if (lane == 0) red[k][wid] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double m = red[k][0];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) m = red[k][w] > m ? red[k][w] : m;
+        v[k] = m;
+    }
+    __syncthreads();
+}
+
+struct LdsSpeeds {
+    const double *a;
+    __device__ double operator()(int s) const { return a[s]; }
+};
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void batched_kernel(BatchArgs A)
+{
+    constexpr int M = 3, TN = kThreads - 1, NC = TN + 6;
+    __shared__ double s_u[M][NC];
+    __shared__ double s_f[M][NC];
+    __shared__ double s_v[1][NC];
+    __shared__ double s_sr[NC];
+    __shared__ double s_H[NC];
+    __shared__ double s_F[M][kThreads];
+    __shared__ double s_red[3][kThreads / 64];
+    __shared__ double s_al[3];
+    __shared__ int s_job;
+    __shared__ int s_bad;
+    __shared__ unsigned long long s_first;
+
+    const int t = threadIdx.x;
+    const int64_t total = A.total;
+    // The job loop's control flow is kept wave-uniform: the job index is read
+    // once per wave as a scalar, so its exit and every loop bound below are
+    // uniform branches, and a barrier closes each job after thread 0's tail, so
+    // that tail and the next fetch (both on thread 0 alone) stay separate blocks.
+    // Were they merged into one thread-0 path around the loop, the other lanes
+    // of wave 0 would return to the fetch barrier without thread 0 and re-read
+    // a stale job index for ever.
+    for (;;) {
+        if (t == 0) s_job = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        if (job >= A.nprob) break;              // every workgroup leaves once the queue is empty
+        const int b = A.order[job];
+        const int64_t n = A.n[b], off = A.off[b];
+        const double dx = A.dx[b], rdx = A.rdx[b];
+        const int bc = A.bc[b];
+        const int64_t nseg = (n + TN - 1) / TN;
+        int err = 0;
+
+        // speeds of the initial state
+        double spd[3] = {0.0, 0.0, 0.0};
+        for (int64_t i = t; i < n; i += kThreads) {
+            double uc[3] = {A.u[off + i], A.u[total + off + i], A.u[2 * total + off + i]};
+            double lam[3];
+            err |= euler_speeds<1>(uc, A.gamma, lam);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
+        }
+        block_max3(spd, s_red);
+
+        double time = 0.0;
+        // first step at which this thread met a non-physical state (nsteps: none)
+        int64_t first_bad = err ? 0 : A.nsteps;
+        for (int64_t step = 0; step < A.nsteps; ++step) {
+            // dt = cfl / (amax / dx), amax = max(|u| + c) = max(alpha_0, alpha_2)
+            const double am = spd[2] > spd[0] ? spd[2] : spd[0];
+            const double dt = div_rn(A.cfl, div_rn(am, dx));
+            for (int stage = 1; stage <= 3; ++stage) {
+                const double *uin = stage == 1 ? A.u : (stage == 2 ? A.U1 : A.U2);
+                double *out = stage == 1 ? A.U1 : (stage == 2 ? A.U2 : A.u);
+                if (t < 3) s_al[t] = spd[t];
+                double nsp[3] = {0.0, 0.0, 0.0};
+                for (int64_t seg = 0; seg < nseg; ++seg) {
+                    const int64_t g0 = seg * TN;
+                    // stage the segment and its halos
+                    for (int i = t; i < NC; i += kThreads) {
+                        const int64_t g = map_index(g0 - 3 + i, n, bc);
+                        double uc[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) uc[c] = uin[c * total + off + g];
+                        double vel[1], p, H;
+                        if (!euler_cell<1>(uc, A.gamma, vel, p, H)) {
+                            const bool fin = __builtin_isfinite(uc[0]) && __builtin_isfinite(uc[1]) &&
+                                             __builtin_isfinite(uc[2]);
+                            err |= fin ? kErrNonphysical : kErrNonfinite;
+                        }
+                        double fn[3];
+                        euler_normal_flux<1, 0>(uc, vel, p, fn);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            s_u[c][i] = uc[c];
+                            s_f[c][i] = fn[c];
+                        }
+                        s_v[0][i] = vel[0];
+                        s_sr[i] = sqrt_rn(uc[0]);
+                        s_H[i] = H;
+                    }
+                    __syncthreads();
+                    if (g0 + t <= n) {
+                        const LdsStencil<M, 1, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, t};
+                        double F[3];
+                        if (!euler_interface_flux<1, 0, PREC>(S, LdsSpeeds{s_al}, A.gamma, A.eps,
+                                                              A.alpha_R, F))
+                            err |= kErrNonphysical;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) s_F[c][t] = F[c];
+                    }
+                    __syncthreads();
+                    if (t < TN && g0 + t < n) {
+                        const int64_t idx = off + g0 + t;
+                        double un[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const double L = -div_by_recip(s_F[c][t + 1] - s_F[c][t], dx, rdx);
+                            const int64_t o = c * total + idx;
+                            if (stage == 1)
+                                un[c] = uin[o] + dt * L;
+                            else if (stage == 2)
+                                un[c] = 0.75 * A.u[o] + 0.25 * uin[o] + (0.25 * dt) * L;
+                            else
+                                un[c] = (1.0 / 3.0) * A.u[o] + (2.0 / 3.0) * uin[o] + ((2.0 / 3.0) * dt) * L;
+                        }
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) out[c * total + idx] = un[c];
+                        double lam[3];
+                        err |= euler_speeds<1>(un, A.gamma, lam);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) nsp[k] = lam[k] > nsp[k] ? lam[k] : nsp[k];
+                    }
+                    __syncthreads();                // the tile is reused by the next segment
+                }
+                // the next stage reads what this one wrote
+                __threadfence();
+                block_max3(nsp, s_red);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) spd[k] = nsp[k];
+            }
+            if (err && first_bad == A.nsteps) first_bad = step;
+            time = time + dt;
+        }
+        // per-problem outcome (a failed problem keeps being advanced; its columns are
+        // then unspecified): OR of the error bits and the first failing step
+        if (t == 0) {
+            s_bad = 0;
+            s_first = A.nsteps;
+        }
+        __syncthreads();
+        if (err) atomicOr(&s_bad, err);
+        if (first_bad < A.nsteps) atomicMin(&s_first, (unsigned long long)first_bad);
+        __syncthreads();
+        if (t == 0) {
+            const int all_err = s_bad;
+            if (A.t_out) A.t_out[b] = time;
+            if (A.steps_out) A.steps_out[b] = (int64_t)s_first;
+            if (A.status_out)
+                A.status_out[b] = all_err & kErrNonfinite ? WT_ERR_NONFINITE
+                                                          : (all_err ? WT_ERR_NONPHYSICAL : WT_OK);
+            else if (all_err)
+                atomicOr(&A.st->err, all_err);
+        }
+        // s_job, s_bad and s_first are rewritten by thread 0 only after this
+        __syncthreads();
+    }
+}
+
+__global__ void reset_queue_kernel(int32_t *q)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+}
+
+}  // namespace wt
+
+namespace {
+
+using namespace wt;
+
+uint64_t mix(uint64_t h, uint64_t v)
+{
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+uint64_t bits(double d)
+{
+    uint64_t b;
+    std::memcpy(&b, &d, sizeof b);
+    return b;
+}
+
+void free_batch(wt_ctx *c)
+{
+    (void)hipFree(c->B1);
+    (void)hipFree(c->B2);
+    (void)hipFree(c->b_n);
+    (void)hipFree(c->b_off);
+    (void)hipFree(c->b_dx);
+    (void)hipFree(c->b_rdx);
+    (void)hipFree(c->b_bc);
+    (void)hipFree(c->b_order);
+    (void)hipFree(c->b_queue);
+    c->B1 = c->B2 = nullptr;
+    c->b_n = c->b_off = nullptr;
+    c->b_dx = c->b_rdx = nullptr;
+    c->b_bc = c->b_order = c->b_queue = nullptr;
+    c->bcap = 0;
+    c->b_cap = 0;
+}
+
+}  // namespace
+
+namespace wt {
+
+void release_batched(wt_ctx *c)
+{
+    if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+    if (c->b_capture) (void)hipStreamDestroy(c->b_capture);
+    c->b_graph = nullptr;
+    c->b_capture = nullptr;
+    free_batch(c);
+}
+
+}  // namespace wt
+
+extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int64_t *n,
+                                             const int64_t *offset, const double *lo,
+                                             const double *hi, const int32_t *bc,
+                                             const wt_params *P, double *u, int64_t total,
+                                             int64_t nsteps, double *t_out, int32_t *status_out,
+                                             int64_t *steps_out, void *stream)
+{
+    if (!c || !P || !u || !n || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
+    if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 6 || nsteps < 0) return WT_ERR_ARG;
+    if (P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
+    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
+    if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0) || !(P->gamma > 1.0))
+        return WT_ERR_ARG;
+    // problems must be valid and pairwise disjoint inside [0, total)
+    std::vector<int64_t> idx(nprob);
+    std::iota(idx.begin(), idx.end(), 0);
+    for (int64_t b = 0; b < nprob; ++b) {
+        if (n[b] < 6 || offset[b] < 0 || offset[b] + n[b] > total) return WT_ERR_ARG;
+        if (!(hi[b] > lo[b]) || (bc[b] != WT_PERIODIC && bc[b] != WT_TRANSMISSIVE)) return WT_ERR_ARG;
+    }
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return offset[a] < offset[b]; });
+    for (int64_t k = 1; k < nprob; ++k)
+        if (offset[idx[k - 1]] + n[idx[k - 1]] > offset[idx[k]]) return WT_ERR_ARG;
+    // work queue: largest problems first (longest-processing-time order)
+    std::vector<int32_t> order(nprob);
+    for (int64_t b = 0; b < nprob; ++b) order[b] = (int32_t)b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
+    std::vector<double> dx(nprob), rdx(nprob);
+    for (int64_t b = 0; b < nprob; ++b) {
+        dx[b] = (hi[b] - lo[b]) / (double)n[b];
+        rdx[b] = 1.0 / dx[b];
+    }
+    std::vector<int32_t> bcv(bc, bc + nprob);
+
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    // workspace (allocated on first use of a size)
+    const size_t need = (size_t)total * 3;
+    if (need > c->bcap || nprob > c->b_cap) {
+        if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
+        if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+        c->b_graph = nullptr;
+        free_batch(c);
+        if (hipMalloc(&c->B1, need * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->B2, need * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->b_n, nprob * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc(&c->b_off, nprob * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc(&c->b_dx, nprob * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->b_rdx, nprob * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->b_bc, nprob * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->b_order, nprob * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->b_queue, sizeof(int32_t)) != hipSuccess) {
+            free_batch(c);
+            (void)hipGetLastError();
+            return WT_ERR_NOMEM;
+        }
+        c->bcap = need;
+        c->b_cap = nprob;
+    }
+    // problem tables (small host-to-device copies, ordered on the stream)
+    if (hipMemcpyAsync(c->b_n, n, nprob * sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->b_off, offset, nprob * sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->b_dx, dx.data(), nprob * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->b_rdx, rdx.data(), nprob * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->b_bc, bcv.data(), nprob * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->b_order, order.data(), nprob * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return WT_ERR_DEVICE;
+
+    BatchArgs A{};
+    A.u = u;
+    A.U1 = c->B1;
+    A.U2 = c->B2;
+    A.total = total;
+    A.n = c->b_n;
+    A.off = c->b_off;
+    A.dx = c->b_dx;
+    A.rdx = c->b_rdx;
+    A.bc = c->b_bc;
+    A.order = c->b_order;
+    A.queue = c->b_queue;
+    A.t_out = t_out;
+    A.status_out = status_out;
+    A.steps_out = steps_out;
+    A.st = c->st;
+    A.nprob = (int)nprob;
+    A.nsteps = nsteps;
+    A.gamma = P->gamma;
+    A.eps = P->eps;
+    A.alpha_R = P->alpha_R;
+    A.cfl = P->cfl;
+
+    // persistent grid: as many workgroups as are resident at once, at most one per problem
+    int per_cu = 0, ncu = 0;
+    hipError_t e;
+    if (P->precision == WT_FP32_RECON)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<1>, kThreads, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<0>, kThreads, 0);
+    if (e != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                                                 c->device) != hipSuccess)
+        return WT_ERR_DEVICE;
+    int64_t grid = (int64_t)std::max(per_cu, 1) * std::max(ncu, 1);
+    if (grid > nprob) grid = nprob;
+
+    // graph of (queue reset, kernel), captured once per argument set
+    uint64_t key = 0;
+    for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)t_out,
+                       (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out, (uint64_t)nprob,
+                       (uint64_t)total, (uint64_t)nsteps, (uint64_t)P->precision, bits(P->gamma),
+                       bits(P->eps), bits(P->alpha_R), bits(P->cfl), (uint64_t)grid})
+        key = mix(key, v);
+    if (!c->b_graph || c->b_key != key) {
+        if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+        c->b_graph = nullptr;
+        if (!c->b_capture && hipStreamCreateWithFlags(&c->b_capture, hipStreamNonBlocking) != hipSuccess)
+            return WT_ERR_DEVICE;
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(c->b_capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return WT_ERR_DEVICE;
+        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, c->b_capture, c->b_queue);
+        if (P->precision == WT_FP32_RECON)
+            hipLaunchKernelGGL(batched_kernel<1>, dim3((unsigned)grid), dim3(kThreads), 0, c->b_capture, A);
+        else
+            hipLaunchKernelGGL(batched_kernel<0>, dim3((unsigned)grid), dim3(kThreads), 0, c->b_capture, A);
+        const hipError_t le = hipGetLastError();
+        if (hipStreamEndCapture(c->b_capture, &g) != hipSuccess || le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return WT_ERR_DEVICE;
+        }
+        e = hipGraphInstantiate(&c->b_graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->b_graph = nullptr;
+            return WT_ERR_DEVICE;
+        }
+        c->b_key = key;
+    }
+    if (hipGraphLaunch(c->b_graph, s) != hipSuccess) return WT_ERR_DEVICE;
+    return WT_OK;
+}

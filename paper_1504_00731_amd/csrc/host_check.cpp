@@ -68,7 +68,7 @@ int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double ga
                 S.ss[k] = wt::sqrt_rn(uc[0]);
                 S.hh[k] = H;
             }
-            if (!wt::euler_interface_flux<NDIM, DIR>(S, HostSpeeds{al}, gamma, eps, aR, &F[(i + 1) * M])) bad = 1;
+            if (!wt::euler_interface_flux<NDIM, DIR, 0>(S, HostSpeeds{al}, gamma, eps, aR, &F[(i + 1) * M])) bad = 1;
         }
         for (int64_t i = 0; i < nd; ++i)
             for (int c = 0; c < M; ++c) {
@@ -110,7 +110,7 @@ int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc
                 S.uu[k] = u[idx];
                 S.ff[k] = f[idx];
             }
-            F[i + 1] = wt::scalar_interface_flux(S, alpha[0], eps, aR);
+            F[i + 1] = wt::scalar_interface_flux<0>(S, alpha[0], eps, aR);
         }
         for (int64_t i = 0; i < nn; ++i) L[i] = -wt::div_rn(F[i + 1] - F[i], dx[0]);
         return 0;

@@ -30,26 +30,10 @@
 #include "wenotheta.h"
 #include "wt_flux.hpp"
 
+#include "wt_device.hpp"
+
 namespace wt {
 
-constexpr int kThreads = 256;
-constexpr int kSlots = 3;        // ring of Lax-Friedrichs speed slots
-constexpr int kSlotLen = 16;     // [dir * 5 + field]
-constexpr int kErrNonphysical = 1;
-constexpr int kErrNonfinite = 2;
-
-struct DevState {
-    unsigned long long alpha[kSlots][kSlotLen];  // non-negative doubles as bits
-    double dt;
-    double t;
-    double t_end;
-    long long steps;
-    long long max_steps;
-    int done;
-    int err;
-};
-
-// Sweep direction DIR, tile TX x TN with TX * (TN + 1) == kThreads interfaces.
 enum : int { MODE_FIRST = 0, MODE_MID = 1, MODE_LAST_RHS = 2, MODE_LAST_STAGE = 3 };
 
 struct SweepArgs {
@@ -69,103 +53,6 @@ struct SweepArgs {
     int slot_rd, slot_wr, slot_zero;
     int stage;             // 1..3 (MODE_LAST_STAGE)
     int check_done;
-};
-
-__device__ __forceinline__ double bits_to_double(unsigned long long b)
-{
-    return __longlong_as_double(static_cast<long long>(b));
-}
-
-__device__ __forceinline__ unsigned long long double_to_bits(double d)
-{
-    return static_cast<unsigned long long>(__double_as_longlong(d));
-}
-
-// Boundary conditions as index maps (periodic wrap, zero-gradient clamp).
-__device__ __forceinline__ int64_t map_index(int64_t i, int64_t n, int bc)
-{
-    if (bc == WT_PERIODIC) {
-        i %= n;
-        return i < 0 ? i + n : i;
-    }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
-// Raise slot[k] to v (v >= 0).  A relaxed device-scope read first skips the
-// atomic when the slot already holds at least v (values only increase
-// between the zeroing and the reading of a slot).
-__device__ __forceinline__ void slot_max(unsigned long long *p, double v)
-{
-    const unsigned long long vb = double_to_bits(v);
-    const unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (vb > cur) atomicMax(p, vb);
-}
-
-// Block-wide max of NV values per thread, then one slot update per value.
-template <int NV>
-__device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long long *slot,
-                                               const int (&slot_idx)[NV])
-{
-    __shared__ double red[NV][kThreads / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double w = wave_max(v[k]);
-        if (lane == 0) red[k][wid] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        const int k = threadIdx.x;
-        double m = red[k][0];
-#pragma unroll
-        for (int w = 1; w < kThreads / 64; ++w) m = red[k][w] > m ? red[k][w] : m;
-        slot_max(&slot[slot_idx[k]], m);
-    }
-}
-
-// Wave speeds of one cell (canonical state): per direction |u_d - c|, |u_d|,
-// |u_d + c|, with c = sqrt(gamma p / rho).  Returns an error bit mask.
-template <int NDIM>
-__device__ __forceinline__ int euler_speeds(const double *uc, double gamma, double *lam)
-{
-    double vel[NDIM], p, H;
-    const bool ok = euler_cell<NDIM>(uc, gamma, vel, p, H);
-    const double c = sqrt_rn(div_rn(gamma * p, uc[0]));
-#pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-        lam[3 * d + 0] = __builtin_fabs(vel[d] - c);
-        lam[3 * d + 1] = __builtin_fabs(vel[d]);
-        lam[3 * d + 2] = __builtin_fabs(vel[d] + c);
-    }
-    if (ok) return 0;
-    bool finite = true;
-#pragma unroll
-    for (int k = 0; k < NDIM + 2; ++k) finite = finite && __builtin_isfinite(uc[k]);
-    return finite ? kErrNonphysical : kErrNonfinite;
-}
-
-// Lax-Friedrichs speed values per point: one per (direction, field), field
-// s of direction d taking |u_d - c|, |u_d|, |u_d + c| for s = 0, 1, 2 and
-// |u_d| for the shear fields.  Value k lives in slot entry d * 5 + s.
-template <int SYS, int NDIM>
-struct SpeedLayout {
-    static constexpr int M = Ncomp<SYS, NDIM>::value;
-    static constexpr int NV = SYS == SYS_EULER ? NDIM * M : 1;
-    __device__ static constexpr int slot_index(int k) { return SYS == SYS_EULER ? (k / M) * 5 + k % M : 0; }
-    __device__ static constexpr int lam_index(int k)
-    {
-        return 3 * (k / M) + (k % M < 3 ? k % M : 1);
-    }
 };
 
 // ---------------------------------------------------------------------------
@@ -293,37 +180,7 @@ __global__ void copy_dt_kernel(const DevState *st, double *dst)
 // Sweep kernel
 // ---------------------------------------------------------------------------
 
-// Stencil accessors over the staged tile: point k of the interface owned by
-// thread t is tile entry t + k * TX.
-template <int M, int NDIM, int NC, int TX>
-struct LdsStencil {
-    const double (*u)[NC];
-    const double (*fn)[NC];
-    const double (*vel)[NC];
-    const double *sq, *hh;
-    int t;
-    __device__ double U(int k, int c) const { return u[c][t + k * TX]; }
-    __device__ double f(int k, int c) const { return fn[c][t + k * TX]; }
-    __device__ double v(int k, int d) const { return vel[d][t + k * TX]; }
-    __device__ double sr(int k) const { return sq[t + k * TX]; }
-    __device__ double H(int k) const { return hh[t + k * TX]; }
-};
-
-// Lax-Friedrichs speed of field s of the sweep direction, from a slot.
-struct SlotSpeeds {
-    const unsigned long long *slot;
-    int dir;
-    __device__ double operator()(int s) const { return bits_to_double(slot[dir * 5 + s]); }
-};
-
-template <int NC, int TX>
-struct LdsScalarStencil {
-    const double *uu, *ff;
-    int t;
-    __device__ double u(int k) const { return uu[t + k * TX]; }
-    __device__ double f(int k) const { return ff[t + k * TX]; }
-};
-template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE>
+template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE, int PREC>
 #ifndef WT_SWEEP_MIN_WAVES
 #define WT_SWEEP_MIN_WAVES 1
 #endif
@@ -433,13 +290,13 @@ __global__ __launch_bounds__(kThreads, WT_SWEEP_MIN_WAVES) void sweep_kernel(Swe
                 const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
                 const SlotSpeeds al{st->alpha[A.slot_rd], DIR};
                 double F[M];
-                if (!euler_interface_flux<NDIM, DIR>(S, al, A.gamma, A.eps, A.alpha_R, F))
+                if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.eps, A.alpha_R, F))
                     atomicOr(&st->err, kErrNonphysical);
 #pragma unroll
                 for (int q = 0; q < M; ++q) s_F[q][t] = F[q];
             } else {
                 const LdsScalarStencil<NC, TX> S{s_u[0], s_f[0], t};
-                s_F[0][t] = scalar_interface_flux(S, bits_to_double(st->alpha[A.slot_rd][0]), A.eps,
+                s_F[0][t] = scalar_interface_flux<PREC>(S, bits_to_double(st->alpha[A.slot_rd][0]), A.eps,
                                                   A.alpha_R);
             }
         }
@@ -537,7 +394,7 @@ struct TileShape<1> { static constexpr int TX = 8, TN = 31; };
 template <>
 struct TileShape<2> { static constexpr int TX = 8, TN = 31; };
 
-template <int SYS, int NDIM, int DIR, int MODE>
+template <int SYS, int NDIM, int DIR, int MODE, int PREC>
 hipError_t launch_sweep(const SweepArgs &A, hipStream_t s)
 {
     constexpr int TX = TileShape<DIR>::TX, TN = TileShape<DIR>::TN;
@@ -547,40 +404,48 @@ hipError_t launch_sweep(const SweepArgs &A, hipStream_t s)
     if (DIR == 0) blocks = nseg * A.n[1] * A.n[2];
     else if (DIR == 1) blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[2];
     else blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[1];
-    hipLaunchKernelGGL((sweep_kernel<SYS, NDIM, DIR, TX, TN, MODE>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((sweep_kernel<SYS, NDIM, DIR, TX, TN, MODE, PREC>), dim3((unsigned)blocks),
                        dim3(kThreads), 0, s, A);
     return hipGetLastError();
 }
 
-template <int SYS, int NDIM, int DIR>
+template <int SYS, int NDIM, int DIR, int PREC>
 hipError_t launch_sweep_mode(int mode, const SweepArgs &A, hipStream_t s)
 {
     switch (mode) {
-        case MODE_FIRST: return launch_sweep<SYS, NDIM, DIR, MODE_FIRST>(A, s);
-        case MODE_MID: return launch_sweep<SYS, NDIM, DIR, MODE_MID>(A, s);
-        case MODE_LAST_RHS: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_RHS>(A, s);
-        default: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_STAGE>(A, s);
+        case MODE_FIRST: return launch_sweep<SYS, NDIM, DIR, MODE_FIRST, PREC>(A, s);
+        case MODE_MID: return launch_sweep<SYS, NDIM, DIR, MODE_MID, PREC>(A, s);
+        case MODE_LAST_RHS: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_RHS, PREC>(A, s);
+        default: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_STAGE, PREC>(A, s);
     }
 }
 
-template <int SYS, int NDIM>
+template <int SYS, int NDIM, int PREC>
 hipError_t launch_sweep_dir(int dir, int mode, const SweepArgs &A, hipStream_t s)
 {
-    if (dir == 0) return launch_sweep_mode<SYS, NDIM, 0>(mode, A, s);
+    if (dir == 0) return launch_sweep_mode<SYS, NDIM, 0, PREC>(mode, A, s);
     if constexpr (NDIM > 1)
-        if (dir == 1) return launch_sweep_mode<SYS, NDIM, 1>(mode, A, s);
+        if (dir == 1) return launch_sweep_mode<SYS, NDIM, 1, PREC>(mode, A, s);
     if constexpr (NDIM > 2)
-        if (dir == 2) return launch_sweep_mode<SYS, NDIM, 2>(mode, A, s);
+        if (dir == 2) return launch_sweep_mode<SYS, NDIM, 2, PREC>(mode, A, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_any(int sys, int ndim, int dir, int mode, const SweepArgs &A, hipStream_t s)
+template <int PREC>
+hipError_t launch_sweep_prec(int sys, int ndim, int dir, int mode, const SweepArgs &A, hipStream_t s)
 {
-    if (sys == SYS_LINEAR) return launch_sweep_dir<SYS_LINEAR, 1>(dir, mode, A, s);
-    if (sys == SYS_BURGERS) return launch_sweep_dir<SYS_BURGERS, 1>(dir, mode, A, s);
-    if (ndim == 1) return launch_sweep_dir<SYS_EULER, 1>(dir, mode, A, s);
-    if (ndim == 2) return launch_sweep_dir<SYS_EULER, 2>(dir, mode, A, s);
-    return launch_sweep_dir<SYS_EULER, 3>(dir, mode, A, s);
+    if (sys == SYS_LINEAR) return launch_sweep_dir<SYS_LINEAR, 1, PREC>(dir, mode, A, s);
+    if (sys == SYS_BURGERS) return launch_sweep_dir<SYS_BURGERS, 1, PREC>(dir, mode, A, s);
+    if (ndim == 1) return launch_sweep_dir<SYS_EULER, 1, PREC>(dir, mode, A, s);
+    if (ndim == 2) return launch_sweep_dir<SYS_EULER, 2, PREC>(dir, mode, A, s);
+    return launch_sweep_dir<SYS_EULER, 3, PREC>(dir, mode, A, s);
+}
+
+hipError_t launch_sweep_any(int sys, int ndim, int prec, int dir, int mode, const SweepArgs &A,
+                            hipStream_t s)
+{
+    if (prec == WT_FP32_RECON) return launch_sweep_prec<1>(sys, ndim, dir, mode, A, s);
+    return launch_sweep_prec<0>(sys, ndim, dir, mode, A, s);
 }
 
 hipError_t launch_alpha(int sys, int ndim, const double *u, int64_t ncell, double a, double gamma,
@@ -608,27 +473,7 @@ hipError_t launch_alpha(int sys, int ndim, const double *u, int64_t ncell, doubl
 // ---------------------------------------------------------------------------
 // Context and C ABI
 // ---------------------------------------------------------------------------
-// Per-kernel timing with HIP events recorded on the launch stream around each
-// sweep launch (enabled by wenotheta_profile).  Kinds: sweep direction d in
-// its non-final role (d) or as the final sweep of a stage or RHS (3 + d).
-constexpr int kProfKinds = 6;
-constexpr int kProfPairs = 4096;
-
-struct wt_ctx {
-    int device = 0;
-    wt::DevState *st = nullptr;
-    double *U1 = nullptr, *U2 = nullptr, *D = nullptr;
-    size_t cap = 0;       // doubles per workspace buffer
-    int64_t g = 0;        // stage counter (selects the speed slots)
-    // profiler
-    bool prof = false;
-    hipEvent_t ev[2 * kProfPairs] = {};
-    int ev_kind[kProfPairs] = {};
-    int nev = 0;
-    double prof_ms[kProfKinds] = {};
-    int64_t prof_n[kProfKinds] = {};
-    int64_t prof_dropped = 0;
-};
+#include "wt_ctx.hpp"
 
 namespace {
 
@@ -648,7 +493,7 @@ wt_status validate(const wt_grid *G, const wt_params *P, Shape &S)
     if (!G || !P) return WT_ERR_ARG;
     if (G->ndim < 1 || G->ndim > 3) return WT_ERR_ARG;
     if (P->system < WT_LINEAR || P->system > WT_EULER) return WT_ERR_ARG;
-    if (P->precision != WT_FP64) return WT_ERR_UNSUPPORTED;
+    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
     if (P->system != WT_EULER && G->ndim != 1) return WT_ERR_UNSUPPORTED;
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0)) return WT_ERR_ARG;
     if (P->system == WT_EULER && !(P->gamma > 1.0)) return WT_ERR_ARG;
@@ -701,13 +546,13 @@ wt_status ensure_workspace(wt_ctx *c, const Shape &S)
 }
 
 // Launch one sweep, bracketed by profiling events when enabled.
-hipError_t timed_sweep(wt_ctx *c, int sys, int ndim, int dir, int mode, const SweepArgs &A,
-                       hipStream_t s)
+hipError_t timed_sweep(wt_ctx *c, int sys, int ndim, int prec, int dir, int mode,
+                       const SweepArgs &A, hipStream_t s)
 {
     const bool rec = c->prof && c->nev < kProfPairs;
     if (c->prof && !rec) c->prof_dropped++;
     if (rec && hipEventRecord(c->ev[2 * c->nev], s) != hipSuccess) return hipErrorUnknown;
-    const hipError_t e = launch_sweep_any(sys, ndim, dir, mode, A, s);
+    const hipError_t e = launch_sweep_any(sys, ndim, prec, dir, mode, A, s);
     if (e != hipSuccess) return e;
     if (rec) {
         if (hipEventRecord(c->ev[2 * c->nev + 1], s) != hipSuccess) return hipErrorUnknown;
@@ -776,7 +621,7 @@ wt_status queue_stage(wt_ctx *c, const Shape &S, const wt_params *P, const doubl
         A.dx = S.dx[d];
         A.rdx = 1.0 / S.dx[d];
         A.bc = S.bc[d];
-        if (timed_sweep(c, P->system, S.ndim, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
+        if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
     }
     c->g += 1;
     return WT_OK;
@@ -803,6 +648,10 @@ wt_status queue_step(wt_ctx *c, const Shape &S, const wt_params *P, double *u, d
     return WT_OK;
 }
 
+}  // namespace
+
+namespace wt {
+
 // Read and clear the device error word (synchronises the stream).
 wt_status collect(wt_ctx *c, hipStream_t s, DevState *host)
 {
@@ -822,7 +671,7 @@ wt_status collect(wt_ctx *c, hipStream_t s, DevState *host)
     return WT_OK;
 }
 
-}  // namespace
+}  // namespace wt
 
 extern "C" {
 
@@ -874,6 +723,7 @@ wt_status wenotheta_ctx_destroy(wt_ctx *c)
     (void)hipFree(c->st);
     for (int k = 0; k < 2 * kProfPairs; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    wt::release_batched(c);
     delete c;
     return WT_OK;
 }
@@ -940,7 +790,7 @@ wt_status wenotheta_rhs(wt_ctx *c, const wt_grid *G, const wt_params *P, const d
         A.dx = S.dx[d];
         A.rdx = 1.0 / S.dx[d];
         A.bc = S.bc[d];
-        if (timed_sweep(c, P->system, S.ndim, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
+        if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
     }
     return WT_OK;
 }

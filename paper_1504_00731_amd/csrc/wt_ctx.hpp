@@ -1,0 +1,53 @@
+// Context of the C ABI: device state, workspace and the kernel timer.
+// Shared by the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "wenotheta.h"
+#include "wt_device.hpp"
+
+// Per-kernel timing with HIP events recorded on the launch stream around each
+// sweep launch (enabled by wenotheta_profile).  Kinds: sweep direction d in
+// its non-final role (d) or as the final sweep of a stage or RHS (3 + d).
+constexpr int kProfKinds = 6;
+constexpr int kProfPairs = 4096;
+
+struct wt_ctx {
+    int device = 0;
+    wt::DevState *st = nullptr;
+    double *U1 = nullptr, *U2 = nullptr, *D = nullptr;
+    size_t cap = 0;       // doubles per workspace buffer
+    int64_t g = 0;        // stage counter (selects the speed slots)
+    // profiler
+    bool prof = false;
+    hipEvent_t ev[2 * kProfPairs] = {};
+    int ev_kind[kProfPairs] = {};
+    int nev = 0;
+    double prof_ms[kProfKinds] = {};
+    int64_t prof_n[kProfKinds] = {};
+    int64_t prof_dropped = 0;
+    // batched solves: packed stage buffers and per-problem tables
+    double *B1 = nullptr, *B2 = nullptr;
+    size_t bcap = 0;            // doubles per packed stage buffer
+    int64_t *b_n = nullptr, *b_off = nullptr;
+    double *b_dx = nullptr, *b_rdx = nullptr;
+    int32_t *b_bc = nullptr, *b_order = nullptr, *b_queue = nullptr;
+    int64_t b_cap = 0;          // problems the tables hold
+    // graph of the last batched launch and the arguments it was captured with
+    hipGraphExec_t b_graph = nullptr;
+    hipStream_t b_capture = nullptr;
+    uint64_t b_key = 0;
+};
+
+
+namespace wt {
+// Read (and clear) the device error word after synchronising the stream;
+// folds completed timing events into the profile.
+wt_status collect(wt_ctx *c, hipStream_t s, DevState *host);
+// Free the batched-solve workspace and graph.
+void release_batched(wt_ctx *c);
+}  // namespace wt

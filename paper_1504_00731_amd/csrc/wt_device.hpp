@@ -1,0 +1,164 @@
+// Device-side building blocks shared by the gfx950 kernels: the device state
+// of a context, index maps of the boundary conditions, wave/block max
+// reductions into the Lax-Friedrichs speed slots, the wave speeds of a cell,
+// and accessors that serve an interface's stencil from a staged LDS tile.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wenotheta.h"
+#include "wt_flux.hpp"
+
+namespace wt {
+
+constexpr int kThreads = 256;
+constexpr int kSlots = 3;        // ring of Lax-Friedrichs speed slots
+constexpr int kSlotLen = 16;     // [dir * 5 + field]
+constexpr int kErrNonphysical = 1;
+constexpr int kErrNonfinite = 2;
+
+struct DevState {
+    unsigned long long alpha[kSlots][kSlotLen];  // non-negative doubles as bits
+    double dt;
+    double t;
+    double t_end;
+    long long steps;
+    long long max_steps;
+    int done;
+    int err;
+};
+
+// Sweep direction DIR, tile TX x TN with TX * (TN + 1) == kThreads interfaces.
+
+__device__ __forceinline__ double bits_to_double(unsigned long long b)
+{
+    return __longlong_as_double(static_cast<long long>(b));
+}
+
+__device__ __forceinline__ unsigned long long double_to_bits(double d)
+{
+    return static_cast<unsigned long long>(__double_as_longlong(d));
+}
+
+// Boundary conditions as index maps (periodic wrap, zero-gradient clamp).
+__device__ __forceinline__ int64_t map_index(int64_t i, int64_t n, int bc)
+{
+    if (bc == WT_PERIODIC) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Raise slot[k] to v (v >= 0).  A relaxed device-scope read first skips the
+// atomic when the slot already holds at least v (values only increase
+// between the zeroing and the reading of a slot).
+__device__ __forceinline__ void slot_max(unsigned long long *p, double v)
+{
+    const unsigned long long vb = double_to_bits(v);
+    const unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (vb > cur) atomicMax(p, vb);
+}
+
+// Block-wide max of NV values per thread, then one slot update per value.
+template <int NV>
+__device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long long *slot,
+                                               const int (&slot_idx)[NV])
+{
+    __shared__ double red[NV][kThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double w = wave_max(v[k]);
+        if (lane == 0) red[k][wid] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x;
+        double m = red[k][0];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) m = red[k][w] > m ? red[k][w] : m;
+        slot_max(&slot[slot_idx[k]], m);
+    }
+}
+
+// Wave speeds of one cell (canonical state): per direction |u_d - c|, |u_d|,
+// |u_d + c|, with c = sqrt(gamma p / rho).  Returns an error bit mask.
+template <int NDIM>
+__device__ __forceinline__ int euler_speeds(const double *uc, double gamma, double *lam)
+{
+    double vel[NDIM], p, H;
+    const bool ok = euler_cell<NDIM>(uc, gamma, vel, p, H);
+    const double c = sqrt_rn(div_rn(gamma * p, uc[0]));
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        lam[3 * d + 0] = __builtin_fabs(vel[d] - c);
+        lam[3 * d + 1] = __builtin_fabs(vel[d]);
+        lam[3 * d + 2] = __builtin_fabs(vel[d] + c);
+    }
+    if (ok) return 0;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < NDIM + 2; ++k) finite = finite && __builtin_isfinite(uc[k]);
+    return finite ? kErrNonphysical : kErrNonfinite;
+}
+
+// Lax-Friedrichs speed values per point: one per (direction, field), field
+// s of direction d taking |u_d - c|, |u_d|, |u_d + c| for s = 0, 1, 2 and
+// |u_d| for the shear fields.  Value k lives in slot entry d * 5 + s.
+template <int SYS, int NDIM>
+struct SpeedLayout {
+    static constexpr int M = Ncomp<SYS, NDIM>::value;
+    static constexpr int NV = SYS == SYS_EULER ? NDIM * M : 1;
+    __device__ static constexpr int slot_index(int k) { return SYS == SYS_EULER ? (k / M) * 5 + k % M : 0; }
+    __device__ static constexpr int lam_index(int k)
+    {
+        return 3 * (k / M) + (k % M < 3 ? k % M : 1);
+    }
+};
+
+// Stencil accessors over the staged tile: point k of the interface owned by
+// thread t is tile entry t + k * TX.
+template <int M, int NDIM, int NC, int TX>
+struct LdsStencil {
+    const double (*u)[NC];
+    const double (*fn)[NC];
+    const double (*vel)[NC];
+    const double *sq, *hh;
+    int t;
+    __device__ double U(int k, int c) const { return u[c][t + k * TX]; }
+    __device__ double f(int k, int c) const { return fn[c][t + k * TX]; }
+    __device__ double v(int k, int d) const { return vel[d][t + k * TX]; }
+    __device__ double sr(int k) const { return sq[t + k * TX]; }
+    __device__ double H(int k) const { return hh[t + k * TX]; }
+};
+
+// Lax-Friedrichs speed of field s of the sweep direction, from a slot.
+struct SlotSpeeds {
+    const unsigned long long *slot;
+    int dir;
+    __device__ double operator()(int s) const { return bits_to_double(slot[dir * 5 + s]); }
+};
+
+template <int NC, int TX>
+struct LdsScalarStencil {
+    const double *uu, *ff;
+    int t;
+    __device__ double u(int k) const { return uu[t + k * TX]; }
+    __device__ double f(int k) const { return ff[t + k * TX]; }
+};
+
+}  // namespace wt

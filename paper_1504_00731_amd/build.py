@@ -1,4 +1,5 @@
-"""Build the HIP library libwenotheta.so for gfx950 (in-tree, next to this file)."""
+"""Build the HIP libraries for gfx950 (in-tree, next to this file): libwenotheta.so, the
+solver, and libwt_probe.so, elementwise probes of its device arithmetic for the tests."""
 from __future__ import annotations
 
 import os
@@ -12,6 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwenotheta.so")
 SOURCES = ["wenotheta.hip", "batched.hip"]
+PROBE_LIB = os.path.join(HERE, "libwt_probe.so")
+PROBE_SOURCES = ["arith_probe.hip"]
 ARCH = os.environ.get("WENOTHETA_ARCH", "gfx950")
 
 # No floating-point contraction (the kernels reproduce a fixed sequence of
@@ -28,9 +31,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the library)")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _build_one(out: str, sources: list, verbose: bool) -> str:
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH] + FLAGS + ["-I" + INCLUDE, "-I" + CSRC,
                                                          "-o", tmp] + srcs
     if verbose:
@@ -38,9 +41,15 @@ def build(verbose: bool = False) -> str:
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libwenotheta.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError("hipcc failed building " + os.path.basename(out))
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Builds both libraries; returns the solver library's path."""
+    _build_one(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _build_one(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

@@ -43,7 +43,8 @@ struct BatchArgs {
     DevState *st;
     int nprob;
     int64_t nsteps;
-    double gamma, eps, alpha_R, cfl;
+    double gamma, cfl;
+    WenoConst W;
 };
 
 // Block-wide max of three per-thread values; every thread gets the result.
@@ -160,8 +161,7 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchArgs A)
                     if (g0 + t <= n) {
                         const LdsStencil<M, 1, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, t};
                         double F[3];
-                        if (!euler_interface_flux<1, 0, PREC>(S, LdsSpeeds{s_al}, A.gamma, A.eps,
-                                                              A.alpha_R, F))
+                        if (!euler_interface_flux<1, 0, PREC>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
                             err |= kErrNonphysical;
 #pragma unroll
                         for (int c = 0; c < 3; ++c) s_F[c][t] = F[c];
@@ -370,8 +370,7 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     A.nprob = (int)nprob;
     A.nsteps = nsteps;
     A.gamma = P->gamma;
-    A.eps = P->eps;
-    A.alpha_R = P->alpha_R;
+    A.W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
     A.cfl = P->cfl;
 
     // persistent grid: as many workgroups as are resident at once, at most one per problem

@@ -68,7 +68,10 @@ int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double ga
                 S.ss[k] = wt::sqrt_rn(uc[0]);
                 S.hh[k] = H;
             }
-            if (!wt::euler_interface_flux<NDIM, DIR, 0>(S, HostSpeeds{al}, gamma, eps, aR, &F[(i + 1) * M])) bad = 1;
+            if (!wt::euler_interface_flux<NDIM, DIR, 0>(S, HostSpeeds{al}, gamma,
+                                                        wt::WenoConst{eps, aR, 1.0 / eps},
+                                                        &F[(i + 1) * M]))
+                bad = 1;
         }
         for (int64_t i = 0; i < nd; ++i)
             for (int c = 0; c < M; ++c) {
@@ -88,10 +91,20 @@ extern "C" {
 double wth_div_finish(double q, double a, double b) { return wt::div_finish(q, a, b); }
 double wth_sqrt_finish(double s, double x) { return wt::sqrt_finish(s, x); }
 double wth_div_by_recip(double a, double b, double y) { return wt::div_by_recip(a, b, y); }
+double wth_div_by_recip_checked(double a, double b, double y)
+{
+    return wt::div_by_recip_checked(a, b, y);
+}
+double wth_recip_refine(double b, double y0) { return wt::recip_refine(b, y0); }
+
+double wth_weno_fp32(const double *s, double eps, double aR)
+{
+    return wt::weno_theta_fp32_recon(s, eps, (float)aR);
+}
 
 double wth_weno(const double *s, double eps, double aR)
 {
-    return wt::weno_theta(s[0], s[1], s[2], s[3], s[4], s[5], eps, aR);
+    return wt::weno_theta(s[0], s[1], s[2], s[3], s[4], s[5], eps, aR, 1.0 / eps);
 }
 
 // Full L(u) for the Euler equations (alpha: [ndim][5] LF speeds per field) or
@@ -110,7 +123,7 @@ int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc
                 S.uu[k] = u[idx];
                 S.ff[k] = f[idx];
             }
-            F[i + 1] = wt::scalar_interface_flux<0>(S, alpha[0], eps, aR);
+            F[i + 1] = wt::scalar_interface_flux<0>(S, alpha[0], wt::WenoConst{eps, aR, 1.0 / eps});
         }
         for (int64_t i = 0; i < nn; ++i) L[i] = -wt::div_rn(F[i + 1] - F[i], dx[0]);
         return 0;

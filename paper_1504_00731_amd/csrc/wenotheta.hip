@@ -48,7 +48,8 @@ struct SweepArgs {
     double dx;             // spacing along the sweep
     double rdx;            // 1 / dx rounded to nearest (host-computed)
     double a;              // linear advection speed
-    double gamma, eps, alpha_R;
+    double gamma;
+    WenoConst W;
     int bc;                // boundary condition along the sweep
     int slot_rd, slot_wr, slot_zero;
     int stage;             // 1..3 (MODE_LAST_STAGE)
@@ -290,14 +291,13 @@ __global__ __launch_bounds__(kThreads, WT_SWEEP_MIN_WAVES) void sweep_kernel(Swe
                 const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
                 const SlotSpeeds al{st->alpha[A.slot_rd], DIR};
                 double F[M];
-                if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.eps, A.alpha_R, F))
+                if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.W, F))
                     atomicOr(&st->err, kErrNonphysical);
 #pragma unroll
                 for (int q = 0; q < M; ++q) s_F[q][t] = F[q];
             } else {
                 const LdsScalarStencil<NC, TX> S{s_u[0], s_f[0], t};
-                s_F[0][t] = scalar_interface_flux<PREC>(S, bits_to_double(st->alpha[A.slot_rd][0]), A.eps,
-                                                  A.alpha_R);
+                s_F[0][t] = scalar_interface_flux<PREC>(S, bits_to_double(st->alpha[A.slot_rd][0]), A.W);
             }
         }
     }
@@ -583,8 +583,7 @@ SweepArgs base_args(wt_ctx *c, const Shape &S, const wt_params *P)
     A.ncell = S.ncell;
     A.a = P->a;
     A.gamma = P->gamma;
-    A.eps = P->eps;
-    A.alpha_R = P->alpha_R;
+    A.W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
     A.D = c->D;
     return A;
 }

@@ -32,12 +32,12 @@ namespace wt {
 // One interface reconstruction of six split values in precision mode PREC
 // (0: FP64 with the plain operation order, 1: FP32 reconstruction).
 template <int PREC>
-WT_HD double reconstruct(const double *v, double eps, double alpha_R)
+WT_HD double reconstruct(const double *v, const WenoConst &W)
 {
     if constexpr (PREC == 0)
-        return weno_theta(v[0], v[1], v[2], v[3], v[4], v[5], eps, alpha_R);
+        return weno_theta(v[0], v[1], v[2], v[3], v[4], v[5], W.eps, W.alpha_R, W.reps);
     else
-        return weno_theta_fp32_recon(v, eps, (float)alpha_R);
+        return weno_theta_fp32_recon(v, W.eps, (float)W.alpha_R);
 }
 
 // Normal flux of a cell in canonical component order for direction DIR:
@@ -58,8 +58,8 @@ WT_HD void euler_normal_flux(const double *uc, const double *vel, double p, doub
 // flux in canonical component order.  Returns false if the Roe sound speed is
 // not real.
 template <int NDIM, int DIR, int PREC, class Acc, class Alpha>
-WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, double eps,
-                                double alpha_R, double *F)
+WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, const WenoConst &W,
+                                double *F)
 {
     constexpr int M = NDIM + 2;
     constexpr int NT = NDIM - 1;
@@ -79,6 +79,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, dou
     double acc[M];
 #pragma unroll 1
     for (int it = 0; it < M; ++it) {
+        WT_RELOAD();                            // stencil values come from memory per field
         const int s = it == 1 ? 2 : (it == 2 ? 1 : it);
         // row s of L in permuted order
         double ln0, ln1, lE, lt[NT > 0 ? NT : 1];
@@ -122,18 +123,22 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, dou
                 w[k] = ln0 * S.f(k, 0) + S.f(k, ax);
             }
         }
-        // split and reconstruct: sign +1 on j-2..j+3, sign -1 mirrored
+        // split v+- = (w +- a q) / 2 at each point, then reconstruct: sign +1 on
+        // j-2..j+3, sign -1 on the mirrored stencil
+        double vp[6], vm[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double aq = a * q[k];
+            vp[k] = 0.5 * (w[k] + aq);
+            vm[5 - k] = 0.5 * (w[k] - aq);
+        }
         double h = 0.0;
 #pragma unroll 1
         for (int sg = 0; sg < 2; ++sg) {
             double v[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const double vplus = 0.5 * (w[k] + a * q[k]);
-                const double vminus = 0.5 * (w[5 - k] - a * q[5 - k]);
-                v[k] = sg == 0 ? vplus : vminus;
-            }
-            const double r = reconstruct<PREC>(v, eps, alpha_R);
+            for (int k = 0; k < 6; ++k) v[k] = sg == 0 ? vp[k] : vm[k];
+            const double r = reconstruct<PREC>(v, W);
             h = sg == 0 ? r : h + r;
         }
         // accumulate R h: column s of R in permuted order
@@ -171,7 +176,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, dou
 }
 
 template <int PREC, class Acc>
-WT_HD double scalar_interface_flux(const Acc &S, double al, double eps, double alpha_R)
+WT_HD double scalar_interface_flux(const Acc &S, double al, const WenoConst &W)
 {
     double vp[6], vm[6];
 #pragma unroll
@@ -180,7 +185,7 @@ WT_HD double scalar_interface_flux(const Acc &S, double al, double eps, double a
         vp[k] = 0.5 * (f + al * x);
         vm[5 - k] = 0.5 * (f - al * x);
     }
-    return reconstruct<PREC>(vp, eps, alpha_R) + reconstruct<PREC>(vm, eps, alpha_R);
+    return reconstruct<PREC>(vp, W) + reconstruct<PREC>(vm, W);
 }
 
 }  // namespace wt

@@ -57,11 +57,12 @@ WT_HD double neighbour(double x, bool up)
     return double_of(bits_of(x) + (away ? 1 : -1));
 }
 
-// Nearest double to a / b given a faithful q (b > 0).
+// Nearest double to a / b given a faithful q (b > 0).  An infinite or NaN q
+// (overflow, or NaN operands) is already the IEEE result.
 WT_HD double div_finish(double q, double a, double b)
 {
     const double r = __builtin_fma(-q, b, a);
-    if (!(r != 0.0) || !(q != 0.0)) return q;   // exact, zero or NaN
+    if (!(r != 0.0) || !(q != 0.0) || !__builtin_isfinite(q)) return q;   // exact, 0, inf, NaN
     const double qn = neighbour(q, r > 0.0);
     const double rn = __builtin_fma(-qn, b, a);
     return __builtin_fabs(rn) < __builtin_fabs(r) ? qn : q;
@@ -102,6 +103,42 @@ WT_HD double div_rn(double a, double b)
     return div_finish(a / b, a, b);
 #else
     return a / b;
+#endif
+}
+
+// a / b rounded to nearest for a >= 0 and b > 0 from y = RN(1 / b), with the
+// range of div_by_recip's proof checked: a = 0, or a and the first product
+// both at least 2^-900 (the remainders a - b q are then exact) and the product
+// far from overflow; otherwise (tiny, huge or NaN) the full division is taken.
+WT_HD double div_by_recip_checked(double a, double b, double y)
+{
+    const double q0 = a * y;
+    if ((a >= 0x1p-900 && q0 >= 0x1p-900 && q0 <= 0x1p+1000) || a == 0.0) {
+        const double q1 = __builtin_fma(__builtin_fma(-b, q0, a), y, q0);
+        return __builtin_fma(__builtin_fma(-b, q1, a), y, q1);
+    }
+    return div_rn(a, b);
+}
+
+// 1 / b rounded to nearest from an estimate y0 within 2^-14 (relative) of
+// 1 / b, for 2^-1000 <= b <= 2^1000: two Newton steps (each squares the
+// relative error, and their rounding errors stay far below an ulp) give a
+// faithful reciprocal, and the exact neighbour test makes it the nearest.
+WT_HD double recip_refine(double b, double y0)
+{
+    double y = __builtin_fma(y0, __builtin_fma(-b, y0, 1.0), y0);
+    y = __builtin_fma(y, __builtin_fma(-b, y, 1.0), y);
+    return div_finish(y, 1.0, b);
+}
+
+// 1 / b rounded to nearest for 2^-1000 <= b <= 2^1000: the hardware
+// reciprocal estimate, refined.
+WT_HD double recip_rn(double b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return recip_refine(b, __builtin_amdgcn_rcp(b));
+#else
+    return 1.0 / b;
 #endif
 }
 

@@ -45,9 +45,15 @@ struct GammaTheta {
 
 WT_HD double sq(double x) { return x * x; }
 
+// The scheme's constants as the reconstructions take them: eps, alpha_R and
+// reps = RN(1 / eps) (formed once on the host, where division is IEEE).
+struct WenoConst {
+    double eps, alpha_R, reps;
+};
+
 // s0..s5 = f_{j-2} .. f_{j+3}.
-WT_HD double weno_theta(double s0, double s1, double s2, double s3,
-                                             double s4, double s5, double eps, double alpha_R)
+WT_HD double weno_theta(double s0, double s1, double s2, double s3, double s4, double s5,
+                        double eps, double alpha_R, double reps)
 {
     // candidate fluxes
     const double q0 = (2.0 / 6.0) * s0 - (7.0 / 6.0) * s1 + (11.0 / 6.0) * s2;
@@ -92,10 +98,11 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3,
     const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
 
     // alpha_k = gamma_k (1 + tau / (eps + beta~_k)); restricted indicators are
-    // all zero, so the four quotients are one: tau / (eps + 0) = tau / eps
+    // all zero, so the four quotients are one: tau / (eps + 0) = tau / eps,
+    // formed from the nearest reciprocal of eps
     double d0, d1, d2, d3;
     if (restricted) {
-        d0 = div_rn(tau, eps);
+        d0 = div_by_recip_checked(tau, eps, reps);
         d1 = d0;
         d2 = d0;
         d3 = d0;
@@ -111,10 +118,11 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3,
     const double a3 = g3 * (1.0 + d3);
     const double sum = a0 + a1 + a2 + a3;
 
-    // omega_k = alpha_k / sum share the denominator: one reciprocal
+    // omega_k = alpha_k / sum share the denominator: one reciprocal (sum is at
+    // least about 1, since the alpha_k are at least the gamma_k, which sum to 1)
     double w0, w1, w2, w3;
-    if (sum <= 0x1.fffffffffffffp+1023) {
-        const double y = div_rn(1.0, sum);
+    if (sum <= 0x1p+1000) {
+        const double y = recip_rn(sum);
         w0 = div_by_recip(a0, sum, y);
         w1 = div_by_recip(a1, sum, y);
         w2 = div_by_recip(a2, sum, y);

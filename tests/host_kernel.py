@@ -84,3 +84,17 @@ def div_by_recip(a, b, y) -> float:
     f.restype = ctypes.c_double
     f.argtypes = [ctypes.c_double] * 3
     return f(a, b, y)
+
+
+def div_by_recip_checked(a, b, y) -> float:
+    f = lib().wth_div_by_recip_checked
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_double] * 3
+    return f(a, b, y)
+
+
+def recip_refine(b, y0) -> float:
+    f = lib().wth_recip_refine
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_double] * 2
+    return f(b, y0)

@@ -133,3 +133,36 @@ def test_markstein_quotients_on_hard_cases():
     a_hard = float.fromhex("0x1.6666666666663p-2")
     b_hard = float.fromhex("0x1.ffffffffffffbp-4")
     assert HK.div_by_recip(a_hard, b_hard, 1.0 / b_hard) == a_hard / b_hard
+
+
+def test_restricted_quotient_from_the_reciprocal_of_eps():
+    """tau / eps in the restricted case is formed from RN(1/eps) with two FMA corrections
+    where the first product is zero or normal and far from overflow, else by full division:
+    equal to IEEE division for the paper's eps and others, over tau from 0 and subnormal to
+    huge, including significands next to powers of two."""
+    rng = np.random.default_rng(5)
+    for eps in (1e-10, 1e-6, 1e-40, 3.0, float.fromhex("0x1.fffffffffffffp-34")):
+        y = 1.0 / eps
+        taus = [0.0, 5e-324, 1e-310, 2.0 ** -960, 1e-300, 1.0, 1e290, 1e300, 1.7e308]
+        taus += [math.ldexp(1 + i * 2.0 ** -52, e) for i in range(0, 64) for e in (-40, -3, 0, 7, 60)]
+        taus += [math.ldexp(1 - i * 2.0 ** -53, e) for i in range(1, 64) for e in (-20, 0, 30)]
+        taus += list(np.exp(rng.uniform(-700, 700, 4000)))
+        for tau in taus:
+            got = HK.div_by_recip_checked(tau, eps, y)
+            want = tau / eps
+            assert got == want or (math.isinf(got) and math.isinf(want)), (tau, eps, got, want)
+
+
+def test_reciprocal_refinement_from_coarse_estimates():
+    """The device reciprocal refines the hardware estimate with two Newton steps and the
+    exact neighbour test: from any estimate within 2^-14 (relative) it must give RN(1/b).
+    Estimates here are the nearest reciprocal perturbed by up to 2^-14, both ways, for b
+    spread over [2^-1000, 2^1000] and b with all-ones or near-power-of-two significands."""
+    rng = np.random.default_rng(6)
+    bs = list(np.exp(rng.uniform(-690, 690, 3000)))
+    bs += [math.ldexp(2 - k * 2.0 ** -52, e) for k in range(1, 40) for e in (-1000, -5, 0, 9, 999)]
+    bs += [math.ldexp(1 + k * 2.0 ** -52, e) for k in range(0, 40) for e in (-3, 0, 11)]
+    for b in bs:
+        want = 1.0 / b
+        for rel in (0.0, 2.0 ** -14, -(2.0 ** -14), 3e-6, -7e-9, 2.0 ** -40):
+            assert HK.recip_refine(b, want * (1.0 + rel)) == want, (b, rel)

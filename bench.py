@@ -151,12 +151,17 @@ def timed(stream, fn):
     return ev0.elapsed_time(ev1), r
 
 
-def run_grid(wt, ctx, case, precision, steps, warmup, profile):
+def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None):
     import torch
     g = wt.Grid(n=case.n, lo=case.lo, hi=case.hi, bc=case.bc)
     p = wt.Params(system=case.system, gamma=case.gamma, cfl=case.cfl, alpha_R=case.alpha_R,
                   precision=precision)
     u_init = torch.from_numpy(case.u).cuda()
+    if tile_choice is None:
+        tiles = wt.wenotheta_tune(ctx, g, p, u_init)      # untimed set-up: y/z tile shapes
+    else:
+        tiles = tuple([0] + [tile_choice] * (case.ndim - 1))
+        wt.wenotheta_set_tiles(ctx, g, p, tiles)
     if warmup > 0:
         u = u_init.clone()
         wt.wenotheta_solve(ctx, g, p, u, float("inf"), max_steps=warmup)
@@ -175,7 +180,8 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile):
         wt.wenotheta_profile(ctx, False)
     assert k == steps, (k, steps)
     assert bool(torch.isfinite(u).all()), "non-finite state after the timed steps"
-    return {"ms": ms, "wall": wall, "t_sim": t_sim, "u": u, "prof": prof}
+    return {"ms": ms, "wall": wall, "t_sim": t_sim, "u": u, "prof": prof,
+            "tiles": [list(wt.TILE_SHAPES[v]) if d > 0 else [1, 255] for d, v in enumerate(tiles)]}
 
 
 def run_batched(wt, ctx, B, precision, steps, warmup):
@@ -273,6 +279,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--n", type=int, default=None, help="points per dimension (default: full size)")
     ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--tiles", default="auto", choices=["auto", "0", "1", "2", "3"],
+                    help="y/z-sweep tile shape: tuned (auto) or forced variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
@@ -300,7 +308,8 @@ def main():
           f"warmup={args.warmup}", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     ctx = wt.Context(0)
-    r = run_grid(wt, ctx, case, prec, args.steps, args.warmup, profile=True)
+    tile_choice = None if args.tiles == "auto" else int(args.tiles)
+    r = run_grid(wt, ctx, case, prec, args.steps, args.warmup, profile=True, tile_choice=tile_choice)
     ms, prof = r["ms"], r["prof"]
 
     sec = ms / 1e3
@@ -334,7 +343,8 @@ def main():
         "config": {"workload": f"{desc}, {'x'.join(map(str, case.n))} points, "
                                f"{args.steps} RK3 steps, CFL {case.cfl}, {args.precision}",
                    "grid": list(case.n), "steps": args.steps, "cfl": case.cfl,
-                   "alpha_R": case.alpha_R, "precision": args.precision},
+                   "alpha_R": case.alpha_R, "precision": args.precision,
+                   "tiles_tx_tn": r["tiles"]},
         "roofline": {"bound": "alu", "kernel": kind, "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak,
@@ -353,10 +363,12 @@ def main():
     }
     if not args.no_companions and args.workload == "euler2d" and prec == wt.WT_FP64:
         print("[bench] companion: same workload, FP32 reconstruction", file=sys.stderr, flush=True)
-        r32 = run_grid(wt, ctx, case, wt.WT_FP32_RECON, args.steps, args.warmup, profile=False)
+        r32 = run_grid(wt, ctx, case, wt.WT_FP32_RECON, args.steps, args.warmup, profile=False,
+                       tile_choice=tile_choice)
         comp = {"euler2d_fp32_recon": {
             "value": cells * args.steps / (r32["ms"] / 1e3), "unit": "cell-updates/s",
-            "ms_per_step": r32["ms"] / args.steps, "l1_rel_vs_fp64": l1_rel(r32["u"], r["u"])}}
+            "ms_per_step": r32["ms"] / args.steps, "l1_rel_vs_fp64": l1_rel(r32["u"], r["u"]),
+            "tiles_tx_tn": r32["tiles"]}}
         del r32
         comp["batched"] = batched_companions(wt, ctx, args.batched_steps)
         comp["batched"]["fp32_recon_over_plain_fp64"] = comp["batched"]["fp32_recon"]["value"] / value

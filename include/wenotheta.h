@@ -172,6 +172,30 @@ wt_status wenotheta_solve_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
                                   int64_t total, int64_t nsteps, double *t_out,
                                   int32_t *status_out, int64_t *steps_out, void *stream);
 
+/* Tile shapes of the sweeps (dimension-by-dimension scheme of Sec. 4.3: one
+ * 1D operator per direction).  The y and z sweeps of the 2D/3D Euler system
+ * run in one of four tile shapes, TX consecutive x-columns by TN points along
+ * the sweep direction, 256 interfaces per workgroup:
+ *   0: 8 x 31 (default)   1: 16 x 15   2: 4 x 63   3: 32 x 7
+ * Every shape computes the same fluxes with the same operations: the results
+ * are bit-identical whichever is used; only the speed differs.  The choice
+ * is kept in the context per grid shape (system, ndim, n, precision; the 16
+ * most recent shapes).
+ *
+ * wenotheta_tune times each shape on `u` (DEVICE, the state layout of
+ * wenotheta_rhs; only read) with the sweep that writes the context's
+ * workspace, keeps the fastest, and writes it to tile_out[0..ndim-1] (HOST,
+ * optional; entry 0, the x sweep, is always 0).  It synchronises `stream`
+ * (do not call it during graph capture) and returns any device error.
+ *
+ * wenotheta_set_tiles sets the shapes for the grid instead: tile[d] in 0..3
+ * for d < ndim (HOST); tile[0] is ignored by the x sweep and systems or
+ * dimensions without choices ignore all entries.  No device work. */
+wt_status wenotheta_tune(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm, const double *u,
+                         int32_t *tile_out, void *stream);
+wt_status wenotheta_set_tiles(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
+                              const int32_t *tile);
+
 /* Wait for the work queued on `stream` and return (and clear) any error the
  * device recorded since the last synchronising call. */
 wt_status wenotheta_sync(wt_ctx *ctx, void *stream);

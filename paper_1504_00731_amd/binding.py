@@ -23,7 +23,8 @@ WT_FP64, WT_FP32_RECON = 0, 1
 
 EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
             "wenotheta_rhs", "wenotheta_step", "wenotheta_solve", "wenotheta_sync",
-            "wenotheta_profile", "wenotheta_profile_read", "wenotheta_solve_batched")
+            "wenotheta_profile", "wenotheta_profile_read", "wenotheta_solve_batched",
+            "wenotheta_tune", "wenotheta_set_tiles")
 PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
                  "sweep_z_final")
 
@@ -80,6 +81,9 @@ def _lib():
         L.wenotheta_solve_batched.argtypes = [vp, ctypes.c_int64, i64p, i64p, dp, dp, i32p, P, vp,
                                               ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
         L.wenotheta_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        i32p3 = ctypes.POINTER(ctypes.c_int32)
+        L.wenotheta_tune.argtypes = [vp, G, P, vp, i32p3, vp]
+        L.wenotheta_set_tiles.argtypes = [vp, G, P, i32p3]
         for name in EXPORTED:
             if name != "wenotheta_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -236,6 +240,28 @@ def wenotheta_solve(ctx: Context, grid: Grid, params: Params, u, t_end, t0=0.0, 
                                   float(t0), float(t_end), int(max_steps), ctypes.byref(t),
                                   ctypes.byref(k), _stream_ptr(stream)), "wenotheta_solve")
     return t.value, k.value
+
+
+TILE_SHAPES = ((8, 31), (16, 15), (4, 63), (32, 7))   # (TX, TN) of the y/z-sweep tile variants
+
+
+def wenotheta_tune(ctx: Context, grid: Grid, params: Params, u, stream=None) -> tuple:
+    """Times the y/z-sweep tile shapes on u and keeps the fastest for this grid in the
+    context; returns the chosen variant per direction.  Synchronises the stream."""
+    out = (ctypes.c_int32 * 3)(0, 0, 0)
+    _check(_lib().wenotheta_tune(ctx.handle, ctypes.byref(grid.c_struct()),
+                                 ctypes.byref(params.c_struct()),
+                                 _dev_ptr(u, "u", state_shape(grid, params)), out,
+                                 _stream_ptr(stream)), "wenotheta_tune")
+    return tuple(out[:grid.ndim])
+
+
+def wenotheta_set_tiles(ctx: Context, grid: Grid, params: Params, tiles) -> None:
+    """Sets the tile variant per direction (0..3) for this grid."""
+    t = list(tiles) + [0] * (3 - len(tiles))
+    arr = (ctypes.c_int32 * 3)(*[int(v) for v in t[:3]])
+    _check(_lib().wenotheta_set_tiles(ctx.handle, ctypes.byref(grid.c_struct()),
+                                      ctypes.byref(params.c_struct()), arr), "wenotheta_set_tiles")
 
 
 def wenotheta_sync(ctx: Context, stream=None):

@@ -67,13 +67,26 @@ __device__ __forceinline__ void block_max3(double (&v)[3], double (*red)[kThread
     __syncthreads();
 }
 
+// A value every lane of the wave holds alike, read once as a scalar (it then
+// lives in scalar registers instead of one vector register pair per lane).
+__device__ __forceinline__ double uniform(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 struct LdsSpeeds {
     const double *a;
     __device__ double operator()(int s) const { return a[s]; }
 };
 
+// The FP64 form is held to 3 waves per SIMD (at most 168 VGPRs): left to
+// itself it takes 174, and it fits 164 without spilling.  The FP32 form
+// reaches 3 waves by itself.
 template <int PREC>
-__global__ __launch_bounds__(kThreads) void batched_kernel(BatchArgs A)
+__global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(BatchArgs A)
 {
     constexpr int M = 3, TN = kThreads - 1, NC = TN + 6;
     __shared__ double s_u[M][NC];
@@ -119,6 +132,8 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchArgs A)
             for (int k = 0; k < 3; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
         }
         block_max3(spd, s_red);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) spd[k] = uniform(spd[k]);
 
         double time = 0.0;
         // first step at which this thread met a non-physical state (nsteps: none)
@@ -126,12 +141,13 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchArgs A)
         for (int64_t step = 0; step < A.nsteps; ++step) {
             // dt = cfl / (amax / dx), amax = max(|u| + c) = max(alpha_0, alpha_2)
             const double am = spd[2] > spd[0] ? spd[2] : spd[0];
-            const double dt = div_rn(A.cfl, div_rn(am, dx));
+            const double dt = uniform(div_rn(A.cfl, div_rn(am, dx)));
             for (int stage = 1; stage <= 3; ++stage) {
                 const double *uin = stage == 1 ? A.u : (stage == 2 ? A.U1 : A.U2);
                 double *out = stage == 1 ? A.U1 : (stage == 2 ? A.U2 : A.u);
                 if (t < 3) s_al[t] = spd[t];
-                double nsp[3] = {0.0, 0.0, 0.0};
+                // the new state's speeds: per-wave maxima over the segments, in LDS
+                if ((t & 63) < 3) s_red[t & 63][t >> 6] = 0.0;
                 for (int64_t seg = 0; seg < nseg; ++seg) {
                     const int64_t g0 = seg * TN;
                     // stage the segment and its halos
@@ -167,6 +183,7 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchArgs A)
                         for (int c = 0; c < 3; ++c) s_F[c][t] = F[c];
                     }
                     __syncthreads();
+                    double lam[3] = {0.0, 0.0, 0.0};
                     if (t < TN && g0 + t < n) {
                         const int64_t idx = off + g0 + t;
                         double un[3];
@@ -183,21 +200,28 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchArgs A)
                         }
 #pragma unroll
                         for (int c = 0; c < 3; ++c) out[c * total + idx] = un[c];
-                        double lam[3];
                         err |= euler_speeds<1>(un, A.gamma, lam);
+                    }
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) nsp[k] = lam[k] > nsp[k] ? lam[k] : nsp[k];
+                    for (int k = 0; k < 3; ++k) {
+                        const double w = wave_max(lam[k]);
+                        if ((t & 63) == 0) s_red[k][t >> 6] = w > s_red[k][t >> 6] ? w : s_red[k][t >> 6];
                     }
                     __syncthreads();                // the tile is reused by the next segment
                 }
                 // the next stage reads what this one wrote
                 __threadfence();
-                block_max3(nsp, s_red);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) spd[k] = nsp[k];
+                for (int k = 0; k < 3; ++k) {
+                    double m = s_red[k][0];
+#pragma unroll
+                    for (int w = 1; w < kThreads / 64; ++w) m = s_red[k][w] > m ? s_red[k][w] : m;
+                    spd[k] = uniform(m);
+                }
+                __syncthreads();                    // s_red is cleared again by the next stage
             }
             if (err && first_bad == A.nsteps) first_bad = step;
-            time = time + dt;
+            time = uniform(time + dt);
         }
         // per-problem outcome (a failed problem keeps being advanced; its columns are
         // then unspecified): OR of the error bits and the first failing step

@@ -181,11 +181,18 @@ __global__ void copy_dt_kernel(const DevState *st, double *dst)
 // Sweep kernel
 // ---------------------------------------------------------------------------
 
+// Minimum waves per SIMD the register allocation must allow: 4 for the 1D
+// Euler sweeps, which then fit 128 VGPRs without spilling; the others are left
+// to the compiler (2D reaches 4 by itself, 3D stays at 3).
+template <int SYS, int NDIM>
+constexpr int sweep_min_waves()
+{
+    return SYS == WT_EULER && NDIM == 1 ? 4 : 1;
+}
+
 template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE, int PREC>
-#ifndef WT_SWEEP_MIN_WAVES
-#define WT_SWEEP_MIN_WAVES 1
-#endif
-__global__ __launch_bounds__(kThreads, WT_SWEEP_MIN_WAVES) void sweep_kernel(SweepArgs A)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<SYS, NDIM>())))
+void sweep_kernel(SweepArgs A)
 {
     static_assert(TX * (TN + 1) == kThreads, "one interface per thread");
     constexpr int M = Ncomp<SYS, NDIM>::value;
@@ -385,67 +392,99 @@ __global__ __launch_bounds__(kThreads, WT_SWEEP_MIN_WAVES) void sweep_kernel(Swe
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
-template <int DIR>
-struct TileShape;
+// Tile shapes (TX columns x TN points along the sweep, TX (TN + 1) = 256
+// interfaces).  x-sweeps: 1 x 255 (a contiguous row segment).  y/z-sweeps of
+// the Euler system in 2D/3D: one of kTileVariants shapes, chosen per grid by
+// wenotheta_tune (default 0); every shape computes the same interface fluxes
+// with the same operations, so the results do not depend on the choice.
+//   0: 8 x 31   1: 16 x 15   2: 4 x 63   3: 32 x 7
+template <int V>
+struct TileYZ;
 template <>
-struct TileShape<0> { static constexpr int TX = 1, TN = 255; };
+struct TileYZ<0> { static constexpr int TX = 8, TN = 31; };
 template <>
-struct TileShape<1> { static constexpr int TX = 8, TN = 31; };
+struct TileYZ<1> { static constexpr int TX = 16, TN = 15; };
 template <>
-struct TileShape<2> { static constexpr int TX = 8, TN = 31; };
+struct TileYZ<2> { static constexpr int TX = 4, TN = 63; };
+template <>
+struct TileYZ<3> { static constexpr int TX = 32, TN = 7; };
 
-template <int SYS, int NDIM, int DIR, int MODE, int PREC>
-hipError_t launch_sweep(const SweepArgs &A, hipStream_t s)
+template <int SYS, int NDIM, int DIR>
+constexpr bool has_tile_variants()
 {
-    constexpr int TX = TileShape<DIR>::TX, TN = TileShape<DIR>::TN;
+    return SYS == SYS_EULER && NDIM > 1 && DIR > 0;
+}
+
+template <int SYS, int NDIM, int DIR, int MODE, int PREC, int TX, int TN>
+hipError_t launch_tile(const SweepArgs &A, hipStream_t s)
+{
     const int64_t nd = A.n[DIR];
     const int64_t nseg = (nd + TN - 1) / TN;
     int64_t blocks;
     if (DIR == 0) blocks = nseg * A.n[1] * A.n[2];
     else if (DIR == 1) blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[2];
     else blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[1];
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_kernel<SYS, NDIM, DIR, TX, TN, MODE, PREC>), dim3((unsigned)blocks),
                        dim3(kThreads), 0, s, A);
     return hipGetLastError();
 }
 
+template <int SYS, int NDIM, int DIR, int MODE, int PREC>
+hipError_t launch_sweep(const SweepArgs &A, int tile, hipStream_t s)
+{
+    if constexpr (!has_tile_variants<SYS, NDIM, DIR>()) {
+        (void)tile;
+        constexpr int TX = DIR == 0 ? 1 : 8, TN = DIR == 0 ? 255 : 31;
+        return launch_tile<SYS, NDIM, DIR, MODE, PREC, TX, TN>(A, s);
+    } else {
+        switch (tile) {
+            case 1: return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<1>::TX, TileYZ<1>::TN>(A, s);
+            case 2: return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<2>::TX, TileYZ<2>::TN>(A, s);
+            case 3: return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<3>::TX, TileYZ<3>::TN>(A, s);
+            default: return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<0>::TX, TileYZ<0>::TN>(A, s);
+        }
+    }
+}
+
 template <int SYS, int NDIM, int DIR, int PREC>
-hipError_t launch_sweep_mode(int mode, const SweepArgs &A, hipStream_t s)
+hipError_t launch_sweep_mode(int mode, const SweepArgs &A, int tile, hipStream_t s)
 {
     switch (mode) {
-        case MODE_FIRST: return launch_sweep<SYS, NDIM, DIR, MODE_FIRST, PREC>(A, s);
-        case MODE_MID: return launch_sweep<SYS, NDIM, DIR, MODE_MID, PREC>(A, s);
-        case MODE_LAST_RHS: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_RHS, PREC>(A, s);
-        default: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_STAGE, PREC>(A, s);
+        case MODE_FIRST: return launch_sweep<SYS, NDIM, DIR, MODE_FIRST, PREC>(A, tile, s);
+        case MODE_MID: return launch_sweep<SYS, NDIM, DIR, MODE_MID, PREC>(A, tile, s);
+        case MODE_LAST_RHS: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_RHS, PREC>(A, tile, s);
+        default: return launch_sweep<SYS, NDIM, DIR, MODE_LAST_STAGE, PREC>(A, tile, s);
     }
 }
 
 template <int SYS, int NDIM, int PREC>
-hipError_t launch_sweep_dir(int dir, int mode, const SweepArgs &A, hipStream_t s)
+hipError_t launch_sweep_dir(int dir, int mode, const SweepArgs &A, int tile, hipStream_t s)
 {
-    if (dir == 0) return launch_sweep_mode<SYS, NDIM, 0, PREC>(mode, A, s);
+    if (dir == 0) return launch_sweep_mode<SYS, NDIM, 0, PREC>(mode, A, tile, s);
     if constexpr (NDIM > 1)
-        if (dir == 1) return launch_sweep_mode<SYS, NDIM, 1, PREC>(mode, A, s);
+        if (dir == 1) return launch_sweep_mode<SYS, NDIM, 1, PREC>(mode, A, tile, s);
     if constexpr (NDIM > 2)
-        if (dir == 2) return launch_sweep_mode<SYS, NDIM, 2, PREC>(mode, A, s);
+        if (dir == 2) return launch_sweep_mode<SYS, NDIM, 2, PREC>(mode, A, tile, s);
     return hipErrorInvalidValue;
 }
 
 template <int PREC>
-hipError_t launch_sweep_prec(int sys, int ndim, int dir, int mode, const SweepArgs &A, hipStream_t s)
+hipError_t launch_sweep_prec(int sys, int ndim, int dir, int mode, const SweepArgs &A, int tile,
+                             hipStream_t s)
 {
-    if (sys == SYS_LINEAR) return launch_sweep_dir<SYS_LINEAR, 1, PREC>(dir, mode, A, s);
-    if (sys == SYS_BURGERS) return launch_sweep_dir<SYS_BURGERS, 1, PREC>(dir, mode, A, s);
-    if (ndim == 1) return launch_sweep_dir<SYS_EULER, 1, PREC>(dir, mode, A, s);
-    if (ndim == 2) return launch_sweep_dir<SYS_EULER, 2, PREC>(dir, mode, A, s);
-    return launch_sweep_dir<SYS_EULER, 3, PREC>(dir, mode, A, s);
+    if (sys == SYS_LINEAR) return launch_sweep_dir<SYS_LINEAR, 1, PREC>(dir, mode, A, tile, s);
+    if (sys == SYS_BURGERS) return launch_sweep_dir<SYS_BURGERS, 1, PREC>(dir, mode, A, tile, s);
+    if (ndim == 1) return launch_sweep_dir<SYS_EULER, 1, PREC>(dir, mode, A, tile, s);
+    if (ndim == 2) return launch_sweep_dir<SYS_EULER, 2, PREC>(dir, mode, A, tile, s);
+    return launch_sweep_dir<SYS_EULER, 3, PREC>(dir, mode, A, tile, s);
 }
 
 hipError_t launch_sweep_any(int sys, int ndim, int prec, int dir, int mode, const SweepArgs &A,
-                            hipStream_t s)
+                            int tile, hipStream_t s)
 {
-    if (prec == WT_FP32_RECON) return launch_sweep_prec<1>(sys, ndim, dir, mode, A, s);
-    return launch_sweep_prec<0>(sys, ndim, dir, mode, A, s);
+    if (prec == WT_FP32_RECON) return launch_sweep_prec<1>(sys, ndim, dir, mode, A, tile, s);
+    return launch_sweep_prec<0>(sys, ndim, dir, mode, A, tile, s);
 }
 
 hipError_t launch_alpha(int sys, int ndim, const double *u, int64_t ncell, double a, double gamma,
@@ -545,14 +584,50 @@ wt_status ensure_workspace(wt_ctx *c, const Shape &S)
     return WT_OK;
 }
 
+uint64_t bits(double d)
+{
+    uint64_t b;
+    std::memcpy(&b, &d, sizeof b);
+    return b;
+}
+
+uint64_t plan_key(const Shape &S, const wt_params *P)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (uint64_t v : {(uint64_t)P->system, (uint64_t)S.ndim, (uint64_t)S.n[0], (uint64_t)S.n[1],
+                       (uint64_t)S.n[2], (uint64_t)P->precision})
+        h = (h ^ v) * 1099511628211ull;
+    return h;
+}
+
+// Tile variant of direction dir for this grid (0 unless tuned or set).
+int plan_tile(const wt_ctx *c, const Shape &S, const wt_params *P, int dir)
+{
+    const uint64_t key = plan_key(S, P);
+    for (int i = 0; i < c->nplans; ++i)
+        if (c->plans[i].key == key) return c->plans[i].tile[dir];
+    return 0;
+}
+
+void set_plan(wt_ctx *c, const Shape &S, const wt_params *P, const int *tile)
+{
+    const uint64_t key = plan_key(S, P);
+    int i = 0;
+    while (i < c->nplans && c->plans[i].key != key) ++i;
+    if (i == c->nplans) i = c->nplans < kTilePlans ? c->nplans++ : kTilePlans - 1;
+    for (; i > 0; --i) c->plans[i] = c->plans[i - 1];          // most recent first
+    c->plans[0].key = key;
+    for (int d = 0; d < 3; ++d) c->plans[0].tile[d] = (int8_t)tile[d];
+}
+
 // Launch one sweep, bracketed by profiling events when enabled.
 hipError_t timed_sweep(wt_ctx *c, int sys, int ndim, int prec, int dir, int mode,
-                       const SweepArgs &A, hipStream_t s)
+                       const SweepArgs &A, int tile, hipStream_t s)
 {
     const bool rec = c->prof && c->nev < kProfPairs;
     if (c->prof && !rec) c->prof_dropped++;
     if (rec && hipEventRecord(c->ev[2 * c->nev], s) != hipSuccess) return hipErrorUnknown;
-    const hipError_t e = launch_sweep_any(sys, ndim, prec, dir, mode, A, s);
+    const hipError_t e = launch_sweep_any(sys, ndim, prec, dir, mode, A, tile, s);
     if (e != hipSuccess) return e;
     if (rec) {
         if (hipEventRecord(c->ev[2 * c->nev + 1], s) != hipSuccess) return hipErrorUnknown;
@@ -620,7 +695,9 @@ wt_status queue_stage(wt_ctx *c, const Shape &S, const wt_params *P, const doubl
         A.dx = S.dx[d];
         A.rdx = 1.0 / S.dx[d];
         A.bc = S.bc[d];
-        if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
+        if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, plan_tile(c, S, P, d), s) !=
+            hipSuccess)
+            return WT_ERR_DEVICE;
     }
     c->g += 1;
     return WT_OK;
@@ -644,6 +721,46 @@ wt_status queue_step(wt_ctx *c, const Shape &S, const wt_params *P, double *u, d
     if ((r = queue_stage(c, S, P, u, u, c->U1, 1, s))) return r;
     if ((r = queue_stage(c, S, P, c->U1, u, c->U2, 2, s))) return r;
     if ((r = queue_stage(c, S, P, c->U2, u, u, 3, s))) return r;
+    return WT_OK;
+}
+
+// The solver graph: kGraphSteps steps of the current grid captured once per
+// argument set and replayed.  A step advances the stage counter by 3, so the
+// speed slots every replay uses are those of the capture.
+wt_status ensure_step_graph(wt_ctx *c, const Shape &S, const wt_params *P, double *u)
+{
+    uint64_t key = plan_key(S, P);
+    for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)c->U1, (uint64_t)(uintptr_t)c->U2,
+                       (uint64_t)(uintptr_t)c->D, (uint64_t)(uintptr_t)c->st, (uint64_t)(c->g % kSlots),
+                       (uint64_t)plan_tile(c, S, P, 1), (uint64_t)plan_tile(c, S, P, 2), bits(P->a),
+                       bits(P->gamma), bits(P->cfl), bits(P->eps), bits(P->alpha_R), bits(S.dx[0]),
+                       bits(S.dx[1]), bits(S.dx[2]), (uint64_t)S.bc[0], (uint64_t)S.bc[1], (uint64_t)S.bc[2]})
+        key = (key ^ v) * 1099511628211ull;
+    if (c->s_graph && c->s_key == key) return WT_OK;
+    if (c->s_graph) (void)hipGraphExecDestroy(c->s_graph);
+    c->s_graph = nullptr;
+    if (!c->s_capture && hipStreamCreateWithFlags(&c->s_capture, hipStreamNonBlocking) != hipSuccess)
+        return WT_ERR_DEVICE;
+    if (hipStreamBeginCapture(c->s_capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return WT_ERR_DEVICE;
+    const int64_t g0 = c->g;
+    wt_status r = WT_OK;
+    for (int i = 0; i < kGraphSteps && r == WT_OK; ++i) r = queue_step(c, S, P, u, 0.0, 1, c->s_capture);
+    c->g = g0;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->s_capture, &g);
+    if (r != WT_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return r != WT_OK ? r : WT_ERR_DEVICE;
+    }
+    const hipError_t ei = hipGraphInstantiate(&c->s_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        c->s_graph = nullptr;
+        return WT_ERR_DEVICE;
+    }
+    c->s_key = key;
     return WT_OK;
 }
 
@@ -722,6 +839,8 @@ wt_status wenotheta_ctx_destroy(wt_ctx *c)
     (void)hipFree(c->st);
     for (int k = 0; k < 2 * kProfPairs; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    if (c->s_graph) (void)hipGraphExecDestroy(c->s_graph);
+    if (c->s_capture) (void)hipStreamDestroy(c->s_capture);
     wt::release_batched(c);
     delete c;
     return WT_OK;
@@ -789,7 +908,9 @@ wt_status wenotheta_rhs(wt_ctx *c, const wt_grid *G, const wt_params *P, const d
         A.dx = S.dx[d];
         A.rdx = 1.0 / S.dx[d];
         A.bc = S.bc[d];
-        if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, s) != hipSuccess) return WT_ERR_DEVICE;
+        if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, plan_tile(c, S, P, d), s) !=
+            hipSuccess)
+            return WT_ERR_DEVICE;
     }
     return WT_OK;
 }
@@ -833,14 +954,26 @@ wt_status wenotheta_solve(wt_ctx *c, const wt_grid *G, const wt_params *P, doubl
                        (long long)max_steps);
     if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
     if ((r = queue_alpha_init(c, S, P, u, s))) return r;
+    // Steps are queued in chunks (1, 2, 4, .. 64 steps) with one synchronisation
+    // per chunk; steps past the end are no-ops on the device.  Without the
+    // profiler the steps are replayed from a captured graph of kGraphSteps.
+    const bool graph = !c->prof;
+    if (graph && (r = ensure_step_graph(c, S, P, u))) return r;
     DevState host{};
     int64_t launched = 0;
-    int64_t chunk = 1;
+    int64_t chunk = graph ? kGraphSteps : 1;
     for (;;) {
         int64_t k = chunk;
         if (max_steps >= 0 && launched + k > max_steps) k = max_steps - launched;
-        for (int64_t i = 0; i < k; ++i)
-            if ((r = queue_step(c, S, P, u, 0.0, 1, s))) return r;
+        if (graph) {
+            for (int64_t i = 0; i < k; i += kGraphSteps) {
+                if (hipGraphLaunch(c->s_graph, s) != hipSuccess) return WT_ERR_DEVICE;
+                c->g += 3 * kGraphSteps;
+            }
+        } else {
+            for (int64_t i = 0; i < k; ++i)
+                if ((r = queue_step(c, S, P, u, 0.0, 1, s))) return r;
+        }
         launched += k;
         if ((r = collect(c, s, &host))) return r;
         if (host.done || (max_steps >= 0 && launched >= max_steps)) break;
@@ -849,6 +982,111 @@ wt_status wenotheta_solve(wt_ctx *c, const wt_grid *G, const wt_params *P, doubl
     if (t_out) *t_out = host.t;
     if (steps_out) *steps_out = host.steps;
     return WT_OK;
+}
+
+wt_status wenotheta_set_tiles(wt_ctx *c, const wt_grid *G, const wt_params *P, const int32_t *tile)
+{
+    if (!c || !tile) return WT_ERR_ARG;
+    Shape S;
+    wt_status r = validate(G, P, S);
+    if (r) return r;
+    int t[3] = {0, 0, 0};
+    for (int d = 0; d < S.ndim; ++d) {
+        if (tile[d] < 0 || tile[d] >= kTileVariants) return WT_ERR_ARG;
+        t[d] = tile[d];
+    }
+    set_plan(c, S, P, t);
+    return WT_OK;
+}
+
+wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const double *u,
+                         int32_t *tile_out, void *stream)
+{
+    if (!c || !u) return WT_ERR_ARG;
+    Shape S;
+    wt_status r = validate(G, P, S);
+    if (r) return r;
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    if ((r = ensure_workspace(c, S))) return r;
+    hipStream_t s = (hipStream_t)stream;
+    int best[3] = {0, 0, 0};
+    if (P->system == WT_EULER && S.ndim > 1) {
+        // Each direction is timed in the role a step gives it (first, accumulating or
+        // stage-finishing sweep), on u, with the stage written to the workspace U2:
+        // set up a CFL dt from the speeds of u, then the divergence of the earlier
+        // directions, as the stage would.
+        hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, 0.0, 0.0, -1ll);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+        if ((r = queue_alpha_init(c, S, P, u, s))) return r;
+        StepArgs B{};
+        B.st = c->st;
+        B.slot = (int)(c->g % kSlots);
+        B.ndim = S.ndim;
+        B.euler = 1;
+        for (int k = 0; k < 3; ++k) B.dx[k] = S.dx[k];
+        B.cfl = P->cfl;
+        hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(64), 0, s, B);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+        SweepArgs A = base_args(c, S, P);
+        A.uin = u;
+        A.u0 = u;
+        A.out = c->U2;
+        A.stage = 1;
+        A.check_done = 0;
+        A.slot_rd = (int)(c->g % kSlots);
+        A.slot_wr = (int)((c->g + 1) % kSlots);
+        A.slot_zero = (int)((c->g + 2) % kSlots);
+        auto args_for = [&](int d) {
+            A.dx = S.dx[d];
+            A.rdx = 1.0 / S.dx[d];
+            A.bc = S.bc[d];
+            return d == S.ndim - 1 ? MODE_LAST_STAGE : (d == 0 ? MODE_FIRST : MODE_MID);
+        };
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return WT_ERR_DEVICE;
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return WT_ERR_DEVICE;
+        }
+        for (int d = 1; d < S.ndim && r == WT_OK; ++d) {
+            // the divergence of the directions before d, as the stage forms it
+            // (an accumulating sweep timed for an earlier direction added to it
+            // several times)
+            for (int e = 0; e < d && r == WT_OK; ++e) {
+                const int me = args_for(e);
+                if (launch_sweep_any(P->system, S.ndim, P->precision, e, me, A, best[e], s) != hipSuccess)
+                    r = WT_ERR_DEVICE;
+            }
+            const int mode = args_for(d);
+            {
+                // candidates interleaved over rounds; each keeps its fastest launch
+                float ms_best[kTileVariants];
+                for (int v = 0; v < kTileVariants; ++v) ms_best[v] = 1e30f;
+                for (int round = 0; round < 4 && r == WT_OK; ++round)
+                    for (int v = 0; v < kTileVariants && r == WT_OK; ++v) {
+                        float ms = 0.0f;
+                        if (hipEventRecord(e0, s) != hipSuccess ||
+                            launch_sweep_any(P->system, S.ndim, P->precision, d, mode, A, v, s) != hipSuccess ||
+                            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                            r = WT_ERR_DEVICE;
+                            break;
+                        }
+                        if (round > 0 && ms < ms_best[v]) ms_best[v] = ms;   // round 0 warms up
+                    }
+                for (int v = 1; v < kTileVariants; ++v)
+                    if (ms_best[v] < ms_best[best[d]]) best[d] = v;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (r) return r;
+    }
+    set_plan(c, S, P, best);
+    if (tile_out)
+        for (int d = 0; d < S.ndim; ++d) tile_out[d] = best[d];
+    DevState host{};
+    return collect(c, s, &host);
 }
 
 wt_status wenotheta_sync(wt_ctx *c, void *stream)

@@ -16,6 +16,15 @@
 constexpr int kProfKinds = 6;
 constexpr int kProfPairs = 4096;
 
+// Tile shape chosen for the y/z sweeps of one grid shape (see wenotheta_tune).
+struct wt_tile_plan {
+    uint64_t key = 0;     // system, ndim, n[], precision
+    int8_t tile[3] = {0, 0, 0};
+};
+constexpr int kTilePlans = 16;
+constexpr int kTileVariants = 4;
+constexpr int kGraphSteps = 8;        // steps per captured solver graph
+
 struct wt_ctx {
     int device = 0;
     wt::DevState *st = nullptr;
@@ -41,6 +50,13 @@ struct wt_ctx {
     hipGraphExec_t b_graph = nullptr;
     hipStream_t b_capture = nullptr;
     uint64_t b_key = 0;
+    // graph of kGraphSteps solver steps and the arguments it was captured with
+    hipGraphExec_t s_graph = nullptr;
+    hipStream_t s_capture = nullptr;
+    uint64_t s_key = 0;
+    // tile plans per grid shape, most recent first
+    wt_tile_plan plans[kTilePlans];
+    int nplans = 0;
 };
 
 

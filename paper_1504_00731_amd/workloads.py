@@ -248,7 +248,7 @@ def euler2d_smooth_periodic(seed: int = 0, n: int = 64) -> Case:
 # 3D Euler workload
 # --------------------------------------------------------------------------
 
-def euler3d_seeded(seed: int = 0, n: int = 512, nspheres: int = 8) -> Case:
+def euler3d_seeded(seed: int = 0, n: int = 512, nspheres: int = 8, edge: float = 2.0) -> Case:
     """Isentropic-vortex background in x-y, uniform in z, with spherical density
     jumps, on the periodic unit cube; CFL 0.5, 100 steps.
     Draws: centre (x_c, y_c) ~ U(0.25, 0.75)^2, strength beta ~ U(1, 5); then per
@@ -256,8 +256,13 @@ def euler3d_seeded(seed: int = 0, n: int = 512, nspheres: int = 8) -> Case:
     Background (r = periodic distance to the centre / 0.1):
       rho = [1 - (gamma-1) beta^2/(8 gamma pi^2) e^{1-r^2}]^{1/(gamma-1)}, p = rho^gamma,
       (u, v, w) = (1, 1, 0) + beta/(2 pi) e^{(1-r^2)/2} (-dy, dx, 0)/0.1.
-    Inside a sphere (periodic minimum image) rho is multiplied by the ratio; p and
-    the velocity are unchanged."""
+    Inside a sphere (periodic minimum image) rho is multiplied by the ratio, by the
+    largest ratio where spheres overlap (so every density jump stays within the
+    drawn range); p and the velocity are unchanged.  The sphere surface is a
+    front of width edge * dx (tanh profile, edge = 2 by default; 0 gives the sharp
+    jump): a sharp surface cut by grid lines leaves one-cell chords (a single
+    dense cell between light ones) that the unlimited scheme turns into negative
+    densities within a few steps."""
     g = 1.4
     rng = np.random.default_rng(seed)
     xc, yc = rng.uniform(0.25, 0.75, 2)
@@ -280,13 +285,19 @@ def euler3d_seeded(seed: int = 0, n: int = 512, nspheres: int = 8) -> Case:
     U = np.empty((5, n, n, n))
     for kz in range(n):
         z = x1[kz]
-        rho = rho2.copy()
+        fac_rho = np.ones_like(rho2)
         for (c, rad, ratio) in spheres:
             dz = wrap(z - c[2])
-            if abs(dz) > rad:
+            if abs(dz) > rad + 4.0 * edge / n:
                 continue
             d2 = wrap(x1[None, :] - c[0]) ** 2 + wrap(x1[:, None] - c[1]) ** 2 + dz * dz
-            rho = np.where(d2 < rad * rad, rho * ratio, rho)
+            if edge > 0.0:
+                w = edge / n
+                inside = 0.5 * (1.0 - np.tanh((np.sqrt(d2) - rad) / (0.5 * w)))
+                fac_rho = np.maximum(fac_rho, 1.0 + (ratio - 1.0) * inside)
+            else:
+                fac_rho = np.where(d2 < rad * rad, np.maximum(fac_rho, ratio), fac_rho)
+        rho = rho2 * fac_rho
         U[:, kz] = conserved(rho, [u2, v2, np.zeros_like(u2)], p2, g)
     c = Case("euler3d_seeded", EULER, U, (0.0,) * 3, (1.0,) * 3, (PERIODIC,) * 3, steps=100,
              extra={"xc": xc, "yc": yc, "beta": beta})

@@ -62,9 +62,8 @@ def loop_parents(asm: str, symbol: str) -> dict:
     parents, cur, chain = {}, None, []
     for raw in lines[start + 1:end]:
         m = _LABEL.match(raw)
-        if m:
+        if m:                               # the label line may carry the first annotation
             cur, chain = m.group(1), []
-            continue
         mp = _PARENT.search(raw)
         if mp:
             chain.append("BB" + mp.group(1))

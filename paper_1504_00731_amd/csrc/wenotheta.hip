@@ -54,7 +54,11 @@ struct SweepArgs {
     int slot_rd, slot_wr, slot_zero;
     int stage;             // 1..3 (MODE_LAST_STAGE)
     int check_done;
+    int64_t tiles;         // y/z sweeps: tiles of the grid, and tiles per XCD
+    int64_t tiles_per_xcd;
 };
+
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, one L2 each
 
 // ---------------------------------------------------------------------------
 // Lax-Friedrichs speeds of a state (grid-stride reduction into one slot)
@@ -215,8 +219,20 @@ void sweep_kernel(SweepArgs A)
     const int64_t nseg = (nd + TN - 1) / TN;
     const int64_t ngx = DIR == 0 ? 1 : (nx + TX - 1) / TX;
 
-    // block -> (x0, seg, base): base is the offset of sweep index 0 of column x0
-    int64_t b = blockIdx.x, seg, x0 = 0, base;
+    // block -> tile.  Workgroups are dealt to the 8 XCDs round-robin (block i to
+    // XCD i mod 8), each with its own L2; the y/z tiles of neighbouring column
+    // groups share cache lines (8 doubles are half a 128-byte line) and those of
+    // neighbouring segments share halo rows.  So XCD x takes the contiguous tile
+    // range [x * per, (x + 1) * per) in order, per = ceil(tiles / 8); the grid is
+    // rounded up to a multiple of 8 and surplus blocks leave at once.
+    int64_t b = blockIdx.x;
+    if constexpr (DIR != 0) {
+        const int64_t per = A.tiles_per_xcd;
+        b = (b % kXcds) * per + b / kXcds;
+        if (b >= A.tiles) return;
+    }
+    // tile -> (x0, seg, base): base is the offset of sweep index 0 of column x0
+    int64_t seg, x0 = 0, base;
     int64_t sstride;
     if constexpr (DIR == 0) {
         seg = b % nseg;
@@ -424,9 +440,15 @@ hipError_t launch_tile(const SweepArgs &A, hipStream_t s)
     if (DIR == 0) blocks = nseg * A.n[1] * A.n[2];
     else if (DIR == 1) blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[2];
     else blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[1];
+    SweepArgs B = A;
+    if (DIR != 0) {
+        B.tiles = blocks;
+        B.tiles_per_xcd = (blocks + kXcds - 1) / kXcds;
+        blocks = B.tiles_per_xcd * kXcds;
+    }
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_kernel<SYS, NDIM, DIR, TX, TN, MODE, PREC>), dim3((unsigned)blocks),
-                       dim3(kThreads), 0, s, A);
+                       dim3(kThreads), 0, s, B);
     return hipGetLastError();
 }
 
@@ -1074,8 +1096,9 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
                         }
                         if (round > 0 && ms < ms_best[v]) ms_best[v] = ms;   // round 0 warms up
                     }
+                // another shape replaces the default only if clearly faster
                 for (int v = 1; v < kTileVariants; ++v)
-                    if (ms_best[v] < ms_best[best[d]]) best[d] = v;
+                    if (ms_best[v] < 0.98f * ms_best[0] && ms_best[v] < ms_best[best[d]]) best[d] = v;
             }
         }
         (void)hipEventDestroy(e0);

@@ -71,13 +71,10 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3, double s4, d
     // product test decides it without the quotient unless bmax is within
     // 2^-40 of alpha_R (eps + bmin); RN is monotone, so outside that band the
     // decision equals the one on the rounded quotient.
-    double bmax = b0, bmin = b0;
-    bmax = b1 > bmax ? b1 : bmax;
-    bmax = b2 > bmax ? b2 : bmax;
-    bmax = b3 > bmax ? b3 : bmax;
-    bmin = b1 < bmin ? b1 : bmin;
-    bmin = b2 < bmin ? b2 : bmin;
-    bmin = b3 < bmin ? b3 : bmin;
+    // (the indicators are sums of squares, never -0, so for finite data the
+    // hardware max/min give exactly the running comparisons of the definition)
+    const double bmax = __builtin_fmax(__builtin_fmax(__builtin_fmax(b0, b1), b2), b3);
+    const double bmin = __builtin_fmin(__builtin_fmin(__builtin_fmin(b0, b1), b2), b3);
     const double den = eps + bmin;
     const double lim = alpha_R * den;
     bool restricted;

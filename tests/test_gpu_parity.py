@@ -247,6 +247,38 @@ def test_full_size_euler2d_rhs_sampled(ctx):
     assert err <= RHS_TOL and np.array_equal(g, ref), err
 
 
+def test_full_size_euler3d_rhs_sampled(ctx):
+    """3D Euler workload at full size, 512^3 (the launch configuration the benchmark
+    times): RHS at sampled points -- random, on the sphere surfaces and through the
+    vortex centre, on the periodic faces, edges and corners -- each computed by the
+    oracle, bit for bit."""
+    import torch
+    n = 512
+    c = W.euler3d_seeded(0, n)
+    got = gpu_rhs(ctx, c)
+    rng = np.random.default_rng(3)
+    pts = set(rng.integers(0, n ** 3, 600).tolist())
+    # steepest density gradients (sphere fronts) and the vortex centre line
+    rho = c.u[0]
+    gx = np.abs(np.roll(rho, -1, axis=2) - rho)
+    steep = np.argpartition(gx.ravel(), -200)[-200:]
+    pts.update(steep.tolist())
+    xc, yc = c.extra["xc"], c.extra["yc"]
+    ic, jc = int(xc * n), int(yc * n)
+    for k in rng.integers(0, n, 20).tolist():
+        pts.add((k * n + jc) * n + ic)
+    for k in (0, n - 1):
+        for j in (0, 1, n - 2, n - 1):
+            for i in (0, 2, n - 3, n - 1):
+                pts.add((k * n + j) * n + i)
+    del gx
+    cells = np.array(sorted(pts), dtype=np.int64)
+    ref = oracle.rhs_points(oracle_problem(c), c.u, cells)
+    g = got.reshape(5, -1)[:, cells].T
+    assert np.array_equal(g, ref)
+    torch.cuda.empty_cache()
+
+
 def test_full_size_euler2d_symmetry_and_free_stream(ctx):
     """At 4096^2: diagonal-symmetric quadrant data stay exactly symmetric over two steps,
     and a constant state is preserved (to the ulp the printed stage form allows)."""

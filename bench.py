@@ -82,10 +82,10 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, y_tile: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary of the
-    2D Euler 4096^2 FP64 sweeps, or None when there is none or the kernel sources have
-    changed since the counters were taken."""
+    2D Euler 4096^2 FP64 sweeps, or None when there is none, the kernel sources have
+    changed since the counters were taken, or the y sweep runs another tile shape."""
     path = os.path.join(ROOT, "profiles", "traffic_euler2d_4096_fp64.txt")
     if not os.path.exists(path):
         return None
@@ -95,6 +95,8 @@ def measured_traffic(kernel: str):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("sources_sha256") != kernel_sources_hash() or kernel + ".bytes" not in kv:
+        return None
+    if kernel.startswith("sweep_y") and kv.get("y_tile") != y_tile:
         return None
     return float(kv[kernel + ".bytes"])
 
@@ -177,8 +179,12 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None)
         tiles = tuple([0] + [tile_choice] * (case.ndim - 1))
         wt.wenotheta_set_tiles(ctx, g, p, tiles)
     if warmup > 0:
+        # single CFL steps, queued like the timed ones (the solver's graph would also
+        # run its no-op tail steps, which a kernel trace would count)
         u = u_init.clone()
-        wt.wenotheta_solve(ctx, g, p, u, float("inf"), max_steps=warmup)
+        for _ in range(warmup):
+            wt.wenotheta_step(ctx, g, p, u)
+        wt.wenotheta_sync(ctx)
         del u
     u = u_init.clone()
     if profile:
@@ -372,8 +378,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": kind, "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": (measured_traffic(kind) if args.workload == "euler2d" and
-                                 case.n == (4096, 4096) and prec == wt.WT_FP64 else None),
+                     "traffic": (measured_traffic(kind, "x".join(map(str, r["tiles"][1])))
+                                 if args.workload == "euler2d" and case.n == (4096, 4096) and
+                                 prec == wt.WT_FP64 else None),
                      "avg_launch_ms": tot_ms / launches, "launches": launches,
                      "algorithmic_ops_per_launch": ops,
                      "ops_counted_as": "fp64 lane operations" + (

@@ -25,7 +25,7 @@ _HDR = os.path.join(_HERE, "wto_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 LINEAR, BURGERS, EULER = 0, 1, 2
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 DIAG_LEN = 19
 DIAG_NAMES = ("q0", "q1", "q2", "q3", "b0", "b1", "b2", "b3", "R", "restricted",
               "tau5", "tau6", "theta", "w0", "w1", "w2", "w3", "h", "tau")
@@ -58,7 +58,8 @@ class _Problem(ctypes.Structure):
                 ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
                 ("bc", ctypes.c_int32 * 3), ("a", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("eps", ctypes.c_double), ("alpha_R", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("alpha_R", ctypes.c_double),
+                ("gravity", ctypes.c_double * 3)]
 
 
 @dataclass
@@ -74,6 +75,7 @@ class Problem:
     cfl: float = 0.5
     eps: float = 1e-10
     alpha_R: float = 50.0
+    gravity: tuple = (0.0, 0.0, 0.0)
 
     @property
     def m(self) -> int:
@@ -97,6 +99,9 @@ class Problem:
         p.a, p.gamma, p.cfl, p.eps, p.alpha_R = (float(self.a), float(self.gamma),
                                                  float(self.cfl), float(self.eps),
                                                  float(self.alpha_R))
+        g = list(self.gravity) + [0.0] * (3 - len(self.gravity))
+        for k in range(3):
+            p.gravity[k] = float(g[k])
         return p
 
 

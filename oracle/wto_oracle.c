@@ -149,9 +149,12 @@ static int ncomp(const wto_problem *P)
 }
 
 /* Boundary conditions as index maps onto interior points.  Periodic: wrap.
- * Transmissive (zero gradient): copy the nearest interior point.
- * Reading: the paper names the conditions (Sec. 3.2, 4.2) without giving a
- * ghost-point rule; three ghost points per side are what S^6 needs. */
+ * Transmissive (zero gradient): copy the nearest interior point.  Reflective
+ * (a wall at the grid's end, half a spacing beyond the outermost point): the
+ * mirror image of the point across the wall, whose momentum normal to the wall
+ * is negated (see reflected()).
+ * Reading: the paper names the conditions (Sec. 3.2, 4.2, 4.3) without giving
+ * a ghost-point rule; three ghost points per side are what S^6 needs. */
 static int64_t map_index(int64_t i, int64_t n, int32_t bc)
 {
     if (bc == WTO_PERIODIC) {
@@ -159,9 +162,20 @@ static int64_t map_index(int64_t i, int64_t n, int32_t bc)
         if (i < 0) i += n;
         return i;
     }
+    if (bc == WTO_REFLECTIVE) {
+        if (i < 0) return -1 - i;
+        if (i >= n) return 2 * n - 1 - i;
+        return i;
+    }
     if (i < 0) return 0;
     if (i >= n) return n - 1;
     return i;
+}
+
+/* Whether point i of a line of n points is a reflected ghost point. */
+static int reflected(int64_t i, int64_t n, int32_t bc)
+{
+    return bc == WTO_REFLECTIVE && (i < 0 || i >= n);
 }
 
 static int64_t stride_of(const wto_problem *P, int d)
@@ -189,8 +203,10 @@ static int validate(const wto_problem *P)
         if (d < P->ndim) {
             if (P->n[d] < 6) return WTO_ERR_ARG;
             if (!(P->dx[d] > 0.0)) return WTO_ERR_ARG;
-            if (P->bc[d] != WTO_PERIODIC && P->bc[d] != WTO_TRANSMISSIVE)
+            if (P->bc[d] != WTO_PERIODIC && P->bc[d] != WTO_TRANSMISSIVE &&
+                P->bc[d] != WTO_REFLECTIVE)
                 return WTO_ERR_ARG;
+            if (P->bc[d] == WTO_REFLECTIVE && P->system != WTO_EULER) return WTO_ERR_UNSUPPORTED;
         } else if (P->n[d] != 1) {
             return WTO_ERR_ARG;
         }
@@ -198,6 +214,11 @@ static int validate(const wto_problem *P)
     if (!(P->eps > 0.0) || !(P->cfl > 0.0)) return WTO_ERR_ARG;
     if (P->alpha_R < 0.0 || P->alpha_R != P->alpha_R) return WTO_ERR_ARG;
     if (P->system == WTO_EULER && !(P->gamma > 1.0)) return WTO_ERR_ARG;
+    for (int d = 0; d < 3; ++d) {
+        if (!isfinite(P->gravity[d])) return WTO_ERR_ARG;
+        if (P->gravity[d] != 0.0 && (P->system != WTO_EULER || d >= P->ndim))
+            return WTO_ERR_ARG;
+    }
     return WTO_OK;
 }
 
@@ -392,6 +413,7 @@ static int euler_interface_stencils(const wto_problem *P, const double *u, int d
         const int64_t cell = base + map_index(i - 2 + k, P->n[d], P->bc[d]) * sd;
         double uc[MAXM];
         for (int c = 0; c < m; ++c) uc[c] = u[c * N + cell];
+        if (reflected(i - 2 + k, P->n[d], P->bc[d])) uc[1 + d] = -uc[1 + d];
         int st = primitives(uc, ndim, P->gamma, &Pk[k]);
         if (st) return st;
         for (int c = 0; c < m; ++c) Up[k][c] = uc[perm[c]];
@@ -531,6 +553,29 @@ static double cfl_dt(const wto_problem *P, const double *amax)
 /* Spatial operator                                                         */
 /* ------------------------------------------------------------------------ */
 
+static int has_gravity(const wto_problem *P)
+{
+    return P->gravity[0] != 0.0 || P->gravity[1] != 0.0 || P->gravity[2] != 0.0;
+}
+
+/* Gravity source (Sec. 4.3, TEST 6: the y-momentum and energy equations gain
+ * -g rho and -g rho v).  For an acceleration -g_d along each axis: momentum d
+ * gains -(g_d rho) and the energy -(g_x m_x + g_y m_y + g_z m_z), summed in
+ * axis order; added to L(u) at point j after the flux divergence. */
+static void add_gravity(const wto_problem *P, const double *u, int64_t N, int64_t j,
+                        double *Lc, int64_t stride)
+{
+    const int ndim = P->ndim;
+    const double rho = u[j];
+    double e = 0.0;
+    for (int d = 0; d < ndim; ++d) {
+        const double md = u[(1 + d) * N + j];
+        Lc[(1 + d) * stride] = Lc[(1 + d) * stride] + (-(P->gravity[d] * rho));
+        e = d == 0 ? P->gravity[0] * md : e + P->gravity[d] * md;
+    }
+    Lc[(ndim + 1) * stride] = Lc[(ndim + 1) * stride] + (-e);
+}
+
 int wto_rhs(const wto_problem *P, const double *u, const double *f,
             const double *alpha_in, double *L)
 {
@@ -599,8 +644,11 @@ int wto_rhs(const wto_problem *P, const double *u, const double *f,
         }
         if (err) break;
     }
-    if (!err)
+    if (!err) {
         for (int64_t k = 0; k < m * N; ++k) L[k] = -D[k];
+        if (has_gravity(P))
+            for (int64_t j = 0; j < N; ++j) add_gravity(P, u, N, j, &L[j], N);
+    }
     free(D);
     return err;
 }
@@ -651,6 +699,7 @@ int wto_rhs_points(const wto_problem *P, const double *u, const double *alpha_in
             }
         }
         for (int c = 0; c < m; ++c) Lpts[k * m + c] = -Dsum[c];
+        if (has_gravity(P)) add_gravity(P, u, N, cell, &Lpts[k * m], 1);
     }
     return WTO_OK;
 }

@@ -21,19 +21,22 @@ extern "C" {
 enum { WTO_OK = 0, WTO_ERR_ARG = 1, WTO_ERR_UNSUPPORTED = 2,
        WTO_ERR_NONPHYSICAL = 3, WTO_ERR_NONFINITE = 4 };
 enum { WTO_LINEAR = 0, WTO_BURGERS = 1, WTO_EULER = 2 };
-enum { WTO_PERIODIC = 0, WTO_TRANSMISSIVE = 1 };
+enum { WTO_PERIODIC = 0, WTO_TRANSMISSIVE = 1, WTO_REFLECTIVE = 2 };
 
 typedef struct {
     int32_t ndim;      /* 1, 2 or 3 (scalar systems: 1 only)                 */
     int32_t system;    /* WTO_LINEAR (f = a u), WTO_BURGERS (f = u^2/2), WTO_EULER */
     int64_t n[3];      /* points per dimension (n[k] = 1 for k >= ndim)     */
     double  dx[3];     /* grid spacing per dimension                        */
-    int32_t bc[3];     /* WTO_PERIODIC or WTO_TRANSMISSIVE per dimension     */
+    int32_t bc[3];     /* WTO_PERIODIC, WTO_TRANSMISSIVE or WTO_REFLECTIVE
+                          (Euler only) per dimension                          */
     double  a;         /* advection speed of WTO_LINEAR                     */
     double  gamma;     /* ratio of specific heats (Euler)                   */
     double  cfl;       /* CFL number                                        */
     double  eps;       /* epsilon of the nonlinear weights (1e-10)          */
     double  alpha_R;   /* restriction threshold; 0 disables, +inf = linear  */
+    double  gravity[3];/* Euler: gravitational acceleration g_d along -x_d;
+                          source (0, -rho g, -(g . m)) (Sec. 4.3, TEST 6)   */
 } wto_problem;
 
 /* Number of diagnostic values written by wto_weno_theta_diag. */

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 LINEAR, BURGERS, EULER = 0, 1, 2
 
 
@@ -41,6 +41,7 @@ class Case:
     t_end: float | None = None
     steps: int | None = None
     extra: dict = field(default_factory=dict)
+    gravity: tuple = (0.0, 0.0, 0.0)
 
     @property
     def ndim(self) -> int:
@@ -358,3 +359,47 @@ def batched_1d(seed: int = 0, nprob: int = 4096, nmin: int = 256, nmax: int = 16
     return Batch(u=np.ascontiguousarray(np.concatenate(parts, axis=1)), n=n, offset=offset,
                  lo=np.zeros(nprob), hi=np.ones(nprob),
                  bc=np.full(nprob, TRANSMISSIVE, dtype=np.int32), steps=steps)
+
+
+# ---------------------------------------------------------------------------
+# Reflective walls and gravity (Sec. 4.2 TEST 5, Sec. 4.3 TESTs 6 and 7)
+# ---------------------------------------------------------------------------
+
+def blast_waves(n: int = 801) -> Case:
+    """Two interacting blast waves (Sec. 4.2, TEST 5): (rho, u, p) = (1, 0, 1000) on
+    (0, 0.1), (1, 0, 0.01) on (0.1, 0.9), (1, 0, 100) on (0.9, 1); reflective walls at
+    both ends; alpha_R = 10 (Sec. 4.2 sets 10 for this problem and Lax's); t = 0.038."""
+    x = grid_points(n, 0.0, 1.0, REFLECTIVE)
+    p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0))
+    u = conserved(np.ones(n), [np.zeros(n)], p)
+    return Case("blast_waves", EULER, u, (0.0,), (1.0,), (REFLECTIVE,), t_end=0.038, alpha_R=10.0)
+
+
+def rayleigh_taylor(nx: int = 120, ny: int = 360, g: float = 0.1) -> Case:
+    """Rayleigh-Taylor instability (Sec. 4.3, TEST 6) on (-0.25, 0.25) x (-0.75, 0.75):
+    rho = 2 for y >= 0, 1 below; p = 2.5 - rho g y; u = 0,
+    v = 0.01/4 (1 + cos 4 pi x)(1 + cos 4 pi y / 3); periodic in x, reflective in y;
+    gravity g = 0.1 along -y (source -g rho, -g rho v); t = 9.5."""
+    x = grid_points(nx, -0.25, 0.25, PERIODIC)[None, :]
+    y = grid_points(ny, -0.75, 0.75, REFLECTIVE)[:, None]
+    rho = np.where(y >= 0.0, 2.0, 1.0) * np.ones_like(x)
+    p = 2.5 - rho * g * y
+    v = 0.01 / 4.0 * (1.0 + np.cos(4.0 * np.pi * x)) * (1.0 + np.cos(4.0 * np.pi * y / 3.0))
+    u = conserved(rho, [np.zeros_like(rho), v], p)
+    return Case("rayleigh_taylor", EULER, u, (-0.25, -0.75), (0.25, 0.75), (PERIODIC, REFLECTIVE),
+                t_end=9.5, gravity=(0.0, g, 0.0))
+
+
+def implosion(n: int = 400) -> Case:
+    """Implosion problem (Sec. 4.3, TEST 7) on (0, 1)^2: (rho, p) = (1, 1) for
+    x + y > 1/2, (0.125, 0.14) otherwise, at rest; reflective walls all round;
+    alpha_R = 1; t = 5."""
+    x = grid_points(n, 0.0, 1.0, REFLECTIVE)[None, :]
+    y = grid_points(n, 0.0, 1.0, REFLECTIVE)[:, None]
+    outer = (x + y) > 0.5
+    rho = np.where(outer, 1.0, 0.125)
+    p = np.where(outer, 1.0, 0.14)
+    z = np.zeros_like(rho)
+    u = conserved(rho, [z, z], p)
+    return Case("implosion", EULER, u, (0.0, 0.0), (1.0, 1.0), (REFLECTIVE, REFLECTIVE),
+                t_end=5.0, alpha_R=1.0)

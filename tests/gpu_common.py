@@ -20,7 +20,8 @@ def grid_params(case: W.Case, alpha_R=None, cfl=None):
 def oracle_problem(case: W.Case, alpha_R=None, cfl=None) -> oracle.Problem:
     return oracle.Problem(ndim=case.ndim, system=case.system, n=case.n, dx=case.dx, bc=case.bc,
                           a=case.a, gamma=case.gamma, cfl=case.cfl if cfl is None else cfl,
-                          alpha_R=case.alpha_R if alpha_R is None else alpha_R)
+                          alpha_R=case.alpha_R if alpha_R is None else alpha_R,
+                          gravity=tuple(case.gravity))
 
 
 def to_dev(a):

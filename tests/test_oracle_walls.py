@@ -1,0 +1,160 @@
+"""Pins of the oracle's reflective walls and gravity source (Sec. 4.2 TEST 5, Sec. 4.3
+TESTs 6 and 7), checked against what the geometry and the mathematics fix:
+
+* a reflective wall is the mirror image of the flow across it: the RHS of a problem with
+  walls equals, bit for bit, that of the periodic problem on the doubled (mirrored)
+  domain, given the same Lax-Friedrichs speeds (the doubled domain's, since mirroring
+  swaps the two acoustic speeds |u -+ c|);
+* a uniform state under gravity stays uniform, and its momentum and energy follow the
+  closed form m(t) = m0 - g rho t, E(t) = E0 - g (m0 t - g rho t^2 / 2), which the
+  three-stage Runge-Kutta method integrates exactly (polynomials of degree <= 2);
+* the Rayleigh-Taylor data are even in x, and the solution keeps that mirror symmetry
+  exactly with gravity and walls (the paper's point for WENO-theta); the implosion data
+  are symmetric about the diagonal, and stay so exactly with walls all round.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_00731_amd import workloads as W
+from tests.gpu_common import oracle_problem
+
+
+def _mirror_double(u, axis, normal_comp):
+    """State on the doubled domain along `axis` (a state array axis): the mirror image
+    (normal momentum negated) followed by the original."""
+    mir = np.flip(u, axis=axis).copy()
+    mir[normal_comp] = -mir[normal_comp]
+    return np.concatenate([mir, u], axis=axis)
+
+
+def _seeded_1d(seed, n):
+    c = W.euler1d_seeded(seed, n)
+    return c.u
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_reflective_rhs_is_the_mirrored_periodic_rhs_1d(seed):
+    n = 64
+    u = _seeded_1d(seed, n)
+    dx = 1.0 / n
+    Pw = oracle.Problem(ndim=1, system=oracle.EULER, n=(n,), dx=(dx,), bc=(oracle.REFLECTIVE,))
+    ud = _mirror_double(u, axis=1, normal_comp=1)
+    Pd = oracle.Problem(ndim=1, system=oracle.EULER, n=(2 * n,), dx=(dx,), bc=(oracle.PERIODIC,))
+    al, _ = oracle.alpha(Pd, ud)
+    Lw = oracle.rhs(Pw, u, alpha_=al)
+    Ld = oracle.rhs(Pd, ud, alpha_=al)
+    assert np.array_equal(Lw, Ld[:, n:])
+
+
+def test_reflective_rhs_is_the_mirrored_periodic_rhs_2d_3d():
+    rng = np.random.default_rng(4)
+    # 2D: walls in y, periodic in x
+    c = W.euler2d_seeded(3, 24)
+    u = c.u
+    dx = 1.0 / 24
+    Pw = oracle.Problem(ndim=2, system=oracle.EULER, n=(24, 24), dx=(dx, dx),
+                        bc=(oracle.PERIODIC, oracle.REFLECTIVE))
+    ud = _mirror_double(u, axis=1, normal_comp=2)          # state axes (c, y, x)
+    Pd = oracle.Problem(ndim=2, system=oracle.EULER, n=(24, 48), dx=(dx, dx),
+                        bc=(oracle.PERIODIC, oracle.PERIODIC))
+    al, _ = oracle.alpha(Pd, ud)
+    assert np.array_equal(oracle.rhs(Pw, u, alpha_=al), oracle.rhs(Pd, ud, alpha_=al)[:, 24:, :])
+    # 2D: walls all round -> doubled in both directions
+    Pw2 = oracle.Problem(ndim=2, system=oracle.EULER, n=(24, 24), dx=(dx, dx),
+                         bc=(oracle.REFLECTIVE, oracle.REFLECTIVE))
+    ud2 = _mirror_double(_mirror_double(u, axis=1, normal_comp=2), axis=2, normal_comp=1)
+    Pd2 = oracle.Problem(ndim=2, system=oracle.EULER, n=(48, 48), dx=(dx, dx),
+                         bc=(oracle.PERIODIC, oracle.PERIODIC))
+    al2, _ = oracle.alpha(Pd2, ud2)
+    assert np.array_equal(oracle.rhs(Pw2, u, alpha_=al2), oracle.rhs(Pd2, ud2, alpha_=al2)[:, 24:, 24:])
+    # 3D: walls in z
+    c3 = W.euler3d_seeded(2, 12, edge=0.0)
+    u3 = c3.u
+    h = 1.0 / 12
+    Pw3 = oracle.Problem(ndim=3, system=oracle.EULER, n=(12, 12, 12), dx=(h, h, h),
+                         bc=(oracle.PERIODIC, oracle.PERIODIC, oracle.REFLECTIVE))
+    ud3 = _mirror_double(u3, axis=1, normal_comp=3)        # state axes (c, z, y, x)
+    Pd3 = oracle.Problem(ndim=3, system=oracle.EULER, n=(12, 12, 24), dx=(h, h, h),
+                         bc=(oracle.PERIODIC,) * 3)
+    al3, _ = oracle.alpha(Pd3, ud3)
+    assert np.array_equal(oracle.rhs(Pw3, u3, alpha_=al3), oracle.rhs(Pd3, ud3, alpha_=al3)[:, 12:])
+
+
+@pytest.mark.parametrize("ndim,axis", [(1, 0), (2, 1), (3, 2), (3, 0)])
+def test_gravity_on_a_uniform_state_follows_the_closed_form(ndim, axis):
+    g, rho, p = 0.37, 1.3, 0.9
+    vel = [0.2, -0.1, 0.05][:ndim]
+    n = (8,) * ndim
+    shape = tuple(reversed(n))
+    u0 = W.conserved(np.full(shape, rho), [np.full(shape, v) for v in vel], p)
+    grav = [0.0, 0.0, 0.0]
+    grav[axis] = g
+    P = oracle.Problem(ndim=ndim, system=oracle.EULER, n=n, dx=(0.1,) * ndim,
+                       bc=(oracle.PERIODIC,) * ndim, gravity=tuple(grav))
+    dt, k = 0.01, 7
+    u = u0.copy()
+    for _ in range(k):
+        u, _ = oracle.step(P, u, dt)
+    t = dt * k
+    m0 = u0[1 + axis].ravel()[0]
+    want_m = m0 - g * rho * t
+    want_E = u0[ndim + 1].ravel()[0] - g * (m0 * t - g * rho * t * t / 2.0)
+    flat = u.reshape(ndim + 2, -1)
+    assert np.all(flat == flat[:, :1])                       # stays uniform, exactly
+    assert np.array_equal(flat[0], u0[0].ravel())
+    for d in range(ndim):
+        if d != axis:
+            assert np.array_equal(flat[1 + d], u0[1 + d].ravel())
+    assert abs(flat[1 + axis, 0] - want_m) <= 1e-14 * abs(want_m) + 1e-16
+    assert abs(flat[ndim + 1, 0] - want_E) <= 1e-14 * abs(want_E)
+
+
+def test_rayleigh_taylor_keeps_its_mirror_symmetry():
+    c = W.rayleigh_taylor(32, 96)
+    P = oracle_problem(c)
+    u = c.u.copy()
+    for _ in range(6):
+        u, _ = oracle.step(P, u)
+    # x -> -x on the periodic vertex grid: point j <-> (nx - j) mod nx; u_x odd
+    nx = c.u.shape[2]
+    idx = (-np.arange(nx)) % nx
+    mir = u[:, :, idx]
+    assert np.array_equal(u[0], mir[0]) and np.array_equal(u[2], mir[2]) and np.array_equal(u[3], mir[3])
+    assert np.array_equal(u[1], -mir[1])
+    assert not np.array_equal(u, c.u)                       # it did move
+
+
+def test_implosion_keeps_its_diagonal_symmetry():
+    c = W.implosion(40)
+    P = oracle_problem(c)
+    u = c.u.copy()
+    for _ in range(8):
+        u, _ = oracle.step(P, u)
+    assert np.array_equal(u[0], u[0].T) and np.array_equal(u[3], u[3].T)
+    assert np.array_equal(u[1], u[2].T)
+
+
+def test_blast_waves_stay_physical_and_conserve_mass_closely():
+    """With walls the per-field LF speeds let the wall's mass flux differ from zero by
+    the difference of the two acoustic dissipations; at rest next to the walls (here)
+    the mass stays conserved to rounding over the early steps."""
+    c = W.blast_waves(201)
+    P = oracle_problem(c)
+    u = c.u.copy()
+    for _ in range(20):
+        u, _ = oracle.step(P, u)
+    assert abs(u[0].sum() - c.u[0].sum()) <= 1e-12 * c.u[0].sum()
+    assert np.all(u[0] > 0)
+
+
+def test_wall_and_gravity_arguments_are_checked():
+    with pytest.raises(oracle.OracleError):
+        oracle.rhs(oracle.Problem(ndim=1, system=oracle.LINEAR, n=(16,), dx=(0.1,),
+                                  bc=(oracle.REFLECTIVE,)), np.ones((1, 16)))
+    with pytest.raises(oracle.OracleError):
+        oracle.rhs(oracle.Problem(ndim=1, system=oracle.EULER, n=(16,), dx=(0.1,),
+                                  bc=(oracle.PERIODIC,), gravity=(0.0, 1.0, 0.0)),
+                   W.conserved(np.ones(16), [np.zeros(16)], 1.0))

@@ -64,7 +64,11 @@ typedef enum {
 
 typedef enum {
     WT_PERIODIC = 0,     /* wrap-around                                     */
-    WT_TRANSMISSIVE = 1  /* zero gradient: ghost points copy the nearest point */
+    WT_TRANSMISSIVE = 1, /* zero gradient: ghost points copy the nearest point */
+    WT_REFLECTIVE = 2    /* wall half a spacing beyond the end points (Euler
+                            only; Sec. 4.2 TEST 5, Sec. 4.3 TESTs 6, 7): ghost
+                            points are the mirror images of the points across
+                            the wall, with the momentum normal to it negated */
 } wt_bc;
 
 typedef enum {
@@ -100,6 +104,10 @@ typedef struct {
     double eps;         /* epsilon of the nonlinear weights (> 0), 1e-10 (Sec. 3.1) */
     double alpha_R;     /* restriction threshold of beta~_k (>= 0; 0 switches it
                            off, +inf gives the linear weights), 50 (Sec. 4.2) */
+    double gravity[3];  /* Euler: gravitational acceleration g_d pointing along
+                           -x_d (finite; 0 beyond ndim).  The source of Sec. 4.3
+                           TEST 6 is added to L: momentum d gains -g_d rho, the
+                           energy -(g_x m_x + g_y m_y + g_z m_z).  All 0: none. */
 } wt_params;
 
 typedef struct wt_ctx wt_ctx;
@@ -143,14 +151,15 @@ wt_status wenotheta_solve(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm
                           double *t_out, int64_t *steps_out, void *stream);
 
 /* Batched solves: nprob independent 1D Euler problems (prm->system must be
- * WT_EULER) packed side by side in one state, each advanced by nsteps CFL
+ * WT_EULER, prm->gravity all 0, else WT_ERR_UNSUPPORTED) packed side by side
+ * in one state, each advanced by nsteps CFL
  * steps of its own (dt_b = cfl / (amax_b / dx_b)), in one persistent kernel
  * launched through a captured HIP graph.
  *   u       DEVICE, FP64, [3][total] component-major: problem b occupies
  *           columns offset[b] .. offset[b] + n[b] - 1; advanced in place;
  *   n, offset, lo, hi, bc   HOST arrays of nprob entries: points (>= 6),
  *           first column, domain ends (dx_b = (hi - lo) / n) and boundary
- *           condition of each problem; the column ranges must be disjoint
+ *           condition (any wt_bc) of each problem; the column ranges must be disjoint
  *           and inside [0, total);
  *   t_out      optional DEVICE array of nprob doubles: the time each problem
  *              reached;

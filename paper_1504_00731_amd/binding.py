@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libwenotheta.so")
 WT_OK, WT_ERR_ARG, WT_ERR_UNSUPPORTED, WT_ERR_NONPHYSICAL = 0, 1, 2, 3
 WT_ERR_NONFINITE, WT_ERR_DEVICE, WT_ERR_NOMEM = 4, 5, 6
 WT_LINEAR, WT_BURGERS, WT_EULER = 0, 1, 2
-WT_PERIODIC, WT_TRANSMISSIVE = 0, 1
+WT_PERIODIC, WT_TRANSMISSIVE, WT_REFLECTIVE = 0, 1, 2
 WT_FP64, WT_FP32_RECON = 0, 1
 
 EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
@@ -50,7 +50,8 @@ class wt_grid(ctypes.Structure):
 class wt_params(ctypes.Structure):
     _fields_ = [("system", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("a", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("eps", ctypes.c_double), ("alpha_R", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("alpha_R", ctypes.c_double),
+                ("gravity", ctypes.c_double * 3)]
 
 
 _LIB = None
@@ -129,12 +130,16 @@ class Params:
     eps: float = 1e-10
     alpha_R: float = 50.0
     precision: int = WT_FP64
+    gravity: tuple = (0.0, 0.0, 0.0)
 
     def c_struct(self) -> wt_params:
         p = wt_params()
         p.system, p.precision = int(self.system), int(self.precision)
         p.a, p.gamma, p.cfl = float(self.a), float(self.gamma), float(self.cfl)
         p.eps, p.alpha_R = float(self.eps), float(self.alpha_R)
+        g = list(self.gravity) + [0.0] * (3 - len(self.gravity))
+        for k in range(3):
+            p.gravity[k] = float(g[k])
         return p
 
 

@@ -156,6 +156,7 @@ __global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(Ba
                         double uc[3];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) uc[c] = uin[c * total + off + g];
+                        if (reflected(g0 - 3 + i, n, bc)) uc[1] = -uc[1];
                         double vel[1], p, H;
                         if (!euler_cell<1>(uc, A.gamma, vel, p, H)) {
                             const bool fin = __builtin_isfinite(uc[0]) && __builtin_isfinite(uc[1]) &&
@@ -317,6 +318,7 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 6 || nsteps < 0) return WT_ERR_ARG;
     if (P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
     if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
+    if (P->gravity[0] != 0.0 || P->gravity[1] != 0.0 || P->gravity[2] != 0.0) return WT_ERR_UNSUPPORTED;
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0) || !(P->gamma > 1.0))
         return WT_ERR_ARG;
     // problems must be valid and pairwise disjoint inside [0, total)
@@ -324,7 +326,9 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     std::iota(idx.begin(), idx.end(), 0);
     for (int64_t b = 0; b < nprob; ++b) {
         if (n[b] < 6 || offset[b] < 0 || offset[b] + n[b] > total) return WT_ERR_ARG;
-        if (!(hi[b] > lo[b]) || (bc[b] != WT_PERIODIC && bc[b] != WT_TRANSMISSIVE)) return WT_ERR_ARG;
+        if (!(hi[b] > lo[b]) ||
+            (bc[b] != WT_PERIODIC && bc[b] != WT_TRANSMISSIVE && bc[b] != WT_REFLECTIVE))
+            return WT_ERR_ARG;
     }
     std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return offset[a] < offset[b]; });
     for (int64_t k = 1; k < nprob; ++k)

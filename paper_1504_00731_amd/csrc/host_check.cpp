@@ -7,18 +7,13 @@
 #include <cstdlib>
 #include <vector>
 
+#include "wt_bc.hpp"
 #include "wt_flux.hpp"
 
 namespace {
 
-int64_t map_index(int64_t i, int64_t n, int bc)
-{
-    if (bc == 0) {
-        i %= n;
-        return i < 0 ? i + n : i;
-    }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
+using wt::map_index;
+using wt::reflected;
 
 template <int NDIM>
 struct HostStencil {
@@ -61,6 +56,7 @@ int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double ga
                 const int64_t idx = base + map_index(i - 2 + k, nd, bc) * sd;
                 double uc[M];
                 for (int c = 0; c < M; ++c) uc[c] = u[c * N + idx];
+                if (reflected(i - 2 + k, nd, bc)) uc[1 + DIR] = -uc[1 + DIR];
                 double p, H;
                 if (!wt::euler_cell<NDIM>(uc, gamma, S.vv[k], p, H)) bad = 1;
                 for (int c = 0; c < M; ++c) S.uu[k][c] = uc[c];
@@ -97,6 +93,10 @@ double wth_div_by_recip_checked(double a, double b, double y)
 }
 double wth_recip_refine(double b, double y0) { return wt::recip_refine(b, y0); }
 
+// The boundary index map and mirror flag, for CPU checks of their range.
+int64_t wth_map_index(int64_t i, int64_t n, int bc) { return wt::map_index(i, n, bc); }
+int wth_reflected(int64_t i, int64_t n, int bc) { return wt::reflected(i, n, bc) ? 1 : 0; }
+
 double wth_weno_fp32(const double *s, double eps, double aR)
 {
     return wt::weno_theta_fp32_recon(s, eps, (float)aR);
@@ -111,7 +111,7 @@ double wth_weno(const double *s, double eps, double aR)
 // for a 1D scalar state with given flux values f (alpha[0]).
 int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc,
             const double *alpha, double gamma, double eps, double aR, const double *u,
-            const double *f, double *L)
+            const double *f, double *L, const double *grav)
 {
     if (sys != 2) {
         const int64_t nn = n[0];
@@ -143,6 +143,18 @@ int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc
         bad |= euler_sweep<3, 2>(n, dx[2], bc[2], alpha + 10, gamma, eps, aR, u, D.data(), false);
     }
     for (int64_t k = 0; k < N * M; ++k) L[k] = -D[k];
+    if (grav && (grav[0] != 0.0 || grav[1] != 0.0 || grav[2] != 0.0))
+        for (int64_t j = 0; j < N; ++j) {
+            // the final sweep's source term, in its order
+            const double rho = u[j];
+            double e = 0.0;
+            for (int d = 0; d < ndim; ++d) {
+                const double md = u[(1 + d) * N + j];
+                L[(1 + d) * N + j] = L[(1 + d) * N + j] + (-(grav[d] * rho));
+                e = d == 0 ? grav[0] * md : e + grav[d] * md;
+            }
+            L[(ndim + 1) * N + j] = L[(ndim + 1) * N + j] + (-e);
+        }
     return bad;
 }
 

@@ -56,6 +56,8 @@ struct SweepArgs {
     int check_done;
     int64_t tiles;         // y/z sweeps: tiles of the grid, and tiles per XCD
     int64_t tiles_per_xcd;
+    double grav[3];        // gravitational acceleration along -x_d (Euler)
+    int has_grav;          // any grav[d] != 0: the source is added to L
 };
 
 constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, one L2 each
@@ -271,6 +273,7 @@ void sweep_kernel(SweepArgs A)
             double uc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) uc[c] = A.uin[c * ncell + idx];
+            if (reflected(g0 - 3 + r, nd, A.bc)) uc[1 + DIR] = -uc[1 + DIR];
             double vel[NDIM], p, H;
             const bool ok = euler_cell<NDIM>(uc, A.gamma, vel, p, H);
             if (!ok) {
@@ -349,6 +352,20 @@ void sweep_kernel(SweepArgs A)
                 } else {
                     if constexpr (NDIM == 1) Lc[c] = -Dd;
                     else Lc[c] = -(A.D[o] + Dd);
+                }
+            }
+            if constexpr (EULER && (MODE == MODE_LAST_RHS || MODE == MODE_LAST_STAGE)) {
+                // gravity source (Sec. 4.3, TEST 6) of the stage's input state
+                if (A.has_grav) {
+                    const double rho = A.uin[idx];
+                    double e = 0.0;
+#pragma unroll
+                    for (int d = 0; d < NDIM; ++d) {
+                        const double md = A.uin[(1 + d) * ncell + idx];
+                        Lc[1 + d] = Lc[1 + d] + (-(A.grav[d] * rho));
+                        e = d == 0 ? A.grav[0] * md : e + A.grav[d] * md;
+                    }
+                    Lc[NDIM + 1] = Lc[NDIM + 1] + (-e);
                 }
             }
             if constexpr (MODE == MODE_LAST_RHS) {
@@ -559,6 +576,10 @@ wt_status validate(const wt_grid *G, const wt_params *P, Shape &S)
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0)) return WT_ERR_ARG;
     if (P->system == WT_EULER && !(P->gamma > 1.0)) return WT_ERR_ARG;
     if (P->system == WT_LINEAR && !std::isfinite(P->a)) return WT_ERR_ARG;
+    for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(P->gravity[d])) return WT_ERR_ARG;
+        if (P->gravity[d] != 0.0 && (P->system != WT_EULER || d >= G->ndim)) return WT_ERR_ARG;
+    }
     S.ndim = G->ndim;
     S.m = P->system == WT_EULER ? G->ndim + 2 : 1;
     S.ncell = 1;
@@ -566,7 +587,9 @@ wt_status validate(const wt_grid *G, const wt_params *P, Shape &S)
         if (k < G->ndim) {
             if (G->n[k] < 6 || G->n[k] > (int64_t(1) << 31)) return WT_ERR_ARG;
             if (!(G->hi[k] > G->lo[k])) return WT_ERR_ARG;
-            if (G->bc[k] != WT_PERIODIC && G->bc[k] != WT_TRANSMISSIVE) return WT_ERR_ARG;
+            if (G->bc[k] != WT_PERIODIC && G->bc[k] != WT_TRANSMISSIVE && G->bc[k] != WT_REFLECTIVE)
+                return WT_ERR_ARG;
+            if (G->bc[k] == WT_REFLECTIVE && P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
             S.n[k] = G->n[k];
             S.dx[k] = (G->hi[k] - G->lo[k]) / (double)G->n[k];
             S.bc[k] = G->bc[k];
@@ -682,6 +705,10 @@ SweepArgs base_args(wt_ctx *c, const Shape &S, const wt_params *P)
     A.gamma = P->gamma;
     A.W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
     A.D = c->D;
+    for (int d = 0; d < 3; ++d) {
+        A.grav[d] = P->gravity[d];
+        A.has_grav |= P->gravity[d] != 0.0;
+    }
     return A;
 }
 
@@ -755,7 +782,8 @@ wt_status ensure_step_graph(wt_ctx *c, const Shape &S, const wt_params *P, doubl
     for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)c->U1, (uint64_t)(uintptr_t)c->U2,
                        (uint64_t)(uintptr_t)c->D, (uint64_t)(uintptr_t)c->st, (uint64_t)(c->g % kSlots),
                        (uint64_t)plan_tile(c, S, P, 1), (uint64_t)plan_tile(c, S, P, 2), bits(P->a),
-                       bits(P->gamma), bits(P->cfl), bits(P->eps), bits(P->alpha_R), bits(S.dx[0]),
+                       bits(P->gamma), bits(P->cfl), bits(P->eps), bits(P->alpha_R),
+                       bits(P->gravity[0]), bits(P->gravity[1]), bits(P->gravity[2]), bits(S.dx[0]),
                        bits(S.dx[1]), bits(S.dx[2]), (uint64_t)S.bc[0], (uint64_t)S.bc[1], (uint64_t)S.bc[2]})
         key = (key ^ v) * 1099511628211ull;
     if (c->s_graph && c->s_key == key) return WT_OK;

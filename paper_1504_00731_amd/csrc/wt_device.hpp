@@ -5,6 +5,7 @@
 #pragma once
 #pragma clang fp contract(off)
 
+#include "wt_bc.hpp"
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -41,16 +42,6 @@ __device__ __forceinline__ double bits_to_double(unsigned long long b)
 __device__ __forceinline__ unsigned long long double_to_bits(double d)
 {
     return static_cast<unsigned long long>(__double_as_longlong(d));
-}
-
-// Boundary conditions as index maps (periodic wrap, zero-gradient clamp).
-__device__ __forceinline__ int64_t map_index(int64_t i, int64_t n, int bc)
-{
-    if (bc == WT_PERIODIC) {
-        i %= n;
-        return i < 0 ? i + n : i;
-    }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
 __device__ __forceinline__ double wave_max(double v)

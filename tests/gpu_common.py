@@ -13,7 +13,8 @@ def grid_params(case: W.Case, alpha_R=None, cfl=None):
     g = wt.Grid(n=case.n, lo=case.lo, hi=case.hi, bc=case.bc)
     p = wt.Params(system=case.system, a=case.a, gamma=case.gamma,
                   cfl=case.cfl if cfl is None else cfl,
-                  alpha_R=case.alpha_R if alpha_R is None else alpha_R)
+                  alpha_R=case.alpha_R if alpha_R is None else alpha_R,
+                  gravity=tuple(case.gravity))
     return g, p
 
 

@@ -18,11 +18,13 @@ def lib():
     global _lib
     if _lib is None:
         srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".cpp"))]
+        srcs.append(os.path.join(ROOT, "include", "wenotheta.h"))
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(map(os.path.getmtime, srcs)):
             os.makedirs(os.path.dirname(LIB), exist_ok=True)
             tmp = LIB + ".tmp%d" % os.getpid()
             subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
-                            "-Wno-unknown-pragmas", "-fPIC", "-shared", "-o", tmp,
+                            "-Wno-unknown-pragmas", "-fPIC", "-shared",
+                            "-I" + os.path.join(ROOT, "include"), "-o", tmp,
                             os.path.join(CSRC, "host_check.cpp")], check=True)
             os.replace(tmp, LIB)
         L = ctypes.CDLL(LIB)
@@ -32,7 +34,7 @@ def lib():
         L.wth_rhs.restype = ctypes.c_int
         L.wth_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), dp,
                               ctypes.POINTER(ctypes.c_int), dp, ctypes.c_double, ctypes.c_double,
-                              ctypes.c_double, dp, dp, dp]
+                              ctypes.c_double, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -60,8 +62,9 @@ def rhs(P, u, alpha, f=None):
         f = P.a * u if P.system == 0 else 0.5 * u * u
     f = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
     L = np.zeros_like(u)
+    grav = np.ascontiguousarray(list(P.gravity) + [0.0] * (3 - len(P.gravity)), dtype=np.float64)
     bad = lib().wth_rhs(P.system, P.ndim, n, dx, bc, _dp(al), P.gamma, P.eps, P.alpha_R,
-                        _dp(u), _dp(f), _dp(L))
+                        _dp(u), _dp(f), _dp(L), _dp(grav))
     return L, bad
 
 
@@ -98,3 +101,17 @@ def recip_refine(b, y0) -> float:
     f.restype = ctypes.c_double
     f.argtypes = [ctypes.c_double] * 2
     return f(b, y0)
+
+
+def map_index(i, n, bc) -> int:
+    f = lib().wth_map_index
+    f.restype = ctypes.c_int64
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    return f(i, n, bc)
+
+
+def reflected(i, n, bc) -> bool:
+    f = lib().wth_reflected
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    return bool(f(i, n, bc))

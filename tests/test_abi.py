@@ -47,10 +47,32 @@ def test_status_strings(lib):
     assert f(99) == b"unknown status"
 
 
-def test_struct_layout_matches_header():
-    # wt_grid: int32, int32, int64[3], double[3], double[3], int32[3], int32
-    assert ctypes.sizeof(binding.wt_grid) == 4 + 4 + 24 + 24 + 24 + 12 + 4
-    assert ctypes.sizeof(binding.wt_params) == 4 + 4 + 5 * 8
+def test_struct_layout_matches_header(tmp_path):
+    """Sizes and field offsets of the binding's structures equal those a C compiler
+    gives the header's (compiled here with gcc against include/wenotheta.h)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not available")
+    fields = {"wt_grid": [f[0] for f in binding.wt_grid._fields_],
+              "wt_params": [f[0] for f in binding.wt_params._fields_]}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "wenotheta.h"', "int main(void) {"]
+    for st, names in fields.items():
+        src.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for n in names:
+            src.append(f'printf("{st} {n} %zu\\n", offsetof({st}, {n}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st, names in fields.items():
+        cls = getattr(binding, st)
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for n in names:
+            assert got[(st, n)] == getattr(cls, n).offset, (st, n)
 
 
 def test_missing_library_fails_loudly(monkeypatch):

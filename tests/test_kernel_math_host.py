@@ -166,3 +166,41 @@ def test_reciprocal_refinement_from_coarse_estimates():
         want = 1.0 / b
         for rel in (0.0, 2.0 ** -14, -(2.0 ** -14), 3e-6, -7e-9, 2.0 ** -40):
             assert HK.recip_refine(b, want * (1.0 + rel)) == want, (b, rel)
+
+
+@pytest.mark.parametrize("make", [lambda: W.blast_waves(120), lambda: W.rayleigh_taylor(16, 48),
+                                  lambda: W.implosion(24)])
+def test_rhs_with_walls_and_gravity_matches_oracle(make):
+    """Reflective walls and the gravity source through the kernels' arithmetic on the
+    host: the RHS equals the oracle's bit for bit, also after the flow has moved."""
+    from tests.gpu_common import oracle_problem
+    c = make()
+    P = oracle_problem(c)
+    u = c.u
+    for _ in range(2):
+        al, _ = oracle.alpha(P, u)
+        got, bad = HK.rhs(P, u, al)
+        assert not bad
+        assert np.array_equal(got, oracle.rhs(P, u, alpha_=al))
+        u, _ = oracle.step(P, u)
+
+
+def test_boundary_maps_stay_inside_the_line():
+    """The kernels stage whole tiles (up to 261 points from 3 before the tile), which
+    can reach far past the last ghost point of a short line: every boundary map must
+    land inside the line for every such index, and on the ghost points -3..-1 and
+    n..n+2 give the plain rule (wrap, nearest end point, mirror image with the flag).
+    (A mirror 2n - 1 - i without the period 2n fell to -162 on a 48-point line.)"""
+    for n in list(range(6, 40)) + [48, 100, 131, 255, 256, 300]:
+        for bc in (0, 1, 2):
+            for i in list(range(-300, -3)) + list(range(n + 3, n + 600, 7)):
+                assert 0 <= HK.map_index(i, n, bc) < n, (n, bc, i)
+            for i in list(range(-3, 0)) + list(range(n, n + 3)) + [0, 1, n - 1]:
+                k = HK.map_index(i, n, bc)
+                if bc == 0:
+                    assert k == i % n
+                elif bc == 1:
+                    assert k == min(max(i, 0), n - 1)
+                else:
+                    want = -1 - i if i < 0 else (2 * n - 1 - i if i >= n else i)
+                    assert k == want and HK.reflected(i, n, bc) == (i < 0 or i >= n)

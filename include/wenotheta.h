@@ -68,7 +68,11 @@ typedef enum {
     WT_REFLECTIVE = 2    /* wall half a spacing beyond the end points (Euler
                             only; Sec. 4.2 TEST 5, Sec. 4.3 TESTs 6, 7): ghost
                             points are the mirror images of the points across
-                            the wall, with the momentum normal to it negated */
+                            the wall, with the momentum normal to it negated;
+                            the split of that direction gives the two acoustic
+                            fields (u_d -+ c) the larger of their two maximum
+                            speeds, computed or given, as over the mirror-
+                            extended domain where they exchange speeds */
 } wt_bc;
 
 typedef enum {

@@ -496,7 +496,9 @@ static double scalar_flux(const wto_problem *P, double u)
 
 /* Reading: alpha = max |f'(u)| over the whole domain (Remark on flux
  * splitting) is taken per characteristic field, alpha_s = max |lambda_s|,
- * and re-evaluated from the state of every Runge-Kutta stage. */
+ * and re-evaluated from the state of every Runge-Kutta stage.  These are
+ * the maxima over the grid's points; pair_wall_speeds() below completes
+ * them for reflective walls where the split uses them. */
 int wto_alpha(const wto_problem *P, const double *u, double *alpha, double *amax)
 {
     int st = validate(P);
@@ -538,6 +540,24 @@ int wto_alpha(const wto_problem *P, const double *u, double *alpha, double *amax
         }
     }
     return WTO_OK;
+}
+
+/* Behind reflective walls in direction d the domain is the mirror-extended
+ * one (the ghost points are its point values), where u_d changes sign and
+ * the two acoustic fields (u_d - c, u_d + c) exchange their speeds, so over
+ * that whole domain both have the larger maximum.  Applied to the speeds the
+ * split uses, computed or given. */
+static void pair_wall_speeds(const wto_problem *P, double *alpha)
+{
+    if (P->system != WTO_EULER) return;
+    const int m = ncomp(P);
+    for (int d = 0; d < P->ndim; ++d)
+        if (P->bc[d] == WTO_REFLECTIVE) {
+            double *a = &alpha[d * m];
+            const double both = a[2] > a[0] ? a[2] : a[0];
+            a[0] = both;
+            a[2] = both;
+        }
 }
 
 /* Reading of "a proper CFL condition" (Sec. 2.1):
@@ -594,6 +614,7 @@ int wto_rhs(const wto_problem *P, const double *u, const double *f,
         st = wto_alpha(P, u, alpha, amax);
         if (st) return st;
     }
+    pair_wall_speeds(P, alpha);
 
     if (P->system != WTO_EULER) {
         const int64_t n = P->n[0];
@@ -668,6 +689,7 @@ int wto_rhs_points(const wto_problem *P, const double *u, const double *alpha_in
         st = wto_alpha(P, u, alpha, amax);
         if (st) return st;
     }
+    pair_wall_speeds(P, alpha);
     for (int64_t k = 0; k < npts; ++k) {
         const int64_t cell = cells[k];
         if (cell < 0 || cell >= N) return WTO_ERR_ARG;
@@ -799,6 +821,7 @@ int wto_decisions_1d(const wto_problem *P, const double *u, const double *alpha_
         st = wto_alpha(P, u, alpha, amax);
         if (st) return st;
     }
+    pair_wall_speeds(P, alpha);
     for (int64_t i = -1; i < n; ++i) {
         double vp[MAXM][6], vm[MAXM][6];
         if (P->system != WTO_EULER) {

@@ -145,7 +145,8 @@ __global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(Ba
             for (int stage = 1; stage <= 3; ++stage) {
                 const double *uin = stage == 1 ? A.u : (stage == 2 ? A.U1 : A.U2);
                 double *out = stage == 1 ? A.U1 : (stage == 2 ? A.U2 : A.u);
-                if (t < 3) s_al[t] = spd[t];
+                if (t < 3)
+                    s_al[t] = split_speed([&spd](int k) { return spd[k]; }, t, bc == WT_REFLECTIVE);
                 // the new state's speeds: per-wave maxima over the segments, in LDS
                 if ((t & 63) < 3) s_red[t & 63][t >> 6] = 0.0;
                 for (int64_t seg = 0; seg < nseg; ++seg) {

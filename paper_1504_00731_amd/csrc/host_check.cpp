@@ -27,7 +27,11 @@ struct HostStencil {
 
 struct HostSpeeds {
     const double *al;
-    double operator()(int s) const { return al[s]; }
+    bool walls;
+    double operator()(int s) const
+    {
+        return wt::split_speed([this](int k) { return al[k]; }, s, walls);
+    }
 };
 
 struct HostScalar {
@@ -64,7 +68,7 @@ int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double ga
                 S.ss[k] = wt::sqrt_rn(uc[0]);
                 S.hh[k] = H;
             }
-            if (!wt::euler_interface_flux<NDIM, DIR, 0>(S, HostSpeeds{al}, gamma,
+            if (!wt::euler_interface_flux<NDIM, DIR, 0>(S, HostSpeeds{al, bc == WT_REFLECTIVE}, gamma,
                                                         wt::WenoConst{eps, aR, 1.0 / eps},
                                                         &F[(i + 1) * M]))
                 bad = 1;

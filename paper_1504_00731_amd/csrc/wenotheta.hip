@@ -315,7 +315,7 @@ void sweep_kernel(SweepArgs A)
         if (valid) {
             if constexpr (EULER) {
                 const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
-                const SlotSpeeds al{st->alpha[A.slot_rd], DIR};
+                const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.bc == WT_REFLECTIVE};
                 double F[M];
                 if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.W, F))
                     atomicOr(&st->err, kErrNonphysical);

@@ -42,4 +42,19 @@ WT_HD bool reflected(int64_t i, int64_t n, int bc)
     return k >= n;
 }
 
+// Lax-Friedrichs speed of characteristic field s in direction d, given the
+// per-field maxima a(0..m-1) over the grid (0: u_d - c, 1: u_d, 2: u_d + c,
+// 3..: u_d).  Behind reflective walls in d the solution is the mirror-extended
+// one, in which u_d changes sign and the two acoustic fields exchange their
+// speeds, so both take the larger maximum.
+template <class Speeds>
+WT_HD double split_speed(const Speeds &a, int s, bool walls)
+{
+    if (walls && (s == 0 || s == 2)) {
+        const double a0 = a(0), a2 = a(2);
+        return a2 > a0 ? a2 : a0;
+    }
+    return a(s);
+}
+
 }  // namespace wt

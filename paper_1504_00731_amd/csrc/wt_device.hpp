@@ -138,10 +138,17 @@ struct LdsStencil {
 };
 
 // Lax-Friedrichs speed of field s of the sweep direction, from a slot.
+// Speeds of the sweep direction read from a slot (per-field maxima), paired
+// for the acoustic fields behind reflective walls.
 struct SlotSpeeds {
     const unsigned long long *slot;
     int dir;
-    __device__ double operator()(int s) const { return bits_to_double(slot[dir * 5 + s]); }
+    bool walls;
+    __device__ double raw(int s) const { return bits_to_double(slot[dir * 5 + s]); }
+    __device__ double operator()(int s) const
+    {
+        return split_speed([this](int k) { return raw(k); }, s, walls);
+    }
 };
 
 template <int NC, int TX>

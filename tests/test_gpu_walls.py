@@ -96,6 +96,61 @@ def test_implosion_diagonal_symmetry_on_the_gpu(ctx):
         assert np.array_equal(u[0], u[0].T) and np.array_equal(u[1], u[2].T)
 
 
+def _mirror_double(u, axis, normal_comp):
+    mir = np.flip(u, axis=axis).copy()
+    mir[normal_comp] = -mir[normal_comp]
+    return np.concatenate([mir, u], axis=axis)
+
+
+def test_walls_are_the_mirrored_periodic_problem_on_the_gpu(ctx):
+    """20 CFL steps of a 2D problem with walls all round equal, bit for bit, the same
+    steps of the periodic problem on the doubled (mirrored) grid, both on the GPU: the
+    walls' ghost points, the paired acoustic speeds and the time step agree with the
+    mirror image everywhere (also with the y tiles reaching past the grid)."""
+    c = W.euler2d_seeded(2, 72)
+    ud = _mirror_double(_mirror_double(c.u, axis=1, normal_comp=2), axis=2, normal_comp=1)
+    cw = W.Case("walls", W.EULER, c.u, (0.0, 0.0), (1.0, 1.0), (W.REFLECTIVE, W.REFLECTIVE))
+    cd = W.Case("doubled", W.EULER, ud, (-1.0, -1.0), (1.0, 1.0), (W.PERIODIC, W.PERIODIC))
+    for prec in (wt.WT_FP64, wt.WT_FP32_RECON):
+        uw, udd = _steps(ctx, cw, 20, prec), _steps(ctx, cd, 20, prec)
+        assert np.array_equal(uw, udd[:, 72:, 72:])
+
+
+def test_implosion_at_the_paper_size_and_time(ctx):
+    """TEST 7 as printed: 400 x 400, walls all round, alpha_R = 1, to t = 5 (about 17000
+    CFL steps).  The density stays exactly symmetric about the diagonal (the paper's point
+    for this test), and with walls all round mass and energy are conserved to rounding."""
+    c = W.implosion(400)
+    m0 = c.u.reshape(4, -1).sum(axis=1)
+    for prec in (wt.WT_FP64, wt.WT_FP32_RECON):
+        g, p = grid_params(c)
+        p.precision = prec
+        u = to_dev(c.u)
+        t, k = wt.wenotheta_solve(ctx, g, p, u, c.t_end)
+        a = u.cpu().numpy()
+        assert t == c.t_end and k > 10000
+        assert np.array_equal(a[0], a[0].T) and np.array_equal(a[1], a[2].T)
+        m1 = a.reshape(4, -1).sum(axis=1)
+        for comp in (0, 3):
+            assert abs(m1[comp] - m0[comp]) <= 1e-11 * m0[comp], (prec, comp)
+
+
+def test_rayleigh_taylor_at_the_paper_size_and_time(ctx):
+    """TEST 6 as printed: 120 x 360, periodic in x, walls in y, gravity 0.1, to t = 9.5
+    (about 17800 steps): mass is conserved to rounding, the heavy fluid has sunk (the
+    centre of mass moved down) and the flow stayed physical."""
+    c = W.rayleigh_taylor(120, 360)
+    y = W.grid_points(360, -0.75, 0.75, W.REFLECTIVE)[:, None]
+    g, p = grid_params(c)
+    u = to_dev(c.u)
+    t, k = wt.wenotheta_solve(ctx, g, p, u, c.t_end)
+    a = u.cpu().numpy()
+    assert t == c.t_end and k > 10000
+    assert abs(a[0].sum() - c.u[0].sum()) <= 1e-11 * c.u[0].sum()
+    assert (a[0] * y).sum() < (c.u[0] * y).sum() - 1e-3 * c.u[0].sum()
+    assert a[0].min() > 0.5
+
+
 def test_blast_waves_solve_until_the_collision(ctx):
     """TEST 5 at a reduced grid with the CFL step to t = 0.025, shortly before the two
     blast waves collide (about t = 0.027, where the scheme as read here turns the
@@ -142,14 +197,13 @@ def test_wall_and_gravity_arguments(ctx):
         with pytest.raises(wt.WenoThetaError) as e:
             wt.wenotheta_rhs(ctx, g, p, u, L)
         assert e.value.code == 1
-    s = W.scalar_modes(0, 64) if hasattr(W, "scalar_modes") else None
-    if s is not None:
-        gs, ps = grid_params(s)
-        gs.bc = (wt.WT_REFLECTIVE,)
-        us = to_dev(s.u)
-        with pytest.raises(wt.WenoThetaError) as e:
-            wt.wenotheta_rhs(ctx, gs, ps, us, torch.empty_like(us))
-        assert e.value.code == 2
+    s = W.scalar_modes(0, 64)
+    gs, ps = grid_params(s)
+    gs.bc = (wt.WT_REFLECTIVE,)
+    us = to_dev(s.u)
+    with pytest.raises(wt.WenoThetaError) as e:
+        wt.wenotheta_rhs(ctx, gs, ps, us, torch.empty_like(us))
+    assert e.value.code == 2
     B = W.batched_1d(seed=1, nprob=4, nmin=20, nmax=40)
     with pytest.raises(wt.WenoThetaError) as e:
         wt.wenotheta_solve_batched(ctx, wt.Params(system=wt.WT_EULER, gravity=(1.0, 0, 0)),

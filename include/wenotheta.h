@@ -185,6 +185,34 @@ wt_status wenotheta_solve_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
                                   int64_t total, int64_t nsteps, double *t_out,
                                   int32_t *status_out, int64_t *steps_out, void *stream);
 
+/* Batched 2D solves: nprob independent 2D Euler problems of their own sizes
+ * (dimension-by-dimension scheme of Sec. 4.3), packed side by side in one
+ * state, each advanced by nsteps CFL steps of its own
+ * (dt_b = cfl / (amax_x / dx_b + amax_y / dy_b)) in one persistent kernel
+ * launched through a captured HIP graph; one workgroup runs a whole problem.
+ * prm->system must be WT_EULER and prm->gravity all 0 (else
+ * WT_ERR_UNSUPPORTED).
+ *   u       DEVICE, FP64, [4][total] component-major (rho, m_x, m_y, E):
+ *           problem b occupies columns offset[b] .. offset[b] + nx[b] ny[b] - 1,
+ *           its points x fastest (column offset[b] + y nx[b] + x); advanced in
+ *           place;
+ *   nx, ny, offset   HOST arrays of nprob entries: points per direction
+ *           (>= 6 each) and first column; the column ranges must be disjoint
+ *           and inside [0, total);
+ *   lo, hi, bc       HOST arrays of 2 nprob entries, [problem][x, y]: domain
+ *           ends (dx = (hi - lo) / n per direction) and boundary condition
+ *           (any wt_bc) per direction;
+ *   t_out, status_out, steps_out   as for wenotheta_solve_batched.
+ * The step of each problem is the one wenotheta_step performs on it alone
+ * (bit for bit in WT_FP64).  Asynchronous after the problem tables are
+ * uploaded.  Calls on one context share the stage buffers of
+ * wenotheta_solve_batched: the two must not overlap. */
+wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *nx,
+                                     const int64_t *ny, const int64_t *offset, const double *lo,
+                                     const double *hi, const int32_t *bc, const wt_params *prm,
+                                     double *u, int64_t total, int64_t nsteps, double *t_out,
+                                     int32_t *status_out, int64_t *steps_out, void *stream);
+
 /* Tile shapes of the sweeps (dimension-by-dimension scheme of Sec. 4.3: one
  * 1D operator per direction).  The y and z sweeps of the 2D/3D Euler system
  * run in one of four tile shapes, TX consecutive x-columns by TN points along

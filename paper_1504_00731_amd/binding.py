@@ -24,7 +24,7 @@ WT_FP64, WT_FP32_RECON = 0, 1
 EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
             "wenotheta_rhs", "wenotheta_step", "wenotheta_solve", "wenotheta_sync",
             "wenotheta_profile", "wenotheta_profile_read", "wenotheta_solve_batched",
-            "wenotheta_tune", "wenotheta_set_tiles")
+            "wenotheta_solve_batched_2d", "wenotheta_tune", "wenotheta_set_tiles")
 PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
                  "sweep_z_final")
 
@@ -81,6 +81,9 @@ def _lib():
         i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
         L.wenotheta_solve_batched.argtypes = [vp, ctypes.c_int64, i64p, i64p, dp, dp, i32p, P, vp,
                                               ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
+        L.wenotheta_solve_batched_2d.argtypes = [vp, ctypes.c_int64, i64p, i64p, i64p, dp, dp, i32p,
+                                                 P, vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp,
+                                                 vp]
         L.wenotheta_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
         i32p3 = ctypes.POINTER(ctypes.c_int32)
         L.wenotheta_tune.argtypes = [vp, G, P, vp, i32p3, vp]
@@ -309,6 +312,36 @@ def wenotheta_solve_batched(ctx: Context, params: Params, u, n, offset, lo, hi, 
         _dev_ptr(t_out, "t_out", (nprob,)), _dev_int_ptr(status_out, "status_out", nprob, 32),
         _dev_int_ptr(steps_out, "steps_out", nprob, 64), _stream_ptr(stream)),
         "wenotheta_solve_batched")
+    return u
+
+
+def wenotheta_solve_batched_2d(ctx: Context, params: Params, u, nx, ny, offset, lo, hi, bc, nsteps,
+                               t_out=None, status_out=None, steps_out=None, stream=None):
+    """Advance packed independent 2D Euler problems (u: [4, total] device tensor; problem b
+    in columns offset[b] .. offset[b] + nx[b] ny[b] - 1, x fastest; lo, hi, bc: [nprob, 2])."""
+    import numpy as np
+    nx = np.ascontiguousarray(nx, dtype=np.int64)
+    ny = np.ascontiguousarray(ny, dtype=np.int64)
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    bc = np.ascontiguousarray(bc, dtype=np.int32)
+    nprob = int(nx.size)
+    if not (ny.size == offset.size == nprob and lo.shape == hi.shape == bc.shape == (nprob, 2)):
+        raise ValueError("problem tables must have one entry (two for lo, hi, bc) per problem")
+    if u.dim() != 2 or u.shape[0] != 4:
+        raise ValueError("u must have shape (4, total)")
+    total = int(u.shape[1])
+    i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(_lib().wenotheta_solve_batched_2d(
+        ctx.handle, nprob, nx.ctypes.data_as(i64p), ny.ctypes.data_as(i64p),
+        offset.ctypes.data_as(i64p), lo.ctypes.data_as(dp), hi.ctypes.data_as(dp),
+        bc.ctypes.data_as(i32p), ctypes.byref(params.c_struct()), _dev_ptr(u, "u"), total,
+        int(nsteps), _dev_ptr(t_out, "t_out", (nprob,)),
+        _dev_int_ptr(status_out, "status_out", nprob, 32),
+        _dev_int_ptr(steps_out, "steps_out", nprob, 64), _stream_ptr(stream)),
+        "wenotheta_solve_batched_2d")
     return u
 
 

@@ -1,5 +1,5 @@
-// Batched solves: many independent 1D Euler problems of uneven sizes advanced
-// by one persistent kernel.
+// Batched solves: many independent 1D or 2D Euler problems of uneven sizes
+// advanced by one persistent kernel.
 //
 // Each workgroup takes a problem from a work queue (largest first), and runs
 // all of that problem's RK3 steps itself: per stage it sweeps the problem in
@@ -11,6 +11,13 @@
 // barrier separate a stage's writes from the next stage's reads.  The whole
 // batch is one graph (queue reset + kernel), captured once per argument set
 // and replayed.
+//
+// 2D problems take per stage an x pass over tiles of 4 rows x 63 points
+// (divergence of the x fluxes into a packed workspace D) and a y pass over
+// tiles of 8 columns x 31 points (L = -(D + y divergence), the stage update and
+// the new speeds), with the grid sweeps' staging, interface routine and
+// operation order; both tile shapes pack several rows or columns, so a short
+// line does not leave most of the 256 threads idle.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -47,18 +54,19 @@ struct BatchArgs {
     WenoConst W;
 };
 
-// Block-wide max of three per-thread values; every thread gets the result.
-__device__ __forceinline__ void block_max3(double (&v)[3], double (*red)[kThreads / 64])
+// Block-wide max of K per-thread values; every thread gets the result.
+template <int K>
+__device__ __forceinline__ void block_max(double (&v)[K], double (*red)[kThreads / 64])
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < K; ++k) {
         const double w = wave_max(v[k]);
         if (lane == 0) red[k][wid] = w;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < K; ++k) {
         double m = red[k][0];
 #pragma unroll
         for (int w = 1; w < kThreads / 64; ++w) m = red[k][w] > m ? red[k][w] : m;
@@ -131,7 +139,7 @@ __global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(Ba
 #pragma unroll
             for (int k = 0; k < 3; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
         }
-        block_max3(spd, s_red);
+        block_max<3>(spd, s_red);
 #pragma unroll
         for (int k = 0; k < 3; ++k) spd[k] = uniform(spd[k]);
 
@@ -250,6 +258,272 @@ __global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(Ba
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D problems
+// ---------------------------------------------------------------------------
+
+// One 2D problem of a batch: nx x ny points (x fastest) from column off of the
+// packed arrays, spacings with their rounded reciprocals, boundary conditions.
+struct Prob2 {
+    int64_t nx, ny, off;
+    double dx, rdx, dy, rdy;
+    int32_t bcx, bcy;
+};
+
+struct Batch2Args {
+    double *u;                 // packed states [4][total], advanced in place
+    double *U1, *U2, *D;       // packed stage buffers and the x divergence
+    int64_t total;
+    const Prob2 *prob;
+    const int32_t *order;      // problems, largest first
+    int32_t *queue;            // next queue position
+    double *t_out;             // time reached per problem (optional)
+    int32_t *status_out;       // status per problem (optional)
+    int64_t *steps_out;        // steps completed per problem (optional)
+    DevState *st;
+    int nprob;
+    int64_t nsteps;
+    double gamma, cfl;
+    WenoConst W;
+};
+
+// Tile of a 2D problem: TX lines (rows for DIR 0, columns for DIR 1), each with
+// TN owned points along DIR and 3-point halos mapped through the boundary; entry
+// r * TX + l holds point g0 - 3 + r of line l0 + l (lines past the last repeat
+// it; their interfaces are never taken).  Returns error bits.
+template <int DIR, int TX, int TN, int NC>
+__device__ __forceinline__ int stage_tile2(const double *uin, int64_t total, const Prob2 &P,
+                                           int64_t l0, int64_t g0, double gamma,
+                                           double (*s_u)[NC], double (*s_f)[NC],
+                                           double (*s_v)[NC], double *s_sr, double *s_H)
+{
+    constexpr int M = 4;
+    const int64_t nd = DIR == 0 ? P.nx : P.ny, nl = DIR == 0 ? P.ny : P.nx;
+    const int bc = DIR == 0 ? P.bcx : P.bcy;
+    int err = 0;
+    for (int i = threadIdx.x; i < (TN + 6) * TX; i += kThreads) {
+        const int r = i / TX, cl = i % TX;
+        const int64_t g = map_index(g0 - 3 + r, nd, bc);
+        const int64_t l = l0 + cl < nl ? l0 + cl : nl - 1;
+        const int64_t idx = P.off + (DIR == 0 ? l * P.nx + g : g * P.nx + l);
+        double uc[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uc[c] = uin[c * total + idx];
+        if (reflected(g0 - 3 + r, nd, bc)) uc[1 + DIR] = -uc[1 + DIR];
+        double vel[2], p, H;
+        if (!euler_cell<2>(uc, gamma, vel, p, H)) {
+            bool fin = true;
+#pragma unroll
+            for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
+            err |= fin ? kErrNonphysical : kErrNonfinite;
+        }
+        double fn[M];
+        euler_normal_flux<2, DIR>(uc, vel, p, fn);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            s_u[c][i] = uc[c];
+            s_f[c][i] = fn[c];
+        }
+        s_v[0][i] = vel[0];
+        s_v[1][i] = vel[1];
+        s_sr[i] = sqrt_rn(uc[0]);
+        s_H[i] = H;
+    }
+    return err;
+}
+
+// Interface fluxes of a staged tile, one interface per thread (between points
+// g0 + it - 1 and g0 + it of line l0 + l, t = it * TX + l), into s_F.
+template <int DIR, int TX, int TN, int NC, int PREC>
+__device__ __forceinline__ int tile_fluxes2(const Prob2 &P, int64_t l0, int64_t g0, const double *al,
+                                            double gamma, const WenoConst &W,
+                                            const double (*s_u)[NC], const double (*s_f)[NC],
+                                            const double (*s_v)[NC], const double *s_sr,
+                                            const double *s_H, double (*s_F)[kThreads])
+{
+    const int t = threadIdx.x, it = t / TX, cl = t % TX;
+    const int64_t nd = DIR == 0 ? P.nx : P.ny, nl = DIR == 0 ? P.ny : P.nx;
+    int err = 0;
+    if (l0 + cl < nl && g0 + it <= nd) {
+        const LdsStencil<4, 2, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
+        double F[4];
+        if (!euler_interface_flux<2, DIR, PREC>(S, LdsSpeeds{al}, gamma, W, F)) err = kErrNonphysical;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_F[q][t] = F[q];
+    }
+    return err;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads, 3) void batched2d_kernel(Batch2Args A)
+{
+    constexpr int M = 4, XTX = 4, XTN = 63, YTX = 8, YTN = 31;
+    constexpr int NC = (YTN + 6) * YTX > (XTN + 6) * XTX ? (YTN + 6) * YTX : (XTN + 6) * XTX;
+    static_assert(XTX * (XTN + 1) == kThreads && YTX * (YTN + 1) == kThreads, "one interface per thread");
+    __shared__ double s_u[M][NC];
+    __shared__ double s_f[M][NC];
+    __shared__ double s_v[2][NC];
+    __shared__ double s_sr[NC];
+    __shared__ double s_H[NC];
+    __shared__ double s_F[M][kThreads];
+    __shared__ double s_red[6][kThreads / 64];
+    __shared__ double s_al[2][M];
+    __shared__ int s_job;
+    __shared__ int s_bad;
+    __shared__ unsigned long long s_first;
+
+    const int t = threadIdx.x;
+    const int64_t total = A.total;
+    // wave-uniform job loop, as in the 1D kernel
+    for (;;) {
+        if (t == 0) s_job = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        if (job >= A.nprob) break;
+        const Prob2 P = A.prob[A.order[job]];
+        const int b = A.order[job];
+        const int64_t ncell = P.nx * P.ny;
+        int err = 0;
+
+        // speeds of the initial state: per direction |u_d - c|, |u_d|, |u_d + c|
+        double spd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t i = t; i < ncell; i += kThreads) {
+            double uc[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) uc[c] = A.u[c * total + P.off + i];
+            double lam[6];
+            err |= euler_speeds<2>(uc, A.gamma, lam);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
+        }
+        block_max<6>(spd, s_red);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) spd[k] = uniform(spd[k]);
+
+        const int64_t xlines = (P.ny + XTX - 1) / XTX, xseg = (P.nx + XTN - 1) / XTN;
+        const int64_t ylines = (P.nx + YTX - 1) / YTX, yseg = (P.ny + YTN - 1) / YTN;
+        double time = 0.0;
+        int64_t first_bad = err ? 0 : A.nsteps;
+        for (int64_t step = 0; step < A.nsteps; ++step) {
+            // dt = cfl / (amax_x / dx + amax_y / dy), amax_d = max(alpha_{d,0}, alpha_{d,2})
+            const double ax = spd[2] > spd[0] ? spd[2] : spd[0];
+            const double ay = spd[5] > spd[3] ? spd[5] : spd[3];
+            const double dt = uniform(div_rn(A.cfl, div_rn(ax, P.dx) + div_rn(ay, P.dy)));
+            for (int stage = 1; stage <= 3; ++stage) {
+                const double *uin = stage == 1 ? A.u : (stage == 2 ? A.U1 : A.U2);
+                double *out = stage == 1 ? A.U1 : (stage == 2 ? A.U2 : A.u);
+                // split speeds of each direction and field (the shear field takes |u_d|)
+                if (t == 0) {
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        const bool walls = (d == 0 ? P.bcx : P.bcy) == WT_REFLECTIVE;
+#pragma unroll
+                        for (int f = 0; f < M; ++f)
+                            s_al[d][f] = split_speed([&spd, d](int k) { return spd[3 * d + (k < 3 ? k : 1)]; },
+                                                     f, walls);
+                    }
+                }
+                if ((t & 63) < 6) s_red[t & 63][t >> 6] = 0.0;
+
+                // x pass: D = x divergence
+                for (int64_t tile = 0; tile < xlines * xseg; ++tile) {
+                    const int64_t l0 = (tile / xseg) * XTX, g0 = (tile % xseg) * XTN;
+                    err |= stage_tile2<0, XTX, XTN, NC>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+                    __syncthreads();
+                    err |= tile_fluxes2<0, XTX, XTN, NC, PREC>(P, l0, g0, s_al[0], A.gamma, A.W, s_u, s_f,
+                                                                s_v, s_sr, s_H, s_F);
+                    __syncthreads();
+                    if (t < XTN * XTX) {
+                        const int it = t / XTX, cl = t % XTX;
+                        const int64_t g = g0 + it, l = l0 + cl;
+                        if (l < P.ny && g < P.nx) {
+                            const int64_t idx = P.off + l * P.nx + g;
+#pragma unroll
+                            for (int c = 0; c < M; ++c)
+                                A.D[c * total + idx] = div_by_recip(s_F[c][t + XTX] - s_F[c][t], P.dx, P.rdx);
+                        }
+                    }
+                    __syncthreads();                // the tile is reused by the next one
+                }
+                // the y pass reads what the x pass wrote
+                __threadfence();
+                __syncthreads();
+
+                // y pass: L = -(D + y divergence), the stage, the new speeds
+                for (int64_t tile = 0; tile < ylines * yseg; ++tile) {
+                    const int64_t l0 = (tile / yseg) * YTX, g0 = (tile % yseg) * YTN;
+                    err |= stage_tile2<1, YTX, YTN, NC>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+                    __syncthreads();
+                    err |= tile_fluxes2<1, YTX, YTN, NC, PREC>(P, l0, g0, s_al[1], A.gamma, A.W, s_u, s_f,
+                                                                s_v, s_sr, s_H, s_F);
+                    __syncthreads();
+                    double lam[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    if (t < YTN * YTX) {
+                        const int it = t / YTX, cl = t % YTX;
+                        const int64_t g = g0 + it, l = l0 + cl;
+                        if (l < P.nx && g < P.ny) {
+                            const int64_t idx = P.off + g * P.nx + l;
+                            double un[M];
+#pragma unroll
+                            for (int c = 0; c < M; ++c) {
+                                const int64_t o = c * total + idx;
+                                const double Dd = div_by_recip(s_F[c][t + YTX] - s_F[c][t], P.dy, P.rdy);
+                                const double L = -(A.D[o] + Dd);
+                                if (stage == 1)
+                                    un[c] = uin[o] + dt * L;
+                                else if (stage == 2)
+                                    un[c] = 0.75 * A.u[o] + 0.25 * uin[o] + (0.25 * dt) * L;
+                                else
+                                    un[c] = (1.0 / 3.0) * A.u[o] + (2.0 / 3.0) * uin[o] + ((2.0 / 3.0) * dt) * L;
+                            }
+#pragma unroll
+                            for (int c = 0; c < M; ++c) out[c * total + idx] = un[c];
+                            err |= euler_speeds<2>(un, A.gamma, lam);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const double w = wave_max(lam[k]);
+                        if ((t & 63) == 0) s_red[k][t >> 6] = w > s_red[k][t >> 6] ? w : s_red[k][t >> 6];
+                    }
+                    __syncthreads();                // the tile is reused by the next one
+                }
+                // the next stage reads what this one wrote
+                __threadfence();
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    double m = s_red[k][0];
+#pragma unroll
+                    for (int w = 1; w < kThreads / 64; ++w) m = s_red[k][w] > m ? s_red[k][w] : m;
+                    spd[k] = uniform(m);
+                }
+                __syncthreads();                    // s_red and s_al are rewritten by the next stage
+            }
+            if (err && first_bad == A.nsteps) first_bad = step;
+            time = uniform(time + dt);
+        }
+        if (t == 0) {
+            s_bad = 0;
+            s_first = A.nsteps;
+        }
+        __syncthreads();
+        if (err) atomicOr(&s_bad, err);
+        if (first_bad < A.nsteps) atomicMin(&s_first, (unsigned long long)first_bad);
+        __syncthreads();
+        if (t == 0) {
+            const int all_err = s_bad;
+            if (A.t_out) A.t_out[b] = time;
+            if (A.steps_out) A.steps_out[b] = (int64_t)s_first;
+            if (A.status_out)
+                A.status_out[b] = all_err & kErrNonfinite ? WT_ERR_NONFINITE
+                                                          : (all_err ? WT_ERR_NONPHYSICAL : WT_OK);
+            else if (all_err)
+                atomicOr(&A.st->err, all_err);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void reset_queue_kernel(int32_t *q)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
@@ -293,6 +567,44 @@ void free_batch(wt_ctx *c)
     c->b_cap = 0;
 }
 
+void free_batch2(wt_ctx *c)
+{
+    (void)hipFree(c->BD);
+    (void)hipFree(c->b2_tab);
+    (void)hipFree(c->b2_order);
+    (void)hipFree(c->b2_queue);
+    c->BD = nullptr;
+    c->b2_tab = nullptr;
+    c->b2_order = c->b2_queue = nullptr;
+    c->bdcap = 0;
+    c->b2_cap = 0;
+}
+
+// Capture (queue reset, kernel) into a graph on the context's capture stream.
+template <class Launch>
+wt_status capture_batch(wt_ctx *c, hipGraphExec_t *exec, int32_t *queue, Launch launch)
+{
+    if (!c->b_capture && hipStreamCreateWithFlags(&c->b_capture, hipStreamNonBlocking) != hipSuccess)
+        return WT_ERR_DEVICE;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->b_capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return WT_ERR_DEVICE;
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, c->b_capture, queue);
+    launch(c->b_capture);
+    const hipError_t le = hipGetLastError();
+    if (hipStreamEndCapture(c->b_capture, &g) != hipSuccess || le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return WT_ERR_DEVICE;
+    }
+    const hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        *exec = nullptr;
+        return WT_ERR_DEVICE;
+    }
+    return WT_OK;
+}
+
 }  // namespace
 
 namespace wt {
@@ -300,10 +612,13 @@ namespace wt {
 void release_batched(wt_ctx *c)
 {
     if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+    if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
     if (c->b_capture) (void)hipStreamDestroy(c->b_capture);
     c->b_graph = nullptr;
+    c->b2_graph = nullptr;
     c->b_capture = nullptr;
     free_batch(c);
+    free_batch2(c);
 }
 
 }  // namespace wt
@@ -351,8 +666,11 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     const size_t need = (size_t)total * 3;
     if (need > c->bcap || nprob > c->b_cap) {
         if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
+        // the stage buffers are shared with the 2D batches: both graphs go
         if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+        if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
         c->b_graph = nullptr;
+        c->b2_graph = nullptr;
         free_batch(c);
         if (hipMalloc(&c->B1, need * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->B2, need * sizeof(double)) != hipSuccess ||
@@ -418,7 +736,8 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     // graph of (queue reset, kernel), captured once per argument set
     uint64_t key = 0;
     for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)t_out,
-                       (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out, (uint64_t)nprob,
+                       (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out,
+                       (uint64_t)(uintptr_t)c->B1, (uint64_t)(uintptr_t)c->B2, (uint64_t)nprob,
                        (uint64_t)total, (uint64_t)nsteps, (uint64_t)P->precision, bits(P->gamma),
                        bits(P->eps), bits(P->alpha_R), bits(P->cfl), (uint64_t)grid})
         key = mix(key, v);
@@ -449,5 +768,154 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
         c->b_key = key;
     }
     if (hipGraphLaunch(c->b_graph, s) != hipSuccess) return WT_ERR_DEVICE;
+    return WT_OK;
+}
+
+extern "C" wt_status wenotheta_solve_batched_2d(wt_ctx *c, int64_t nprob, const int64_t *nx,
+                                                const int64_t *ny, const int64_t *offset,
+                                                const double *lo, const double *hi,
+                                                const int32_t *bc, const wt_params *P, double *u,
+                                                int64_t total, int64_t nsteps, double *t_out,
+                                                int32_t *status_out, int64_t *steps_out, void *stream)
+{
+    if (!c || !P || !u || !nx || !ny || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
+    if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 36 || nsteps < 0) return WT_ERR_ARG;
+    if (P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
+    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
+    if (P->gravity[0] != 0.0 || P->gravity[1] != 0.0 || P->gravity[2] != 0.0) return WT_ERR_UNSUPPORTED;
+    if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0) || !(P->gamma > 1.0))
+        return WT_ERR_ARG;
+    // problems must be valid and pairwise disjoint inside [0, total)
+    std::vector<Prob2> tab(nprob);
+    std::vector<int64_t> cells(nprob);
+    for (int64_t b = 0; b < nprob; ++b) {
+        if (nx[b] < 6 || ny[b] < 6 || nx[b] > total || ny[b] > total / nx[b] || offset[b] < 0) return WT_ERR_ARG;
+        cells[b] = nx[b] * ny[b];
+        if (offset[b] > total - cells[b]) return WT_ERR_ARG;
+        for (int d = 0; d < 2; ++d) {
+            const int32_t k = bc[2 * b + d];
+            if (!(hi[2 * b + d] > lo[2 * b + d]) ||
+                (k != WT_PERIODIC && k != WT_TRANSMISSIVE && k != WT_REFLECTIVE))
+                return WT_ERR_ARG;
+        }
+        Prob2 &q = tab[b];
+        q.nx = nx[b];
+        q.ny = ny[b];
+        q.off = offset[b];
+        q.dx = (hi[2 * b] - lo[2 * b]) / (double)nx[b];
+        q.rdx = 1.0 / q.dx;
+        q.dy = (hi[2 * b + 1] - lo[2 * b + 1]) / (double)ny[b];
+        q.rdy = 1.0 / q.dy;
+        q.bcx = bc[2 * b];
+        q.bcy = bc[2 * b + 1];
+    }
+    std::vector<int64_t> idx(nprob);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return offset[a] < offset[b]; });
+    for (int64_t k = 1; k < nprob; ++k)
+        if (offset[idx[k - 1]] + cells[idx[k - 1]] > offset[idx[k]]) return WT_ERR_ARG;
+    // work queue: largest problems first
+    std::vector<int32_t> order(nprob);
+    for (int64_t b = 0; b < nprob; ++b) order[b] = (int32_t)b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cells[a] > cells[b]; });
+
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    // workspace: stage buffers shared with the 1D batches, then D and the tables
+    const size_t need = (size_t)total * 4;
+    if (need > c->bcap) {
+        if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
+        if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+        if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
+        c->b_graph = nullptr;
+        c->b2_graph = nullptr;
+        (void)hipFree(c->B1);
+        (void)hipFree(c->B2);
+        c->B1 = c->B2 = nullptr;
+        c->bcap = 0;
+        if (hipMalloc(&c->B1, need * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->B2, need * sizeof(double)) != hipSuccess) {
+            (void)hipFree(c->B1);
+            (void)hipFree(c->B2);
+            c->B1 = c->B2 = nullptr;
+            (void)hipGetLastError();
+            return WT_ERR_NOMEM;
+        }
+        c->bcap = need;
+    }
+    if (need > c->bdcap || nprob > c->b2_cap) {
+        if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
+        if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
+        c->b2_graph = nullptr;
+        free_batch2(c);
+        if (hipMalloc(&c->BD, need * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->b2_tab, nprob * sizeof(Prob2)) != hipSuccess ||
+            hipMalloc(&c->b2_order, nprob * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->b2_queue, sizeof(int32_t)) != hipSuccess) {
+            free_batch2(c);
+            (void)hipGetLastError();
+            return WT_ERR_NOMEM;
+        }
+        c->bdcap = need;
+        c->b2_cap = nprob;
+    }
+    if (hipMemcpyAsync(c->b2_tab, tab.data(), nprob * sizeof(Prob2), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->b2_order, order.data(), nprob * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return WT_ERR_DEVICE;
+
+    Batch2Args A{};
+    A.u = u;
+    A.U1 = c->B1;
+    A.U2 = c->B2;
+    A.D = c->BD;
+    A.total = total;
+    A.prob = (const Prob2 *)c->b2_tab;
+    A.order = c->b2_order;
+    A.queue = c->b2_queue;
+    A.t_out = t_out;
+    A.status_out = status_out;
+    A.steps_out = steps_out;
+    A.st = c->st;
+    A.nprob = (int)nprob;
+    A.nsteps = nsteps;
+    A.gamma = P->gamma;
+    A.cfl = P->cfl;
+    A.W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
+
+    // persistent grid: as many workgroups as are resident at once, at most one per problem
+    int per_cu = 0, ncu = 0;
+    hipError_t e;
+    if (P->precision == WT_FP32_RECON)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched2d_kernel<1>, kThreads, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched2d_kernel<0>, kThreads, 0);
+    if (e != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                                                 c->device) != hipSuccess)
+        return WT_ERR_DEVICE;
+    int64_t grid = (int64_t)std::max(per_cu, 1) * std::max(ncu, 1);
+    if (grid > nprob) grid = nprob;
+
+    uint64_t key = 0;
+    for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)t_out,
+                       (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out,
+                       (uint64_t)(uintptr_t)c->B1, (uint64_t)(uintptr_t)c->B2,
+                       (uint64_t)(uintptr_t)c->BD, (uint64_t)nprob, (uint64_t)total, (uint64_t)nsteps,
+                       (uint64_t)P->precision, bits(P->gamma), bits(P->eps), bits(P->alpha_R),
+                       bits(P->cfl), (uint64_t)grid})
+        key = mix(key, v);
+    if (!c->b2_graph || c->b2_key != key) {
+        if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
+        c->b2_graph = nullptr;
+        const wt_status r = capture_batch(c, &c->b2_graph, c->b2_queue, [&](hipStream_t cs) {
+            if (P->precision == WT_FP32_RECON)
+                hipLaunchKernelGGL(batched2d_kernel<1>, dim3((unsigned)grid), dim3(kThreads), 0, cs, A);
+            else
+                hipLaunchKernelGGL(batched2d_kernel<0>, dim3((unsigned)grid), dim3(kThreads), 0, cs, A);
+        });
+        if (r != WT_OK) return r;
+        c->b2_key = key;
+    }
+    if (hipGraphLaunch(c->b2_graph, s) != hipSuccess) return WT_ERR_DEVICE;
     return WT_OK;
 }

@@ -50,6 +50,14 @@ struct wt_ctx {
     hipGraphExec_t b_graph = nullptr;
     hipStream_t b_capture = nullptr;
     uint64_t b_key = 0;
+    // batched 2D solves: x-divergence buffer, problem table, queue order, graph
+    double *BD = nullptr;
+    size_t bdcap = 0;           // doubles of BD
+    void *b2_tab = nullptr;
+    int32_t *b2_order = nullptr, *b2_queue = nullptr;
+    int64_t b2_cap = 0;         // problems the 2D tables hold
+    hipGraphExec_t b2_graph = nullptr;
+    uint64_t b2_key = 0;
     // graph of kGraphSteps solver steps and the arguments it was captured with
     hipGraphExec_t s_graph = nullptr;
     hipStream_t s_capture = nullptr;

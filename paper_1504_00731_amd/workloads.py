@@ -361,6 +361,59 @@ def batched_1d(seed: int = 0, nprob: int = 4096, nmin: int = 256, nmax: int = 16
                  bc=np.full(nprob, TRANSMISSIVE, dtype=np.int32), steps=steps)
 
 
+@dataclass
+class Batch2:
+    """Independent 2D Euler problems packed back to back: u has shape (4, sum nx_b ny_b);
+    problem b occupies columns offset[b] .. offset[b] + nx[b] ny[b] - 1 (x fastest) on
+    [lo[b, 0], hi[b, 0]] x [lo[b, 1], hi[b, 1]] with boundary conditions bc[b, 0..1]."""
+    u: np.ndarray
+    nx: np.ndarray
+    ny: np.ndarray
+    offset: np.ndarray
+    lo: np.ndarray
+    hi: np.ndarray
+    bc: np.ndarray
+    gamma: float = 1.4
+    cfl: float = 0.5
+    alpha_R: float = 50.0
+    steps: int = 100
+
+    @property
+    def nprob(self) -> int:
+        return int(self.nx.size)
+
+    def problem(self, b: int) -> np.ndarray:
+        """State of problem b as (4, ny, nx)."""
+        o, nx, ny = int(self.offset[b]), int(self.nx[b]), int(self.ny[b])
+        return self.u[:, o:o + nx * ny].reshape(4, ny, nx)
+
+
+def batched_2d(seed: int = 0, nprob: int = 4096, smin: int = 32, smax: int = 96,
+               steps: int = 100) -> Batch2:
+    """Batched independent 2D Euler problems on (0,1)^2, cell-centred, transmissive, each
+    with the four-quadrant Riemann data of the 2D workload at its own uneven grid size.
+    Draws per problem, in problem order: nx, ny = round(exp(U(ln smin, ln smax))) (x
+    first), then per quadrant 1..4 rho ~ U(0.1, 1.5), u ~ U(-1, 1), v ~ U(-1, 1),
+    p ~ U(0.03, 1.5); split at 0.5."""
+    rng = np.random.default_rng(seed)
+    nxs, nys, parts = [], [], []
+    for _ in range(nprob):
+        nx = max(int(round(np.exp(rng.uniform(np.log(smin), np.log(smax))))), 6)
+        ny = max(int(round(np.exp(rng.uniform(np.log(smin), np.log(smax))))), 6)
+        S = [[rng.uniform(0.1, 1.5), rng.uniform(-1.0, 1.0), rng.uniform(-1.0, 1.0),
+              rng.uniform(0.03, 1.5)] for _ in range(4)]
+        c = quadrants_2d(S, nx, ny=ny)
+        nxs.append(nx)
+        nys.append(ny)
+        parts.append(c.u.reshape(4, -1))
+    nx = np.asarray(nxs, dtype=np.int64)
+    ny = np.asarray(nys, dtype=np.int64)
+    offset = np.concatenate([[0], np.cumsum(nx * ny)[:-1]]).astype(np.int64)
+    return Batch2(u=np.ascontiguousarray(np.concatenate(parts, axis=1)), nx=nx, ny=ny,
+                  offset=offset, lo=np.zeros((nprob, 2)), hi=np.ones((nprob, 2)),
+                  bc=np.full((nprob, 2), TRANSMISSIVE, dtype=np.int32), steps=steps)
+
+
 # ---------------------------------------------------------------------------
 # Reflective walls and gravity (Sec. 4.2 TEST 5, Sec. 4.3 TESTs 6 and 7)
 # ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@ Prints ONE JSON line (rank 0):
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -70,13 +71,18 @@ def sweep_ops(ndim: int, n: tuple, d: int, final: bool) -> float:
     return interfaces * euler_interface_ops(ndim) + cells * euler_cell_ops(ndim, final)
 
 
+# Sources the grid sweep kernels are compiled from: the translation unit and the device
+# headers (not the batched kernels, the arithmetic probes or the host-side context).
+SWEEP_SOURCES = ("wenotheta.hip", "wt_bc.hpp", "wt_common.hpp", "wt_device.hpp", "wt_flux.hpp",
+                 "wt_physics.hpp", "wt_round.hpp", "wt_weno.hpp")
+
+
 def kernel_sources_hash() -> str:
-    """SHA-256 over the library's kernel sources and public header, in name order."""
+    """SHA-256 over the sources of the grid sweep kernels, in name order."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1504_00731_amd", "csrc")
-    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
-    for f in files + ["../../include/wenotheta.h"]:
+    for f in sorted(SWEEP_SOURCES):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -205,20 +211,27 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None)
 
 
 def run_batched(wt, ctx, B, precision, steps, warmup):
-    """The batched workload through the persistent entry point; returns the timed
-    launch's milliseconds, the final state and the per-problem status."""
+    """A batched workload (1D: Batch, 2D: Batch2) through its persistent entry point;
+    returns the timed launch's milliseconds, the final state and the per-problem status."""
     import torch
     u_init = torch.from_numpy(B.u).cuda()
     st = torch.empty(B.nprob, dtype=torch.int32, device="cuda")
     p = wt.Params(system=wt.WT_EULER, precision=precision, alpha_R=B.alpha_R, cfl=B.cfl)
+    if hasattr(B, "nx"):
+        def launch(u):
+            wt.wenotheta_solve_batched_2d(ctx, p, u, B.nx, B.ny, B.offset, B.lo, B.hi, B.bc, steps,
+                                          status_out=st)
+    else:
+        def launch(u):
+            wt.wenotheta_solve_batched(ctx, p, u, B.n, B.offset, B.lo, B.hi, B.bc, steps,
+                                       status_out=st)
     for _ in range(warmup):
         u = u_init.clone()
-        wt.wenotheta_solve_batched(ctx, p, u, B.n, B.offset, B.lo, B.hi, B.bc, steps, status_out=st)
+        launch(u)
         wt.wenotheta_sync(ctx)
     u = u_init.clone()
     stream = torch.cuda.current_stream()
-    ms, _ = timed(stream, lambda: wt.wenotheta_solve_batched(ctx, p, u, B.n, B.offset, B.lo, B.hi,
-                                                             B.bc, steps, status_out=st))
+    ms, _ = timed(stream, lambda: launch(u))
     wt.wenotheta_sync(ctx)
     return {"ms": ms, "u": u, "status": st.cpu().numpy()}
 
@@ -232,26 +245,48 @@ def batched_companions(wt, ctx, steps):
     FP32 target) under a 2^-24 perturbation of its initial data, about what rounding
     the data to FP32 does.  The same perturbation's effect on all problems is
     reported beside the FP32 difference."""
-    import numpy as np
     from paper_1504_00731_amd import workloads as W
     B = W.batched_1d(seed=0, steps=steps)
-    cells = int(B.n.sum())
-    print(f"[bench] batched {B.nprob} problems, {cells} cells, {steps} steps", file=sys.stderr,
-          flush=True)
+    out = compare_batched(wt, ctx, B, B.n, steps)
+    out["workload"] = (f"batched 1D Euler, {B.nprob} problems, N log-uniform in [256, 16384] "
+                       f"({int(B.n.sum())} cells), seeded piecewise-constant states, transmissive, "
+                       f"{steps} RK3 steps, CFL {B.cfl}")
+    return out
+
+
+def batched2d_companions(wt, ctx, steps):
+    """The same comparison for the batched 2D workload (independent 2D Euler problems of
+    uneven sizes in one persistent launch)."""
+    from paper_1504_00731_amd import workloads as W
+    B = W.batched_2d(seed=0, steps=steps)
+    out = compare_batched(wt, ctx, B, B.nx * B.ny, steps)
+    out["workload"] = (f"batched 2D Euler, {B.nprob} problems, nx and ny log-uniform in [32, 96] "
+                       f"({int((B.nx * B.ny).sum())} cells), seeded four-quadrant Riemann data, "
+                       f"transmissive, {steps} RK3 steps, CFL {B.cfl}")
+    return out
+
+
+def compare_batched(wt, ctx, B, cells_per_problem, steps):
+    """FP64 and FP32-reconstruction runs of a batch, timed, and their differences."""
+    import numpy as np
     import torch
+    from paper_1504_00731_amd import workloads as W
+    cells = int(cells_per_problem.sum())
+    m = B.u.shape[0]
+    print(f"[bench] batched {B.nprob} problems ({m} components), {cells} cells, {steps} steps",
+          file=sys.stderr, flush=True)
     r64 = run_batched(wt, ctx, B, wt.WT_FP64, steps, 1)
     r32 = run_batched(wt, ctx, B, wt.WT_FP32_RECON, steps, 1)
     # sensitivity of each problem at FP32 scale: the FP64 result's response to a 2^-24
     # perturbation of the initial data (untimed)
     rng = np.random.default_rng(1)
-    Bp = W.Batch(u=B.u * (1.0 + 2.0 ** -24 * rng.choice([-1.0, 1.0], size=B.u.shape)), n=B.n,
-                 offset=B.offset, lo=B.lo, hi=B.hi, bc=B.bc, steps=steps)
+    Bp = dataclasses.replace(B, u=B.u * (1.0 + 2.0 ** -24 * rng.choice([-1.0, 1.0], size=B.u.shape)))
     rp = run_batched(wt, ctx, Bp, wt.WT_FP64, steps, 0)
     ok = (r64["status"] == 0) & (r32["status"] == 0) & (rp["status"] == 0)
-    seg = torch.from_numpy(np.repeat(np.arange(B.nprob), B.n)).cuda()
+    seg = torch.from_numpy(np.repeat(np.arange(B.nprob), cells_per_problem)).cuda()
 
-    def per_problem(x):            # [3, total] -> [nprob, 3] sums per problem
-        out = torch.zeros(B.nprob, 3, dtype=torch.float64, device="cuda")
+    def per_problem(x):            # [m, total] -> [nprob, m] sums per problem
+        out = torch.zeros(B.nprob, m, dtype=torch.float64, device="cuda")
         return out.index_add_(0, seg, x.t())
 
     den = per_problem(r64["u"].abs())
@@ -273,16 +308,13 @@ def batched_companions(wt, ctx, steps):
     f32["ill_conditioned_problems"] = int(ill.sum())
     f32["fp64_response_to_2^-24_input_perturbation_all"] = [
         float(x) for x in (dpert[okt].sum(0) / den[okt].sum(0)).cpu()]
-    dmax = torch.zeros(B.nprob, 3, dtype=torch.float64, device="cuda").index_reduce_(
+    dmax = torch.zeros(B.nprob, m, dtype=torch.float64, device="cuda").index_reduce_(
         0, seg, (r32["u"] - r64["u"]).abs().t(), "amax")
-    bmax = torch.zeros(B.nprob, 3, dtype=torch.float64, device="cuda").index_reduce_(
+    bmax = torch.zeros(B.nprob, m, dtype=torch.float64, device="cuda").index_reduce_(
         0, seg, r64["u"].abs().t(), "amax")
     f32["linf_rel_vs_fp64_all"] = [float(x) for x in (dmax[okt].amax(0) / bmax[okt].amax(0)).cpu()]
     f32["conservation_drift_vs_fp64"] = [
         float(x) for x in (s32[okt].sum(0).abs() / den[okt].sum(0)).cpu()]
-    out["workload"] = (f"batched 1D Euler, {B.nprob} problems, N log-uniform in [256, 16384] "
-                       f"({cells} cells), seeded piecewise-constant states, transmissive, "
-                       f"{steps} RK3 steps, CFL {B.cfl}")
     return out
 
 
@@ -309,6 +341,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--n", type=int, default=None, help="points per dimension (default: full size)")
     ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--batched2d-steps", type=int, default=100)
     ap.add_argument("--tiles", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="y/z-sweep tile shape: tuned (auto) or forced variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -405,6 +438,7 @@ def main():
             comp["batched"] = batched_companions(wt, ctx, args.batched_steps)
             comp["batched"]["fp32_recon_over_plain_fp64"] = (comp["batched"]["fp32_recon"]["value"] /
                                                              value)
+            comp["batched_2d"] = batched2d_companions(wt, ctx, args.batched2d_steps)
         line["companions"] = comp
     del r
     if not args.no_cpu_baseline:

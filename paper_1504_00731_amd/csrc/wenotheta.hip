@@ -187,13 +187,14 @@ __global__ void copy_dt_kernel(const DevState *st, double *dst)
 // Sweep kernel
 // ---------------------------------------------------------------------------
 
-// Minimum waves per SIMD the register allocation must allow: 4 for the 1D
-// Euler sweeps, which then fit 128 VGPRs without spilling; the others are left
-// to the compiler (2D reaches 4 by itself, 3D stays at 3).
+// Minimum waves per SIMD the register allocation must allow: 4 for the 1D and
+// 2D Euler sweeps, which then fit 128 VGPRs (the 2D stage-finishing sweep with
+// a 12-byte spill outside its interface loop; at 3 waves it ran 12% slower);
+// 3D is left to the compiler and stays at 3.
 template <int SYS, int NDIM>
 constexpr int sweep_min_waves()
 {
-    return SYS == WT_EULER && NDIM == 1 ? 4 : 1;
+    return SYS == WT_EULER && NDIM <= 2 ? 4 : 1;
 }
 
 template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE, int PREC>

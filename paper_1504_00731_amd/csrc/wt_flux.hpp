@@ -17,9 +17,11 @@
 //
 // Register use.  The characteristic fields are visited by a loop the
 // compiler keeps rolled (the trip count is the same for every lane, so the
-// branches on the field index are uniform); one WENO-theta body serves both
-// split signs.  This keeps the live set to one field's 12 stencil values plus
-// the Roe basis and the flux accumulators, instead of all fields at once.
+// branches on the field index are uniform).  This keeps the live set to one
+// field's 12 split values plus the Roe basis and the flux accumulators,
+// instead of all fields at once.  The two reconstructions of a field (split
+// signs) are independent and are unrolled side by side, so the long division
+// chains of one overlap the other's.
 #pragma once
 #pragma clang fp contract(off)
 
@@ -133,7 +135,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, con
             vm[5 - k] = 0.5 * (w[k] - aq);
         }
         double h = 0.0;
-#pragma unroll 1
+#pragma unroll
         for (int sg = 0; sg < 2; ++sg) {
             double v[6];
 #pragma unroll
@@ -159,7 +161,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, con
             acc[1] = acc[1] + un * h;
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[2 + t] = acc[2 + t] + B.ut[t] * h;
-            acc[M - 1] = acc[M - 1] + B.q2 * h;
+            acc[M - 1] = acc[M - 1] + roe_q2<NDIM, DIR>(B) * h;
         } else {
 #pragma unroll
             for (int t = 0; t < NT; ++t)

@@ -72,7 +72,6 @@ struct RoeBasis {
     double ut[2];              // tangential Roe velocities
     double c;                  // Roe sound speed
     double H;                  // Roe total enthalpy
-    double q2;                 // |v~|^2 / 2
     // left eigenvectors
     double l0n0, l0n1, l0t[2], l0E;    // row 0 (u_n - c)
     double l1n0, l1n1, l1t[2], l1E;    // row 1 (u_n)
@@ -106,7 +105,6 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
     B.un = un;
     B.c = c;
     B.H = H;
-    B.q2 = q2;
     B.l0n0 = 0.5 * (b2 + uc);
     B.l0n1 = -0.5 * (b1 * un + ic);
     B.l1n0 = 1.0 - b2;
@@ -123,6 +121,26 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
     B.l1E = -b1;
     B.l2E = 0.5 * b1;
     return B;
+}
+
+// |v~|^2 / 2 of a Roe basis, recomputed from its velocities in canonical order
+// with the operations of roe_basis (so the same value) where the entropy
+// column of R needs it.  The velocities first pass through an empty asm, so
+// the compiler recomputes the value instead of keeping the one of roe_basis
+// alive across the whole field loop (which cost the 2D stage-finishing sweep
+// a register spill at 4 waves per SIMD).
+template <int NDIM, int DIR>
+WT_HD double roe_q2(const RoeBasis<NDIM> &B)
+{
+    double vt[3];
+    vt[DIR] = B.un;
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) vt[tangential_axis<DIR>(t)] = B.ut[t];
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+    for (int k = 0; k < NDIM; ++k) __asm__ volatile("" : "+v"(vt[k]));
+#endif
+    return 0.5 * sum_sq_xyz<NDIM>(vt);
 }
 
 }  // namespace wt

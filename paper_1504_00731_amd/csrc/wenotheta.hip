@@ -197,15 +197,29 @@ constexpr int sweep_min_waves()
     return SYS == WT_EULER && NDIM <= 2 ? 4 : 1;
 }
 
+// 1D Euler grids are short (65536 points fill only 257 one-interface-per-thread
+// workgroups, one wave per SIMD): there each interface's characteristic fields go
+// to separate threads, 85 interfaces per workgroup, which shortens each thread's
+// dependency chain threefold (3% faster at 65536 points in FP64; the FP32 form,
+// whose chains are shorter, ran 3% slower and keeps one interface per thread).
+template <int SYS, int NDIM, int PREC>
+constexpr bool split_fields()
+{
+    return SYS == WT_EULER && NDIM == 1 && PREC == WT_FP64;
+}
+
 template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE, int PREC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<SYS, NDIM>())))
 void sweep_kernel(SweepArgs A)
 {
-    static_assert(TX * (TN + 1) == kThreads, "one interface per thread");
     constexpr int M = Ncomp<SYS, NDIM>::value;
     constexpr int NC = (TN + 6) * TX;           // staged points of the tile
     constexpr bool EULER = SYS == SYS_EULER;
     constexpr int NV = SpeedLayout<SYS, NDIM>::NV;
+    // 1D Euler: the characteristic fields of an interface on separate threads
+    constexpr bool SPLIT = split_fields<SYS, NDIM, PREC>();
+    static_assert(SPLIT ? TX == 1 && M * (TN + 1) <= kThreads : TX * (TN + 1) == kThreads,
+                  "one interface (or, split, one field of an interface) per thread");
 
     __shared__ double s_u[M][NC];
     __shared__ double s_f[M][NC];                 // normal flux (Euler) / flux values (scalar)
@@ -213,6 +227,7 @@ void sweep_kernel(SweepArgs A)
     __shared__ double s_sr[EULER ? NC : 1];
     __shared__ double s_H[EULER ? NC : 1];
     __shared__ double s_F[M][kThreads];
+    __shared__ double s_h[SPLIT ? M : 1][SPLIT ? TN + 1 : 1];   // h_s per field and interface
 
     DevState *st = A.st;
     if (A.check_done && st->done) return;
@@ -308,8 +323,36 @@ void sweep_kernel(SweepArgs A)
     if (err) atomicOr(&st->err, err);
     __syncthreads();
 
+    // ---- 1D Euler: one characteristic field of an interface per thread ----
+    if constexpr (SPLIT) {
+        const int t = threadIdx.x;
+        const int it = t / M, f = t - it * M;   // interface between points it-1 and it; field
+        const bool valid = t < M * (TN + 1) && g0 + it <= nd;
+        const LdsStencil<M, NDIM, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, it};
+        RoeBasis<NDIM> B{};
+        if (valid) {
+            B = interface_basis<NDIM, DIR>(S, A.gamma);
+            const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.bc == WT_REFLECTIVE};
+            s_h[f][it] = euler_field_flux<NDIM, DIR, PREC>(S, B, f, al, A.W);
+            if (f == 0 && !B.ok) atomicOr(&st->err, kErrNonphysical);
+        }
+        __syncthreads();
+        // back-projection by the field-0 thread, fields in the order of the
+        // one-thread form (so the same sums)
+        if (valid && f == 0) {
+            double acc[M], F[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int fs = field_order(k);
+                backproject_field<NDIM, DIR>(B, fs, s_h[fs][it], acc);
+            }
+            store_interface_flux<NDIM, DIR>(acc, F);
+#pragma unroll
+            for (int q = 0; q < M; ++q) s_F[q][it] = F[q];
+        }
+    }
     // ---- one interface per thread: interface between points it-1 and it ----
-    {
+    else {
         const int t = threadIdx.x;
         const int it = t / TX, cx = t % TX;
         const bool valid = (DIR == 0 || x0 + cx < nx) && g0 + it <= nd;
@@ -355,14 +398,16 @@ void sweep_kernel(SweepArgs A)
                     else Lc[c] = -(A.D[o] + Dd);
                 }
             }
+            // The stage's input state of an owned cell is tile entry t + 3 TX (owned
+            // points are never mirror images), read from LDS instead of HBM.
             if constexpr (EULER && (MODE == MODE_LAST_RHS || MODE == MODE_LAST_STAGE)) {
                 // gravity source (Sec. 4.3, TEST 6) of the stage's input state
                 if (A.has_grav) {
-                    const double rho = A.uin[idx];
+                    const double rho = s_u[0][t + 3 * TX];
                     double e = 0.0;
 #pragma unroll
                     for (int d = 0; d < NDIM; ++d) {
-                        const double md = A.uin[(1 + d) * ncell + idx];
+                        const double md = s_u[1 + d][t + 3 * TX];
                         Lc[1 + d] = Lc[1 + d] + (-(A.grav[d] * rho));
                         e = d == 0 ? A.grav[0] * md : e + A.grav[d] * md;
                     }
@@ -379,21 +424,21 @@ void sweep_kernel(SweepArgs A)
 #pragma unroll
                     for (int c = 0; c < M; ++c) {
                         const int64_t o = c * ncell + idx;
-                        un[c] = A.uin[o] + dt * Lc[c];
+                        un[c] = s_u[c][t + 3 * TX] + dt * Lc[c];
                     }
                 } else if (A.stage == 2) {
                     const double cdt = 0.25 * dt;
 #pragma unroll
                     for (int c = 0; c < M; ++c) {
                         const int64_t o = c * ncell + idx;
-                        un[c] = 0.75 * A.u0[o] + 0.25 * A.uin[o] + cdt * Lc[c];
+                        un[c] = 0.75 * A.u0[o] + 0.25 * s_u[c][t + 3 * TX] + cdt * Lc[c];
                     }
                 } else {
                     const double cdt = (2.0 / 3.0) * dt;
 #pragma unroll
                     for (int c = 0; c < M; ++c) {
                         const int64_t o = c * ncell + idx;
-                        un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * A.uin[o] + cdt * Lc[c];
+                        un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * s_u[c][t + 3 * TX] + cdt * Lc[c];
                     }
                 }
 #pragma unroll
@@ -475,7 +520,8 @@ hipError_t launch_sweep(const SweepArgs &A, int tile, hipStream_t s)
 {
     if constexpr (!has_tile_variants<SYS, NDIM, DIR>()) {
         (void)tile;
-        constexpr int TX = DIR == 0 ? 1 : 8, TN = DIR == 0 ? 255 : 31;
+        constexpr int TX = DIR == 0 ? 1 : 8;
+        constexpr int TN = DIR != 0 ? 31 : (split_fields<SYS, NDIM, PREC>() ? kThreads / Ncomp<SYS, NDIM>::value - 1 : 255);
         return launch_tile<SYS, NDIM, DIR, MODE, PREC, TX, TN>(A, s);
     } else {
         switch (tile) {

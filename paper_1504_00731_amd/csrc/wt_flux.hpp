@@ -56,6 +56,143 @@ WT_HD void euler_normal_flux(const double *uc, const double *vel, double p, doub
     f[NDIM + 1] = un * (uc[NDIM + 1] + p);
 }
 
+// Characteristic field s of an interface (0: u_n - c, 1: u_n, 2: u_n + c, 3..:
+// shear): the stencil projected onto row s of L (q = L u, w = L f), split with the
+// field's Lax-Friedrichs speed a = al(s), v+- = (w +- a q) / 2, and reconstructed,
+// sign +1 on j-2..j+3 and sign -1 on the mirrored stencil; returns h+ + h-.
+template <int NDIM, int DIR, int PREC, class Acc, class Alpha>
+WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, const Alpha &al,
+                              const WenoConst &W)
+{
+    constexpr int NT = NDIM - 1;
+    WT_RELOAD();                                // stencil values come from memory per field
+    // row s of L in permuted order
+    double ln0, ln1, lE, lt[NT > 0 ? NT : 1];
+    int shear = -1;
+    if (s == 0) {
+        ln0 = B.l0n0; ln1 = B.l0n1; lE = B.l0E;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) lt[t] = B.l0t[t];
+    } else if (s == 1) {
+        ln0 = B.l1n0; ln1 = B.l1n1; lE = B.l1E;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) lt[t] = B.l1t[t];
+    } else if (s == 2) {
+        ln0 = B.l2n0; ln1 = B.l2n1; lE = B.l2E;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) lt[t] = B.l2t[t];
+    } else {
+        shear = s - 3;
+        ln0 = -(shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]); ln1 = 0.0; lE = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) lt[t] = 0.0;
+    }
+    const double a = al(s);
+    double w[6], q[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (shear < 0) {
+            double qq = ln0 * S.U(k, 0) + ln1 * S.U(k, 1 + DIR);
+            double ww = ln0 * S.f(k, 0) + ln1 * S.f(k, 1 + DIR);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                qq = qq + lt[t] * S.U(k, 1 + tangential_axis<DIR>(t));
+                ww = ww + lt[t] * S.f(k, 1 + tangential_axis<DIR>(t));
+            }
+            q[k] = qq + lE * S.U(k, NDIM + 1);
+            w[k] = ww + lE * S.f(k, NDIM + 1);
+        } else {
+            // shear row (-u_t, 0, .., 1, .., 0): only two non-zero entries
+            const int ax = 1 + (shear == 0 ? tangential_axis<DIR>(0) : tangential_axis<DIR>(NT - 1));
+            q[k] = ln0 * S.U(k, 0) + S.U(k, ax);
+            w[k] = ln0 * S.f(k, 0) + S.f(k, ax);
+        }
+    }
+    double vp[6], vm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double aq = a * q[k];
+        vp[k] = 0.5 * (w[k] + aq);
+        vm[5 - k] = 0.5 * (w[k] - aq);
+    }
+    double h = 0.0;
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+        double v[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = sg == 0 ? vp[k] : vm[k];
+        const double r = reconstruct<PREC>(v, W);
+        h = sg == 0 ? r : h + r;
+    }
+    return h;
+}
+
+// Field visiting order of the back-projection: 0, 2, 1, 3, 4, so that every
+// component sums R h as (R_0 h_0 + R_2 h_2) + R_1 h_1 + R_3 h_3 + R_4 h_4.
+WT_HD constexpr int field_order(int it)
+{
+    return it == 1 ? 2 : (it == 2 ? 1 : it);
+}
+
+// Add column s of R times h_s to the accumulators (permuted order rho, m_n,
+// m_t.., E); the first field in field_order initialises them.
+template <int NDIM, int DIR>
+WT_HD void backproject_field(const RoeBasis<NDIM> &B, int s, double h, double *acc)
+{
+    constexpr int M = NDIM + 2, NT = NDIM - 1;
+    const double un = B.un, c = B.c;
+    if (s == 0) {
+        acc[0] = h;
+        acc[1] = (un - c) * h;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[2 + t] = B.ut[t] * h;
+        acc[M - 1] = (B.H - un * c) * h;
+    } else if (s == 2) {
+        acc[0] = acc[0] + h;
+        acc[1] = acc[1] + (un + c) * h;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[2 + t] = acc[2 + t] + B.ut[t] * h;
+        acc[M - 1] = acc[M - 1] + (B.H + un * c) * h;
+    } else if (s == 1) {
+        acc[0] = acc[0] + h;
+        acc[1] = acc[1] + un * h;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[2 + t] = acc[2 + t] + B.ut[t] * h;
+        acc[M - 1] = acc[M - 1] + roe_q2<NDIM, DIR>(B) * h;
+    } else {
+        const int shear = s - 3;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (t == shear) acc[2 + t] = acc[2 + t] + h;
+        acc[M - 1] = acc[M - 1] + (shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]) * h;
+    }
+}
+
+// The accumulators in canonical component order.
+template <int NDIM, int DIR>
+WT_HD void store_interface_flux(const double *acc, double *F)
+{
+    constexpr int M = NDIM + 2, NT = NDIM - 1;
+    F[0] = acc[0];
+    F[1 + DIR] = acc[1];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) F[1 + tangential_axis<DIR>(t)] = acc[2 + t];
+    F[M - 1] = acc[M - 1];
+}
+
+// Roe basis of the interface between stencil points 2 and 3.
+template <int NDIM, int DIR, class Acc>
+WT_HD RoeBasis<NDIM> interface_basis(const Acc &S, double gamma)
+{
+    double velL[NDIM], velR[NDIM];
+#pragma unroll
+    for (int k = 0; k < NDIM; ++k) {
+        velL[k] = S.v(2, k);
+        velR[k] = S.v(3, k);
+    }
+    return roe_basis<NDIM, DIR>(S.sr(2), velL, S.H(2), S.sr(3), velR, S.H(3), gamma);
+}
+
 // al(s): Lax-Friedrichs speed of field s for this direction.  F receives the
 // flux in canonical component order.  Returns false if the Roe sound speed is
 // not real.
@@ -64,116 +201,15 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, con
                                 double *F)
 {
     constexpr int M = NDIM + 2;
-    constexpr int NT = NDIM - 1;
-    double velL[NDIM], velR[NDIM];
-#pragma unroll
-    for (int k = 0; k < NDIM; ++k) {
-        velL[k] = S.v(2, k);
-        velR[k] = S.v(3, k);
-    }
-    const RoeBasis<NDIM> B =
-        roe_basis<NDIM, DIR>(S.sr(2), velL, S.H(2), S.sr(3), velR, S.H(3), gamma);
-    const double un = B.un, c = B.c;
-
-    // Back-projection accumulators in permuted order (rho, m_n, m_t.., E).
-    // Fields are visited in the order 0, 2, 1, 3, 4 so that every component
-    // sums R h as (R_0 h_0 + R_2 h_2) + R_1 h_1 + R_3 h_3 + R_4 h_4.
+    const RoeBasis<NDIM> B = interface_basis<NDIM, DIR>(S, gamma);
     double acc[M];
 #pragma unroll 1
     for (int it = 0; it < M; ++it) {
-        WT_RELOAD();                            // stencil values come from memory per field
-        const int s = it == 1 ? 2 : (it == 2 ? 1 : it);
-        // row s of L in permuted order
-        double ln0, ln1, lE, lt[NT > 0 ? NT : 1];
-        int shear = -1;
-        if (s == 0) {
-            ln0 = B.l0n0; ln1 = B.l0n1; lE = B.l0E;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) lt[t] = B.l0t[t];
-        } else if (s == 1) {
-            ln0 = B.l1n0; ln1 = B.l1n1; lE = B.l1E;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) lt[t] = B.l1t[t];
-        } else if (s == 2) {
-            ln0 = B.l2n0; ln1 = B.l2n1; lE = B.l2E;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) lt[t] = B.l2t[t];
-        } else {
-            shear = s - 3;
-            ln0 = -(shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]); ln1 = 0.0; lE = 0.0;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) lt[t] = 0.0;
-        }
-        const double a = al(s);
-        double w[6], q[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            if (shear < 0) {
-                double qq = ln0 * S.U(k, 0) + ln1 * S.U(k, 1 + DIR);
-                double ww = ln0 * S.f(k, 0) + ln1 * S.f(k, 1 + DIR);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    qq = qq + lt[t] * S.U(k, 1 + tangential_axis<DIR>(t));
-                    ww = ww + lt[t] * S.f(k, 1 + tangential_axis<DIR>(t));
-                }
-                q[k] = qq + lE * S.U(k, NDIM + 1);
-                w[k] = ww + lE * S.f(k, NDIM + 1);
-            } else {
-                // shear row (-u_t, 0, .., 1, .., 0): only two non-zero entries
-                const int ax = 1 + (shear == 0 ? tangential_axis<DIR>(0) : tangential_axis<DIR>(NT - 1));
-                q[k] = ln0 * S.U(k, 0) + S.U(k, ax);
-                w[k] = ln0 * S.f(k, 0) + S.f(k, ax);
-            }
-        }
-        // split v+- = (w +- a q) / 2 at each point, then reconstruct: sign +1 on
-        // j-2..j+3, sign -1 on the mirrored stencil
-        double vp[6], vm[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const double aq = a * q[k];
-            vp[k] = 0.5 * (w[k] + aq);
-            vm[5 - k] = 0.5 * (w[k] - aq);
-        }
-        double h = 0.0;
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-            double v[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) v[k] = sg == 0 ? vp[k] : vm[k];
-            const double r = reconstruct<PREC>(v, W);
-            h = sg == 0 ? r : h + r;
-        }
-        // accumulate R h: column s of R in permuted order
-        if (s == 0) {
-            acc[0] = h;
-            acc[1] = (un - c) * h;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[2 + t] = B.ut[t] * h;
-            acc[M - 1] = (B.H - un * c) * h;
-        } else if (s == 2) {
-            acc[0] = acc[0] + h;
-            acc[1] = acc[1] + (un + c) * h;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[2 + t] = acc[2 + t] + B.ut[t] * h;
-            acc[M - 1] = acc[M - 1] + (B.H + un * c) * h;
-        } else if (s == 1) {
-            acc[0] = acc[0] + h;
-            acc[1] = acc[1] + un * h;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[2 + t] = acc[2 + t] + B.ut[t] * h;
-            acc[M - 1] = acc[M - 1] + roe_q2<NDIM, DIR>(B) * h;
-        } else {
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-                if (t == shear) acc[2 + t] = acc[2 + t] + h;
-            acc[M - 1] = acc[M - 1] + (shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]) * h;
-        }
+        const int s = field_order(it);
+        const double h = euler_field_flux<NDIM, DIR, PREC>(S, B, s, al, W);
+        backproject_field<NDIM, DIR>(B, s, h, acc);
     }
-    F[0] = acc[0];
-    F[1 + DIR] = acc[1];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) F[1 + tangential_axis<DIR>(t)] = acc[2 + t];
-    F[M - 1] = acc[M - 1];
+    store_interface_flux<NDIM, DIR>(acc, F);
     return B.ok;
 }
 

@@ -22,6 +22,7 @@ namespace wt {
 
 WT_HD int64_t map_index(int64_t i, int64_t n, int bc)
 {
+    if (i >= 0 && i < n) return i;              // a point of the line (64-bit % only for ghosts)
     if (bc == WT_PERIODIC) {
         i %= n;
         return i < 0 ? i + n : i;
@@ -36,7 +37,7 @@ WT_HD int64_t map_index(int64_t i, int64_t n, int bc)
 
 WT_HD bool reflected(int64_t i, int64_t n, int bc)
 {
-    if (bc != WT_REFLECTIVE) return false;
+    if (bc != WT_REFLECTIVE || (i >= 0 && i < n)) return false;
     int64_t k = i % (2 * n);
     if (k < 0) k += 2 * n;
     return k >= n;

@@ -213,6 +213,34 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
                                      double *u, int64_t total, int64_t nsteps, double *t_out,
                                      int32_t *status_out, int64_t *steps_out, void *stream);
 
+/* Tile variants of the batched kernels, chosen by timing (the batch form of
+ * wenotheta_tune).  Each batched kernel has two variants that compute the same
+ * operations, so results are bit-identical whichever runs:
+ *   1D batches: workgroups of 256 threads sweeping segments of 255 points (0,
+ *               default) or of 128 threads and 127 points (1);
+ *   2D batches: the x pass in tiles of 4 rows x 63 points (0, default) or of
+ *               8 rows x 31 points (1); the y pass in 8 columns x 31 points.
+ * wenotheta_tune_batched / wenotheta_tune_batched_2d take the arguments of the
+ * corresponding solve (u DEVICE, only read: each variant runs probe_steps >= 1
+ * steps on a scratch copy, 3 rounds interleaved, the best launch kept), keep
+ * the fastest variant in the context for batches with the same sizes, layout
+ * and precision (the default stays unless another is more than 2% faster) and
+ * write it to *variant_out (HOST, optional).  Synchronises the stream;
+ * allocates and frees its scratch copy.
+ * wenotheta_set_batched_tiles forces variant (0 or 1) for every later batch of
+ * ndim (1 or 2) dimensions on this context. */
+wt_status wenotheta_tune_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
+                                 const int64_t *offset, const double *lo, const double *hi,
+                                 const int32_t *bc, const wt_params *prm, const double *u,
+                                 int64_t total, int64_t probe_steps, int32_t *variant_out,
+                                 void *stream);
+wt_status wenotheta_tune_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *nx,
+                                    const int64_t *ny, const int64_t *offset, const double *lo,
+                                    const double *hi, const int32_t *bc, const wt_params *prm,
+                                    const double *u, int64_t total, int64_t probe_steps,
+                                    int32_t *variant_out, void *stream);
+wt_status wenotheta_set_batched_tiles(wt_ctx *ctx, int32_t ndim, int32_t variant);
+
 /* Tile shapes of the sweeps (dimension-by-dimension scheme of Sec. 4.3: one
  * 1D operator per direction).  The y and z sweeps of the 2D/3D Euler system
  * run in one of four tile shapes, TX consecutive x-columns by TN points along

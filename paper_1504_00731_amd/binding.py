@@ -24,7 +24,8 @@ WT_FP64, WT_FP32_RECON = 0, 1
 EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
             "wenotheta_rhs", "wenotheta_step", "wenotheta_solve", "wenotheta_sync",
             "wenotheta_profile", "wenotheta_profile_read", "wenotheta_solve_batched",
-            "wenotheta_solve_batched_2d", "wenotheta_tune", "wenotheta_set_tiles")
+            "wenotheta_solve_batched_2d", "wenotheta_tune_batched", "wenotheta_tune_batched_2d",
+            "wenotheta_set_batched_tiles", "wenotheta_tune", "wenotheta_set_tiles")
 PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
                  "sweep_z_final")
 
@@ -84,6 +85,11 @@ def _lib():
         L.wenotheta_solve_batched_2d.argtypes = [vp, ctypes.c_int64, i64p, i64p, i64p, dp, dp, i32p,
                                                  P, vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp,
                                                  vp]
+        L.wenotheta_tune_batched.argtypes = [vp, ctypes.c_int64, i64p, i64p, dp, dp, i32p, P, vp,
+                                             ctypes.c_int64, ctypes.c_int64, i32p, vp]
+        L.wenotheta_tune_batched_2d.argtypes = [vp, ctypes.c_int64, i64p, i64p, i64p, dp, dp, i32p,
+                                                P, vp, ctypes.c_int64, ctypes.c_int64, i32p, vp]
+        L.wenotheta_set_batched_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.wenotheta_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
         i32p3 = ctypes.POINTER(ctypes.c_int32)
         L.wenotheta_tune.argtypes = [vp, G, P, vp, i32p3, vp]
@@ -343,6 +349,68 @@ def wenotheta_solve_batched_2d(ctx: Context, params: Params, u, nx, ny, offset, 
         _dev_int_ptr(steps_out, "steps_out", nprob, 64), _stream_ptr(stream)),
         "wenotheta_solve_batched_2d")
     return u
+
+
+def _batch_tables_1d(n, offset, lo, hi, bc):
+    import numpy as np
+    t = (np.ascontiguousarray(n, dtype=np.int64), np.ascontiguousarray(offset, dtype=np.int64),
+         np.ascontiguousarray(lo, dtype=np.float64), np.ascontiguousarray(hi, dtype=np.float64),
+         np.ascontiguousarray(bc, dtype=np.int32))
+    if not all(a.size == t[0].size for a in t):
+        raise ValueError("problem tables must have one entry per problem")
+    return t
+
+
+def wenotheta_tune_batched(ctx: Context, params: Params, u, n, offset, lo, hi, bc, probe_steps=2,
+                           stream=None) -> int:
+    """Times the tile variants of the 1D batched kernel on a scratch copy of u and keeps
+    the fastest in the context for batches of these sizes; returns it."""
+    n, offset, lo, hi, bc = _batch_tables_1d(n, offset, lo, hi, bc)
+    if u.dim() != 2 or u.shape[0] != 3:
+        raise ValueError("u must have shape (3, total)")
+    i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    v = ctypes.c_int32(-1)
+    _check(_lib().wenotheta_tune_batched(
+        ctx.handle, int(n.size), n.ctypes.data_as(i64p), offset.ctypes.data_as(i64p),
+        lo.ctypes.data_as(dp), hi.ctypes.data_as(dp), bc.ctypes.data_as(i32p),
+        ctypes.byref(params.c_struct()), _dev_ptr(u, "u"), int(u.shape[1]), int(probe_steps),
+        ctypes.byref(v), _stream_ptr(stream)), "wenotheta_tune_batched")
+    return v.value
+
+
+def wenotheta_tune_batched_2d(ctx: Context, params: Params, u, nx, ny, offset, lo, hi, bc,
+                              probe_steps=2, stream=None) -> int:
+    """Times the tile variants of the 2D batched kernel on a scratch copy of u and keeps
+    the fastest in the context for batches of these sizes; returns it."""
+    import numpy as np
+    nx = np.ascontiguousarray(nx, dtype=np.int64)
+    ny = np.ascontiguousarray(ny, dtype=np.int64)
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    bc = np.ascontiguousarray(bc, dtype=np.int32)
+    nprob = int(nx.size)
+    if not (ny.size == offset.size == nprob and lo.shape == hi.shape == bc.shape == (nprob, 2)):
+        raise ValueError("problem tables must have one entry (two for lo, hi, bc) per problem")
+    if u.dim() != 2 or u.shape[0] != 4:
+        raise ValueError("u must have shape (4, total)")
+    i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    v = ctypes.c_int32(-1)
+    _check(_lib().wenotheta_tune_batched_2d(
+        ctx.handle, nprob, nx.ctypes.data_as(i64p), ny.ctypes.data_as(i64p),
+        offset.ctypes.data_as(i64p), lo.ctypes.data_as(dp), hi.ctypes.data_as(dp),
+        bc.ctypes.data_as(i32p), ctypes.byref(params.c_struct()), _dev_ptr(u, "u"),
+        int(u.shape[1]), int(probe_steps), ctypes.byref(v), _stream_ptr(stream)),
+        "wenotheta_tune_batched_2d")
+    return v.value
+
+
+def wenotheta_set_batched_tiles(ctx: Context, ndim: int, variant: int):
+    """Forces the tile variant of every later batch of ndim (1 or 2) dimensions."""
+    _check(_lib().wenotheta_set_batched_tiles(ctx.handle, int(ndim), int(variant)),
+           "wenotheta_set_batched_tiles")
 
 
 def loaded_library_path() -> str:

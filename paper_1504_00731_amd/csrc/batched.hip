@@ -54,9 +54,9 @@ struct BatchArgs {
     WenoConst W;
 };
 
-// Block-wide max of K per-thread values; every thread gets the result.
-template <int K>
-__device__ __forceinline__ void block_max(double (&v)[K], double (*red)[kThreads / 64])
+// Block-wide max of K per-thread values over NW waves; every thread gets the result.
+template <int K, int NW>
+__device__ __forceinline__ void block_max(double (&v)[K], double (*red)[NW])
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -69,7 +69,7 @@ __device__ __forceinline__ void block_max(double (&v)[K], double (*red)[kThreads
     for (int k = 0; k < K; ++k) {
         double m = red[k][0];
 #pragma unroll
-        for (int w = 1; w < kThreads / 64; ++w) m = red[k][w] > m ? red[k][w] : m;
+        for (int w = 1; w < NW; ++w) m = red[k][w] > m ? red[k][w] : m;
         v[k] = m;
     }
     __syncthreads();
@@ -93,17 +93,20 @@ struct LdsSpeeds {
 // The FP64 form is held to 3 waves per SIMD (at most 168 VGPRs): left to
 // itself it takes 174, and it fits 164 without spilling.  The FP32 form
 // reaches 3 waves by itself.
-template <int PREC>
-__global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(BatchArgs A)
+// Workgroups of TPB threads sweep a problem in segments of TPB - 1 points (the
+// tile variants the batch tuner chooses between: 256 and 128 threads).
+template <int PREC, int TPB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(PREC == 0 ? 3 : 1)))
+void batched_kernel(BatchArgs A)
 {
-    constexpr int M = 3, TN = kThreads - 1, NC = TN + 6;
+    constexpr int M = 3, TN = TPB - 1, NC = TN + 6, NW = TPB / 64;
     __shared__ double s_u[M][NC];
     __shared__ double s_f[M][NC];
     __shared__ double s_v[1][NC];
     __shared__ double s_sr[NC];
     __shared__ double s_H[NC];
-    __shared__ double s_F[M][kThreads];
-    __shared__ double s_red[3][kThreads / 64];
+    __shared__ double s_F[M][TPB];
+    __shared__ double s_red[3][NW];
     __shared__ double s_al[3];
     __shared__ int s_job;
     __shared__ int s_bad;
@@ -132,14 +135,14 @@ __global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(Ba
 
         // speeds of the initial state
         double spd[3] = {0.0, 0.0, 0.0};
-        for (int64_t i = t; i < n; i += kThreads) {
+        for (int64_t i = t; i < n; i += TPB) {
             double uc[3] = {A.u[off + i], A.u[total + off + i], A.u[2 * total + off + i]};
             double lam[3];
             err |= euler_speeds<1>(uc, A.gamma, lam);
 #pragma unroll
             for (int k = 0; k < 3; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
         }
-        block_max<3>(spd, s_red);
+        block_max<3, NW>(spd, s_red);
 #pragma unroll
         for (int k = 0; k < 3; ++k) spd[k] = uniform(spd[k]);
 
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(Ba
                 for (int64_t seg = 0; seg < nseg; ++seg) {
                     const int64_t g0 = seg * TN;
                     // stage the segment and its halos
-                    for (int i = t; i < NC; i += kThreads) {
+                    for (int i = t; i < NC; i += TPB) {
                         const int64_t g = map_index(g0 - 3 + i, n, bc);
                         double uc[3];
 #pragma unroll
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kThreads, PREC == 0 ? 3 : 1) void batched_kernel(Ba
                 for (int k = 0; k < 3; ++k) {
                     double m = s_red[k][0];
 #pragma unroll
-                    for (int w = 1; w < kThreads / 64; ++w) m = s_red[k][w] > m ? s_red[k][w] : m;
+                    for (int w = 1; w < NW; ++w) m = s_red[k][w] > m ? s_red[k][w] : m;
                     spd[k] = uniform(m);
                 }
                 __syncthreads();                    // s_red is cleared again by the next stage
@@ -354,10 +357,13 @@ __device__ __forceinline__ int tile_fluxes2(const Prob2 &P, int64_t l0, int64_t 
     return err;
 }
 
-template <int PREC>
-__global__ __launch_bounds__(kThreads, 3) void batched2d_kernel(Batch2Args A)
+// Tile variants the batch tuner chooses between: the x pass in tiles of 4 rows x 63
+// points (XV = 0) or 8 rows x 31 points (XV = 1); the y pass in 8 columns x 31.
+template <int PREC, int XV>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+void batched2d_kernel(Batch2Args A)
 {
-    constexpr int M = 4, XTX = 4, XTN = 63, YTX = 8, YTN = 31;
+    constexpr int M = 4, XTX = XV == 0 ? 4 : 8, XTN = XV == 0 ? 63 : 31, YTX = 8, YTN = 31;
     constexpr int NC = (YTN + 6) * YTX > (XTN + 6) * XTX ? (YTN + 6) * YTX : (XTN + 6) * XTX;
     static_assert(XTX * (XTN + 1) == kThreads && YTX * (YTN + 1) == kThreads, "one interface per thread");
     __shared__ double s_u[M][NC];
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(kThreads, 3) void batched2d_kernel(Batch2Args A)
 #pragma unroll
             for (int k = 0; k < 6; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
         }
-        block_max<6>(spd, s_red);
+        block_max<6, kThreads / 64>(spd, s_red);
 #pragma unroll
         for (int k = 0; k < 6; ++k) spd[k] = uniform(spd[k]);
 
@@ -580,31 +586,6 @@ void free_batch2(wt_ctx *c)
     c->b2_cap = 0;
 }
 
-// Capture (queue reset, kernel) into a graph on the context's capture stream.
-template <class Launch>
-wt_status capture_batch(wt_ctx *c, hipGraphExec_t *exec, int32_t *queue, Launch launch)
-{
-    if (!c->b_capture && hipStreamCreateWithFlags(&c->b_capture, hipStreamNonBlocking) != hipSuccess)
-        return WT_ERR_DEVICE;
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(c->b_capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return WT_ERR_DEVICE;
-    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, c->b_capture, queue);
-    launch(c->b_capture);
-    const hipError_t le = hipGetLastError();
-    if (hipStreamEndCapture(c->b_capture, &g) != hipSuccess || le != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return WT_ERR_DEVICE;
-    }
-    const hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        *exec = nullptr;
-        return WT_ERR_DEVICE;
-    }
-    return WT_OK;
-}
-
 }  // namespace
 
 namespace wt {
@@ -623,12 +604,47 @@ void release_batched(wt_ctx *c)
 
 }  // namespace wt
 
-extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int64_t *n,
-                                             const int64_t *offset, const double *lo,
-                                             const double *hi, const int32_t *bc,
-                                             const wt_params *P, double *u, int64_t total,
-                                             int64_t nsteps, double *t_out, int32_t *status_out,
-                                             int64_t *steps_out, void *stream)
+namespace {
+
+constexpr int kBatchVariants = 2;     // tile variants of each batched kernel
+constexpr uint64_t kAnyBatch = ~0ull; // variant key of wenotheta_set_batched_tiles: every batch
+
+// The variant of a batch: the tuned one for its signature, a forced one, else 0.
+int batch_variant(int var, uint64_t key, uint64_t sig)
+{
+    return key == sig || key == kAnyBatch ? var : 0;
+}
+
+// Signature of a batch for the tuned-variant lookup: sizes, layout, precision.
+uint64_t batch_signature(int ndim, int64_t nprob, const int64_t *n0, const int64_t *n1,
+                         int64_t total, int precision)
+{
+    uint64_t h = mix(mix(mix((uint64_t)ndim, (uint64_t)nprob), (uint64_t)total), (uint64_t)precision);
+    for (int64_t b = 0; b < nprob; ++b) {
+        h = mix(h, (uint64_t)n0[b]);
+        if (n1) h = mix(h, (uint64_t)n1[b]);
+    }
+    return h;
+}
+
+// Persistent grid: as many workgroups as are resident at once, at most one per problem.
+template <class Kernel>
+wt_status persistent_grid(wt_ctx *c, Kernel k, int threads, int64_t nprob, int64_t *grid)
+{
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+        return WT_ERR_DEVICE;
+    *grid = std::min<int64_t>((int64_t)std::max(per_cu, 1) * std::max(ncu, 1), nprob);
+    return WT_OK;
+}
+
+// ---- 1D batches ----
+
+// Validate a 1D batch, upload its tables and size the workspace; fills A.
+wt_status prepare_1d(wt_ctx *c, int64_t nprob, const int64_t *n, const int64_t *offset,
+                     const double *lo, const double *hi, const int32_t *bc, const wt_params *P,
+                     double *u, int64_t total, int64_t nsteps, hipStream_t s, BatchArgs *A)
 {
     if (!c || !P || !u || !n || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 6 || nsteps < 0) return WT_ERR_ARG;
@@ -641,7 +657,7 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     std::vector<int64_t> idx(nprob);
     std::iota(idx.begin(), idx.end(), 0);
     for (int64_t b = 0; b < nprob; ++b) {
-        if (n[b] < 6 || offset[b] < 0 || offset[b] + n[b] > total) return WT_ERR_ARG;
+        if (n[b] < 6 || offset[b] < 0 || offset[b] > total - n[b]) return WT_ERR_ARG;
         if (!(hi[b] > lo[b]) ||
             (bc[b] != WT_PERIODIC && bc[b] != WT_TRANSMISSIVE && bc[b] != WT_REFLECTIVE))
             return WT_ERR_ARG;
@@ -661,7 +677,6 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     std::vector<int32_t> bcv(bc, bc + nprob);
 
     if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
-    hipStream_t s = (hipStream_t)stream;
     // workspace (allocated on first use of a size)
     const size_t need = (size_t)total * 3;
     if (need > c->bcap || nprob > c->b_cap) {
@@ -698,85 +713,58 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
         hipStreamSynchronize(s) != hipSuccess)
         return WT_ERR_DEVICE;
 
-    BatchArgs A{};
-    A.u = u;
-    A.U1 = c->B1;
-    A.U2 = c->B2;
-    A.total = total;
-    A.n = c->b_n;
-    A.off = c->b_off;
-    A.dx = c->b_dx;
-    A.rdx = c->b_rdx;
-    A.bc = c->b_bc;
-    A.order = c->b_order;
-    A.queue = c->b_queue;
-    A.t_out = t_out;
-    A.status_out = status_out;
-    A.steps_out = steps_out;
-    A.st = c->st;
-    A.nprob = (int)nprob;
-    A.nsteps = nsteps;
-    A.gamma = P->gamma;
-    A.W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
-    A.cfl = P->cfl;
-
-    // persistent grid: as many workgroups as are resident at once, at most one per problem
-    int per_cu = 0, ncu = 0;
-    hipError_t e;
-    if (P->precision == WT_FP32_RECON)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<1>, kThreads, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<0>, kThreads, 0);
-    if (e != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
-                                                 c->device) != hipSuccess)
-        return WT_ERR_DEVICE;
-    int64_t grid = (int64_t)std::max(per_cu, 1) * std::max(ncu, 1);
-    if (grid > nprob) grid = nprob;
-
-    // graph of (queue reset, kernel), captured once per argument set
-    uint64_t key = 0;
-    for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)t_out,
-                       (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out,
-                       (uint64_t)(uintptr_t)c->B1, (uint64_t)(uintptr_t)c->B2, (uint64_t)nprob,
-                       (uint64_t)total, (uint64_t)nsteps, (uint64_t)P->precision, bits(P->gamma),
-                       bits(P->eps), bits(P->alpha_R), bits(P->cfl), (uint64_t)grid})
-        key = mix(key, v);
-    if (!c->b_graph || c->b_key != key) {
-        if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
-        c->b_graph = nullptr;
-        if (!c->b_capture && hipStreamCreateWithFlags(&c->b_capture, hipStreamNonBlocking) != hipSuccess)
-            return WT_ERR_DEVICE;
-        hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(c->b_capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return WT_ERR_DEVICE;
-        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, c->b_capture, c->b_queue);
-        if (P->precision == WT_FP32_RECON)
-            hipLaunchKernelGGL(batched_kernel<1>, dim3((unsigned)grid), dim3(kThreads), 0, c->b_capture, A);
-        else
-            hipLaunchKernelGGL(batched_kernel<0>, dim3((unsigned)grid), dim3(kThreads), 0, c->b_capture, A);
-        const hipError_t le = hipGetLastError();
-        if (hipStreamEndCapture(c->b_capture, &g) != hipSuccess || le != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return WT_ERR_DEVICE;
-        }
-        e = hipGraphInstantiate(&c->b_graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            c->b_graph = nullptr;
-            return WT_ERR_DEVICE;
-        }
-        c->b_key = key;
-    }
-    if (hipGraphLaunch(c->b_graph, s) != hipSuccess) return WT_ERR_DEVICE;
+    *A = BatchArgs{};
+    A->u = u;
+    A->U1 = c->B1;
+    A->U2 = c->B2;
+    A->total = total;
+    A->n = c->b_n;
+    A->off = c->b_off;
+    A->dx = c->b_dx;
+    A->rdx = c->b_rdx;
+    A->bc = c->b_bc;
+    A->order = c->b_order;
+    A->queue = c->b_queue;
+    A->st = c->st;
+    A->nprob = (int)nprob;
+    A->nsteps = nsteps;
+    A->gamma = P->gamma;
+    A->W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
+    A->cfl = P->cfl;
     return WT_OK;
 }
 
-extern "C" wt_status wenotheta_solve_batched_2d(wt_ctx *c, int64_t nprob, const int64_t *nx,
-                                                const int64_t *ny, const int64_t *offset,
-                                                const double *lo, const double *hi,
-                                                const int32_t *bc, const wt_params *P, double *u,
-                                                int64_t total, int64_t nsteps, double *t_out,
-                                                int32_t *status_out, int64_t *steps_out, void *stream)
+// Queue reset and the 1D kernel of tile variant v (0: 256 threads, 1: 128) on stream s.
+wt_status enqueue_1d(wt_ctx *c, const BatchArgs &A, int precision, int v, hipStream_t s)
+{
+    int64_t grid = 0;
+    wt_status r;
+    const int threads = v == 0 ? 256 : 128;
+    if (precision == WT_FP32_RECON)
+        r = v == 0 ? persistent_grid(c, batched_kernel<1, 256>, threads, A.nprob, &grid)
+                   : persistent_grid(c, batched_kernel<1, 128>, threads, A.nprob, &grid);
+    else
+        r = v == 0 ? persistent_grid(c, batched_kernel<0, 256>, threads, A.nprob, &grid)
+                   : persistent_grid(c, batched_kernel<0, 128>, threads, A.nprob, &grid);
+    if (r != WT_OK) return r;
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, A.queue);
+    const dim3 g((unsigned)grid), b((unsigned)threads);
+    if (precision == WT_FP32_RECON) {
+        if (v == 0) hipLaunchKernelGGL((batched_kernel<1, 256>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((batched_kernel<1, 128>), g, b, 0, s, A);
+    } else {
+        if (v == 0) hipLaunchKernelGGL((batched_kernel<0, 256>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((batched_kernel<0, 128>), g, b, 0, s, A);
+    }
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_DEVICE;
+}
+
+// ---- 2D batches ----
+
+wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t *ny,
+                     const int64_t *offset, const double *lo, const double *hi, const int32_t *bc,
+                     const wt_params *P, double *u, int64_t total, int64_t nsteps, hipStream_t s,
+                     Batch2Args *A)
 {
     if (!c || !P || !u || !nx || !ny || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 36 || nsteps < 0) return WT_ERR_ARG;
@@ -820,7 +808,6 @@ extern "C" wt_status wenotheta_solve_batched_2d(wt_ctx *c, int64_t nprob, const 
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cells[a] > cells[b]; });
 
     if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
-    hipStream_t s = (hipStream_t)stream;
     // workspace: stage buffers shared with the 1D batches, then D and the tables
     const size_t need = (size_t)total * 4;
     if (need > c->bcap) {
@@ -864,58 +851,244 @@ extern "C" wt_status wenotheta_solve_batched_2d(wt_ctx *c, int64_t nprob, const 
         hipStreamSynchronize(s) != hipSuccess)
         return WT_ERR_DEVICE;
 
-    Batch2Args A{};
-    A.u = u;
-    A.U1 = c->B1;
-    A.U2 = c->B2;
-    A.D = c->BD;
-    A.total = total;
-    A.prob = (const Prob2 *)c->b2_tab;
-    A.order = c->b2_order;
-    A.queue = c->b2_queue;
-    A.t_out = t_out;
-    A.status_out = status_out;
-    A.steps_out = steps_out;
-    A.st = c->st;
-    A.nprob = (int)nprob;
-    A.nsteps = nsteps;
-    A.gamma = P->gamma;
-    A.cfl = P->cfl;
-    A.W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
+    *A = Batch2Args{};
+    A->u = u;
+    A->U1 = c->B1;
+    A->U2 = c->B2;
+    A->D = c->BD;
+    A->total = total;
+    A->prob = (const Prob2 *)c->b2_tab;
+    A->order = c->b2_order;
+    A->queue = c->b2_queue;
+    A->st = c->st;
+    A->nprob = (int)nprob;
+    A->nsteps = nsteps;
+    A->gamma = P->gamma;
+    A->cfl = P->cfl;
+    A->W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
+    return WT_OK;
+}
 
-    // persistent grid: as many workgroups as are resident at once, at most one per problem
-    int per_cu = 0, ncu = 0;
-    hipError_t e;
-    if (P->precision == WT_FP32_RECON)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched2d_kernel<1>, kThreads, 0);
+// Queue reset and the 2D kernel of tile variant v (x pass 0: 4 x 63, 1: 8 x 31) on s.
+wt_status enqueue_2d(wt_ctx *c, const Batch2Args &A, int precision, int v, hipStream_t s)
+{
+    int64_t grid = 0;
+    wt_status r;
+    if (precision == WT_FP32_RECON)
+        r = v == 0 ? persistent_grid(c, batched2d_kernel<1, 0>, kThreads, A.nprob, &grid)
+                   : persistent_grid(c, batched2d_kernel<1, 1>, kThreads, A.nprob, &grid);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched2d_kernel<0>, kThreads, 0);
-    if (e != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
-                                                 c->device) != hipSuccess)
-        return WT_ERR_DEVICE;
-    int64_t grid = (int64_t)std::max(per_cu, 1) * std::max(ncu, 1);
-    if (grid > nprob) grid = nprob;
+        r = v == 0 ? persistent_grid(c, batched2d_kernel<0, 0>, kThreads, A.nprob, &grid)
+                   : persistent_grid(c, batched2d_kernel<0, 1>, kThreads, A.nprob, &grid);
+    if (r != WT_OK) return r;
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, A.queue);
+    const dim3 g((unsigned)grid), b(kThreads);
+    if (precision == WT_FP32_RECON) {
+        if (v == 0) hipLaunchKernelGGL((batched2d_kernel<1, 0>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((batched2d_kernel<1, 1>), g, b, 0, s, A);
+    } else {
+        if (v == 0) hipLaunchKernelGGL((batched2d_kernel<0, 0>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((batched2d_kernel<0, 1>), g, b, 0, s, A);
+    }
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_DEVICE;
+}
 
+// Replay (capturing first if the arguments changed) the graph of an enqueue call.
+template <class Enqueue>
+wt_status run_graph(wt_ctx *c, hipGraphExec_t *exec, uint64_t *exec_key, uint64_t key,
+                    hipStream_t s, Enqueue enqueue)
+{
+    if (!*exec || *exec_key != key) {
+        if (*exec) (void)hipGraphExecDestroy(*exec);
+        *exec = nullptr;
+        if (!c->b_capture && hipStreamCreateWithFlags(&c->b_capture, hipStreamNonBlocking) != hipSuccess)
+            return WT_ERR_DEVICE;
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(c->b_capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return WT_ERR_DEVICE;
+        const wt_status r = enqueue(c->b_capture);
+        if (hipStreamEndCapture(c->b_capture, &g) != hipSuccess || r != WT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r != WT_OK ? r : WT_ERR_DEVICE;
+        }
+        const hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            *exec = nullptr;
+            return WT_ERR_DEVICE;
+        }
+        *exec_key = key;
+    }
+    return hipGraphLaunch(*exec, s) == hipSuccess ? WT_OK : WT_ERR_DEVICE;
+}
+
+uint64_t launch_key(const void *u, const void *t_out, const void *status_out, const void *steps_out,
+                    const wt_ctx *c, int64_t nprob, int64_t total, int64_t nsteps, const wt_params *P,
+                    int variant)
+{
     uint64_t key = 0;
     for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)t_out,
                        (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out,
                        (uint64_t)(uintptr_t)c->B1, (uint64_t)(uintptr_t)c->B2,
                        (uint64_t)(uintptr_t)c->BD, (uint64_t)nprob, (uint64_t)total, (uint64_t)nsteps,
                        (uint64_t)P->precision, bits(P->gamma), bits(P->eps), bits(P->alpha_R),
-                       bits(P->cfl), (uint64_t)grid})
+                       bits(P->cfl), (uint64_t)variant})
         key = mix(key, v);
-    if (!c->b2_graph || c->b2_key != key) {
-        if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
-        c->b2_graph = nullptr;
-        const wt_status r = capture_batch(c, &c->b2_graph, c->b2_queue, [&](hipStream_t cs) {
-            if (P->precision == WT_FP32_RECON)
-                hipLaunchKernelGGL(batched2d_kernel<1>, dim3((unsigned)grid), dim3(kThreads), 0, cs, A);
-            else
-                hipLaunchKernelGGL(batched2d_kernel<0>, dim3((unsigned)grid), dim3(kThreads), 0, cs, A);
-        });
-        if (r != WT_OK) return r;
-        c->b2_key = key;
+    return key;
+}
+
+// Time each tile variant on a scratch copy of the batch (probe_steps steps, 3 rounds
+// interleaved, best launch kept); the default variant stays unless another is more
+// than 2% faster.  prepare fills the kernel arguments for a state pointer.
+template <class Args, class Prepare, class Enqueue>
+wt_status tune_variants(wt_ctx *c, const double *u, size_t state_doubles, int64_t nprob,
+                        int precision, hipStream_t s, Prepare prepare, Enqueue enqueue, int *best)
+{
+    double *scratch = nullptr;
+    int32_t *status = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    wt_status r = WT_OK;
+    float ms[kBatchVariants];
+    for (int v = 0; v < kBatchVariants; ++v) ms[v] = 3.0e38f;
+    if (hipMalloc(&scratch, state_doubles * sizeof(double)) != hipSuccess ||
+        hipMalloc(&status, nprob * sizeof(int32_t)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        r = WT_ERR_NOMEM;
+    } else {
+        Args A{};
+        r = prepare(scratch, &A);
+        A.status_out = status;          // non-physical problems are reported here, not in the context
+        for (int round = 0; round < 3 && r == WT_OK; ++round)
+            for (int v = 0; v < kBatchVariants && r == WT_OK; ++v) {
+                if (hipMemcpyAsync(scratch, u, state_doubles * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+                        hipSuccess ||
+                    hipEventRecord(e0, s) != hipSuccess) {
+                    r = WT_ERR_DEVICE;
+                    break;
+                }
+                r = enqueue(A, precision, v, s);
+                float t = 0.0f;
+                if (r == WT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                   hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                    r = WT_ERR_DEVICE;
+                if (r == WT_OK && t < ms[v]) ms[v] = t;
+            }
     }
-    if (hipGraphLaunch(c->b2_graph, s) != hipSuccess) return WT_ERR_DEVICE;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    (void)hipFree(status);
+    if (r != WT_OK) {
+        (void)hipGetLastError();
+        return r;
+    }
+    int v_best = 0;
+    for (int v = 1; v < kBatchVariants; ++v)
+        if (ms[v] < 0.98f * ms[v_best]) v_best = v;
+    *best = v_best;
+    return WT_OK;
+}
+
+}  // namespace
+
+extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int64_t *n,
+                                             const int64_t *offset, const double *lo,
+                                             const double *hi, const int32_t *bc,
+                                             const wt_params *P, double *u, int64_t total,
+                                             int64_t nsteps, double *t_out, int32_t *status_out,
+                                             int64_t *steps_out, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    BatchArgs A;
+    wt_status r = prepare_1d(c, nprob, n, offset, lo, hi, bc, P, u, total, nsteps, s, &A);
+    if (r != WT_OK) return r;
+    A.t_out = t_out;
+    A.status_out = status_out;
+    A.steps_out = steps_out;
+    const int v = batch_variant(c->b_var, c->b_var_key, batch_signature(1, nprob, n, nullptr, total, P->precision));
+    const int prec = P->precision;
+    return run_graph(c, &c->b_graph, &c->b_key,
+                     launch_key(u, t_out, status_out, steps_out, c, nprob, total, nsteps, P, v), s,
+                     [&](hipStream_t cs) { return enqueue_1d(c, A, prec, v, cs); });
+}
+
+extern "C" wt_status wenotheta_solve_batched_2d(wt_ctx *c, int64_t nprob, const int64_t *nx,
+                                                const int64_t *ny, const int64_t *offset,
+                                                const double *lo, const double *hi,
+                                                const int32_t *bc, const wt_params *P, double *u,
+                                                int64_t total, int64_t nsteps, double *t_out,
+                                                int32_t *status_out, int64_t *steps_out, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Batch2Args A;
+    wt_status r = prepare_2d(c, nprob, nx, ny, offset, lo, hi, bc, P, u, total, nsteps, s, &A);
+    if (r != WT_OK) return r;
+    A.t_out = t_out;
+    A.status_out = status_out;
+    A.steps_out = steps_out;
+    const int v = batch_variant(c->b2_var, c->b2_var_key, batch_signature(2, nprob, nx, ny, total, P->precision));
+    const int prec = P->precision;
+    return run_graph(c, &c->b2_graph, &c->b2_key,
+                     launch_key(u, t_out, status_out, steps_out, c, nprob, total, nsteps, P, v), s,
+                     [&](hipStream_t cs) { return enqueue_2d(c, A, prec, v, cs); });
+}
+
+extern "C" wt_status wenotheta_tune_batched(wt_ctx *c, int64_t nprob, const int64_t *n,
+                                            const int64_t *offset, const double *lo,
+                                            const double *hi, const int32_t *bc,
+                                            const wt_params *P, const double *u, int64_t total,
+                                            int64_t probe_steps, int32_t *variant_out, void *stream)
+{
+    if (!c || !P || !u || probe_steps < 1) return WT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int best = 0;
+    const wt_status r = tune_variants<BatchArgs>(
+        c, u, (size_t)total * 3, nprob, P->precision, s,
+        [&](double *scratch, BatchArgs *A) {
+            return prepare_1d(c, nprob, n, offset, lo, hi, bc, P, scratch, total, probe_steps, s, A);
+        },
+        [&](const BatchArgs &A, int prec, int v, hipStream_t cs) { return enqueue_1d(c, A, prec, v, cs); },
+        &best);
+    if (r != WT_OK) return r;
+    c->b_var = best;
+    c->b_var_key = batch_signature(1, nprob, n, nullptr, total, P->precision);
+    if (variant_out) *variant_out = best;
+    return WT_OK;
+}
+
+extern "C" wt_status wenotheta_tune_batched_2d(wt_ctx *c, int64_t nprob, const int64_t *nx,
+                                               const int64_t *ny, const int64_t *offset,
+                                               const double *lo, const double *hi,
+                                               const int32_t *bc, const wt_params *P,
+                                               const double *u, int64_t total, int64_t probe_steps,
+                                               int32_t *variant_out, void *stream)
+{
+    if (!c || !P || !u || probe_steps < 1) return WT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int best = 0;
+    const wt_status r = tune_variants<Batch2Args>(
+        c, u, (size_t)total * 4, nprob, P->precision, s,
+        [&](double *scratch, Batch2Args *A) {
+            return prepare_2d(c, nprob, nx, ny, offset, lo, hi, bc, P, scratch, total, probe_steps, s, A);
+        },
+        [&](const Batch2Args &A, int prec, int v, hipStream_t cs) { return enqueue_2d(c, A, prec, v, cs); },
+        &best);
+    if (r != WT_OK) return r;
+    c->b2_var = best;
+    c->b2_var_key = batch_signature(2, nprob, nx, ny, total, P->precision);
+    if (variant_out) *variant_out = best;
+    return WT_OK;
+}
+
+extern "C" wt_status wenotheta_set_batched_tiles(wt_ctx *c, int32_t ndim, int32_t variant)
+{
+    if (!c || (ndim != 1 && ndim != 2) || variant < 0 || variant >= kBatchVariants) return WT_ERR_ARG;
+    if (ndim == 1) {
+        c->b_var = variant;
+        c->b_var_key = kAnyBatch;
+    } else {
+        c->b2_var = variant;
+        c->b2_var_key = kAnyBatch;
+    }
     return WT_OK;
 }

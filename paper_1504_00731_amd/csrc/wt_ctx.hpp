@@ -58,6 +58,9 @@ struct wt_ctx {
     int64_t b2_cap = 0;         // problems the 2D tables hold
     hipGraphExec_t b2_graph = nullptr;
     uint64_t b2_key = 0;
+    // tile variants chosen by the batch tuners, for the batch signature they were tuned on
+    int b_var = 0, b2_var = 0;
+    uint64_t b_var_key = 0, b2_var_key = 0;
     // graph of kGraphSteps solver steps and the arguments it was captured with
     hipGraphExec_t s_graph = nullptr;
     hipStream_t s_capture = nullptr;

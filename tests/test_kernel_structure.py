@@ -63,8 +63,10 @@ def test_batched_job_fetch_is_in_the_job_loop():
     """After the queue atomic, the fetch barrier follows with no loop header in between,
     and the job index is read as a scalar (one value per wave)."""
     asm = _device_asm("batched.hip")
-    syms = kernel_symbols(asm, "_ZN2wt14batched_kernel")
-    assert len(syms) == 2
+    syms1 = kernel_symbols(asm, "_ZN2wt14batched_kernel")
+    syms2 = kernel_symbols(asm, "_ZN2wt16batched2d_kernel")
+    assert len(syms1) == 4 and len(syms2) == 4         # 2 precisions x 2 tile variants each
+    syms = syms1 + syms2
     lines = asm.split("\n")
     for s in syms:
         a = next(i for i, l in enumerate(lines) if l.startswith(s + ":"))

@@ -187,14 +187,15 @@ __global__ void copy_dt_kernel(const DevState *st, double *dst)
 // Sweep kernel
 // ---------------------------------------------------------------------------
 
-// Minimum waves per SIMD the register allocation must allow: 4 for the 1D and
-// 2D Euler sweeps, which then fit 128 VGPRs (the 2D stage-finishing sweep with
-// a 12-byte spill outside its interface loop; at 3 waves it ran 12% slower);
-// 3D is left to the compiler and stays at 3.
-template <int SYS, int NDIM>
+// Minimum waves per SIMD the register allocation must allow (measured on the
+// benchmark grids): 4 for the Euler sweeps in FP64, which then fit 128 VGPRs
+// (spill-free in 1D and 2D; in 3D with 12-28 bytes held outside the interface
+// loop, still 13% faster than at 3 waves); 5 for the 2D FP32 sweeps (96 VGPRs,
+// 6% faster than at 4).
+template <int SYS, int NDIM, int PREC>
 constexpr int sweep_min_waves()
 {
-    return SYS == WT_EULER && NDIM <= 2 ? 4 : 1;
+    return SYS == WT_EULER && NDIM == 2 && PREC != 0 ? 5 : (SYS == WT_EULER ? 4 : 1);
 }
 
 // 1D Euler grids are short (65536 points fill only 257 one-interface-per-thread
@@ -209,7 +210,7 @@ constexpr bool split_fields()
 }
 
 template <int SYS, int NDIM, int DIR, int TX, int TN, int MODE, int PREC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<SYS, NDIM>())))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<SYS, NDIM, PREC>())))
 void sweep_kernel(SweepArgs A)
 {
     constexpr int M = Ncomp<SYS, NDIM>::value;
@@ -226,7 +227,16 @@ void sweep_kernel(SweepArgs A)
     __shared__ double s_v[EULER ? NDIM : 1][EULER ? NC : 1];
     __shared__ double s_sr[EULER ? NC : 1];
     __shared__ double s_H[EULER ? NC : 1];
-    __shared__ double s_F[M][kThreads];
+    // FP32 forms and 3D: the interface fluxes take the place of the staged normal
+    // fluxes, which nobody reads once every interface is done; the smaller tile lets
+    // one more workgroup share a CU (5 instead of 4 for the FP32 2D sweeps, 4 instead
+    // of 3 for 3D).  The FP64 1D and 2D sweeps are bound by registers at 4 waves.
+    constexpr bool ALIAS_F = PREC != 0 || NDIM == 3;
+    static_assert(!ALIAS_F || NC >= kThreads, "the flux rows fit in the staged rows");
+    __shared__ double s_Fown[ALIAS_F ? 1 : M][ALIAS_F ? 1 : kThreads];
+    double (*s_F)[kThreads];
+    if constexpr (ALIAS_F) s_F = reinterpret_cast<double (*)[kThreads]>(&s_f[0][0]);
+    else s_F = reinterpret_cast<double (*)[kThreads]>(&s_Fown[0][0]);
     __shared__ double s_h[SPLIT ? M : 1][SPLIT ? TN + 1 : 1];   // h_s per field and interface
 
     DevState *st = A.st;
@@ -344,7 +354,7 @@ void sweep_kernel(SweepArgs A)
 #pragma unroll
             for (int k = 0; k < M; ++k) {
                 const int fs = field_order(k);
-                backproject_field<NDIM, DIR>(B, fs, s_h[fs][it], acc);
+                backproject_field<NDIM, DIR, fresh_rows<NDIM, PREC>()>(B, fs, s_h[fs][it], acc);
             }
             store_interface_flux<NDIM, DIR>(acc, F);
 #pragma unroll
@@ -356,19 +366,22 @@ void sweep_kernel(SweepArgs A)
         const int t = threadIdx.x;
         const int it = t / TX, cx = t % TX;
         const bool valid = (DIR == 0 || x0 + cx < nx) && g0 + it <= nd;
+        double F[M];
         if (valid) {
             if constexpr (EULER) {
                 const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
                 const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.bc == WT_REFLECTIVE};
-                double F[M];
                 if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.W, F))
                     atomicOr(&st->err, kErrNonphysical);
-#pragma unroll
-                for (int q = 0; q < M; ++q) s_F[q][t] = F[q];
             } else {
                 const LdsScalarStencil<NC, TX> S{s_u[0], s_f[0], t};
-                s_F[0][t] = scalar_interface_flux<PREC>(S, bits_to_double(st->alpha[A.slot_rd][0]), A.W);
+                F[0] = scalar_interface_flux<PREC>(S, bits_to_double(st->alpha[A.slot_rd][0]), A.W);
             }
+        }
+        if constexpr (ALIAS_F) __syncthreads();     // every stencil read of s_f is done
+        if (valid) {
+#pragma unroll
+            for (int q = 0; q < M; ++q) s_F[q][t] = F[q];
         }
     }
     __syncthreads();

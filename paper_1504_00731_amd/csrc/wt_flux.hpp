@@ -56,6 +56,15 @@ WT_HD void euler_normal_flux(const double *uc, const double *vel, double p, doub
     f[NDIM + 1] = un * (uc[NDIM + 1] + p);
 }
 
+// Whether the sweeps of this form recompute the rows of L and columns of R per
+// field (opaque<true>) instead of letting the compiler keep them across the
+// field loop: the FP32 forms and 3D, whose occupancy the saved registers raise.
+template <int NDIM, int PREC>
+constexpr bool fresh_rows()
+{
+    return PREC != 0 || NDIM == 3;
+}
+
 // Characteristic field s of an interface (0: u_n - c, 1: u_n, 2: u_n + c, 3..:
 // shear): the stencil projected onto row s of L (q = L u, w = L f), split with the
 // field's Lax-Friedrichs speed a = al(s), v+- = (w +- a q) / 2, and reconstructed,
@@ -69,18 +78,8 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
     // row s of L in permuted order
     double ln0, ln1, lE, lt[NT > 0 ? NT : 1];
     int shear = -1;
-    if (s == 0) {
-        ln0 = B.l0n0; ln1 = B.l0n1; lE = B.l0E;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) lt[t] = B.l0t[t];
-    } else if (s == 1) {
-        ln0 = B.l1n0; ln1 = B.l1n1; lE = B.l1E;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) lt[t] = B.l1t[t];
-    } else if (s == 2) {
-        ln0 = B.l2n0; ln1 = B.l2n1; lE = B.l2E;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) lt[t] = B.l2t[t];
+    if (s < 3) {
+        left_row<NDIM, fresh_rows<NDIM, PREC>()>(B, s, ln0, ln1, lt, lE);
     } else {
         shear = s - 3;
         ln0 = -(shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]); ln1 = 0.0; lE = 0.0;
@@ -136,11 +135,11 @@ WT_HD constexpr int field_order(int it)
 
 // Add column s of R times h_s to the accumulators (permuted order rho, m_n,
 // m_t.., E); the first field in field_order initialises them.
-template <int NDIM, int DIR>
+template <int NDIM, int DIR, bool FRESH>
 WT_HD void backproject_field(const RoeBasis<NDIM> &B, int s, double h, double *acc)
 {
     constexpr int M = NDIM + 2, NT = NDIM - 1;
-    const double un = B.un, c = B.c;
+    const double un = opaque<FRESH>(B.un), c = opaque<FRESH>(B.c);
     if (s == 0) {
         acc[0] = h;
         acc[1] = (un - c) * h;
@@ -207,7 +206,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, con
     for (int it = 0; it < M; ++it) {
         const int s = field_order(it);
         const double h = euler_field_flux<NDIM, DIR, PREC>(S, B, s, al, W);
-        backproject_field<NDIM, DIR>(B, s, h, acc);
+        backproject_field<NDIM, DIR, fresh_rows<NDIM, PREC>()>(B, s, h, acc);
     }
     store_interface_flux<NDIM, DIR>(acc, F);
     return B.ok;

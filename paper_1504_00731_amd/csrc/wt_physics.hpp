@@ -72,10 +72,11 @@ struct RoeBasis {
     double ut[2];              // tangential Roe velocities
     double c;                  // Roe sound speed
     double H;                  // Roe total enthalpy
-    // left eigenvectors
-    double l0n0, l0n1, l0t[2], l0E;    // row 0 (u_n - c)
-    double l1n0, l1n1, l1t[2], l1E;    // row 1 (u_n)
-    double l2n0, l2n1, l2t[2], l2E;    // row 2 (u_n + c)
+    // left eigenvectors, formed row by row from these (left_row)
+    double b1;                 // (gamma - 1) / c^2
+    double b2;                 // b1 |v~|^2 / 2
+    double uc;                 // u_n / c
+    double ic;                 // 1 / c
     bool ok;
 };
 
@@ -105,22 +106,52 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
     B.un = un;
     B.c = c;
     B.H = H;
-    B.l0n0 = 0.5 * (b2 + uc);
-    B.l0n1 = -0.5 * (b1 * un + ic);
-    B.l1n0 = 1.0 - b2;
-    B.l1n1 = b1 * un;
-    B.l2n0 = 0.5 * (b2 - uc);
-    B.l2n1 = -0.5 * (b1 * un - ic);
-#pragma unroll
-    for (int t = 0; t < NDIM - 1; ++t) {
-        B.l0t[t] = -0.5 * (b1 * B.ut[t]);
-        B.l1t[t] = b1 * B.ut[t];
-        B.l2t[t] = -0.5 * (b1 * B.ut[t]);
-    }
-    B.l0E = 0.5 * b1;
-    B.l1E = -b1;
-    B.l2E = 0.5 * b1;
+    B.b1 = b1;
+    B.b2 = b2;
+    B.uc = uc;
+    B.ic = ic;
     return B;
+}
+
+// With FRESH, a value the compiler must treat as new here: the expressions
+// formed from it stay where they are written instead of being hoisted out of
+// the field loop, where they would all be live at once (and, in 3D and in the
+// FP32 forms, cost a wave per SIMD or spill).  Without FRESH the compiler may
+// keep them across the loop, which the FP64 1D and 2D sweeps can afford.
+template <bool FRESH>
+WT_HD double opaque(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (FRESH) __asm__ volatile("" : "+v"(x));
+#endif
+    return x;
+}
+
+// Row s (0: u_n - c, 1: u_n, 2: u_n + c) of the left eigenvectors in permuted
+// order: coefficients of rho, m_n, the tangential momenta and E.
+template <int NDIM, bool FRESH>
+WT_HD void left_row(const RoeBasis<NDIM> &B, int s, double &ln0, double &ln1, double *lt, double &lE)
+{
+    const double b1 = opaque<FRESH>(B.b1), b2 = opaque<FRESH>(B.b2), un = opaque<FRESH>(B.un);
+    if (s == 0) {
+        ln0 = 0.5 * (b2 + opaque<FRESH>(B.uc));
+        ln1 = -0.5 * (b1 * un + opaque<FRESH>(B.ic));
+#pragma unroll
+        for (int t = 0; t < NDIM - 1; ++t) lt[t] = -0.5 * (b1 * opaque<FRESH>(B.ut[t]));
+        lE = 0.5 * b1;
+    } else if (s == 1) {
+        ln0 = 1.0 - b2;
+        ln1 = b1 * un;
+#pragma unroll
+        for (int t = 0; t < NDIM - 1; ++t) lt[t] = b1 * opaque<FRESH>(B.ut[t]);
+        lE = -b1;
+    } else {
+        ln0 = 0.5 * (b2 - opaque<FRESH>(B.uc));
+        ln1 = -0.5 * (b1 * un - opaque<FRESH>(B.ic));
+#pragma unroll
+        for (int t = 0; t < NDIM - 1; ++t) lt[t] = -0.5 * (b1 * opaque<FRESH>(B.ut[t]));
+        lE = 0.5 * b1;
+    }
 }
 
 // |v~|^2 / 2 of a Roe basis, recomputed from its velocities in canonical order

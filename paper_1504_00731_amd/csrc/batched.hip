@@ -94,9 +94,12 @@ struct LdsSpeeds {
 // itself it takes 174, and it fits 164 without spilling.  The FP32 form
 // reaches 3 waves by itself.
 // Workgroups of TPB threads sweep a problem in segments of TPB - 1 points (the
-// tile variants the batch tuner chooses between: 256 and 128 threads).
+// tile variants the batch tuner chooses between: 256 and 128 threads).  The FP64
+// form recomputes the rows of L and columns of R per field and runs at 4 waves per
+// SIMD (a small spill outside the interface loop; 2% faster than 3 waves); the FP32
+// form keeps them and runs at 3 (at 4 it spilled inside the loop, 14% slower).
 template <int PREC, int TPB>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(PREC == 0 ? 3 : 1)))
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(PREC == 0 ? 4 : 3)))
 void batched_kernel(BatchArgs A)
 {
     constexpr int M = 3, TN = TPB - 1, NC = TN + 6, NW = TPB / 64;
@@ -190,7 +193,7 @@ void batched_kernel(BatchArgs A)
                     if (g0 + t <= n) {
                         const LdsStencil<M, 1, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, t};
                         double F[3];
-                        if (!euler_interface_flux<1, 0, PREC>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
+                        if (!euler_interface_flux<1, 0, PREC, PREC == 0>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
                             err |= kErrNonphysical;
 #pragma unroll
                         for (int c = 0; c < 3; ++c) s_F[c][t] = F[c];
@@ -350,7 +353,7 @@ __device__ __forceinline__ int tile_fluxes2(const Prob2 &P, int64_t l0, int64_t 
     if (l0 + cl < nl && g0 + it <= nd) {
         const LdsStencil<4, 2, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
         double F[4];
-        if (!euler_interface_flux<2, DIR, PREC>(S, LdsSpeeds{al}, gamma, W, F)) err = kErrNonphysical;
+        if (!euler_interface_flux<2, DIR, PREC, true>(S, LdsSpeeds{al}, gamma, W, F)) err = kErrNonphysical;
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_F[q][t] = F[q];
     }
@@ -359,6 +362,8 @@ __device__ __forceinline__ int tile_fluxes2(const Prob2 &P, int64_t l0, int64_t 
 
 // Tile variants the batch tuner chooses between: the x pass in tiles of 4 rows x 63
 // points (XV = 0) or 8 rows x 31 points (XV = 1); the y pass in 8 columns x 31.
+// Rows of L and columns of R are recomputed per field (fewer registers live across
+// the field loop: the FP64 form's spill falls from 84 to 28 bytes at 3 waves).
 template <int PREC, int XV>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void batched2d_kernel(Batch2Args A)

@@ -343,7 +343,7 @@ void sweep_kernel(SweepArgs A)
         if (valid) {
             B = interface_basis<NDIM, DIR>(S, A.gamma);
             const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.bc == WT_REFLECTIVE};
-            s_h[f][it] = euler_field_flux<NDIM, DIR, PREC>(S, B, f, al, A.W);
+            s_h[f][it] = euler_field_flux<NDIM, DIR, PREC, fresh_rows<NDIM, PREC>()>(S, B, f, al, A.W);
             if (f == 0 && !B.ok) atomicOr(&st->err, kErrNonphysical);
         }
         __syncthreads();

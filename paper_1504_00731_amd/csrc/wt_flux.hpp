@@ -69,7 +69,7 @@ constexpr bool fresh_rows()
 // shear): the stencil projected onto row s of L (q = L u, w = L f), split with the
 // field's Lax-Friedrichs speed a = al(s), v+- = (w +- a q) / 2, and reconstructed,
 // sign +1 on j-2..j+3 and sign -1 on the mirrored stencil; returns h+ + h-.
-template <int NDIM, int DIR, int PREC, class Acc, class Alpha>
+template <int NDIM, int DIR, int PREC, bool FRESH, class Acc, class Alpha>
 WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, const Alpha &al,
                               const WenoConst &W)
 {
@@ -79,7 +79,7 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
     double ln0, ln1, lE, lt[NT > 0 ? NT : 1];
     int shear = -1;
     if (s < 3) {
-        left_row<NDIM, fresh_rows<NDIM, PREC>()>(B, s, ln0, ln1, lt, lE);
+        left_row<NDIM, FRESH>(B, s, ln0, ln1, lt, lE);
     } else {
         shear = s - 3;
         ln0 = -(shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]); ln1 = 0.0; lE = 0.0;
@@ -194,8 +194,8 @@ WT_HD RoeBasis<NDIM> interface_basis(const Acc &S, double gamma)
 
 // al(s): Lax-Friedrichs speed of field s for this direction.  F receives the
 // flux in canonical component order.  Returns false if the Roe sound speed is
-// not real.
-template <int NDIM, int DIR, int PREC, class Acc, class Alpha>
+// not real.  FRESH: rows of L and columns of R recomputed per field.
+template <int NDIM, int DIR, int PREC, bool FRESH = fresh_rows<NDIM, PREC>(), class Acc, class Alpha>
 WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, const WenoConst &W,
                                 double *F)
 {
@@ -205,8 +205,8 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, con
 #pragma unroll 1
     for (int it = 0; it < M; ++it) {
         const int s = field_order(it);
-        const double h = euler_field_flux<NDIM, DIR, PREC>(S, B, s, al, W);
-        backproject_field<NDIM, DIR, fresh_rows<NDIM, PREC>()>(B, s, h, acc);
+        const double h = euler_field_flux<NDIM, DIR, PREC, FRESH>(S, B, s, al, W);
+        backproject_field<NDIM, DIR, FRESH>(B, s, h, acc);
     }
     store_interface_flux<NDIM, DIR>(acc, F);
     return B.ok;

@@ -82,10 +82,7 @@ __global__ __launch_bounds__(kThreads) void alpha_kernel(const double *u, int64_
             for (int c = 0; c < NDIM + 2; ++c) uc[c] = u[c * ncell + i];
             err |= euler_speeds<NDIM>(uc, gamma, lam);
 #pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                const double l = lam[SpeedLayout<SYS, NDIM>::lam_index(k)];
-                v[k] = l > v[k] ? l : v[k];
-            }
+            for (int k = 0; k < NV; ++k) v[k] = lam[k] > v[k] ? lam[k] : v[k];
         } else {
             const double x = u[i];
             if (!__builtin_isfinite(x)) err |= kErrNonfinite;
@@ -94,10 +91,14 @@ __global__ __launch_bounds__(kThreads) void alpha_kernel(const double *u, int64_
         }
     }
     if (err) atomicOr(&st->err, err);
-    int idx[NV];
+    constexpr int NS = SpeedLayout<SYS, NDIM>::NS;
+    int src[NS], idx[NS];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) idx[k] = SpeedLayout<SYS, NDIM>::slot_index(k);
-    block_slot_max<NV>(v, st->alpha[slot], idx);
+    for (int j = 0; j < NS; ++j) {
+        src[j] = SpeedLayout<SYS, NDIM>::value_of_slot(j);
+        idx[j] = SpeedLayout<SYS, NDIM>::slot_index(j);
+    }
+    block_slot_max<NV, NS>(v, st->alpha[slot], src, idx);
 }
 
 // Set slot `slot` to the given values (or zero) and zero slot `zero_slot`.
@@ -461,7 +462,7 @@ void sweep_kernel(SweepArgs A)
                     double lam[3 * NDIM];
                     err2 |= euler_speeds<NDIM>(un, A.gamma, lam);
 #pragma unroll
-                    for (int k = 0; k < NV; ++k) spd[k] = lam[SpeedLayout<SYS, NDIM>::lam_index(k)];
+                    for (int k = 0; k < NV; ++k) spd[k] = lam[k];
                 } else {
                     if (!__builtin_isfinite(un[0])) err2 |= kErrNonfinite;
                     spd[0] = SYS == SYS_LINEAR ? __builtin_fabs(A.a) : __builtin_fabs(un[0]);
@@ -471,10 +472,14 @@ void sweep_kernel(SweepArgs A)
     }
     if constexpr (MODE == MODE_LAST_STAGE) {
         if (err2) atomicOr(&st->err, err2);
-        int sidx[NV];
+        constexpr int NS = SpeedLayout<SYS, NDIM>::NS;
+        int src[NS], sidx[NS];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) sidx[k] = SpeedLayout<SYS, NDIM>::slot_index(k);
-        block_slot_max<NV>(spd, st->alpha[A.slot_wr], sidx);
+        for (int j = 0; j < NS; ++j) {
+            src[j] = SpeedLayout<SYS, NDIM>::value_of_slot(j);
+            sidx[j] = SpeedLayout<SYS, NDIM>::slot_index(j);
+        }
+        block_slot_max<NV, NS>(spd, st->alpha[A.slot_wr], src, sidx);
         if (blockIdx.x == 0 && threadIdx.x < kSlotLen)
             __hip_atomic_store(&st->alpha[A.slot_zero][threadIdx.x], 0ull, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

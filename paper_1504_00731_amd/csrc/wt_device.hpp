@@ -44,13 +44,13 @@ __device__ __forceinline__ unsigned long long double_to_bits(double d)
     return static_cast<unsigned long long>(__double_as_longlong(d));
 }
 
+// Maximum over the wave of non-negative speeds (the hardware max: one
+// instruction per step; a NaN speed, which the caller reports as an error
+// anyway, is dropped instead of taken).
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
+    for (int off = 32; off > 0; off >>= 1) v = __builtin_fmax(v, __shfl_xor(v, off, 64));
     return v;
 }
 
@@ -64,10 +64,12 @@ __device__ __forceinline__ void slot_max(unsigned long long *p, double v)
     if (vb > cur) atomicMax(p, vb);
 }
 
-// Block-wide max of NV values per thread, then one slot update per value.
-template <int NV>
+// Block-wide max of NV values per thread, then one slot update per slot
+// entry: entry slot_idx[j] takes the block maximum of value src[j] (several
+// entries may share a value).
+template <int NV, int NS>
 __device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long long *slot,
-                                               const int (&slot_idx)[NV])
+                                               const int (&src)[NS], const int (&slot_idx)[NS])
 {
     __shared__ double red[NV][kThreads / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -77,12 +79,12 @@ __device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long lo
         if (lane == 0) red[k][wid] = w;
     }
     __syncthreads();
-    if (threadIdx.x < NV) {
-        const int k = threadIdx.x;
-        double m = red[k][0];
+    if (threadIdx.x < NS) {
+        const int j = threadIdx.x;
+        double m = red[src[j]][0];
 #pragma unroll
-        for (int w = 1; w < kThreads / 64; ++w) m = red[k][w] > m ? red[k][w] : m;
-        slot_max(&slot[slot_idx[k]], m);
+        for (int w = 1; w < kThreads / 64; ++w) m = __builtin_fmax(m, red[src[j]][w]);
+        slot_max(&slot[slot_idx[j]], m);
     }
 }
 
@@ -107,17 +109,19 @@ __device__ __forceinline__ int euler_speeds(const double *uc, double gamma, doub
     return finite ? kErrNonphysical : kErrNonfinite;
 }
 
-// Lax-Friedrichs speed values per point: one per (direction, field), field
-// s of direction d taking |u_d - c|, |u_d|, |u_d + c| for s = 0, 1, 2 and
-// |u_d| for the shear fields.  Value k lives in slot entry d * 5 + s.
+// Lax-Friedrichs speeds: per direction d the distinct values |u_d - c|,
+// |u_d|, |u_d + c| (value 3 d + s, the order of euler_speeds), reduced once
+// each; slot entry d * 5 + s of field s takes value 3 d + s for s = 0, 1, 2
+// and 3 d + 1 for the shear fields (NS entries in all).
 template <int SYS, int NDIM>
 struct SpeedLayout {
     static constexpr int M = Ncomp<SYS, NDIM>::value;
-    static constexpr int NV = SYS == SYS_EULER ? NDIM * M : 1;
-    __device__ static constexpr int slot_index(int k) { return SYS == SYS_EULER ? (k / M) * 5 + k % M : 0; }
-    __device__ static constexpr int lam_index(int k)
+    static constexpr int NV = SYS == SYS_EULER ? 3 * NDIM : 1;
+    static constexpr int NS = SYS == SYS_EULER ? NDIM * M : 1;
+    __device__ static constexpr int slot_index(int j) { return SYS == SYS_EULER ? (j / M) * 5 + j % M : 0; }
+    __device__ static constexpr int value_of_slot(int j)
     {
-        return 3 * (k / M) + (k % M < 3 ? k % M : 1);
+        return SYS == SYS_EULER ? 3 * (j / M) + (j % M < 3 ? j % M : 1) : 0;
     }
 };
 

@@ -218,8 +218,11 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
  * operations, so results are bit-identical whichever runs:
  *   1D batches: workgroups of 256 threads sweeping segments of 255 points (0,
  *               default) or of 128 threads and 127 points (1);
- *   2D batches: the x pass in tiles of 4 rows x 63 points (0, default) or of
- *               8 rows x 31 points (1); the y pass in 8 columns x 31 points.
+ *   2D batches: the persistent kernel with the x pass in tiles of 4 rows x 63
+ *               points (0, default) or of 8 rows x 31 points (1), or the flat
+ *               form (each pass one launch over the tiles of all problems, the
+ *               problems' speeds, steps and errors in device arrays) with x tiles
+ *               of 8 x 31 (2) or 4 x 63 (3); the y pass in 8 columns x 31.
  * wenotheta_tune_batched / wenotheta_tune_batched_2d take the arguments of the
  * corresponding solve (u DEVICE, only read: each variant runs probe_steps >= 1
  * steps on a scratch copy, 3 rounds interleaved, the best launch kept), keep
@@ -227,8 +230,8 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
  * and precision (the default stays unless another is more than 2% faster) and
  * write it to *variant_out (HOST, optional).  Synchronises the stream;
  * allocates and frees its scratch copy.
- * wenotheta_set_batched_tiles forces variant (0 or 1) for every later batch of
- * ndim (1 or 2) dimensions on this context. */
+ * wenotheta_set_batched_tiles forces variant (1D: 0 or 1; 2D: 0 to 3) for every
+ * later batch of ndim (1 or 2) dimensions on this context. */
 wt_status wenotheta_tune_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
                                  const int64_t *offset, const double *lo, const double *hi,
                                  const int32_t *bc, const wt_params *prm, const double *u,

@@ -281,6 +281,14 @@ struct Batch2Args {
     double *U1, *U2, *D;       // packed stage buffers and the x divergence
     int64_t total;
     const Prob2 *prob;
+    // flat form: per-pass tile tables (x pass in 8 x 31 and 4 x 63 tiles, y pass in
+    // 8 x 31) and the per-problem state
+    const int32_t *xt_prob[2], *xt_local[2], *yt_prob, *yt_local;
+    int64_t ntx[2], nty;
+    unsigned long long *f_spd;
+    double *f_dt, *f_time;
+    int32_t *f_err;
+    int64_t *f_first;
     const int32_t *order;      // problems, largest first
     int32_t *queue;            // next queue position
     double *t_out;             // time reached per problem (optional)
@@ -535,6 +543,208 @@ void batched2d_kernel(Batch2Args A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D problems, flat form: every pass is one launch over the tiles of all
+// problems (tile -> problem from a table), with the problems' Lax-Friedrichs
+// speeds, time steps and error flags in per-problem device arrays; one step is
+// a time-step kernel and an x and a y pass per stage.  The grid sweeps'
+// occupancy instead of one workgroup per problem; the same tile routines and
+// operation order, so each problem still equals its solve alone.
+// ---------------------------------------------------------------------------
+
+constexpr int kFlatSpeeds = 8;            // speeds per problem and slot (6 used)
+
+struct Flat2Args {
+    const double *uin, *u0;    // stage input, state at the start of the step
+    double *out;               // stage output
+    double *D;                 // x divergence
+    int64_t total;
+    const Prob2 *prob;
+    const int32_t *tile_prob;  // problem of each tile (tiles listed problem by problem)
+    const int32_t *tile_local; // index of the tile within its problem
+    int64_t ntiles, tiles_per_xcd;
+    unsigned long long *spd;   // [3][nprob][kFlatSpeeds] speed slots (bits of doubles >= 0)
+    double *dt;                // [nprob] time step of the current step
+    double *time;              // [nprob] time reached
+    int32_t *err;              // [nprob] error bits
+    int64_t *first;            // [nprob] first step with an error (nsteps: none)
+    int nprob;
+    int rd, wr, zero;          // slots this stage reads, writes and clears
+    int stage;                 // 1..3
+    int64_t step, nsteps;
+    double gamma, cfl;
+    WenoConst W;
+    double *t_out;
+    int32_t *status_out;
+    int64_t *steps_out;
+    DevState *st;
+};
+
+__device__ __forceinline__ unsigned long long *flat_slot(const Flat2Args &A, int slot, int b)
+{
+    return A.spd + ((int64_t)slot * A.nprob + b) * kFlatSpeeds;
+}
+
+// Initial speeds of each problem (one workgroup per problem) into slot 0; slots
+// 1 and 2 cleared; time, error flags and first failing step initialised.
+__global__ __launch_bounds__(kThreads) void flat2_init_kernel(Flat2Args A)
+{
+    __shared__ double red[6][kThreads / 64];
+    const int b = blockIdx.x;
+    const Prob2 P = A.prob[b];
+    const int64_t ncell = P.nx * P.ny;
+    double spd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int err = 0;
+    for (int64_t i = threadIdx.x; i < ncell; i += kThreads) {
+        double uc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) uc[c] = A.uin[c * A.total + P.off + i];
+        double lam[6];
+        err |= euler_speeds<2>(uc, A.gamma, lam);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
+    }
+    block_max<6, kThreads / 64>(spd, red);
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    if (err) atomicOr(&s_err, err);
+    __syncthreads();
+    if (threadIdx.x < kFlatSpeeds) {
+        const int k = threadIdx.x;
+        flat_slot(A, 0, b)[k] = k < 6 ? double_to_bits(spd[k]) : 0ull;
+        flat_slot(A, 1, b)[k] = 0ull;
+        flat_slot(A, 2, b)[k] = 0ull;
+    }
+    if (threadIdx.x == 0) {
+        A.time[b] = 0.0;
+        A.err[b] = s_err;
+        A.first[b] = s_err ? 0 : A.nsteps;
+    }
+}
+
+// Start of step A.step: the first failing step of the step before, this
+// step's dt (from the speeds of the step's initial state, slot 0) and the time
+// after it, in the order of the persistent kernel.
+__global__ void flat2_dt_kernel(Flat2Args A)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.nprob) return;
+    if (A.step > 0 && A.err[b] && A.first[b] == A.nsteps) A.first[b] = A.step - 1;
+    const Prob2 P = A.prob[b];
+    const unsigned long long *sl = flat_slot(A, 0, b);
+    const double l0 = bits_to_double(sl[0]), l2 = bits_to_double(sl[2]);
+    const double l3 = bits_to_double(sl[3]), l5 = bits_to_double(sl[5]);
+    const double ax = l2 > l0 ? l2 : l0;
+    const double ay = l5 > l3 ? l5 : l3;
+    const double dt = div_rn(A.cfl, div_rn(ax, P.dx) + div_rn(ay, P.dy));
+    A.dt[b] = dt;
+    A.time[b] = A.time[b] + dt;
+}
+
+// After the last step: outputs, like the persistent kernel's per-problem tail.
+__global__ void flat2_finish_kernel(Flat2Args A)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.nprob) return;
+    const int e = A.err[b];
+    int64_t first = A.first[b];
+    if (A.nsteps > 0 && e && first == A.nsteps) first = A.nsteps - 1;
+    if (A.t_out) A.t_out[b] = A.time[b];
+    if (A.steps_out) A.steps_out[b] = first;
+    if (A.status_out)
+        A.status_out[b] = e & kErrNonfinite ? WT_ERR_NONFINITE : (e ? WT_ERR_NONPHYSICAL : WT_OK);
+    else if (e)
+        atomicOr(&A.st->err, e);
+}
+
+// One pass (DIR 0: x, writing D; DIR 1: y, finishing the stage) over the tiles of
+// all problems, tile shape TX x TN along DIR.
+template <int DIR, int TX, int TN, int PREC>
+__global__ __launch_bounds__(kThreads) void flat2_pass_kernel(Flat2Args A)
+{
+    constexpr int M = 4, NC = (TN + 6) * TX;
+    static_assert(TX * (TN + 1) == kThreads, "one interface per thread");
+    __shared__ double s_u[M][NC];
+    __shared__ double s_f[M][NC];
+    __shared__ double s_v[2][NC];
+    __shared__ double s_sr[NC];
+    __shared__ double s_H[NC];
+    __shared__ double s_F[M][kThreads];
+    __shared__ double s_al[M];
+
+    // block -> tile: each XCD takes a contiguous range of the table, so the tiles
+    // of a problem (which share halo lines) meet in one L2
+    int64_t tile = blockIdx.x;
+    tile = (tile % kXcds) * A.tiles_per_xcd + tile / kXcds;
+    if (tile >= A.ntiles) return;
+    const int b = A.tile_prob[tile];
+    const int local = A.tile_local[tile];
+    const Prob2 P = A.prob[b];
+    const int t = threadIdx.x;
+    const int64_t nd = DIR == 0 ? P.nx : P.ny;
+    const int64_t nseg = (nd + TN - 1) / TN;
+    const int64_t l0 = (local / nseg) * TX, g0 = (local % nseg) * TN;
+
+    // split speeds of this direction (the shear field takes |u_d|), paired at walls
+    if (t == 0) {
+        const unsigned long long *sl = flat_slot(A, A.rd, b);
+        const bool walls = (DIR == 0 ? P.bcx : P.bcy) == WT_REFLECTIVE;
+#pragma unroll
+        for (int f = 0; f < M; ++f)
+            s_al[f] = split_speed([sl](int k) { return bits_to_double(sl[3 * DIR + (k < 3 ? k : 1)]); },
+                                  f, walls);
+    }
+    int err = stage_tile2<DIR, TX, TN, NC>(A.uin, A.total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+    __syncthreads();
+    err |= tile_fluxes2<DIR, TX, TN, NC, PREC>(P, l0, g0, s_al, A.gamma, A.W, s_u, s_f, s_v, s_sr, s_H, s_F);
+    __syncthreads();
+    const int it = t / TX, cl = t % TX;
+    const int64_t g = g0 + it, l = l0 + cl;
+    if constexpr (DIR == 0) {
+        if (t < TN * TX && l < P.ny && g < P.nx) {
+            const int64_t idx = P.off + l * P.nx + g;
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                A.D[c * A.total + idx] = div_by_recip(s_F[c][t + TX] - s_F[c][t], P.dx, P.rdx);
+        }
+        if (err) atomicOr(&A.err[b], err);
+    } else {
+        double lam[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (t < TN * TX && l < P.nx && g < P.ny) {
+            const int64_t idx = P.off + g * P.nx + l;
+            const double dt = A.dt[b];
+            double un[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const int64_t o = c * A.total + idx;
+                const double Dd = div_by_recip(s_F[c][t + TX] - s_F[c][t], P.dy, P.rdy);
+                const double L = -(A.D[o] + Dd);
+                if (A.stage == 1)
+                    un[c] = A.uin[o] + dt * L;
+                else if (A.stage == 2)
+                    un[c] = 0.75 * A.u0[o] + 0.25 * A.uin[o] + (0.25 * dt) * L;
+                else
+                    un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * A.uin[o] + ((2.0 / 3.0) * dt) * L;
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) A.out[c * A.total + idx] = un[c];
+            err |= euler_speeds<2>(un, A.gamma, lam);
+        }
+        if (err) atomicOr(&A.err[b], err);
+        // the new state's speeds: block maxima, one slot update per value
+        int src[6], idx6[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            src[k] = k;
+            idx6[k] = k;
+        }
+        block_slot_max<6, 6>(lam, flat_slot(A, A.wr, b), src, idx6);
+        if (local == 0 && t < kFlatSpeeds)
+            __hip_atomic_store(&flat_slot(A, A.zero, b)[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 __global__ void reset_queue_kernel(int32_t *q)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
@@ -584,11 +794,17 @@ void free_batch2(wt_ctx *c)
     (void)hipFree(c->b2_tab);
     (void)hipFree(c->b2_order);
     (void)hipFree(c->b2_queue);
+    (void)hipFree(c->f2_state);
+    (void)hipFree(c->f2_tab);
     c->BD = nullptr;
     c->b2_tab = nullptr;
     c->b2_order = c->b2_queue = nullptr;
+    c->f2_state = nullptr;
+    c->f2_tab = nullptr;
     c->bdcap = 0;
     c->b2_cap = 0;
+    c->f2_state_cap = 0;
+    c->f2_tab_cap = 0;
 }
 
 }  // namespace
@@ -611,7 +827,8 @@ void release_batched(wt_ctx *c)
 
 namespace {
 
-constexpr int kBatchVariants = 2;     // tile variants of each batched kernel
+constexpr int kBatchVariants1D = 2;   // tile variants of the 1D batched kernel
+constexpr int kBatchVariants2D = 4;   // 2D: persistent 4x63 / 8x31 x tiles, flat 8x31 / 4x63
 constexpr uint64_t kAnyBatch = ~0ull; // variant key of wenotheta_set_batched_tiles: every batch
 
 // The variant of a batch: the tuned one for its signature, a forced one, else 0.
@@ -766,10 +983,16 @@ wt_status enqueue_1d(wt_ctx *c, const BatchArgs &A, int precision, int v, hipStr
 
 // ---- 2D batches ----
 
+// Tiles of a pass over lines of nd points (nl lines) in TX x TN tiles.
+int64_t pass_tiles(int64_t nd, int64_t nl, int tx, int tn)
+{
+    return ((nl + tx - 1) / tx) * ((nd + tn - 1) / tn);
+}
+
 wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t *ny,
                      const int64_t *offset, const double *lo, const double *hi, const int32_t *bc,
                      const wt_params *P, double *u, int64_t total, int64_t nsteps, hipStream_t s,
-                     Batch2Args *A)
+                     Batch2Args *A, bool flat)
 {
     if (!c || !P || !u || !nx || !ny || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 36 || nsteps < 0) return WT_ERR_ARG;
@@ -871,12 +1094,152 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
     A->gamma = P->gamma;
     A->cfl = P->cfl;
     A->W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
+    if (!flat) return WT_OK;
+
+    // flat form: tile tables, problem by problem (x pass in 8 x 31 and in 4 x 63
+    // tiles, y pass in 8 x 31), and the per-problem state
+    int64_t ntx[2] = {0, 0}, nty = 0;
+    for (int64_t b = 0; b < nprob; ++b) {
+        ntx[0] += pass_tiles(nx[b], ny[b], 8, 31);
+        ntx[1] += pass_tiles(nx[b], ny[b], 4, 63);
+        nty += pass_tiles(ny[b], nx[b], 8, 31);
+    }
+    const int64_t entries = 2 * (ntx[0] + ntx[1] + nty);
+    if (entries > (int64_t(1) << 31)) return WT_ERR_ARG;
+    std::vector<int32_t> ttab(entries);
+    int64_t pos = 0;
+    auto list = [&](int64_t n, auto tiles_of) {   // (problem, local tile) pairs as two arrays
+        int64_t k = 0;
+        for (int64_t b = 0; b < nprob; ++b)
+            for (int64_t j = 0, m = tiles_of(b); j < m; ++j, ++k) {
+                ttab[pos + k] = (int32_t)b;
+                ttab[pos + n + k] = (int32_t)j;
+            }
+        pos += 2 * n;
+    };
+    list(ntx[0], [&](int64_t b) { return pass_tiles(nx[b], ny[b], 8, 31); });
+    list(ntx[1], [&](int64_t b) { return pass_tiles(nx[b], ny[b], 4, 63); });
+    list(nty, [&](int64_t b) { return pass_tiles(ny[b], nx[b], 8, 31); });
+    const size_t state_bytes = (size_t)nprob * (3 * kFlatSpeeds * sizeof(unsigned long long) +
+                                                2 * sizeof(double) + sizeof(int32_t) + sizeof(int64_t));
+    if (nprob > c->f2_state_cap || entries > c->f2_tab_cap) {
+        if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
+        if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
+        c->b2_graph = nullptr;
+        (void)hipFree(c->f2_state);
+        (void)hipFree(c->f2_tab);
+        c->f2_state = nullptr;
+        c->f2_tab = nullptr;
+        c->f2_state_cap = c->f2_tab_cap = 0;
+        if (hipMalloc(&c->f2_state, state_bytes) != hipSuccess ||
+            hipMalloc(&c->f2_tab, entries * sizeof(int32_t)) != hipSuccess) {
+            (void)hipFree(c->f2_state);
+            (void)hipFree(c->f2_tab);
+            c->f2_state = nullptr;
+            c->f2_tab = nullptr;
+            (void)hipGetLastError();
+            return WT_ERR_NOMEM;
+        }
+        c->f2_state_cap = nprob;
+        c->f2_tab_cap = entries;
+    }
+    if (hipMemcpyAsync(c->f2_tab, ttab.data(), entries * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return WT_ERR_DEVICE;
+    const int32_t *t0 = c->f2_tab;
+    A->xt_prob[0] = t0;
+    A->xt_local[0] = t0 + ntx[0];
+    A->xt_prob[1] = t0 + 2 * ntx[0];
+    A->xt_local[1] = t0 + 2 * ntx[0] + ntx[1];
+    A->yt_prob = t0 + 2 * (ntx[0] + ntx[1]);
+    A->yt_local = A->yt_prob + nty;
+    A->ntx[0] = ntx[0];
+    A->ntx[1] = ntx[1];
+    A->nty = nty;
+    char *p = (char *)c->f2_state;
+    A->f_spd = (unsigned long long *)p;
+    p += (size_t)nprob * 3 * kFlatSpeeds * sizeof(unsigned long long);
+    A->f_dt = (double *)p;
+    p += (size_t)nprob * sizeof(double);
+    A->f_time = (double *)p;
+    p += (size_t)nprob * sizeof(double);
+    A->f_first = (int64_t *)p;
+    p += (size_t)nprob * sizeof(int64_t);
+    A->f_err = (int32_t *)p;
     return WT_OK;
 }
 
-// Queue reset and the 2D kernel of tile variant v (x pass 0: 4 x 63, 1: 8 x 31) on s.
+// The flat form on stream s: initial speeds, nsteps x (time step, 3 x (x pass,
+// y pass)), outputs.  xv: x tiles 8 x 31 (0) or 4 x 63 (1).
+wt_status enqueue_2d_flat(const Batch2Args &B, int precision, int xv, hipStream_t s)
+{
+    Flat2Args F{};
+    F.total = B.total;
+    F.prob = B.prob;
+    F.D = B.D;
+    F.spd = B.f_spd;
+    F.dt = B.f_dt;
+    F.time = B.f_time;
+    F.err = B.f_err;
+    F.first = B.f_first;
+    F.nprob = B.nprob;
+    F.nsteps = B.nsteps;
+    F.gamma = B.gamma;
+    F.cfl = B.cfl;
+    F.W = B.W;
+    F.t_out = B.t_out;
+    F.status_out = B.status_out;
+    F.steps_out = B.steps_out;
+    F.st = B.st;
+    const unsigned per_problem = (unsigned)((B.nprob + 255) / 256);
+    F.uin = B.u;
+    hipLaunchKernelGGL(flat2_init_kernel, dim3((unsigned)B.nprob), dim3(kThreads), 0, s, F);
+    auto pass = [&](int dir, const int32_t *tp, const int32_t *tl, int64_t n) {
+        Flat2Args G = F;
+        G.tile_prob = tp;
+        G.tile_local = tl;
+        G.ntiles = n;
+        G.tiles_per_xcd = (n + kXcds - 1) / kXcds;
+        const dim3 grid((unsigned)(G.tiles_per_xcd * kXcds)), block(kThreads);
+        if (dir == 0) {
+            if (precision == WT_FP32_RECON) {
+                if (xv == 0) hipLaunchKernelGGL((flat2_pass_kernel<0, 8, 31, 1>), grid, block, 0, s, G);
+                else hipLaunchKernelGGL((flat2_pass_kernel<0, 4, 63, 1>), grid, block, 0, s, G);
+            } else {
+                if (xv == 0) hipLaunchKernelGGL((flat2_pass_kernel<0, 8, 31, 0>), grid, block, 0, s, G);
+                else hipLaunchKernelGGL((flat2_pass_kernel<0, 4, 63, 0>), grid, block, 0, s, G);
+            }
+        } else {
+            if (precision == WT_FP32_RECON)
+                hipLaunchKernelGGL((flat2_pass_kernel<1, 8, 31, 1>), grid, block, 0, s, G);
+            else
+                hipLaunchKernelGGL((flat2_pass_kernel<1, 8, 31, 0>), grid, block, 0, s, G);
+        }
+    };
+    for (int64_t step = 0; step < B.nsteps; ++step) {
+        F.step = step;
+        hipLaunchKernelGGL(flat2_dt_kernel, dim3(per_problem), dim3(256), 0, s, F);
+        for (int stage = 1; stage <= 3; ++stage) {
+            F.stage = stage;
+            F.uin = stage == 1 ? B.u : (stage == 2 ? B.U1 : B.U2);
+            F.out = stage == 1 ? B.U1 : (stage == 2 ? B.U2 : B.u);
+            F.u0 = B.u;
+            F.rd = stage - 1;
+            F.wr = stage % 3;
+            F.zero = (stage + 1) % 3;
+            pass(0, B.xt_prob[xv], B.xt_local[xv], B.ntx[xv]);
+            pass(1, B.yt_prob, B.yt_local, B.nty);
+        }
+    }
+    hipLaunchKernelGGL(flat2_finish_kernel, dim3(per_problem), dim3(256), 0, s, F);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_DEVICE;
+}
+
+// The 2D batch in variant v on s: the persistent kernel with x tiles 4 x 63 (0)
+// or 8 x 31 (1), or the flat form with x tiles 8 x 31 (2) or 4 x 63 (3).
 wt_status enqueue_2d(wt_ctx *c, const Batch2Args &A, int precision, int v, hipStream_t s)
 {
+    if (v >= 2) return enqueue_2d_flat(A, precision, v - 2, s);
     int64_t grid = 0;
     wt_status r;
     if (precision == WT_FP32_RECON)
@@ -929,13 +1292,14 @@ wt_status run_graph(wt_ctx *c, hipGraphExec_t *exec, uint64_t *exec_key, uint64_
 
 uint64_t launch_key(const void *u, const void *t_out, const void *status_out, const void *steps_out,
                     const wt_ctx *c, int64_t nprob, int64_t total, int64_t nsteps, const wt_params *P,
-                    int variant)
+                    int variant, uint64_t signature)
 {
-    uint64_t key = 0;
+    uint64_t key = signature;
     for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)t_out,
                        (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out,
                        (uint64_t)(uintptr_t)c->B1, (uint64_t)(uintptr_t)c->B2,
-                       (uint64_t)(uintptr_t)c->BD, (uint64_t)nprob, (uint64_t)total, (uint64_t)nsteps,
+                       (uint64_t)(uintptr_t)c->BD, (uint64_t)(uintptr_t)c->f2_state,
+                       (uint64_t)(uintptr_t)c->f2_tab, (uint64_t)nprob, (uint64_t)total, (uint64_t)nsteps,
                        (uint64_t)P->precision, bits(P->gamma), bits(P->eps), bits(P->alpha_R),
                        bits(P->cfl), (uint64_t)variant})
         key = mix(key, v);
@@ -947,14 +1311,15 @@ uint64_t launch_key(const void *u, const void *t_out, const void *status_out, co
 // than 2% faster.  prepare fills the kernel arguments for a state pointer.
 template <class Args, class Prepare, class Enqueue>
 wt_status tune_variants(wt_ctx *c, const double *u, size_t state_doubles, int64_t nprob,
-                        int precision, hipStream_t s, Prepare prepare, Enqueue enqueue, int *best)
+                        int precision, int nvar, hipStream_t s, Prepare prepare, Enqueue enqueue,
+                        int *best)
 {
     double *scratch = nullptr;
     int32_t *status = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     wt_status r = WT_OK;
-    float ms[kBatchVariants];
-    for (int v = 0; v < kBatchVariants; ++v) ms[v] = 3.0e38f;
+    float ms[kBatchVariants2D];
+    for (int v = 0; v < nvar; ++v) ms[v] = 3.0e38f;
     if (hipMalloc(&scratch, state_doubles * sizeof(double)) != hipSuccess ||
         hipMalloc(&status, nprob * sizeof(int32_t)) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -964,7 +1329,7 @@ wt_status tune_variants(wt_ctx *c, const double *u, size_t state_doubles, int64_
         r = prepare(scratch, &A);
         A.status_out = status;          // non-physical problems are reported here, not in the context
         for (int round = 0; round < 3 && r == WT_OK; ++round)
-            for (int v = 0; v < kBatchVariants && r == WT_OK; ++v) {
+            for (int v = 0; v < nvar && r == WT_OK; ++v) {
                 if (hipMemcpyAsync(scratch, u, state_doubles * sizeof(double), hipMemcpyDeviceToDevice, s) !=
                         hipSuccess ||
                     hipEventRecord(e0, s) != hipSuccess) {
@@ -988,7 +1353,7 @@ wt_status tune_variants(wt_ctx *c, const double *u, size_t state_doubles, int64_
         return r;
     }
     int v_best = 0;
-    for (int v = 1; v < kBatchVariants; ++v)
+    for (int v = 1; v < nvar; ++v)
         if (ms[v] < 0.98f * ms[v_best]) v_best = v;
     *best = v_best;
     return WT_OK;
@@ -1010,10 +1375,11 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
     A.t_out = t_out;
     A.status_out = status_out;
     A.steps_out = steps_out;
-    const int v = batch_variant(c->b_var, c->b_var_key, batch_signature(1, nprob, n, nullptr, total, P->precision));
+    const uint64_t sig = batch_signature(1, nprob, n, nullptr, total, P->precision);
+    const int v = batch_variant(c->b_var, c->b_var_key, sig);
     const int prec = P->precision;
     return run_graph(c, &c->b_graph, &c->b_key,
-                     launch_key(u, t_out, status_out, steps_out, c, nprob, total, nsteps, P, v), s,
+                     launch_key(u, t_out, status_out, steps_out, c, nprob, total, nsteps, P, v, sig), s,
                      [&](hipStream_t cs) { return enqueue_1d(c, A, prec, v, cs); });
 }
 
@@ -1025,16 +1391,18 @@ extern "C" wt_status wenotheta_solve_batched_2d(wt_ctx *c, int64_t nprob, const 
                                                 int32_t *status_out, int64_t *steps_out, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
+    if (!c || !P || !nx || !ny) return WT_ERR_ARG;
+    const uint64_t sig = batch_signature(2, nprob, nx, ny, total, P->precision);
+    const int v = batch_variant(c->b2_var, c->b2_var_key, sig);
     Batch2Args A;
-    wt_status r = prepare_2d(c, nprob, nx, ny, offset, lo, hi, bc, P, u, total, nsteps, s, &A);
+    wt_status r = prepare_2d(c, nprob, nx, ny, offset, lo, hi, bc, P, u, total, nsteps, s, &A, v >= 2);
     if (r != WT_OK) return r;
     A.t_out = t_out;
     A.status_out = status_out;
     A.steps_out = steps_out;
-    const int v = batch_variant(c->b2_var, c->b2_var_key, batch_signature(2, nprob, nx, ny, total, P->precision));
     const int prec = P->precision;
     return run_graph(c, &c->b2_graph, &c->b2_key,
-                     launch_key(u, t_out, status_out, steps_out, c, nprob, total, nsteps, P, v), s,
+                     launch_key(u, t_out, status_out, steps_out, c, nprob, total, nsteps, P, v, sig), s,
                      [&](hipStream_t cs) { return enqueue_2d(c, A, prec, v, cs); });
 }
 
@@ -1048,7 +1416,7 @@ extern "C" wt_status wenotheta_tune_batched(wt_ctx *c, int64_t nprob, const int6
     hipStream_t s = (hipStream_t)stream;
     int best = 0;
     const wt_status r = tune_variants<BatchArgs>(
-        c, u, (size_t)total * 3, nprob, P->precision, s,
+        c, u, (size_t)total * 3, nprob, P->precision, kBatchVariants1D, s,
         [&](double *scratch, BatchArgs *A) {
             return prepare_1d(c, nprob, n, offset, lo, hi, bc, P, scratch, total, probe_steps, s, A);
         },
@@ -1072,9 +1440,10 @@ extern "C" wt_status wenotheta_tune_batched_2d(wt_ctx *c, int64_t nprob, const i
     hipStream_t s = (hipStream_t)stream;
     int best = 0;
     const wt_status r = tune_variants<Batch2Args>(
-        c, u, (size_t)total * 4, nprob, P->precision, s,
+        c, u, (size_t)total * 4, nprob, P->precision, kBatchVariants2D, s,
         [&](double *scratch, Batch2Args *A) {
-            return prepare_2d(c, nprob, nx, ny, offset, lo, hi, bc, P, scratch, total, probe_steps, s, A);
+            return prepare_2d(c, nprob, nx, ny, offset, lo, hi, bc, P, scratch, total, probe_steps, s, A,
+                              true);
         },
         [&](const Batch2Args &A, int prec, int v, hipStream_t cs) { return enqueue_2d(c, A, prec, v, cs); },
         &best);
@@ -1087,7 +1456,9 @@ extern "C" wt_status wenotheta_tune_batched_2d(wt_ctx *c, int64_t nprob, const i
 
 extern "C" wt_status wenotheta_set_batched_tiles(wt_ctx *c, int32_t ndim, int32_t variant)
 {
-    if (!c || (ndim != 1 && ndim != 2) || variant < 0 || variant >= kBatchVariants) return WT_ERR_ARG;
+    if (!c || (ndim != 1 && ndim != 2) || variant < 0 ||
+        variant >= (ndim == 1 ? kBatchVariants1D : kBatchVariants2D))
+        return WT_ERR_ARG;
     if (ndim == 1) {
         c->b_var = variant;
         c->b_var_key = kAnyBatch;

@@ -60,7 +60,6 @@ struct SweepArgs {
     int has_grav;          // any grav[d] != 0: the source is added to L
 };
 
-constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, one L2 each
 
 // ---------------------------------------------------------------------------
 // Lax-Friedrichs speeds of a state (grid-stride reduction into one slot)

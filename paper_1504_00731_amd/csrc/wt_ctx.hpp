@@ -58,6 +58,11 @@ struct wt_ctx {
     int64_t b2_cap = 0;         // problems the 2D tables hold
     hipGraphExec_t b2_graph = nullptr;
     uint64_t b2_key = 0;
+    // flat form of the 2D batches: per-problem state and per-pass tile tables
+    void *f2_state = nullptr;
+    int64_t f2_state_cap = 0;   // problems
+    int32_t *f2_tab = nullptr;
+    int64_t f2_tab_cap = 0;     // int32 entries
     // tile variants chosen by the batch tuners, for the batch signature they were tuned on
     int b_var = 0, b2_var = 0;
     uint64_t b_var_key = 0, b2_var_key = 0;

@@ -18,6 +18,7 @@ namespace wt {
 constexpr int kThreads = 256;
 constexpr int kSlots = 3;        // ring of Lax-Friedrichs speed slots
 constexpr int kSlotLen = 16;     // [dir * 5 + field]
+constexpr int kXcds = 8;         // accelerator complex dies of an MI355X, one L2 each
 constexpr int kErrNonphysical = 1;
 constexpr int kErrNonfinite = 2;
 

@@ -172,11 +172,15 @@ def test_batched_2d_fp32_reconstruction(ctx):
     assert np.array_equal(u32[:, o:o + n], u64[:, o:o + n])
 
 
-def test_batched_2d_full_size_sampled(ctx):
-    """The benchmark batch (4096 problems, 32..96 points per side, 100 steps): the
-    largest, the smallest and seeded other problems against the oracle."""
+@pytest.mark.parametrize("variant", [0, 2])
+def test_batched_2d_full_size_sampled(variant):
+    """The benchmark batch (4096 problems, 32..96 points per side, 100 steps), in the
+    persistent form (0) and the flat form (2): the largest, the smallest and seeded
+    other problems against the oracle."""
     B = W.batched_2d(seed=0)
-    got, t, st, ks = _run(ctx, B, B.steps)
+    with wt.Context(0) as ctx:
+        wt.wenotheta_set_batched_tiles(ctx, 2, variant)
+        got, t, st, ks = _run(ctx, B, B.steps)
     cells = B.nx * B.ny
     pick = [int(np.argmax(cells)), int(np.argmin(cells))]
     pick += [int(b) for b in np.random.default_rng(1).choice(B.nprob, 6, replace=False)]

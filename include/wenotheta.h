@@ -216,8 +216,10 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
 /* Tile variants of the batched kernels, chosen by timing (the batch form of
  * wenotheta_tune).  Each batched kernel has two variants that compute the same
  * operations, so results are bit-identical whichever runs:
- *   1D batches: workgroups of 256 threads sweeping segments of 255 points (0,
- *               default) or of 128 threads and 127 points (1);
+ *   1D batches: the persistent kernel with workgroups of 256 threads sweeping
+ *               segments of 255 points (0, default) or of 128 threads and 127
+ *               points (1), or the flat form (each stage one launch over the
+ *               255-point segments of all problems) (2);
  *   2D batches: the persistent kernel with the x pass in tiles of 4 rows x 63
  *               points (0, default) or of 8 rows x 31 points (1), or the flat
  *               form (each pass one launch over the tiles of all problems, the
@@ -230,7 +232,7 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
  * and precision (the default stays unless another is more than 2% faster) and
  * write it to *variant_out (HOST, optional).  Synchronises the stream;
  * allocates and frees its scratch copy.
- * wenotheta_set_batched_tiles forces variant (1D: 0 or 1; 2D: 0 to 3) for every
+ * wenotheta_set_batched_tiles forces variant (1D: 0 to 2; 2D: 0 to 3) for every
  * later batch of ndim (1 or 2) dimensions on this context. */
 wt_status wenotheta_tune_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
                                  const int64_t *offset, const double *lo, const double *hi,

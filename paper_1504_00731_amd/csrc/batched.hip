@@ -39,6 +39,13 @@ struct BatchArgs {
     double *u;                 // packed states [3][total], advanced in place
     double *U1, *U2;           // packed stage buffers
     int64_t total;
+    // flat form: segment table and the per-problem state
+    const int32_t *ft_prob, *ft_local;
+    int64_t nft;
+    unsigned long long *f_spd;
+    double *f_dt, *f_time;
+    int32_t *f_err;
+    int64_t *f_first;
     const int64_t *n, *off;    // points and first column of each problem
     const double *dx, *rdx;    // spacing and its rounded reciprocal
     const int32_t *bc;         // boundary condition of each problem
@@ -348,7 +355,9 @@ __device__ __forceinline__ int stage_tile2(const double *uin, int64_t total, con
 
 // Interface fluxes of a staged tile, one interface per thread (between points
 // g0 + it - 1 and g0 + it of line l0 + l, t = it * TX + l), into s_F.
-template <int DIR, int TX, int TN, int NC, int PREC>
+// With ALIAS, s_F overlays s_f: the fluxes are stored after a barrier that
+// closes every thread's stencil reads.
+template <int DIR, int TX, int TN, int NC, int PREC, bool ALIAS = false>
 __device__ __forceinline__ int tile_fluxes2(const Prob2 &P, int64_t l0, int64_t g0, const double *al,
                                             double gamma, const WenoConst &W,
                                             const double (*s_u)[NC], const double (*s_f)[NC],
@@ -358,10 +367,14 @@ __device__ __forceinline__ int tile_fluxes2(const Prob2 &P, int64_t l0, int64_t 
     const int t = threadIdx.x, it = t / TX, cl = t % TX;
     const int64_t nd = DIR == 0 ? P.nx : P.ny, nl = DIR == 0 ? P.ny : P.nx;
     int err = 0;
-    if (l0 + cl < nl && g0 + it <= nd) {
+    const bool valid = l0 + cl < nl && g0 + it <= nd;
+    double F[4];
+    if (valid) {
         const LdsStencil<4, 2, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
-        double F[4];
         if (!euler_interface_flux<2, DIR, PREC, true>(S, LdsSpeeds{al}, gamma, W, F)) err = kErrNonphysical;
+    }
+    if constexpr (ALIAS) __syncthreads();
+    if (valid) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_F[q][t] = F[q];
     }
@@ -661,16 +674,23 @@ __global__ void flat2_finish_kernel(Flat2Args A)
 // One pass (DIR 0: x, writing D; DIR 1: y, finishing the stage) over the tiles of
 // all problems, tile shape TX x TN along DIR.
 template <int DIR, int TX, int TN, int PREC>
-__global__ __launch_bounds__(kThreads) void flat2_pass_kernel(Flat2Args A)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC == 0 ? 4 : 5)))
+void flat2_pass_kernel(Flat2Args A)
 {
     constexpr int M = 4, NC = (TN + 6) * TX;
-    static_assert(TX * (TN + 1) == kThreads, "one interface per thread");
+    static_assert(TX * (TN + 1) == kThreads && NC >= kThreads, "one interface per thread");
     __shared__ double s_u[M][NC];
     __shared__ double s_f[M][NC];
     __shared__ double s_v[2][NC];
     __shared__ double s_sr[NC];
     __shared__ double s_H[NC];
-    __shared__ double s_F[M][kThreads];
+    // FP32: the interface fluxes take the rows of the staged normal fluxes (read by
+    // no one once every interface is done), for a fifth workgroup per CU
+    constexpr bool ALIAS_F = PREC != 0;
+    __shared__ double s_Fown[ALIAS_F ? 1 : M][ALIAS_F ? 1 : kThreads];
+    double (*s_F)[kThreads];
+    if constexpr (ALIAS_F) s_F = reinterpret_cast<double (*)[kThreads]>(&s_f[0][0]);
+    else s_F = reinterpret_cast<double (*)[kThreads]>(&s_Fown[0][0]);
     __shared__ double s_al[M];
 
     // block -> tile: each XCD takes a contiguous range of the table, so the tiles
@@ -697,7 +717,8 @@ __global__ __launch_bounds__(kThreads) void flat2_pass_kernel(Flat2Args A)
     }
     int err = stage_tile2<DIR, TX, TN, NC>(A.uin, A.total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
     __syncthreads();
-    err |= tile_fluxes2<DIR, TX, TN, NC, PREC>(P, l0, g0, s_al, A.gamma, A.W, s_u, s_f, s_v, s_sr, s_H, s_F);
+    err |= tile_fluxes2<DIR, TX, TN, NC, PREC, ALIAS_F>(P, l0, g0, s_al, A.gamma, A.W, s_u, s_f, s_v, s_sr,
+                                                         s_H, s_F);
     __syncthreads();
     const int it = t / TX, cl = t % TX;
     const int64_t g = g0 + it, l = l0 + cl;
@@ -745,6 +766,191 @@ __global__ __launch_bounds__(kThreads) void flat2_pass_kernel(Flat2Args A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// 1D problems, flat form: the same organisation as the 2D flat form, one pass
+// per stage over the 255-point segments of all problems.
+// ---------------------------------------------------------------------------
+
+constexpr int kFlat1Speeds = 4;           // speeds per problem and slot (3 used)
+
+struct Flat1Args {
+    const double *uin, *u0;    // stage input, state at the start of the step
+    double *out;               // stage output
+    int64_t total;
+    const int64_t *n, *off;    // problem tables
+    const double *dx, *rdx;
+    const int32_t *bc;
+    const int32_t *tile_prob, *tile_local;
+    int64_t ntiles, tiles_per_xcd;
+    unsigned long long *spd;   // [3][nprob][kFlat1Speeds]
+    double *dt, *time;
+    int32_t *err;
+    int64_t *first;
+    int nprob;
+    int rd, wr, zero, stage;
+    int64_t step, nsteps;
+    double gamma, cfl;
+    WenoConst W;
+    double *t_out;
+    int32_t *status_out;
+    int64_t *steps_out;
+    DevState *st;
+};
+
+__device__ __forceinline__ unsigned long long *flat1_slot(const Flat1Args &A, int slot, int b)
+{
+    return A.spd + ((int64_t)slot * A.nprob + b) * kFlat1Speeds;
+}
+
+__global__ __launch_bounds__(kThreads) void flat1_init_kernel(Flat1Args A)
+{
+    __shared__ double red[3][kThreads / 64];
+    __shared__ int s_err;
+    const int b = blockIdx.x;
+    const int64_t n = A.n[b], off = A.off[b];
+    double spd[3] = {0.0, 0.0, 0.0};
+    int err = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+        double uc[3] = {A.uin[off + i], A.uin[A.total + off + i], A.uin[2 * A.total + off + i]};
+        double lam[3];
+        err |= euler_speeds<1>(uc, A.gamma, lam);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) spd[k] = lam[k] > spd[k] ? lam[k] : spd[k];
+    }
+    block_max<3, kThreads / 64>(spd, red);
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    if (err) atomicOr(&s_err, err);
+    __syncthreads();
+    if (threadIdx.x < kFlat1Speeds) {
+        const int k = threadIdx.x;
+        flat1_slot(A, 0, b)[k] = k < 3 ? double_to_bits(spd[k]) : 0ull;
+        flat1_slot(A, 1, b)[k] = 0ull;
+        flat1_slot(A, 2, b)[k] = 0ull;
+    }
+    if (threadIdx.x == 0) {
+        A.time[b] = 0.0;
+        A.err[b] = s_err;
+        A.first[b] = s_err ? 0 : A.nsteps;
+    }
+}
+
+__global__ void flat1_dt_kernel(Flat1Args A)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.nprob) return;
+    if (A.step > 0 && A.err[b] && A.first[b] == A.nsteps) A.first[b] = A.step - 1;
+    const unsigned long long *sl = flat1_slot(A, 0, b);
+    const double l0 = bits_to_double(sl[0]), l2 = bits_to_double(sl[2]);
+    const double am = l2 > l0 ? l2 : l0;
+    const double dt = div_rn(A.cfl, div_rn(am, A.dx[b]));
+    A.dt[b] = dt;
+    A.time[b] = A.time[b] + dt;
+}
+
+__global__ void flat1_finish_kernel(Flat1Args A)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.nprob) return;
+    const int e = A.err[b];
+    int64_t first = A.first[b];
+    if (A.nsteps > 0 && e && first == A.nsteps) first = A.nsteps - 1;
+    if (A.t_out) A.t_out[b] = A.time[b];
+    if (A.steps_out) A.steps_out[b] = first;
+    if (A.status_out)
+        A.status_out[b] = e & kErrNonfinite ? WT_ERR_NONFINITE : (e ? WT_ERR_NONPHYSICAL : WT_OK);
+    else if (e)
+        atomicOr(&A.st->err, e);
+}
+
+// One stage over the 255-point segments of all problems.
+template <int PREC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void flat1_pass_kernel(Flat1Args A)
+{
+    constexpr int M = 3, TN = kThreads - 1, NC = TN + 6;
+    __shared__ double s_u[M][NC];
+    __shared__ double s_f[M][NC];
+    __shared__ double s_v[1][NC];
+    __shared__ double s_sr[NC];
+    __shared__ double s_H[NC];
+    __shared__ double s_F[M][kThreads];
+    __shared__ double s_al[M];
+
+    int64_t tile = blockIdx.x;
+    tile = (tile % kXcds) * A.tiles_per_xcd + tile / kXcds;
+    if (tile >= A.ntiles) return;
+    const int b = A.tile_prob[tile];
+    const int64_t g0 = (int64_t)A.tile_local[tile] * TN;
+    const int64_t n = A.n[b], off = A.off[b];
+    const int bc = A.bc[b];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        const unsigned long long *sl = flat1_slot(A, A.rd, b);
+#pragma unroll
+        for (int f = 0; f < M; ++f)
+            s_al[f] = split_speed([sl](int k) { return bits_to_double(sl[k]); }, f, bc == WT_REFLECTIVE);
+    }
+    int err = 0;
+    for (int i = t; i < NC; i += kThreads) {
+        const int64_t g = map_index(g0 - 3 + i, n, bc);
+        double uc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uc[c] = A.uin[c * A.total + off + g];
+        if (reflected(g0 - 3 + i, n, bc)) uc[1] = -uc[1];
+        double vel[1], p, H;
+        if (!euler_cell<1>(uc, A.gamma, vel, p, H)) {
+            const bool fin = __builtin_isfinite(uc[0]) && __builtin_isfinite(uc[1]) && __builtin_isfinite(uc[2]);
+            err |= fin ? kErrNonphysical : kErrNonfinite;
+        }
+        double fn[3];
+        euler_normal_flux<1, 0>(uc, vel, p, fn);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s_u[c][i] = uc[c];
+            s_f[c][i] = fn[c];
+        }
+        s_v[0][i] = vel[0];
+        s_sr[i] = sqrt_rn(uc[0]);
+        s_H[i] = H;
+    }
+    __syncthreads();
+    if (g0 + t <= n) {
+        const LdsStencil<M, 1, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, t};
+        double F[3];
+        if (!euler_interface_flux<1, 0, PREC, PREC == 0>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
+            err |= kErrNonphysical;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_F[c][t] = F[c];
+    }
+    __syncthreads();
+    double lam[3] = {0.0, 0.0, 0.0};
+    if (t < TN && g0 + t < n) {
+        const int64_t idx = off + g0 + t;
+        const double dt = A.dt[b], dx = A.dx[b], rdx = A.rdx[b];
+        double un[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double L = -div_by_recip(s_F[c][t + 1] - s_F[c][t], dx, rdx);
+            const int64_t o = c * A.total + idx;
+            if (A.stage == 1)
+                un[c] = A.uin[o] + dt * L;
+            else if (A.stage == 2)
+                un[c] = 0.75 * A.u0[o] + 0.25 * A.uin[o] + (0.25 * dt) * L;
+            else
+                un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * A.uin[o] + ((2.0 / 3.0) * dt) * L;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) A.out[c * A.total + idx] = un[c];
+        err |= euler_speeds<1>(un, A.gamma, lam);
+    }
+    if (err) atomicOr(&A.err[b], err);
+    const int src[3] = {0, 1, 2}, dst[3] = {0, 1, 2};
+    block_slot_max<3, 3>(lam, flat1_slot(A, A.wr, b), src, dst);
+    if (g0 == 0 && t < kFlat1Speeds)
+        __hip_atomic_store(&flat1_slot(A, A.zero, b)[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void reset_queue_kernel(int32_t *q)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
@@ -771,6 +977,11 @@ uint64_t bits(double d)
 
 void free_batch(wt_ctx *c)
 {
+    (void)hipFree(c->f1_state);
+    (void)hipFree(c->f1_tab);
+    c->f1_state = nullptr;
+    c->f1_tab = nullptr;
+    c->f1_state_cap = c->f1_tab_cap = 0;
     (void)hipFree(c->B1);
     (void)hipFree(c->B2);
     (void)hipFree(c->b_n);
@@ -827,7 +1038,7 @@ void release_batched(wt_ctx *c)
 
 namespace {
 
-constexpr int kBatchVariants1D = 2;   // tile variants of the 1D batched kernel
+constexpr int kBatchVariants1D = 3;   // 1D: persistent 256 / 128 threads, flat
 constexpr int kBatchVariants2D = 4;   // 2D: persistent 4x63 / 8x31 x tiles, flat 8x31 / 4x63
 constexpr uint64_t kAnyBatch = ~0ull; // variant key of wenotheta_set_batched_tiles: every batch
 
@@ -866,7 +1077,7 @@ wt_status persistent_grid(wt_ctx *c, Kernel k, int threads, int64_t nprob, int64
 // Validate a 1D batch, upload its tables and size the workspace; fills A.
 wt_status prepare_1d(wt_ctx *c, int64_t nprob, const int64_t *n, const int64_t *offset,
                      const double *lo, const double *hi, const int32_t *bc, const wt_params *P,
-                     double *u, int64_t total, int64_t nsteps, hipStream_t s, BatchArgs *A)
+                     double *u, int64_t total, int64_t nsteps, hipStream_t s, BatchArgs *A, bool flat)
 {
     if (!c || !P || !u || !n || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 6 || nsteps < 0) return WT_ERR_ARG;
@@ -953,12 +1164,116 @@ wt_status prepare_1d(wt_ctx *c, int64_t nprob, const int64_t *n, const int64_t *
     A->gamma = P->gamma;
     A->W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
     A->cfl = P->cfl;
+    if (!flat) return WT_OK;
+
+    // flat form: the 255-point segments of all problems, problem by problem
+    int64_t nft = 0;
+    for (int64_t b = 0; b < nprob; ++b) nft += (n[b] + kThreads - 2) / (kThreads - 1);
+    if (2 * nft > (int64_t(1) << 31)) return WT_ERR_ARG;
+    std::vector<int32_t> ttab(2 * nft);
+    for (int64_t b = 0, k = 0; b < nprob; ++b)
+        for (int64_t j = 0, m = (n[b] + kThreads - 2) / (kThreads - 1); j < m; ++j, ++k) {
+            ttab[k] = (int32_t)b;
+            ttab[nft + k] = (int32_t)j;
+        }
+    const size_t state_bytes = (size_t)nprob * (3 * kFlat1Speeds * sizeof(unsigned long long) +
+                                                2 * sizeof(double) + sizeof(int64_t) + sizeof(int32_t));
+    if (nprob > c->f1_state_cap || 2 * nft > c->f1_tab_cap) {
+        if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
+        if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+        c->b_graph = nullptr;
+        (void)hipFree(c->f1_state);
+        (void)hipFree(c->f1_tab);
+        c->f1_state = nullptr;
+        c->f1_tab = nullptr;
+        c->f1_state_cap = c->f1_tab_cap = 0;
+        if (hipMalloc(&c->f1_state, state_bytes) != hipSuccess ||
+            hipMalloc(&c->f1_tab, 2 * nft * sizeof(int32_t)) != hipSuccess) {
+            (void)hipFree(c->f1_state);
+            (void)hipFree(c->f1_tab);
+            c->f1_state = nullptr;
+            c->f1_tab = nullptr;
+            (void)hipGetLastError();
+            return WT_ERR_NOMEM;
+        }
+        c->f1_state_cap = nprob;
+        c->f1_tab_cap = 2 * nft;
+    }
+    if (hipMemcpyAsync(c->f1_tab, ttab.data(), 2 * nft * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return WT_ERR_DEVICE;
+    A->ft_prob = c->f1_tab;
+    A->ft_local = c->f1_tab + nft;
+    A->nft = nft;
+    char *p = (char *)c->f1_state;
+    A->f_spd = (unsigned long long *)p;
+    p += (size_t)nprob * 3 * kFlat1Speeds * sizeof(unsigned long long);
+    A->f_dt = (double *)p;
+    p += (size_t)nprob * sizeof(double);
+    A->f_time = (double *)p;
+    p += (size_t)nprob * sizeof(double);
+    A->f_first = (int64_t *)p;
+    p += (size_t)nprob * sizeof(int64_t);
+    A->f_err = (int32_t *)p;
     return WT_OK;
 }
 
-// Queue reset and the 1D kernel of tile variant v (0: 256 threads, 1: 128) on stream s.
+// The 1D flat form on stream s: initial speeds, nsteps x (time step, 3 passes), outputs.
+wt_status enqueue_1d_flat(const BatchArgs &B, int precision, hipStream_t s)
+{
+    Flat1Args F{};
+    F.total = B.total;
+    F.n = B.n;
+    F.off = B.off;
+    F.dx = B.dx;
+    F.rdx = B.rdx;
+    F.bc = B.bc;
+    F.tile_prob = B.ft_prob;
+    F.tile_local = B.ft_local;
+    F.ntiles = B.nft;
+    F.tiles_per_xcd = (B.nft + kXcds - 1) / kXcds;
+    F.spd = B.f_spd;
+    F.dt = B.f_dt;
+    F.time = B.f_time;
+    F.err = B.f_err;
+    F.first = B.f_first;
+    F.nprob = B.nprob;
+    F.nsteps = B.nsteps;
+    F.gamma = B.gamma;
+    F.cfl = B.cfl;
+    F.W = B.W;
+    F.t_out = B.t_out;
+    F.status_out = B.status_out;
+    F.steps_out = B.steps_out;
+    F.st = B.st;
+    const unsigned per_problem = (unsigned)((B.nprob + 255) / 256);
+    const dim3 grid((unsigned)(F.tiles_per_xcd * kXcds)), block(kThreads);
+    F.uin = B.u;
+    hipLaunchKernelGGL(flat1_init_kernel, dim3((unsigned)B.nprob), dim3(kThreads), 0, s, F);
+    for (int64_t step = 0; step < B.nsteps; ++step) {
+        F.step = step;
+        hipLaunchKernelGGL(flat1_dt_kernel, dim3(per_problem), dim3(256), 0, s, F);
+        for (int stage = 1; stage <= 3; ++stage) {
+            F.stage = stage;
+            F.uin = stage == 1 ? B.u : (stage == 2 ? B.U1 : B.U2);
+            F.out = stage == 1 ? B.U1 : (stage == 2 ? B.U2 : B.u);
+            F.u0 = B.u;
+            F.rd = stage - 1;
+            F.wr = stage % 3;
+            F.zero = (stage + 1) % 3;
+            if (precision == WT_FP32_RECON) hipLaunchKernelGGL(flat1_pass_kernel<1>, grid, block, 0, s, F);
+            else hipLaunchKernelGGL(flat1_pass_kernel<0>, grid, block, 0, s, F);
+        }
+    }
+    hipLaunchKernelGGL(flat1_finish_kernel, dim3(per_problem), dim3(256), 0, s, F);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_DEVICE;
+}
+
+// The 1D batch in variant v on s: the persistent kernel with workgroups of 256 (0)
+// or 128 threads (1), or the flat form (2).
 wt_status enqueue_1d(wt_ctx *c, const BatchArgs &A, int precision, int v, hipStream_t s)
 {
+    if (v == 2) return enqueue_1d_flat(A, precision, s);
     int64_t grid = 0;
     wt_status r;
     const int threads = v == 0 ? 256 : 128;
@@ -1299,7 +1614,8 @@ uint64_t launch_key(const void *u, const void *t_out, const void *status_out, co
                        (uint64_t)(uintptr_t)status_out, (uint64_t)(uintptr_t)steps_out,
                        (uint64_t)(uintptr_t)c->B1, (uint64_t)(uintptr_t)c->B2,
                        (uint64_t)(uintptr_t)c->BD, (uint64_t)(uintptr_t)c->f2_state,
-                       (uint64_t)(uintptr_t)c->f2_tab, (uint64_t)nprob, (uint64_t)total, (uint64_t)nsteps,
+                       (uint64_t)(uintptr_t)c->f2_tab, (uint64_t)(uintptr_t)c->f1_state,
+                       (uint64_t)(uintptr_t)c->f1_tab, (uint64_t)nprob, (uint64_t)total, (uint64_t)nsteps,
                        (uint64_t)P->precision, bits(P->gamma), bits(P->eps), bits(P->alpha_R),
                        bits(P->cfl), (uint64_t)variant})
         key = mix(key, v);
@@ -1369,14 +1685,15 @@ extern "C" wt_status wenotheta_solve_batched(wt_ctx *c, int64_t nprob, const int
                                              int64_t *steps_out, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
+    if (!c || !P || !n) return WT_ERR_ARG;
+    const uint64_t sig = batch_signature(1, nprob, n, nullptr, total, P->precision);
+    const int v = batch_variant(c->b_var, c->b_var_key, sig);
     BatchArgs A;
-    wt_status r = prepare_1d(c, nprob, n, offset, lo, hi, bc, P, u, total, nsteps, s, &A);
+    wt_status r = prepare_1d(c, nprob, n, offset, lo, hi, bc, P, u, total, nsteps, s, &A, v == 2);
     if (r != WT_OK) return r;
     A.t_out = t_out;
     A.status_out = status_out;
     A.steps_out = steps_out;
-    const uint64_t sig = batch_signature(1, nprob, n, nullptr, total, P->precision);
-    const int v = batch_variant(c->b_var, c->b_var_key, sig);
     const int prec = P->precision;
     return run_graph(c, &c->b_graph, &c->b_key,
                      launch_key(u, t_out, status_out, steps_out, c, nprob, total, nsteps, P, v, sig), s,
@@ -1418,7 +1735,7 @@ extern "C" wt_status wenotheta_tune_batched(wt_ctx *c, int64_t nprob, const int6
     const wt_status r = tune_variants<BatchArgs>(
         c, u, (size_t)total * 3, nprob, P->precision, kBatchVariants1D, s,
         [&](double *scratch, BatchArgs *A) {
-            return prepare_1d(c, nprob, n, offset, lo, hi, bc, P, scratch, total, probe_steps, s, A);
+            return prepare_1d(c, nprob, n, offset, lo, hi, bc, P, scratch, total, probe_steps, s, A, true);
         },
         [&](const BatchArgs &A, int prec, int v, hipStream_t cs) { return enqueue_1d(c, A, prec, v, cs); },
         &best);

@@ -58,7 +58,11 @@ struct wt_ctx {
     int64_t b2_cap = 0;         // problems the 2D tables hold
     hipGraphExec_t b2_graph = nullptr;
     uint64_t b2_key = 0;
-    // flat form of the 2D batches: per-problem state and per-pass tile tables
+    // flat forms of the 1D and 2D batches: per-problem state and tile tables
+    void *f1_state = nullptr;
+    int64_t f1_state_cap = 0;   // problems
+    int32_t *f1_tab = nullptr;
+    int64_t f1_tab_cap = 0;     // int32 entries
     void *f2_state = nullptr;
     int64_t f2_state_cap = 0;   // problems
     int32_t *f2_tab = nullptr;

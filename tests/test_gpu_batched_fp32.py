@@ -135,11 +135,15 @@ def test_batched_argument_errors(ctx):
     assert e.value.code == 2
 
 
-def test_batched_full_size_sampled(ctx):
+@pytest.mark.parametrize("variant", [0, 2])
+def test_batched_full_size_sampled(variant):
     """The batched workload at full size (4096 problems, N log-uniform in [256, 16384],
-    500 steps): the 6 smallest problems against the oracle, bit for bit."""
+    500 steps), persistent (0) and flat (2) form: the 6 smallest problems against the
+    oracle, bit for bit."""
     B = W.batched_1d(seed=0)
-    got, t, st, k = _run_batched(ctx, B, 500)
+    with wt.Context(0) as ctx:
+        wt.wenotheta_set_batched_tiles(ctx, 1, variant)
+        got, t, st, k = _run_batched(ctx, B, 500)
     ok = st == 0
     assert ok.sum() >= 0.97 * B.nprob           # ~2% of the seeded problems fail (no limiter)
     assert np.all(k[ok] == 500) and np.all(k[~ok] < 500)

@@ -25,7 +25,8 @@ _HDR = os.path.join(_HERE, "wto_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 LINEAR, BURGERS, EULER = 0, 1, 2
-PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
+PERIODIC, TRANSMISSIVE, REFLECTIVE, SIDES = 0, 1, 2, 3
+STATE = 3          # side part holding a given state
 DIAG_LEN = 19
 DIAG_NAMES = ("q0", "q1", "q2", "q3", "b0", "b1", "b2", "b3", "R", "restricted",
               "tau5", "tau6", "theta", "w0", "w1", "w2", "w3", "h", "tau")
@@ -53,13 +54,31 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+class _Side(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32 * 2), ("state", (ctypes.c_double * 5) * 2),
+                ("split0", ctypes.c_double), ("split_speed", ctypes.c_double)]
+
+
 class _Problem(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("system", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
                 ("bc", ctypes.c_int32 * 3), ("a", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("alpha_R", ctypes.c_double),
-                ("gravity", ctypes.c_double * 3)]
+                ("gravity", ctypes.c_double * 3), ("lo", ctypes.c_double * 3),
+                ("sides", ctypes.POINTER(_Side)), ("t", ctypes.c_double)]
+
+
+@dataclass
+class Side:
+    """One end of a dimension whose bc is SIDES (mirrors ``wto_side``): rule kind[0]
+    (TRANSMISSIVE, REFLECTIVE or STATE) on grid lines whose coordinate along the next
+    axis is below split0 + split_speed * t, kind[1] on the others; a STATE part puts
+    state[part] (conserved, m entries) into every ghost point."""
+    kind: tuple = (TRANSMISSIVE, TRANSMISSIVE)
+    state: tuple = ((), ())
+    split0: float = math.inf
+    split_speed: float = 0.0
 
 
 @dataclass
@@ -76,6 +95,9 @@ class Problem:
     eps: float = 1e-10
     alpha_R: float = 50.0
     gravity: tuple = (0.0, 0.0, 0.0)
+    lo: tuple = (0.0, 0.0, 0.0)
+    sides: tuple | None = None       # 6 Side entries [dim][lower, upper] for bc SIDES
+    t: float = 0.0
 
     @property
     def m(self) -> int:
@@ -100,8 +122,24 @@ class Problem:
                                                  float(self.cfl), float(self.eps),
                                                  float(self.alpha_R))
         g = list(self.gravity) + [0.0] * (3 - len(self.gravity))
+        lo = list(self.lo) + [0.0] * (3 - len(self.lo))
         for k in range(3):
             p.gravity[k] = float(g[k])
+            p.lo[k] = float(lo[k])
+        p.t = float(self.t)
+        if self.sides is not None:
+            if len(self.sides) != 6:
+                raise ValueError("sides: 6 entries [dim][lower, upper]")
+            arr = (_Side * 6)()
+            for i, sd in enumerate(self.sides):
+                for k in range(2):
+                    arr[i].kind[k] = int(sd.kind[k])
+                    for c, v in enumerate(sd.state[k]):
+                        arr[i].state[k][c] = float(v)
+                arr[i].split0 = float(sd.split0)
+                arr[i].split_speed = float(sd.split_speed)
+            p.sides = ctypes.cast(arr, ctypes.POINTER(_Side))
+            p._keep = arr                 # the table lives as long as the struct
         return p
 
 

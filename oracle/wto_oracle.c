@@ -17,6 +17,11 @@
  *                 epsilon = 1e-10 (remark iii of Sec. 3.1)
  *   Sec. 4.2/4.3  Euler equations, characteristic-wise reconstruction with the
  *                 Roe mean matrix, dimension by dimension in 2D/3D.
+ *   Sec. 4.3      TEST 9's boundaries as sides made of two parts (a given
+ *                 state, a wall, zero gradient) split at a point that may move.
+ *                 Parity unpinned: the times at which wto_step's stages take
+ *                 moving splits (t, t + dt, t + dt/2; a reading) are checked
+ *                 only against the stages assembled by hand.
  *
  * Built with -O2 -ffp-contract=off and without -ffast-math: every operation
  * below is one IEEE double rounding, evaluated left to right as written.
@@ -178,6 +183,50 @@ static int reflected(int64_t i, int64_t n, int32_t bc)
     return bc == WTO_REFLECTIVE && (i < 0 || i >= n);
 }
 
+static int64_t stride_of(const wto_problem *P, int d);
+
+/* Part (0 or 1) of side S of dimension d that the ghost points of the grid
+ * line starting at offset `base` belong to: 0 where the line's coordinate
+ * along the next axis lies below the split point at time P->t.
+ * Reading: Sec. 4.3 (TEST 9) gives the bottom and top boundaries as intervals
+ * of x on which a rule holds; a ghost point takes the rule of the interval
+ * that holds its own line's coordinate, x_j = lo + (j + 1/2) dx, with all
+ * three ghost points of a line on the same side of the split. */
+static int side_part(const wto_problem *P, int d, int64_t base, const wto_side *S)
+{
+    if (P->ndim == 1) return 0;
+    const int a = (d + 1) % P->ndim;
+    const int64_t j = (base / stride_of(P, a)) % P->n[a];
+    const double x = P->lo[a] + ((double)j + 0.5) * P->dx[a];
+    return x < S->split0 + S->split_speed * P->t ? 0 : 1;
+}
+
+/* Conserved state (canonical order) of point i of the grid line along d
+ * starting at offset `base`; i may be a ghost point (-3..-1, n..n+2). */
+static void line_point(const wto_problem *P, const double *u, int d, int64_t base,
+                       int64_t i, double *uc)
+{
+    const int m = P->ndim + 2;
+    const int64_t n = P->n[d], N = P->n[0] * P->n[1] * P->n[2];
+    int32_t rule = P->bc[d];
+    if (rule == WTO_SIDES) {
+        if (i >= 0 && i < n) {
+            rule = WTO_TRANSMISSIVE;           /* an interior point: itself */
+        } else {
+            const wto_side *S = &P->sides[2 * d + (i < 0 ? 0 : 1)];
+            const int part = side_part(P, d, base, S);
+            rule = S->kind[part];
+            if (rule == WTO_STATE) {
+                for (int c = 0; c < m; ++c) uc[c] = S->state[part][c];
+                return;
+            }
+        }
+    }
+    const int64_t cell = base + map_index(i, n, rule) * stride_of(P, d);
+    for (int c = 0; c < m; ++c) uc[c] = u[c * N + cell];
+    if (reflected(i, n, rule)) uc[1 + d] = -uc[1 + d];
+}
+
 static int64_t stride_of(const wto_problem *P, int d)
 {
     return d == 0 ? 1 : (d == 1 ? P->n[0] : P->n[0] * P->n[1]);
@@ -204,9 +253,26 @@ static int validate(const wto_problem *P)
             if (P->n[d] < 6) return WTO_ERR_ARG;
             if (!(P->dx[d] > 0.0)) return WTO_ERR_ARG;
             if (P->bc[d] != WTO_PERIODIC && P->bc[d] != WTO_TRANSMISSIVE &&
-                P->bc[d] != WTO_REFLECTIVE)
+                P->bc[d] != WTO_REFLECTIVE && P->bc[d] != WTO_SIDES)
                 return WTO_ERR_ARG;
-            if (P->bc[d] == WTO_REFLECTIVE && P->system != WTO_EULER) return WTO_ERR_UNSUPPORTED;
+            if ((P->bc[d] == WTO_REFLECTIVE || P->bc[d] == WTO_SIDES) && P->system != WTO_EULER)
+                return WTO_ERR_UNSUPPORTED;
+            if (P->bc[d] == WTO_SIDES) {
+                if (!P->sides || !isfinite(P->t) || !isfinite(P->lo[(d + 1) % P->ndim]))
+                    return WTO_ERR_ARG;
+                for (int e = 0; e < 2; ++e) {
+                    const wto_side *S = &P->sides[2 * d + e];
+                    if (S->split0 != S->split0 || !isfinite(S->split_speed)) return WTO_ERR_ARG;
+                    for (int k = 0; k < 2; ++k) {
+                        if (S->kind[k] != WTO_TRANSMISSIVE && S->kind[k] != WTO_REFLECTIVE &&
+                            S->kind[k] != WTO_STATE)
+                            return WTO_ERR_ARG;
+                        if (S->kind[k] == WTO_STATE)
+                            for (int c = 0; c < P->ndim + 2; ++c)
+                                if (!isfinite(S->state[k][c])) return WTO_ERR_ARG;
+                    }
+                }
+            }
         } else if (P->n[d] != 1) {
             return WTO_ERR_ARG;
         }
@@ -403,17 +469,13 @@ static int euler_interface_stencils(const wto_problem *P, const double *u, int d
                                     double R[MAXM][MAXM], int *perm)
 {
     const int ndim = P->ndim, m = ndim + 2;
-    const int64_t N = total_points(P);
-    const int64_t sd = stride_of(P, d);
     direction_perm(ndim, d, perm);
 
     double Up[6][MAXM], Fp[6][MAXM];
     prim_t Pk[6];
     for (int k = 0; k < 6; ++k) {
-        const int64_t cell = base + map_index(i - 2 + k, P->n[d], P->bc[d]) * sd;
         double uc[MAXM];
-        for (int c = 0; c < m; ++c) uc[c] = u[c * N + cell];
-        if (reflected(i - 2 + k, P->n[d], P->bc[d])) uc[1 + d] = -uc[1 + d];
+        line_point(P, u, d, base, i - 2 + k, uc);
         int st = primitives(uc, ndim, P->gamma, &Pk[k]);
         if (st) return st;
         for (int c = 0; c < m; ++c) Up[k][c] = uc[perm[c]];
@@ -542,17 +604,29 @@ int wto_alpha(const wto_problem *P, const double *u, double *alpha, double *amax
     return WTO_OK;
 }
 
+/* Whether dimension d has a wall: reflective ends, or a side with a
+ * reflective part. */
+static int has_wall(const wto_problem *P, int d)
+{
+    if (P->bc[d] == WTO_REFLECTIVE) return 1;
+    if (P->bc[d] != WTO_SIDES) return 0;
+    for (int e = 0; e < 2; ++e)
+        for (int k = 0; k < 2; ++k)
+            if (P->sides[2 * d + e].kind[k] == WTO_REFLECTIVE) return 1;
+    return 0;
+}
+
 /* Behind reflective walls in direction d the domain is the mirror-extended
  * one (the ghost points are its point values), where u_d changes sign and
  * the two acoustic fields (u_d - c, u_d + c) exchange their speeds, so over
  * that whole domain both have the larger maximum.  Applied to the speeds the
- * split uses, computed or given. */
+ * split uses, computed or given, also where only part of a side is a wall. */
 static void pair_wall_speeds(const wto_problem *P, double *alpha)
 {
     if (P->system != WTO_EULER) return;
     const int m = ncomp(P);
     for (int d = 0; d < P->ndim; ++d)
-        if (P->bc[d] == WTO_REFLECTIVE) {
+        if (has_wall(P, d)) {
             double *a = &alpha[d * m];
             const double both = a[2] > a[0] ? a[2] : a[0];
             a[0] = both;
@@ -747,18 +821,26 @@ int wto_step(const wto_problem *P, double *u, double dt, double *dt_used)
     double *u2 = (double *)malloc(sizeof(double) * M);
     if (!L || !u1 || !u2) { free(L); free(u1); free(u2); return WTO_ERR_ARG; }
 
+    /* Reading: boundary data that move (WTO_SIDES splits) are taken at the
+     * times the stages approximate, t^n, t^n + dt and t^n + dt/2 (the
+     * abscissae of the 3-stage scheme); the paper states none. */
+    wto_problem Q = *P;
+
     /* u(1) = u^n + dt L(u^n) */
-    st = wto_rhs(P, u, NULL, alpha, L);
+    Q.t = P->t;
+    st = wto_rhs(&Q, u, NULL, alpha, L);
     if (!st) {
         for (int64_t k = 0; k < M; ++k) u1[k] = u[k] + dt * L[k];
         /* u(2) = 3/4 u^n + 1/4 u(1) + 1/4 dt L(u(1)) */
-        st = wto_rhs(P, u1, NULL, NULL, L);
+        Q.t = P->t + dt;
+        st = wto_rhs(&Q, u1, NULL, NULL, L);
     }
     if (!st) {
         for (int64_t k = 0; k < M; ++k)
             u2[k] = 0.75 * u[k] + 0.25 * u1[k] + 0.25 * dt * L[k];
         /* u^{n+1} = 1/3 u^n + 2/3 u(2) + 2/3 dt L(u(2)) */
-        st = wto_rhs(P, u2, NULL, NULL, L);
+        Q.t = P->t + 0.5 * dt;
+        st = wto_rhs(&Q, u2, NULL, NULL, L);
     }
     if (!st)
         for (int64_t k = 0; k < M; ++k)
@@ -776,6 +858,7 @@ int wto_solve(const wto_problem *P, double *u, double t0, double t_end,
     if (st) return st;
     double t = t0;
     int64_t steps = 0;
+    wto_problem Q = *P;
     while (t < t_end && (max_steps < 0 || steps < max_steps)) {
         double alpha[3 * MAXM], amax[3];
         st = wto_alpha(P, u, alpha, amax);
@@ -786,7 +869,8 @@ int wto_solve(const wto_problem *P, double *u, double t0, double t_end,
          * being followed by a round-off-sized step. */
         int last = 0;
         if (t + dt >= t_end - 1e-6 * dt) { dt = t_end - t; last = 1; }
-        st = wto_step(P, u, dt, NULL);
+        Q.t = t;
+        st = wto_step(&Q, u, dt, NULL);
         if (st) break;
         t = last ? t_end : t + dt;
         ++steps;
@@ -811,7 +895,7 @@ int wto_decisions_1d(const wto_problem *P, const double *u, const double *alpha_
 {
     int st = validate(P);
     if (st) return st;
-    if (P->ndim != 1) return WTO_ERR_UNSUPPORTED;
+    if (P->ndim != 1 || P->bc[0] == WTO_SIDES) return WTO_ERR_UNSUPPORTED;
     const int m = ncomp(P);
     const int64_t n = P->n[0];
     double alpha[MAXM], amax[1];

@@ -21,15 +21,34 @@ extern "C" {
 enum { WTO_OK = 0, WTO_ERR_ARG = 1, WTO_ERR_UNSUPPORTED = 2,
        WTO_ERR_NONPHYSICAL = 3, WTO_ERR_NONFINITE = 4 };
 enum { WTO_LINEAR = 0, WTO_BURGERS = 1, WTO_EULER = 2 };
-enum { WTO_PERIODIC = 0, WTO_TRANSMISSIVE = 1, WTO_REFLECTIVE = 2 };
+enum { WTO_PERIODIC = 0, WTO_TRANSMISSIVE = 1, WTO_REFLECTIVE = 2, WTO_SIDES = 3 };
+/* Rule of one part of a side (bc WTO_SIDES): WTO_TRANSMISSIVE, WTO_REFLECTIVE,
+ * or WTO_STATE, a given state in every ghost point. */
+enum { WTO_STATE = 3 };
+
+/* One end of one dimension d whose bc is WTO_SIDES (Euler only).  The ghost
+ * points beyond that end on the grid line through coordinate x along the next
+ * axis a = (d + 1) mod ndim, x = lo[a] + (j + 1/2) dx[a] for the line's index
+ * j, follow the rule kind[0] where x < split0 + split_speed * t, else kind[1]
+ * (1D: always kind[0]).  A WTO_STATE part puts the conserved state state[part]
+ * (rho, m_x, .., E; m entries) into each ghost point.  This describes the
+ * boundaries of Sec. 4.3 TEST 9: inflow of a given state, a wall on part of
+ * a side and the given state on the rest, and a side whose given state
+ * changes at a point that moves with the shock. */
+typedef struct {
+    int32_t kind[2];
+    double  state[2][5];
+    double  split0;
+    double  split_speed;
+} wto_side;
 
 typedef struct {
     int32_t ndim;      /* 1, 2 or 3 (scalar systems: 1 only)                 */
     int32_t system;    /* WTO_LINEAR (f = a u), WTO_BURGERS (f = u^2/2), WTO_EULER */
     int64_t n[3];      /* points per dimension (n[k] = 1 for k >= ndim)     */
     double  dx[3];     /* grid spacing per dimension                        */
-    int32_t bc[3];     /* WTO_PERIODIC, WTO_TRANSMISSIVE or WTO_REFLECTIVE
-                          (Euler only) per dimension                          */
+    int32_t bc[3];     /* WTO_PERIODIC, WTO_TRANSMISSIVE, WTO_REFLECTIVE or
+                          WTO_SIDES (Euler only) per dimension               */
     double  a;         /* advection speed of WTO_LINEAR                     */
     double  gamma;     /* ratio of specific heats (Euler)                   */
     double  cfl;       /* CFL number                                        */
@@ -37,6 +56,13 @@ typedef struct {
     double  alpha_R;   /* restriction threshold; 0 disables, +inf = linear  */
     double  gravity[3];/* Euler: gravitational acceleration g_d along -x_d;
                           source (0, -rho g, -(g . m)) (Sec. 4.3, TEST 6)   */
+    double  lo[3];     /* coordinate of the domain's lower end per dimension
+                          (grid line coordinates of the WTO_SIDES splits)   */
+    const wto_side *sides; /* 6 sides [d][lower, upper end], read where
+                          bc[d] == WTO_SIDES (NULL if none)                 */
+    double  t;         /* time of the state: wto_rhs evaluates moving splits
+                          at t; wto_step advances from t (its stages at t,
+                          t + dt, t + dt/2); wto_solve ignores it (uses t0)  */
 } wto_problem;
 
 /* Number of diagnostic values written by wto_weno_theta_diag. */

@@ -17,12 +17,26 @@ components (rho, rho u, [rho v, [rho w,]] E).
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
 
-PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
+PERIODIC, TRANSMISSIVE, REFLECTIVE, SIDES = 0, 1, 2, 3
+STATE = 3                 # side part holding a given state
 LINEAR, BURGERS, EULER = 0, 1, 2
+
+
+@dataclass
+class SideSpec:
+    """One end of a dimension whose boundary condition is SIDES: rule kind[0]
+    (TRANSMISSIVE, REFLECTIVE or STATE) on the grid lines whose coordinate along the
+    next axis ((d + 1) mod ndim) is below split0 + split_speed * t, kind[1] on the
+    others; a STATE part puts the conserved state state[part] into the ghost points."""
+    kind: tuple = (TRANSMISSIVE, TRANSMISSIVE)
+    state: tuple = ((), ())
+    split0: float = math.inf
+    split_speed: float = 0.0
 
 
 @dataclass
@@ -42,6 +56,7 @@ class Case:
     steps: int | None = None
     extra: dict = field(default_factory=dict)
     gravity: tuple = (0.0, 0.0, 0.0)
+    sides: tuple | None = None    # 6 SideSpec [dim][lower, upper] where bc is SIDES
 
     @property
     def ndim(self) -> int:
@@ -456,3 +471,38 @@ def implosion(n: int = 400) -> Case:
     u = conserved(rho, [z, z], p)
     return Case("implosion", EULER, u, (0.0, 0.0), (1.0, 1.0), (REFLECTIVE, REFLECTIVE),
                 t_end=5.0, alpha_R=1.0)
+
+
+def double_mach(nx: int = 800, ny: int = 200) -> Case:
+    """Double Mach reflection of a Mach 10 shock (Sec. 4.3, TEST 9) on (0, 4) x (0, 1),
+    t = 0.2 (the paper's grid is 800 x 200).  The shock leaves the bottom at
+    x0 = 1/6 at 60 degrees to the x axis; behind it (x < x0 + y / tan 60)
+    (rho, u, v, p) = (8, 8.25 cos 30, -8.25 sin 30, 116.5), ahead (1.4, 0, 0, 1).
+    Sides: inflow of the post-shock state on the left, zero gradient on the right; at
+    the bottom the post-shock state for x < x0 and a wall beyond; at the top the
+    post-shock state for x < x_s(t) and the pre-shock state beyond, with
+    x_s(t) = x0 + 1 / tan 60 + M_s a_pre t / cos 30 (M_s = 10, a_pre the pre-shock
+    sound speed).  alpha_R = 10: the paper gives none for this problem, asks for a
+    small one where there are shocks and takes 10 for its strongest 1D shocks (Sec.
+    4.2); at the default 50 the first step already leaves a non-physical state."""
+    gamma = 1.4
+    x0 = 1.0 / 6.0
+    c30, s30, t60 = math.cos(math.pi / 6.0), math.sin(math.pi / 6.0), math.tan(math.pi / 3.0)
+    post = (8.0, 8.25 * c30, -8.25 * s30, 116.5)
+    pre = (1.4, 0.0, 0.0, 1.0)
+    a_pre = math.sqrt(gamma * pre[3] / pre[0])
+    cons = lambda w: tuple(float(v) for v in conserved(w[0], [w[1], w[2]], w[3], gamma))
+    U_post, U_pre = cons(post), cons(pre)
+    x = grid_points(nx, 0.0, 4.0, TRANSMISSIVE)[None, :]
+    y = grid_points(ny, 0.0, 1.0, TRANSMISSIVE)[:, None]
+    behind = x < x0 + y / t60
+    u = np.stack([np.where(behind, a, b) for a, b in zip(U_post, U_pre)])
+    sides = (SideSpec((STATE, STATE), (U_post, U_post)),              # x = 0: inflow
+             SideSpec((TRANSMISSIVE, TRANSMISSIVE)),                  # x = 4
+             SideSpec((STATE, REFLECTIVE), (U_post, ()), split0=x0),  # y = 0
+             SideSpec((STATE, STATE), (U_post, U_pre), split0=x0 + 1.0 / t60,
+                      split_speed=10.0 * a_pre / c30),                 # y = 1
+             SideSpec(), SideSpec())
+    return Case("double_mach", EULER, u, (0.0, 0.0), (4.0, 1.0), (SIDES, SIDES), gamma=gamma,
+                t_end=0.2, sides=sides, alpha_R=10.0,
+                extra={"x0": x0, "post": post, "pre": pre, "mach": 10.0, "a_pre": a_pre})

@@ -18,11 +18,20 @@ def grid_params(case: W.Case, alpha_R=None, cfl=None):
     return g, p
 
 
-def oracle_problem(case: W.Case, alpha_R=None, cfl=None) -> oracle.Problem:
+def oracle_sides(sides):
+    """The oracle's form of a workload's side table (None stays None)."""
+    if sides is None:
+        return None
+    return tuple(oracle.Side(kind=s.kind, state=s.state, split0=s.split0,
+                             split_speed=s.split_speed) for s in sides)
+
+
+def oracle_problem(case: W.Case, alpha_R=None, cfl=None, t=0.0) -> oracle.Problem:
     return oracle.Problem(ndim=case.ndim, system=case.system, n=case.n, dx=case.dx, bc=case.bc,
                           a=case.a, gamma=case.gamma, cfl=case.cfl if cfl is None else cfl,
                           alpha_R=case.alpha_R if alpha_R is None else alpha_R,
-                          gravity=tuple(case.gravity))
+                          gravity=tuple(case.gravity), lo=tuple(case.lo),
+                          sides=oracle_sides(case.sides), t=t)
 
 
 def to_dev(a):

@@ -118,14 +118,23 @@ def build_case(workload: str, n: int | None):
         return W.euler1d_seeded(0, n or 65536), "1D Euler, seeded Riemann data with density wave"
     if workload == "euler3d":
         return W.euler3d_seeded(0, n or 512), "3D Euler, seeded vortex with density spheres"
+    if workload == "double_mach":
+        ny = n or 200
+        return (W.double_mach(4 * ny, ny),
+                "2D Euler, double Mach reflection of a Mach 10 shock (Sec. 4.3 TEST 9)")
     raise SystemExit(f"unknown workload {workload}")
 
 
 def cpu_baseline(case, workload):
     """The oracle on the host: one full RK3 step of the workload (bounded sample)."""
     import oracle
+    sides = None
+    if case.sides is not None:
+        sides = tuple(oracle.Side(kind=sd.kind, state=sd.state, split0=sd.split0,
+                                  split_speed=sd.split_speed) for sd in case.sides)
     P = oracle.Problem(ndim=case.ndim, system=case.system, n=case.n, dx=case.dx, bc=case.bc,
-                       gamma=case.gamma, cfl=case.cfl, alpha_R=case.alpha_R)
+                       gamma=case.gamma, cfl=case.cfl, alpha_R=case.alpha_R, lo=tuple(case.lo),
+                       sides=sides)
     oracle.lib()
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     cells = 1
@@ -179,6 +188,9 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None)
     p = wt.Params(system=case.system, gamma=case.gamma, cfl=case.cfl, alpha_R=case.alpha_R,
                   precision=precision)
     u_init = torch.from_numpy(case.u).cuda()
+    if case.sides is not None:
+        wt.wenotheta_set_sides(ctx, [wt.Side(kind=sd.kind, state=sd.state, split0=sd.split0,
+                                             split_speed=sd.split_speed) for sd in case.sides], 0.0)
     if tile_choice is None:
         tiles = wt.wenotheta_tune(ctx, g, p, u_init)      # untimed set-up: y/z tile shapes
     else:
@@ -366,9 +378,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="euler2d", choices=["euler2d", "euler1d", "euler3d"])
+    ap.add_argument("--workload", default="euler2d", choices=["euler2d", "euler1d", "euler3d", "double_mach"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--n", type=int, default=None, help="points per dimension (default: full size)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="points per dimension (double_mach: in y, 4n in x; default: full size)")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--batched2d-steps", type=int, default=100)
     ap.add_argument("--tiles", default="auto", choices=["auto", "0", "1", "2", "3"],

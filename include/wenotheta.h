@@ -65,7 +65,7 @@ typedef enum {
 typedef enum {
     WT_PERIODIC = 0,     /* wrap-around                                     */
     WT_TRANSMISSIVE = 1, /* zero gradient: ghost points copy the nearest point */
-    WT_REFLECTIVE = 2    /* wall half a spacing beyond the end points (Euler
+    WT_REFLECTIVE = 2,   /* wall half a spacing beyond the end points (Euler
                             only; Sec. 4.2 TEST 5, Sec. 4.3 TESTs 6, 7): ghost
                             points are the mirror images of the points across
                             the wall, with the momentum normal to it negated;
@@ -73,7 +73,33 @@ typedef enum {
                             fields (u_d -+ c) the larger of their two maximum
                             speeds, computed or given, as over the mirror-
                             extended domain where they exchange speeds */
+    WT_SIDES = 3         /* Euler only: each end follows its entry of the
+                            context's side table (wenotheta_set_sides)       */
 } wt_bc;
+
+/* Rule of one part of a side. */
+typedef enum {
+    WT_SIDE_TRANSMISSIVE = 1, /* zero gradient, as WT_TRANSMISSIVE           */
+    WT_SIDE_REFLECTIVE = 2,   /* a wall, as WT_REFLECTIVE (a dimension with a
+                                 wall part anywhere pairs its acoustic speeds) */
+    WT_SIDE_STATE = 3         /* every ghost point holds the given state     */
+} wt_side_kind;
+
+/* One end of one dimension d of a grid whose bc[d] is WT_SIDES (Sec. 4.3,
+ * TEST 9: inflow of a given state; a wall on part of a side and a given state
+ * on the rest; a side whose given state changes at a point moving with a
+ * shock).  The ghost points beyond that end on the grid line with coordinate
+ * x = lo[a] + (j + 1/2) dx_a along the next axis a = (d + 1) mod ndim follow
+ * kind[0] where x < split0 + split_speed * t, kind[1] elsewhere (1D: always
+ * kind[0]); t is the time of the state being differentiated.  A
+ * WT_SIDE_STATE part puts the conserved state state[part] (rho, m_x, ..., E:
+ * ndim + 2 entries) into each of the line's ghost points. */
+typedef struct {
+    int32_t kind[2];      /* wt_side_kind of part 0 and part 1              */
+    double state[2][5];   /* given states of WT_SIDE_STATE parts            */
+    double split0;        /* split point at t = 0 (+-inf: one part only)    */
+    double split_speed;   /* its speed (finite)                             */
+} wt_side;
 
 typedef enum {
     WT_FP64 = 0,         /* every step in IEEE double precision, in the plain
@@ -132,7 +158,8 @@ const char *wenotheta_status_string(int32_t status);
  * alpha_host (HOST array of ndim*m values, [dir][field]) is given.
  * f: optional device array of caller-evaluated flux point values f(u_j), for
  * the 1D scalar case only; it then requires alpha_host (alpha = max|f'(u)|,
- * remark on flux splitting).  Asynchronous. */
+ * remark on flux splitting).  Moving side splits (WT_SIDES) are taken at the
+ * context's time (wenotheta_set_sides).  Asynchronous. */
 wt_status wenotheta_rhs(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
                         const double *u, const double *f, const double *alpha_host,
                         double *L_out, void *stream);
@@ -140,7 +167,9 @@ wt_status wenotheta_rhs(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
 /* One 3-stage TVD Runge-Kutta step (Sec. 2.1) of u in place.  dt > 0 is used
  * as given; dt <= 0 selects the CFL step dt = cfl / sum_d(amax_d / dx_d),
  * amax_d the largest wave speed in direction d.  dt_used_dev: optional
- * DEVICE pointer receiving the step taken.  Asynchronous. */
+ * DEVICE pointer receiving the step taken.  The step starts at the context's
+ * time t and advances it to t + dt; its stages take moving side splits at
+ * t, t + dt and t + dt/2.  Asynchronous. */
 wt_status wenotheta_step(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
                          double *u, double dt, double *dt_used_dev, void *stream);
 
@@ -148,11 +177,23 @@ wt_status wenotheta_step(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
  * clipped to end at t_end (a step that would leave less than 1e-6 of itself
  * to go is stretched to t_end), or until max_steps steps have been taken
  * (max_steps < 0: no limit).  Synchronises; *t_out and *steps_out (HOST,
- * optional) receive the time reached and the steps taken.  Returns any error
- * the device recorded. */
+ * optional) receive the time reached and the steps taken, which also becomes
+ * the context's time.  Returns any error the device recorded. */
 wt_status wenotheta_solve(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
                           double *u, double t0, double t_end, int64_t max_steps,
                           double *t_out, int64_t *steps_out, void *stream);
+
+/* Side table of the context for grids with bc[k] == WT_SIDES (sides[2k] the
+ * lower and sides[2k + 1] the upper end of dimension k; entries of other
+ * dimensions are not read), and the context's time t (HOST value, finite):
+ * the time wenotheta_rhs takes moving splits at and wenotheta_step starts
+ * from.  sides (HOST, 6 entries, copied) may be NULL to remove the table.
+ * WT_ERR_ARG for an unknown kind, a NaN split0, a non-finite split_speed or a
+ * non-finite entry of a given state (all 5, unused ones too); a given state that is not physical (rho <= 0 or
+ * p <= 0) is reported by the device as WT_ERR_NONPHYSICAL when a ghost point
+ * takes it.  Calls with WT_SIDES grids return WT_ERR_ARG while no table is
+ * set.  Stream-ordered (the time is set on the stream). */
+wt_status wenotheta_set_sides(wt_ctx *ctx, const wt_side *sides, double t, void *stream);
 
 /* Batched solves: nprob independent 1D Euler problems (prm->system must be
  * WT_EULER, prm->gravity all 0, else WT_ERR_UNSUPPORTED) packed side by side

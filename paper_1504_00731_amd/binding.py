@@ -18,14 +18,16 @@ LIB_PATH = os.path.join(HERE, "libwenotheta.so")
 WT_OK, WT_ERR_ARG, WT_ERR_UNSUPPORTED, WT_ERR_NONPHYSICAL = 0, 1, 2, 3
 WT_ERR_NONFINITE, WT_ERR_DEVICE, WT_ERR_NOMEM = 4, 5, 6
 WT_LINEAR, WT_BURGERS, WT_EULER = 0, 1, 2
-WT_PERIODIC, WT_TRANSMISSIVE, WT_REFLECTIVE = 0, 1, 2
+WT_PERIODIC, WT_TRANSMISSIVE, WT_REFLECTIVE, WT_SIDES = 0, 1, 2, 3
+WT_SIDE_TRANSMISSIVE, WT_SIDE_REFLECTIVE, WT_SIDE_STATE = 1, 2, 3
 WT_FP64, WT_FP32_RECON = 0, 1
 
 EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
             "wenotheta_rhs", "wenotheta_step", "wenotheta_solve", "wenotheta_sync",
             "wenotheta_profile", "wenotheta_profile_read", "wenotheta_solve_batched",
             "wenotheta_solve_batched_2d", "wenotheta_tune_batched", "wenotheta_tune_batched_2d",
-            "wenotheta_set_batched_tiles", "wenotheta_tune", "wenotheta_set_tiles")
+            "wenotheta_set_batched_tiles", "wenotheta_tune", "wenotheta_set_tiles",
+            "wenotheta_set_sides")
 PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
                  "sweep_z_final")
 
@@ -46,6 +48,11 @@ class wt_grid(ctypes.Structure):
                 ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 3),
                 ("reserved1", ctypes.c_int32)]
+
+
+class wt_side(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32 * 2), ("state", (ctypes.c_double * 5) * 2),
+                ("split0", ctypes.c_double), ("split_speed", ctypes.c_double)]
 
 
 class wt_params(ctypes.Structure):
@@ -94,6 +101,7 @@ def _lib():
         i32p3 = ctypes.POINTER(ctypes.c_int32)
         L.wenotheta_tune.argtypes = [vp, G, P, vp, i32p3, vp]
         L.wenotheta_set_tiles.argtypes = [vp, G, P, i32p3]
+        L.wenotheta_set_sides.argtypes = [vp, ctypes.POINTER(wt_side), ctypes.c_double, vp]
         for name in EXPORTED:
             if name != "wenotheta_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -128,6 +136,18 @@ class Grid:
             g.hi[k] = float(self.hi[k]) if inside else 1.0
             g.bc[k] = int(self.bc[k]) if inside else 0
         return g
+
+
+@dataclass
+class Side:
+    """One end of a WT_SIDES dimension (``wt_side``): rule kind[0] (WT_SIDE_TRANSMISSIVE,
+    WT_SIDE_REFLECTIVE or WT_SIDE_STATE) on the grid lines whose coordinate along the
+    next axis is below split0 + split_speed * t, kind[1] on the others; a WT_SIDE_STATE
+    part puts state[part] (conserved, ndim + 2 entries) into the ghost points."""
+    kind: tuple = (WT_SIDE_TRANSMISSIVE, WT_SIDE_TRANSMISSIVE)
+    state: tuple = ((), ())
+    split0: float = math.inf
+    split_speed: float = 0.0
 
 
 @dataclass
@@ -276,6 +296,26 @@ def wenotheta_set_tiles(ctx: Context, grid: Grid, params: Params, tiles) -> None
     arr = (ctypes.c_int32 * 3)(*[int(v) for v in t[:3]])
     _check(_lib().wenotheta_set_tiles(ctx.handle, ctypes.byref(grid.c_struct()),
                                       ctypes.byref(params.c_struct()), arr), "wenotheta_set_tiles")
+
+
+def wenotheta_set_sides(ctx: Context, sides, t: float = 0.0, stream=None) -> None:
+    """Sets the context's side table (6 Side entries [dim][lower, upper], or None to
+    remove it) for grids with WT_SIDES dimensions, and the context's time t."""
+    ptr = None
+    if sides is not None:
+        if len(sides) != 6:
+            raise ValueError("sides: 6 entries [dim][lower, upper]")
+        arr = (wt_side * 6)()
+        for i, sd in enumerate(sides):
+            for k in range(2):
+                arr[i].kind[k] = int(sd.kind[k])
+                for c, v in enumerate(sd.state[k]):
+                    arr[i].state[k][c] = float(v)
+            arr[i].split0 = float(sd.split0)
+            arr[i].split_speed = float(sd.split_speed)
+        ptr = ctypes.cast(arr, ctypes.POINTER(wt_side))
+    _check(_lib().wenotheta_set_sides(ctx.handle, ptr, float(t), _stream_ptr(stream)),
+           "wenotheta_set_sides")
 
 
 def wenotheta_sync(ctx: Context, stream=None):

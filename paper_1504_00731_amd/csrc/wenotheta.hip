@@ -58,7 +58,51 @@ struct SweepArgs {
     int64_t tiles_per_xcd;
     double grav[3];        // gravitational acceleration along -x_d (Euler)
     int has_grav;          // any grav[d] != 0: the source is added to L
+    int walls;             // a wall on the sweep's dimension: acoustic speeds paired
+    // WT_SIDES: the lower and upper ends' sides, and the coordinate origin and
+    // spacing of the axis their splits run along ((DIR + 1) mod ndim)
+    wt_side side[2];
+    double tlo, tdx;
 };
+
+// Time of the state a sweep differentiates: the context's time for a
+// right-hand side (stage 0), t^n, t^n + dt and t^n + dt/2 for the stages of a
+// step (the abscissae of the 3-stage scheme).
+__device__ __forceinline__ double stage_time(const DevState *st, int stage)
+{
+    if (stage == 2) return st->tn + st->dt;
+    if (stage == 3) return st->tn + 0.5 * st->dt;
+    return stage == 1 ? st->tn : st->t;
+}
+
+// Ghost point gi (< 0 or >= nd) of a grid line of a WT_SIDES dimension (Sec.
+// 4.3, TEST 9): the side of that end is split along the next axis; the
+// line's coordinate there, lo + (jt + 1/2) dx, below the split point at the
+// stage's time selects part 0.  A given state fills the point; a wall part is
+// the mirror image with the normal momentum negated; otherwise zero gradient.
+template <int NDIM, int DIR, int M>
+__device__ __forceinline__ void side_point(const SweepArgs &A, const DevState *st, int64_t gi,
+                                           int64_t nd, int64_t at, int64_t sstride, int64_t jt,
+                                           double *uc)
+{
+    const wt_side &S = A.side[gi < 0 ? 0 : 1];
+    int part = 0;
+    if constexpr (NDIM > 1) {
+        const double x = A.tlo + ((double)jt + 0.5) * A.tdx;
+        part = x < S.split0 + S.split_speed * stage_time(st, A.stage) ? 0 : 1;
+    }
+    const int kind = S.kind[part];
+    if (kind == WT_SIDE_STATE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) uc[c] = S.state[part][c];
+        return;
+    }
+    const int rule = kind == WT_SIDE_REFLECTIVE ? WT_REFLECTIVE : WT_TRANSMISSIVE;
+    const int64_t idx = at + map_index(gi, nd, rule) * sstride;
+#pragma unroll
+    for (int c = 0; c < M; ++c) uc[c] = A.uin[c * A.ncell + idx];
+    if (reflected(gi, nd, rule)) uc[1 + DIR] = -uc[1 + DIR];
+}
 
 
 // ---------------------------------------------------------------------------
@@ -138,6 +182,7 @@ __global__ void step_begin_kernel(StepArgs A)
         st->done = 1;
         return;
     }
+    st->tn = st->t;
     double dt = A.dt_fixed;
     if (!(dt > 0.0)) {
         // dt = cfl / sum_d amax_d / dx_d, amax_d = max(|u_d| + c) = max(alpha_{d,0}, alpha_{d,2})
@@ -167,15 +212,22 @@ __global__ void step_begin_kernel(StepArgs A)
     st->steps = st->steps + 1;
 }
 
-__global__ void solve_init_kernel(DevState *st, double t0, double t_end, long long max_steps)
+// set_t = 0 keeps the context's time (a single step starts from it).
+__global__ void solve_init_kernel(DevState *st, double t0, double t_end, long long max_steps,
+                                  int set_t)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->t = t0;
+        if (set_t) st->t = t0;
         st->t_end = t_end;
         st->steps = 0;
         st->max_steps = max_steps;
         st->done = 0;
     }
+}
+
+__global__ void set_time_kernel(DevState *st, double t)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->t = t;
 }
 
 __global__ void copy_dt_kernel(const DevState *st, double *dst)
@@ -262,11 +314,13 @@ void sweep_kernel(SweepArgs A)
     // tile -> (x0, seg, base): base is the offset of sweep index 0 of column x0
     int64_t seg, x0 = 0, base;
     int64_t sstride;
+    int64_t tline = 0;                           // line index along the split axis (WT_SIDES)
     if constexpr (DIR == 0) {
         seg = b % nseg;
         const int64_t row = b / nseg;            // y + z * ny
         base = row * nx;
         sstride = 1;
+        tline = NDIM == 3 ? row % ny : row;
     } else if constexpr (DIR == 1) {
         const int64_t gx = b % ngx;
         const int64_t r = b / ngx;
@@ -275,6 +329,7 @@ void sweep_kernel(SweepArgs A)
         x0 = gx * TX;
         base = z * nx * ny + x0;
         sstride = nx;
+        tline = z;
     } else {
         const int64_t gx = b % ngx;
         const int64_t r = b / ngx;
@@ -291,15 +346,20 @@ void sweep_kernel(SweepArgs A)
     int err = 0;
     for (int i = threadIdx.x; i < NC; i += kThreads) {
         const int r = i / TX, cx = i % TX;
-        const int64_t g = map_index(g0 - 3 + r, nd, A.bc);
+        const int64_t gi = g0 - 3 + r;
         int64_t xo = cx;
         if constexpr (DIR != 0) xo = x0 + cx < nx ? cx : nx - 1 - x0;
-        const int64_t idx = base + g * sstride + xo;
         if constexpr (EULER) {
             double uc[M];
+            if (A.bc == WT_SIDES && (gi < 0 || gi >= nd)) {
+                const int64_t jt = DIR == 0 || (NDIM == 3 && DIR == 1) ? tline : x0 + xo;
+                side_point<NDIM, DIR, M>(A, st, gi, nd, base + xo, sstride, jt, uc);
+            } else {
+                const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
 #pragma unroll
-            for (int c = 0; c < M; ++c) uc[c] = A.uin[c * ncell + idx];
-            if (reflected(g0 - 3 + r, nd, A.bc)) uc[1 + DIR] = -uc[1 + DIR];
+                for (int c = 0; c < M; ++c) uc[c] = A.uin[c * ncell + idx];
+                if (reflected(gi, nd, A.bc)) uc[1 + DIR] = -uc[1 + DIR];
+            }
             double vel[NDIM], p, H;
             const bool ok = euler_cell<NDIM>(uc, A.gamma, vel, p, H);
             if (!ok) {
@@ -320,6 +380,7 @@ void sweep_kernel(SweepArgs A)
             s_sr[i] = sqrt_rn(uc[0]);
             s_H[i] = H;
         } else {
+            const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
             const double x = A.uin[idx];
             double f;
             if (A.fgiven) f = A.fgiven[idx];
@@ -342,7 +403,7 @@ void sweep_kernel(SweepArgs A)
         RoeBasis<NDIM> B{};
         if (valid) {
             B = interface_basis<NDIM, DIR>(S, A.gamma);
-            const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.bc == WT_REFLECTIVE};
+            const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.walls != 0};
             s_h[f][it] = euler_field_flux<NDIM, DIR, PREC, fresh_rows<NDIM, PREC>()>(S, B, f, al, A.W);
             if (f == 0 && !B.ok) atomicOr(&st->err, kErrNonphysical);
         }
@@ -370,7 +431,7 @@ void sweep_kernel(SweepArgs A)
         if (valid) {
             if constexpr (EULER) {
                 const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
-                const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.bc == WT_REFLECTIVE};
+                const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.walls != 0};
                 if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.W, F))
                     atomicOr(&st->err, kErrNonphysical);
             } else {
@@ -627,13 +688,17 @@ struct Shape {
     int64_t n[3];
     int64_t ncell;
     double dx[3];
+    double lo[3];
     int bc[3];
+    int walls[3];         // reflective ends, or a side with a wall part
+    bool sides;           // some dimension is WT_SIDES
 };
 
-wt_status validate(const wt_grid *G, const wt_params *P, Shape &S)
+wt_status validate(const wt_ctx *c, const wt_grid *G, const wt_params *P, Shape &S)
 {
     if (!G || !P) return WT_ERR_ARG;
     if (G->ndim < 1 || G->ndim > 3) return WT_ERR_ARG;
+    S.sides = false;
     if (P->system < WT_LINEAR || P->system > WT_EULER) return WT_ERR_ARG;
     if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
     if (P->system != WT_EULER && G->ndim != 1) return WT_ERR_UNSUPPORTED;
@@ -651,17 +716,30 @@ wt_status validate(const wt_grid *G, const wt_params *P, Shape &S)
         if (k < G->ndim) {
             if (G->n[k] < 6 || G->n[k] > (int64_t(1) << 31)) return WT_ERR_ARG;
             if (!(G->hi[k] > G->lo[k])) return WT_ERR_ARG;
-            if (G->bc[k] != WT_PERIODIC && G->bc[k] != WT_TRANSMISSIVE && G->bc[k] != WT_REFLECTIVE)
+            if (G->bc[k] != WT_PERIODIC && G->bc[k] != WT_TRANSMISSIVE && G->bc[k] != WT_REFLECTIVE &&
+                G->bc[k] != WT_SIDES)
                 return WT_ERR_ARG;
-            if (G->bc[k] == WT_REFLECTIVE && P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
+            if ((G->bc[k] == WT_REFLECTIVE || G->bc[k] == WT_SIDES) && P->system != WT_EULER)
+                return WT_ERR_UNSUPPORTED;
+            if (G->bc[k] == WT_SIDES && !c->has_sides) return WT_ERR_ARG;
             S.n[k] = G->n[k];
             S.dx[k] = (G->hi[k] - G->lo[k]) / (double)G->n[k];
+            S.lo[k] = G->lo[k];
             S.bc[k] = G->bc[k];
+            S.walls[k] = G->bc[k] == WT_REFLECTIVE;
+            if (G->bc[k] == WT_SIDES) {
+                S.sides = true;
+                for (int e = 0; e < 2; ++e)
+                    for (int q = 0; q < 2; ++q)
+                        S.walls[k] |= c->sides[2 * k + e].kind[q] == WT_SIDE_REFLECTIVE;
+            }
         } else {
             if (G->n[k] != 1) return WT_ERR_ARG;
             S.n[k] = 1;
             S.dx[k] = 1.0;
+            S.lo[k] = 0.0;
             S.bc[k] = WT_PERIODIC;
+            S.walls[k] = 0;
         }
         S.ncell *= S.n[k];
     }
@@ -776,6 +854,22 @@ SweepArgs base_args(wt_ctx *c, const Shape &S, const wt_params *P)
     return A;
 }
 
+// The arguments of a sweep along direction d.
+void dir_args(SweepArgs &A, const wt_ctx *c, const Shape &S, int d)
+{
+    A.dx = S.dx[d];
+    A.rdx = 1.0 / S.dx[d];
+    A.bc = S.bc[d];
+    A.walls = S.walls[d];
+    if (S.bc[d] == WT_SIDES) {
+        const int a = (d + 1) % S.ndim;
+        A.side[0] = c->sides[2 * d];
+        A.side[1] = c->sides[2 * d + 1];
+        A.tlo = S.lo[a];
+        A.tdx = S.dx[a];
+    }
+}
+
 // Queue the speeds of u into slot g % 3 and zero slot (g + 1) % 3.
 wt_status queue_alpha_init(wt_ctx *c, const Shape &S, const wt_params *P, const double *u,
                            hipStream_t s)
@@ -805,9 +899,7 @@ wt_status queue_stage(wt_ctx *c, const Shape &S, const wt_params *P, const doubl
     A.slot_zero = (int)((c->g + 2) % kSlots);
     for (int d = 0; d < S.ndim; ++d) {
         const int mode = d == S.ndim - 1 ? MODE_LAST_STAGE : (d == 0 ? MODE_FIRST : MODE_MID);
-        A.dx = S.dx[d];
-        A.rdx = 1.0 / S.dx[d];
-        A.bc = S.bc[d];
+        dir_args(A, c, S, d);
         if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, plan_tile(c, S, P, d), s) !=
             hipSuccess)
             return WT_ERR_DEVICE;
@@ -850,6 +942,12 @@ wt_status ensure_step_graph(wt_ctx *c, const Shape &S, const wt_params *P, doubl
                        bits(P->gravity[0]), bits(P->gravity[1]), bits(P->gravity[2]), bits(S.dx[0]),
                        bits(S.dx[1]), bits(S.dx[2]), (uint64_t)S.bc[0], (uint64_t)S.bc[1], (uint64_t)S.bc[2]})
         key = (key ^ v) * 1099511628211ull;
+    if (S.sides) {
+        // the side table and the split axes' origins are captured in the sweeps' arguments
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(c->sides);
+        for (size_t i = 0; i < sizeof c->sides; ++i) key = (key ^ b[i]) * 1099511628211ull;
+        for (int k = 0; k < 3; ++k) key = (key ^ bits(S.lo[k])) * 1099511628211ull;
+    }
     if (c->s_graph && c->s_key == key) return WT_OK;
     if (c->s_graph) (void)hipGraphExecDestroy(c->s_graph);
     c->s_graph = nullptr;
@@ -993,7 +1091,7 @@ wt_status wenotheta_rhs(wt_ctx *c, const wt_grid *G, const wt_params *P, const d
 {
     if (!c || !u || !L) return WT_ERR_ARG;
     Shape S;
-    wt_status r = validate(G, P, S);
+    wt_status r = validate(c, G, P, S);
     if (r) return r;
     if (f && (P->system == WT_EULER || !alpha_host)) return WT_ERR_ARG;
     if (alpha_host)
@@ -1019,9 +1117,7 @@ wt_status wenotheta_rhs(wt_ctx *c, const wt_grid *G, const wt_params *P, const d
     A.slot_rd = (int)(c->g % kSlots);
     for (int d = 0; d < S.ndim; ++d) {
         const int mode = d == S.ndim - 1 ? MODE_LAST_RHS : (d == 0 ? MODE_FIRST : MODE_MID);
-        A.dx = S.dx[d];
-        A.rdx = 1.0 / S.dx[d];
-        A.bc = S.bc[d];
+        dir_args(A, c, S, d);
         if (timed_sweep(c, P->system, S.ndim, P->precision, d, mode, A, plan_tile(c, S, P, d), s) !=
             hipSuccess)
             return WT_ERR_DEVICE;
@@ -1034,13 +1130,13 @@ wt_status wenotheta_step(wt_ctx *c, const wt_grid *G, const wt_params *P, double
 {
     if (!c || !u) return WT_ERR_ARG;
     Shape S;
-    wt_status r = validate(G, P, S);
+    wt_status r = validate(c, G, P, S);
     if (r) return r;
     if (!std::isfinite(dt)) return WT_ERR_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
     if ((r = ensure_workspace(c, S))) return r;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, 0.0, 0.0, -1ll);
+    hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, 0.0, 0.0, -1ll, 0);
     if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
     if ((r = queue_alpha_init(c, S, P, u, s))) return r;
     if ((r = queue_step(c, S, P, u, dt > 0.0 ? dt : 0.0, 0, s))) return r;
@@ -1057,7 +1153,7 @@ wt_status wenotheta_solve(wt_ctx *c, const wt_grid *G, const wt_params *P, doubl
 {
     if (!c || !u) return WT_ERR_ARG;
     Shape S;
-    wt_status r = validate(G, P, S);
+    wt_status r = validate(c, G, P, S);
     if (r) return r;
     if (std::isnan(t0) || std::isnan(t_end) || !std::isfinite(t0)) return WT_ERR_ARG;
     if (!std::isfinite(t_end) && max_steps < 0) return WT_ERR_ARG;
@@ -1065,7 +1161,7 @@ wt_status wenotheta_solve(wt_ctx *c, const wt_grid *G, const wt_params *P, doubl
     if ((r = ensure_workspace(c, S))) return r;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, t0, t_end,
-                       (long long)max_steps);
+                       (long long)max_steps, 1);
     if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
     if ((r = queue_alpha_init(c, S, P, u, s))) return r;
     // Steps are queued in chunks (1, 2, 4, .. 64 steps) with one synchronisation
@@ -1098,11 +1194,40 @@ wt_status wenotheta_solve(wt_ctx *c, const wt_grid *G, const wt_params *P, doubl
     return WT_OK;
 }
 
+wt_status wenotheta_set_sides(wt_ctx *c, const wt_side *sides, double t, void *stream)
+{
+    if (!c || !std::isfinite(t)) return WT_ERR_ARG;
+    if (sides) {
+        for (int i = 0; i < 6; ++i) {
+            const wt_side &e = sides[i];
+            if (std::isnan(e.split0) || !std::isfinite(e.split_speed)) return WT_ERR_ARG;
+            for (int q = 0; q < 2; ++q) {
+                if (e.kind[q] != WT_SIDE_TRANSMISSIVE && e.kind[q] != WT_SIDE_REFLECTIVE &&
+                    e.kind[q] != WT_SIDE_STATE)
+                    return WT_ERR_ARG;
+                if (e.kind[q] == WT_SIDE_STATE)
+                    for (int k = 0; k < 5; ++k)
+                        if (!std::isfinite(e.state[q][k])) return WT_ERR_ARG;
+            }
+        }
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
+    hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, c->st, t);
+    if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    if (sides) {
+        for (int i = 0; i < 6; ++i) c->sides[i] = sides[i];
+        c->has_sides = true;
+    } else {
+        c->has_sides = false;
+    }
+    return WT_OK;
+}
+
 wt_status wenotheta_set_tiles(wt_ctx *c, const wt_grid *G, const wt_params *P, const int32_t *tile)
 {
     if (!c || !tile) return WT_ERR_ARG;
     Shape S;
-    wt_status r = validate(G, P, S);
+    wt_status r = validate(c, G, P, S);
     if (r) return r;
     int t[3] = {0, 0, 0};
     for (int d = 0; d < S.ndim; ++d) {
@@ -1118,7 +1243,7 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
 {
     if (!c || !u) return WT_ERR_ARG;
     Shape S;
-    wt_status r = validate(G, P, S);
+    wt_status r = validate(c, G, P, S);
     if (r) return r;
     if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
     if ((r = ensure_workspace(c, S))) return r;
@@ -1129,7 +1254,7 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
         // stage-finishing sweep), on u, with the stage written to the workspace U2:
         // set up a CFL dt from the speeds of u, then the divergence of the earlier
         // directions, as the stage would.
-        hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, 0.0, 0.0, -1ll);
+        hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, c->st, 0.0, 0.0, -1ll, 0);
         if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
         if ((r = queue_alpha_init(c, S, P, u, s))) return r;
         StepArgs B{};
@@ -1151,9 +1276,7 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
         A.slot_wr = (int)((c->g + 1) % kSlots);
         A.slot_zero = (int)((c->g + 2) % kSlots);
         auto args_for = [&](int d) {
-            A.dx = S.dx[d];
-            A.rdx = 1.0 / S.dx[d];
-            A.bc = S.bc[d];
+            dir_args(A, c, S, d);
             return d == S.ndim - 1 ? MODE_LAST_STAGE : (d == 0 ? MODE_FIRST : MODE_MID);
         };
         hipEvent_t e0, e1;

@@ -77,6 +77,9 @@ struct wt_ctx {
     // tile plans per grid shape, most recent first
     wt_tile_plan plans[kTilePlans];
     int nplans = 0;
+    // side table for grids with WT_SIDES dimensions (wenotheta_set_sides)
+    wt_side sides[6] = {};
+    bool has_sides = false;
 };
 
 

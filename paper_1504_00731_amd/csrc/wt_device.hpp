@@ -27,6 +27,7 @@ struct DevState {
     double dt;
     double t;
     double t_end;
+    double tn;            // time at the start of the current step
     long long steps;
     long long max_steps;
     int done;

@@ -1,0 +1,208 @@
+"""GPU parity of the sides (bc WT_SIDES: per end two parts, each a given state, a wall or
+zero gradient, split at a point that may move; Sec. 4.3 TEST 9) with the oracle, bit for
+bit in FP64: right-hand sides at several times, steps whose stages take the moving splits
+at t, t + dt, t + dt/2, solves through the captured step graph, 1D/2D/3D, every tile shape
+of the y sweep; and the double Mach reflection at the paper's grid and final time."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1504_00731_amd as wt
+from paper_1504_00731_amd import workloads as W
+from tests.gpu_common import grid_params, oracle_problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ST, RF, TR = W.STATE, W.REFLECTIVE, W.TRANSMISSIVE
+
+
+@pytest.fixture
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = wt.Context(0)
+    yield c
+    c.close()
+
+
+def _wt_sides(sides):
+    return [wt.Side(kind=s.kind, state=s.state, split0=s.split0, split_speed=s.split_speed)
+            for s in sides]
+
+
+def _random_case(seed, n, lo, hi):
+    """Random physical interior; every kind of part on some side, moving splits."""
+    rng = np.random.default_rng(seed)
+    ndim = len(n)
+    shape = tuple(reversed(n))
+    rho = rng.uniform(0.5, 2.0, shape)
+    vel = [rng.uniform(-1.0, 1.0, shape) for _ in range(ndim)]
+    p = rng.uniform(0.5, 2.0, shape)
+    u = W.conserved(rho, vel, p)
+    pt = lambda: tuple(float(v) for v in W.conserved(rng.uniform(0.5, 2.0), [rng.uniform(-1, 1)
+                                                     for _ in range(ndim)], rng.uniform(0.5, 2.0)))
+    sides = []
+    for d in range(3):
+        a = (d + 1) % ndim
+        mid = 0.5 * (lo[a] + hi[a])
+        span = hi[a] - lo[a]
+        sides.append(W.SideSpec((ST, RF), (pt(), ()), split0=mid - 0.2 * span, split_speed=0.5 * span))
+        sides.append(W.SideSpec((TR, ST), ((), pt()), split0=mid + 0.1 * span,
+                                split_speed=-0.3 * span))
+    c = W.Case("random_sides", W.EULER, u, lo, hi, (W.SIDES,) * ndim, sides=tuple(sides))
+    return c
+
+
+def _gpu_rhs(ctx, c, t, precision=wt.WT_FP64):
+    import torch
+    g, p = grid_params(c)
+    p.precision = precision
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), t)
+    ud = to_dev(c.u)
+    L = torch.empty_like(ud)
+    wt.wenotheta_rhs(ctx, g, p, ud, L)
+    wt.wenotheta_sync(ctx)
+    return L.cpu().numpy()
+
+
+@pytest.mark.parametrize("t", [0.0, 0.35, 0.9])
+def test_rhs_2d_matches_oracle(ctx, t):
+    """300 x 70: two x segments and three y segments, both ragged."""
+    c = _random_case(1, (300, 70), (0.0, -1.0), (3.0, 0.4))
+    got = _gpu_rhs(ctx, c, t)
+    ref = oracle.rhs(oracle_problem(c, t=t), c.u)
+    assert np.array_equal(got, ref)
+
+
+def test_rhs_3d_and_1d_match_oracle(ctx):
+    c3 = _random_case(2, (20, 18, 16), (0.0, 0.0, 0.0), (1.0, 0.9, 0.8))
+    assert np.array_equal(_gpu_rhs(ctx, c3, 0.4), oracle.rhs(oracle_problem(c3, t=0.4), c3.u))
+    c1 = _random_case(3, (300,), (-1.0,), (1.0,))
+    assert np.array_equal(_gpu_rhs(ctx, c1, 0.2), oracle.rhs(oracle_problem(c1, t=0.2), c1.u))
+
+
+def test_steps_match_oracle(ctx):
+    """Three CFL steps from t = 0.01 of the double Mach problem at 240 x 60; the top split
+    crosses grid lines within each step."""
+    c = W.double_mach(240, 60)
+    g, p = grid_params(c)
+    t0 = 0.01
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), t0)
+    ud = to_dev(c.u)
+    P = oracle_problem(c, t=t0)
+    ref = c.u
+    for _ in range(3):
+        wt.wenotheta_step(ctx, g, p, ud)
+        ref, dt = oracle.step(P, ref)
+        P.t = P.t + dt
+    wt.wenotheta_sync(ctx)
+    assert np.array_equal(ud.cpu().numpy(), ref)
+    # the context's time advanced with the steps: a RHS now takes the splits at P.t
+    import torch
+    L = torch.empty_like(ud)
+    wt.wenotheta_rhs(ctx, g, p, ud, L)
+    wt.wenotheta_sync(ctx)
+    assert np.array_equal(L.cpu().numpy(), oracle.rhs(P, ref))
+
+
+def test_solve_matches_oracle_through_the_graph(ctx):
+    c = W.double_mach(160, 40)
+    g, p = grid_params(c)
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    ud = to_dev(c.u)
+    t, k = wt.wenotheta_solve(ctx, g, p, ud, c.t_end, max_steps=30)
+    ref, t_ref, k_ref = oracle.solve(oracle_problem(c), c.u, c.t_end, max_steps=30)
+    assert (t, k) == (t_ref, k_ref) == (t, 30)
+    assert np.array_equal(ud.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_every_y_tile_shape(ctx, tile):
+    c = _random_case(4, (77, 50), (0.0, 0.0), (1.0, 0.7))
+    g, p = grid_params(c)
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.3)
+    wt.wenotheta_set_tiles(ctx, g, p, (0, tile))
+    got = _gpu_rhs(ctx, c, 0.3)
+    assert np.array_equal(got, oracle.rhs(oracle_problem(c, t=0.3), c.u))
+
+
+def test_tuner_on_a_sides_grid(ctx):
+    c = W.double_mach(200, 50)
+    g, p = grid_params(c)
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    ud = to_dev(c.u)
+    tiles = wt.wenotheta_tune(ctx, g, p, ud)
+    assert len(tiles) == 2
+    assert np.array_equal(ud.cpu().numpy(), c.u)
+
+
+@pytest.mark.parametrize("precision", [wt.WT_FP64, wt.WT_FP32_RECON])
+def test_double_mach_at_the_paper_size_and_time(ctx, precision):
+    """800 x 200 to t = 0.2: physical throughout; the FP64 run's first 20 steps equal
+    the oracle's; along the top row the density falls from the post- to the pre-shock
+    value where the exact shock line meets the top boundary."""
+    c = W.double_mach(800, 200)
+    g, p = grid_params(c)
+    p.precision = precision
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    ud = to_dev(c.u)
+    if precision == wt.WT_FP64:
+        t, k = wt.wenotheta_solve(ctx, g, p, ud, c.t_end, max_steps=20)
+        ref, t_ref, k_ref = oracle.solve(oracle_problem(c), c.u, c.t_end, max_steps=20)
+        assert (t, k) == (t_ref, k_ref)
+        assert np.array_equal(ud.cpu().numpy(), ref)
+        ud = to_dev(c.u)
+    t, k = wt.wenotheta_solve(ctx, g, p, ud, c.t_end)
+    a = ud.cpu().numpy()
+    assert t == c.t_end and k > 1000
+    rho = a[0]
+    assert np.isfinite(a).all() and rho.min() > 0.0
+    assert 1.3 < rho.min() and rho.max() < 30.0
+    top = c.sides[3]
+    xs = top.split0 + top.split_speed * c.t_end
+    x = W.grid_points(800, 0.0, 4.0, W.TRANSMISSIVE)
+    row = rho[-1]
+    cross = x[np.argmax(row < 0.5 * (8.0 + 1.4))]
+    assert abs(cross - xs) < 2.0 * c.dx[0]
+    assert np.all(np.abs(row[x > xs + 0.05] - 1.4) < 1e-3)
+
+
+def test_side_arguments(ctx):
+    import torch
+    c = W.double_mach(40, 10)
+    g, p = grid_params(c)
+    ud = to_dev(c.u)
+    L = torch.empty_like(ud)
+    with pytest.raises(wt.WenoThetaError) as e:          # no side table yet
+        wt.wenotheta_rhs(ctx, g, p, ud, L)
+    assert e.value.code == 1
+    bad = _wt_sides(c.sides)
+    bad[1] = wt.Side(kind=(9, 1))
+    with pytest.raises(wt.WenoThetaError) as e:
+        wt.wenotheta_set_sides(ctx, bad, 0.0)
+    assert e.value.code == 1
+    bad[1] = wt.Side(split0=math.nan)
+    with pytest.raises(wt.WenoThetaError):
+        wt.wenotheta_set_sides(ctx, bad, 0.0)
+    with pytest.raises(wt.WenoThetaError):
+        wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), math.inf)
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    wt.wenotheta_rhs(ctx, g, p, ud, L)                  # now accepted
+    wt.wenotheta_set_sides(ctx, None, 0.0)              # table removed
+    with pytest.raises(wt.WenoThetaError):
+        wt.wenotheta_rhs(ctx, g, p, ud, L)
+    # scalar systems take no sides; batches take no WT_SIDES
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    gs = wt.Grid(n=(16,), lo=(0.0,), hi=(1.0,), bc=(wt.WT_SIDES,))
+    us = to_dev(np.zeros((1, 16)))
+    with pytest.raises(wt.WenoThetaError) as e:
+        wt.wenotheta_rhs(ctx, gs, wt.Params(system=wt.WT_BURGERS), us, torch.empty_like(us))
+    assert e.value.code == 2
+    B = W.batched_1d(seed=1, nprob=3, nmin=8, nmax=20, steps=2)
+    with pytest.raises(wt.WenoThetaError) as e:
+        wt.wenotheta_solve_batched(ctx, wt.Params(), to_dev(B.u), B.n, B.offset, B.lo, B.hi,
+                                   np.full(3, wt.WT_SIDES, dtype=np.int32), 2)
+    assert e.value.code == 1
+    wt.wenotheta_sync(ctx)

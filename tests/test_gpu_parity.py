@@ -247,6 +247,23 @@ def test_full_size_euler2d_rhs_sampled(ctx):
     assert err <= RHS_TOL and np.array_equal(g, ref), err
 
 
+def test_full_size_euler2d_step_in_the_benchmark_configuration(ctx):
+    """The benchmark's workload (seed 1, 4096^2) in its launch configuration (tuned y
+    tiles, the solver's captured step graph, the stage-finishing sweeps): one CFL step
+    equals the oracle's whole step, every output bit for bit."""
+    import torch
+    c = W.euler2d_seeded(1, 4096)
+    g, p = grid_params(c)
+    ud = to_dev(c.u)
+    wt.wenotheta_tune(ctx, g, p, ud)
+    t, k = wt.wenotheta_solve(ctx, g, p, ud, math.inf, max_steps=1)
+    ref, dt = oracle.step(oracle_problem(c), c.u)
+    assert k == 1 and t == dt
+    assert np.array_equal(ud.cpu().numpy(), ref)
+    del ud
+    torch.cuda.empty_cache()
+
+
 def test_full_size_euler3d_rhs_sampled(ctx):
     """3D Euler workload at full size, 512^3 (the launch configuration the benchmark
     times): RHS at sampled points -- random, on the sphere surfaces and through the

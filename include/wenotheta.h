@@ -300,8 +300,9 @@ wt_status wenotheta_set_batched_tiles(wt_ctx *ctx, int32_t ndim, int32_t variant
  * wenotheta_tune times each shape on `u` (DEVICE, the state layout of
  * wenotheta_rhs; only read) with the sweep that writes the context's
  * workspace, keeps the fastest, and writes it to tile_out[0..ndim-1] (HOST,
- * optional; entry 0, the x sweep, is always 0).  It synchronises `stream`
- * (do not call it during graph capture) and returns any device error.
+ * optional; entry 0, the x sweep, is always 0).  The context's time is left
+ * as it was.  It synchronises `stream` (do not call it during graph capture)
+ * and returns any device error.
  *
  * wenotheta_set_tiles sets the shapes for the grid instead: tile[d] in 0..3
  * for d < ndim (HOST); tile[0] is ignored by the x sweep and systems or

@@ -230,6 +230,13 @@ __global__ void set_time_kernel(DevState *st, double t)
     if (threadIdx.x == 0 && blockIdx.x == 0) st->t = t;
 }
 
+// Undo the time advance of the last step begun (the tuner begins one to get a
+// CFL dt but keeps no step).
+__global__ void restore_time_kernel(DevState *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->t = st->tn;
+}
+
 __global__ void copy_dt_kernel(const DevState *st, double *dst)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = st->dt;
@@ -1319,6 +1326,8 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (r) return r;
+        hipLaunchKernelGGL(restore_time_kernel, dim3(1), dim3(64), 0, s, c->st);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
     }
     set_plan(c, S, P, best);
     if (tile_out)

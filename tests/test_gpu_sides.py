@@ -129,13 +129,20 @@ def test_every_y_tile_shape(ctx, tile):
 
 
 def test_tuner_on_a_sides_grid(ctx):
+    """The tuner leaves the state and the context's time as they were: a RHS after it
+    takes the moving split at the time set before."""
+    import torch
     c = W.double_mach(200, 50)
     g, p = grid_params(c)
-    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.05)
     ud = to_dev(c.u)
     tiles = wt.wenotheta_tune(ctx, g, p, ud)
     assert len(tiles) == 2
     assert np.array_equal(ud.cpu().numpy(), c.u)
+    L = torch.empty_like(ud)
+    wt.wenotheta_rhs(ctx, g, p, ud, L)
+    wt.wenotheta_sync(ctx)
+    assert np.array_equal(L.cpu().numpy(), oracle.rhs(oracle_problem(c, t=0.05), c.u))
 
 
 @pytest.mark.parametrize("precision", [wt.WT_FP64, wt.WT_FP32_RECON])

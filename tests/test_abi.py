@@ -55,7 +55,8 @@ def test_struct_layout_matches_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc is not available")
     fields = {"wt_grid": [f[0] for f in binding.wt_grid._fields_],
-              "wt_params": [f[0] for f in binding.wt_params._fields_]}
+              "wt_params": [f[0] for f in binding.wt_params._fields_],
+              "wt_side": [f[0] for f in binding.wt_side._fields_]}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "wenotheta.h"', "int main(void) {"]
     for st, names in fields.items():
         src.append(f'printf("{st} size %zu\\n", sizeof({st}));')

@@ -118,6 +118,34 @@ def test_solve_matches_oracle_through_the_graph(ctx):
     assert np.array_equal(ud.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("n", [(6, 6), (6, 7), (9, 6)])
+def test_smallest_grids(ctx, n):
+    """Six points per line (the stencil's minimum): every tile reaches far past the
+    ghost points; the given states, walls and zero-gradient parts still equal the
+    oracle's."""
+    c = _random_case(7 + n[0], n, (0.0, 0.0), (1.0, 1.0))
+    for t in (0.0, 0.6):
+        assert np.array_equal(_gpu_rhs(ctx, c, t), oracle.rhs(oracle_problem(c, t=t), c.u))
+    c3 = _random_case(11, (6, 6, 6), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    assert np.array_equal(_gpu_rhs(ctx, c3, 0.3), oracle.rhs(oracle_problem(c3, t=0.3), c3.u))
+
+
+def test_split_on_a_line_coordinate(ctx):
+    """A split exactly at a grid line's coordinate puts that line in part 1 (part 0 is
+    strictly below), on both paths; so does a moving split that reaches a line at the
+    stage time."""
+    c = _random_case(9, (40, 30), (0.0, 0.0), (1.0, 0.75))
+    dx = c.dx[0]
+    sides = list(c.sides)
+    x17 = 0.0 + (17 + 0.5) * dx
+    sides[2] = W.SideSpec((ST, RF), (sides[2].state[0], ()), split0=x17, split_speed=0.0)
+    sides[3] = W.SideSpec((ST, TR), (sides[3].state[1], ()), split0=x17 - 0.5 * 2.0,
+                          split_speed=2.0)          # at x17 when t = 0.5
+    c.sides = tuple(sides)
+    for t in (0.5, 0.25):
+        assert np.array_equal(_gpu_rhs(ctx, c, t), oracle.rhs(oracle_problem(c, t=t), c.u))
+
+
 @pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_every_y_tile_shape(ctx, tile):
     c = _random_case(4, (77, 50), (0.0, 0.0), (1.0, 0.7))

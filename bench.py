@@ -5,9 +5,12 @@ three stage updates, all directions) over the whole grid.  The default
 workload is the 2D Euler one: 4096 x 4096 points, seeded four-quadrant Riemann
 data, transmissive boundaries, CFL 0.5, 200 steps, FP64.  Beside it the same
 line reports ("companions") the FP32-reconstruction form of that workload and
-the batched workload (4096 independent 1D Euler problems, N log-uniform in
-[256, 16384], 500 steps, one persistent graph-captured launch) in FP64 and in
-FP32 reconstruction, each with its L1 difference to the FP64 result.
+the batched workloads (4096 independent 1D Euler problems, N log-uniform in
+[256, 16384], 500 steps; 4096 independent 2D problems, 32..96 points per side,
+100 steps), each solved as one captured graph in the form the batch tuner picks
+(the persistent kernel, or the flat form with one launch per stage over all
+problems), in FP64 and in FP32 reconstruction, each with its L1 difference to
+the FP64 result.
 
 Prints ONE JSON line (rank 0):
   value  = grid points x timed steps / wall time of the timed region (inputs

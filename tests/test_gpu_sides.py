@@ -83,6 +83,26 @@ def test_rhs_3d_and_1d_match_oracle(ctx):
     assert np.array_equal(_gpu_rhs(ctx, c1, 0.2), oracle.rhs(oracle_problem(c1, t=0.2), c1.u))
 
 
+def test_sides_with_gravity_match_oracle(ctx):
+    """Sides and the gravity source together: a wall part on the bottom, a given state
+    on the top and inflow on the left, with g along -y; RHS and two steps."""
+    c = _random_case(12, (90, 70), (0.0, 0.0), (1.5, 1.0))
+    c.gravity = (0.0, 0.7, 0.0)
+    got = _gpu_rhs(ctx, c, 0.2)
+    assert np.array_equal(got, oracle.rhs(oracle_problem(c, t=0.2), c.u))
+    g, p = grid_params(c)
+    ud = to_dev(c.u)
+    P = oracle_problem(c, t=0.2)
+    ref = c.u
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.2)
+    for _ in range(2):
+        wt.wenotheta_step(ctx, g, p, ud)
+        ref, dt = oracle.step(P, ref)
+        P.t = P.t + dt
+    wt.wenotheta_sync(ctx)
+    assert np.array_equal(ud.cpu().numpy(), ref)
+
+
 def test_steps_match_oracle(ctx):
     """Three CFL steps from t = 0.01 of the double Mach problem at 240 x 60; the top split
     crosses grid lines within each step."""

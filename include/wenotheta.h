@@ -198,8 +198,9 @@ wt_status wenotheta_set_sides(wt_ctx *ctx, const wt_side *sides, double t, void 
 /* Batched solves: nprob independent 1D Euler problems (prm->system must be
  * WT_EULER, prm->gravity all 0, else WT_ERR_UNSUPPORTED) packed side by side
  * in one state, each advanced by nsteps CFL
- * steps of its own (dt_b = cfl / (amax_b / dx_b)), in one persistent kernel
- * launched through a captured HIP graph.
+ * steps of its own (dt_b = cfl / (amax_b / dx_b)), as one captured HIP graph:
+ * by default one persistent kernel, or the flat form (one launch per stage
+ * over all problems) where the batch tuner below chose it.
  *   u       DEVICE, FP64, [3][total] component-major: problem b occupies
  *           columns offset[b] .. offset[b] + n[b] - 1; advanced in place;
  *   n, offset, lo, hi, bc   HOST arrays of nprob entries: points (>= 6),
@@ -229,8 +230,10 @@ wt_status wenotheta_solve_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
 /* Batched 2D solves: nprob independent 2D Euler problems of their own sizes
  * (dimension-by-dimension scheme of Sec. 4.3), packed side by side in one
  * state, each advanced by nsteps CFL steps of its own
- * (dt_b = cfl / (amax_x / dx_b + amax_y / dy_b)) in one persistent kernel
- * launched through a captured HIP graph; one workgroup runs a whole problem.
+ * (dt_b = cfl / (amax_x / dx_b + amax_y / dy_b)), as one captured HIP graph:
+ * by default one persistent kernel in which one workgroup runs a whole
+ * problem, or the flat form (one launch per pass over the tiles of all
+ * problems) where the batch tuner below chose it.
  * prm->system must be WT_EULER and prm->gravity all 0 (else
  * WT_ERR_UNSUPPORTED).
  *   u       DEVICE, FP64, [4][total] component-major (rho, m_x, m_y, E):
@@ -255,8 +258,8 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
                                      int32_t *status_out, int64_t *steps_out, void *stream);
 
 /* Tile variants of the batched kernels, chosen by timing (the batch form of
- * wenotheta_tune).  Each batched kernel has two variants that compute the same
- * operations, so results are bit-identical whichever runs:
+ * wenotheta_tune).  The variants compute the same operations, so results are
+ * bit-identical whichever runs:
  *   1D batches: the persistent kernel with workgroups of 256 threads sweeping
  *               segments of 255 points (0, default) or of 128 threads and 127
  *               points (1), or the flat form (each stage one launch over the

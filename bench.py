@@ -499,10 +499,23 @@ def main():
     }
     if not args.no_companions and prec == wt.WT_FP64:
         print("[bench] companion: same workload, FP32 reconstruction", file=sys.stderr, flush=True)
-        r32 = run_grid(wt, ctx, case, wt.WT_FP32_RECON, args.steps, args.warmup, profile=False,
+        r32 = run_grid(wt, ctx, case, wt.WT_FP32_RECON, args.steps, args.warmup, profile=True,
                        tile_choice=tile_choice)
         f32 = {"value": cells * args.steps / (r32["ms"] / 1e3), "unit": "cell-updates/s",
                "ms_per_step": r32["ms"] / args.steps, "tiles_tx_tn": r32["tiles"]}
+        # the dominant kernel against the vector lane rate: without packed FP32 (left off in
+        # this build) an FP32 instruction issues at the FP64 rate, so the peak is the same
+        # 256 x 64 x 2.4e9 lane operations/s (the packed FP32 rate is twice that)
+        p32 = r32["prof"]
+        k32 = max(p32, key=lambda kk: p32[kk][0])
+        d32, final32 = names[k32]
+        ops32 = sweep_ops(case.ndim, case.n, d32, final32, euler)
+        ach32 = ops32 / (p32[k32][0] / p32[k32][1] / 1e3)
+        f32["roofline"] = {"bound": "alu", "kernel": k32, "achieved": ach32 / 1e12,
+                           "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach32 / peak,
+                           "avg_launch_ms": p32[k32][0] / p32[k32][1],
+                           "ops_counted_as": "lane operations of the FP64 formulas (the "
+                                             "FP32 reconstruction counted alike)"}
         f32.update(differences(r32["u"], r["u"]))
         comp = {args.workload + "_fp32_recon": f32}
         del r32

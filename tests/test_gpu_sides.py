@@ -166,6 +166,29 @@ def test_split_on_a_line_coordinate(ctx):
         assert np.array_equal(_gpu_rhs(ctx, c, t), oracle.rhs(oracle_problem(c, t=t), c.u))
 
 
+def test_graph_follows_a_new_side_table(ctx):
+    """The solver's captured graph holds the side table in its kernel arguments: after
+    a solve, a new table (another split speed, a wall part turned into a given state)
+    must be used by the next solve on the same grid, not the captured one."""
+    c = W.double_mach(160, 40)
+    g, p = grid_params(c)
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    ud = to_dev(c.u)
+    wt.wenotheta_solve(ctx, g, p, ud, c.t_end, max_steps=16)
+    sides = list(c.sides)
+    sides[3] = W.SideSpec(sides[3].kind, sides[3].state, split0=sides[3].split0,
+                          split_speed=0.5 * sides[3].split_speed)
+    sides[2] = W.SideSpec((ST, ST), (sides[2].state[0], c.sides[3].state[1]),
+                          split0=sides[2].split0)
+    c.sides = tuple(sides)
+    wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.0)
+    ud = to_dev(c.u)
+    t, k = wt.wenotheta_solve(ctx, g, p, ud, c.t_end, max_steps=16)
+    ref, t_ref, k_ref = oracle.solve(oracle_problem(c), c.u, c.t_end, max_steps=16)
+    assert (t, k) == (t_ref, k_ref)
+    assert np.array_equal(ud.cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_every_y_tile_shape(ctx, tile):
     c = _random_case(4, (77, 50), (0.0, 0.0), (1.0, 0.7))

@@ -330,11 +330,20 @@ def compare_batched(wt, ctx, B, cells_per_problem, steps):
     Bp = dataclasses.replace(B, u=B.u * (1.0 + 2.0 ** -24 * rng.choice([-1.0, 1.0], size=B.u.shape)))
     rp = run_batched(wt, ctx, Bp, wt.WT_FP64, steps, 0, tune=False)
     ok = (r64["status"] == 0) & (r32["status"] == 0) & (rp["status"] == 0)
-    seg = torch.from_numpy(np.repeat(np.arange(B.nprob), cells_per_problem)).cuda()
+    # problems are packed in order: per-problem sums as differences of a running sum at
+    # the problems' ends (relative error ~1e-12 here, far below the figures reported).
+    # The columns of problems that failed in any run (unspecified, possibly NaN or huge)
+    # are zeroed first so that they cannot reach the sums of the others.
+    sizes = np.asarray(cells_per_problem, dtype=np.int64)
+    ends = torch.from_numpy(np.cumsum(sizes)).cuda()
+    starts = ends - torch.from_numpy(sizes).cuda()
+    keep = torch.from_numpy(np.repeat(ok, sizes)).cuda()
 
-    def per_problem(x):            # [m, total] -> [nprob, m] sums per problem
-        out = torch.zeros(B.nprob, m, dtype=torch.float64, device="cuda")
-        return out.index_add_(0, seg, x.t())
+    def per_problem(x):            # [m, total] -> [nprob, m] sums per problem (0 if failed)
+        x = torch.where(keep, x, torch.zeros((), dtype=x.dtype, device=x.device))
+        cs = torch.cat([torch.zeros(m, 1, dtype=torch.float64, device="cuda"),
+                        torch.cumsum(x, dim=1)], dim=1)
+        return (cs[:, ends] - cs[:, starts]).t()
 
     den = per_problem(r64["u"].abs())
     dpert = per_problem((rp["u"] - r64["u"]).abs())
@@ -356,11 +365,11 @@ def compare_batched(wt, ctx, B, cells_per_problem, steps):
     f32["ill_conditioned_problems"] = int(ill.sum())
     f32["fp64_response_to_2^-24_input_perturbation_all"] = [
         float(x) for x in (dpert[okt].sum(0) / den[okt].sum(0)).cpu()]
-    dmax = torch.zeros(B.nprob, m, dtype=torch.float64, device="cuda").index_reduce_(
-        0, seg, (r32["u"] - r64["u"]).abs().t(), "amax")
-    bmax = torch.zeros(B.nprob, m, dtype=torch.float64, device="cuda").index_reduce_(
-        0, seg, r64["u"].abs().t(), "amax")
-    f32["linf_rel_vs_fp64_all"] = [float(x) for x in (dmax[okt].amax(0) / bmax[okt].amax(0)).cpu()]
+    # per-problem maxima on the host (a segmented max over packed problems)
+    first = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    dmax = np.maximum.reduceat((r32["u"] - r64["u"]).abs().cpu().numpy(), first, axis=1).T
+    bmax = np.maximum.reduceat(r64["u"].abs().cpu().numpy(), first, axis=1).T
+    f32["linf_rel_vs_fp64_all"] = [float(x) for x in dmax[ok].max(0) / bmax[ok].max(0)]
     f32["conservation_drift_vs_fp64"] = [
         float(x) for x in (s32[okt].sum(0).abs() / den[okt].sum(0)).cpu()]
     return out

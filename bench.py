@@ -246,7 +246,9 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None)
     assert k == steps, (k, steps)
     assert bool(torch.isfinite(u).all()), "non-finite state after the timed steps"
     return {"ms": ms, "wall": wall, "t_sim": t_sim, "u": u, "prof": prof,
-            "tiles": [list(wt.TILE_SHAPES[v]) if d > 0 else [1, 255] for d, v in enumerate(tiles)]}
+            "tiles": [list(wt.TILE_SHAPES[v]) if d > 0 else
+                      (list(wt.X_TILE_SHAPES[v]) if case.system == wt.WT_EULER and case.ndim > 1
+                       else [1, 255]) for d, v in enumerate(tiles)]}
 
 
 def run_batched(wt, ctx, B, precision, steps, warmup, tune=True):

@@ -291,10 +291,13 @@ wt_status wenotheta_tune_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *n
 wt_status wenotheta_set_batched_tiles(wt_ctx *ctx, int32_t ndim, int32_t variant);
 
 /* Tile shapes of the sweeps (dimension-by-dimension scheme of Sec. 4.3: one
- * 1D operator per direction).  The y and z sweeps of the 2D/3D Euler system
- * run in one of four tile shapes, TX consecutive x-columns by TN points along
- * the sweep direction, 256 interfaces per workgroup:
+ * 1D operator per direction), 256 interfaces per workgroup.  The y and z
+ * sweeps of the 2D/3D Euler system run in one of four tile shapes, TX
+ * consecutive x-columns by TN points along the sweep direction:
  *   0: 8 x 31 (default)   1: 16 x 15   2: 4 x 63   3: 32 x 7
+ * and their x sweeps in one of two, rows by TN points along x:
+ *   0: 1 x 255 (default)  1: 8 x 31 (for rows that 255-point segments would
+ *                          leave a nearly empty last segment, e.g. 512 points)
  * Every shape computes the same fluxes with the same operations: the results
  * are bit-identical whichever is used; only the speed differs.  The choice
  * is kept in the context per grid shape (system, ndim, n, precision; the 16
@@ -303,13 +306,13 @@ wt_status wenotheta_set_batched_tiles(wt_ctx *ctx, int32_t ndim, int32_t variant
  * wenotheta_tune times each shape on `u` (DEVICE, the state layout of
  * wenotheta_rhs; only read) with the sweep that writes the context's
  * workspace, keeps the fastest, and writes it to tile_out[0..ndim-1] (HOST,
- * optional; entry 0, the x sweep, is always 0).  The context's time is left
+ * optional; entry 0 is the x sweep's).  The context's time is left
  * as it was.  It synchronises `stream` (do not call it during graph capture)
  * and returns any device error.
  *
- * wenotheta_set_tiles sets the shapes for the grid instead: tile[d] in 0..3
- * for d < ndim (HOST); tile[0] is ignored by the x sweep and systems or
- * dimensions without choices ignore all entries.  No device work. */
+ * wenotheta_set_tiles sets the shapes for the grid instead: tile[0] in 0..1
+ * and tile[d] in 0..3 for 0 < d < ndim (HOST); systems or dimensions without
+ * choices (scalar laws, 1D) ignore the entries.  No device work. */
 wt_status wenotheta_tune(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm, const double *u,
                          int32_t *tile_out, void *stream);
 wt_status wenotheta_set_tiles(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,

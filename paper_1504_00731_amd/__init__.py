@@ -13,4 +13,4 @@ from .binding import (  # noqa: F401
     LibraryMissing, Params, WenoThetaError, state_shape, wenotheta_rhs, wenotheta_solve,
     wenotheta_step, wenotheta_sync, wenotheta_profile, wenotheta_profile_read,
     wenotheta_solve_batched, wenotheta_solve_batched_2d, wenotheta_tune_batched,
-    wenotheta_tune_batched_2d, wenotheta_set_batched_tiles, wenotheta_tune, wenotheta_set_tiles, TILE_SHAPES)
+    wenotheta_tune_batched_2d, wenotheta_set_batched_tiles, wenotheta_tune, wenotheta_set_tiles, TILE_SHAPES, X_TILE_SHAPES)

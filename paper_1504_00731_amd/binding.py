@@ -277,6 +277,7 @@ def wenotheta_solve(ctx: Context, grid: Grid, params: Params, u, t_end, t0=0.0, 
 
 
 TILE_SHAPES = ((8, 31), (16, 15), (4, 63), (32, 7))   # (TX, TN) of the y/z-sweep tile variants
+X_TILE_SHAPES = ((1, 255), (8, 31))                   # (rows, TN) of the x-sweep tile variants
 
 
 def wenotheta_tune(ctx: Context, grid: Grid, params: Params, u, stream=None) -> tuple:

@@ -319,15 +319,17 @@ void sweep_kernel(SweepArgs A)
         if (b >= A.tiles) return;
     }
     // tile -> (x0, seg, base): base is the offset of sweep index 0 of column x0
-    int64_t seg, x0 = 0, base;
+    // x-sweeps: TX rows (row = y + z * ny) from row0, each a segment of TN points;
+    // y/z-sweeps: TX columns from x0.
+    int64_t seg, x0 = 0, row0 = 0, base;
     int64_t sstride;
     int64_t tline = 0;                           // line index along the split axis (WT_SIDES)
+    const int64_t nrows = ny * nz;
     if constexpr (DIR == 0) {
         seg = b % nseg;
-        const int64_t row = b / nseg;            // y + z * ny
-        base = row * nx;
+        row0 = (b / nseg) * TX;
+        base = row0 * nx;
         sstride = 1;
-        tline = NDIM == 3 ? row % ny : row;
     } else if constexpr (DIR == 1) {
         const int64_t gx = b % ngx;
         const int64_t r = b / ngx;
@@ -352,14 +354,31 @@ void sweep_kernel(SweepArgs A)
     // ---- stage the tile (owned points + 3-point halos) ----
     int err = 0;
     for (int i = threadIdx.x; i < NC; i += kThreads) {
-        const int r = i / TX, cx = i % TX;
+        // point r along the sweep of lane cx, kept in LDS at r * TX + cx; x-tiles of
+        // several rows are read row by row (consecutive threads, consecutive x)
+        int r, cx;
+        if constexpr (DIR == 0 && TX > 1) {
+            cx = i / (TN + 6);
+            r = i - cx * (TN + 6);
+        } else {
+            r = i / TX;
+            cx = i % TX;
+        }
+        const int li = r * TX + cx;
         const int64_t gi = g0 - 3 + r;
-        int64_t xo = cx;
+        int64_t xo;                               // offset of the lane's line from base
         if constexpr (DIR != 0) xo = x0 + cx < nx ? cx : nx - 1 - x0;
+        else xo = (row0 + cx < nrows ? cx : nrows - 1 - row0) * nx;
         if constexpr (EULER) {
             double uc[M];
             if (A.bc == WT_SIDES && (gi < 0 || gi >= nd)) {
-                const int64_t jt = DIR == 0 || (NDIM == 3 && DIR == 1) ? tline : x0 + xo;
+                int64_t jt;
+                if constexpr (DIR == 0) {
+                    const int64_t row = row0 + xo / nx;
+                    jt = NDIM == 3 ? row % ny : row;
+                } else {
+                    jt = NDIM == 3 && DIR == 1 ? tline : x0 + xo;
+                }
                 side_point<NDIM, DIR, M>(A, st, gi, nd, base + xo, sstride, jt, uc);
             } else {
                 const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
@@ -379,13 +398,13 @@ void sweep_kernel(SweepArgs A)
             euler_normal_flux<NDIM, DIR>(uc, vel, p, fn);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                s_u[c][i] = uc[c];
-                s_f[c][i] = fn[c];
+                s_u[c][li] = uc[c];
+                s_f[c][li] = fn[c];
             }
 #pragma unroll
-            for (int k = 0; k < NDIM; ++k) s_v[k][i] = vel[k];
-            s_sr[i] = sqrt_rn(uc[0]);
-            s_H[i] = H;
+            for (int k = 0; k < NDIM; ++k) s_v[k][li] = vel[k];
+            s_sr[li] = sqrt_rn(uc[0]);
+            s_H[li] = H;
         } else {
             const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
             const double x = A.uin[idx];
@@ -394,8 +413,8 @@ void sweep_kernel(SweepArgs A)
             else if constexpr (SYS == SYS_LINEAR) f = A.a * x;
             else f = 0.5 * x * x;
             if (!__builtin_isfinite(x) || !__builtin_isfinite(f)) err |= kErrNonfinite;
-            s_u[0][i] = x;
-            s_f[0][i] = f;
+            s_u[0][li] = x;
+            s_f[0][li] = f;
         }
     }
     if (err) atomicOr(&st->err, err);
@@ -433,7 +452,7 @@ void sweep_kernel(SweepArgs A)
     else {
         const int t = threadIdx.x;
         const int it = t / TX, cx = t % TX;
-        const bool valid = (DIR == 0 || x0 + cx < nx) && g0 + it <= nd;
+        const bool valid = (DIR == 0 ? row0 + cx < nrows : x0 + cx < nx) && g0 + it <= nd;
         double F[M];
         if (valid) {
             if constexpr (EULER) {
@@ -463,8 +482,8 @@ void sweep_kernel(SweepArgs A)
         const int t = threadIdx.x;
         const int it = t / TX, cx = t % TX;
         const int64_t g = g0 + it;
-        if ((DIR == 0 || x0 + cx < nx) && g < nd) {
-            const int64_t idx = base + g * sstride + cx;
+        if ((DIR == 0 ? row0 + cx < nrows : x0 + cx < nx) && g < nd) {
+            const int64_t idx = base + g * sstride + (DIR == 0 ? cx * nx : cx);
             double Lc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
@@ -573,10 +592,16 @@ struct TileYZ<2> { static constexpr int TX = 4, TN = 63; };
 template <>
 struct TileYZ<3> { static constexpr int TX = 32, TN = 7; };
 
+// x-sweeps of the Euler system in 2D/3D: 1 x 255 (one row segment; default) or
+// 8 rows x 31 points, for rows whose length leaves a nearly empty last segment of
+// 255 (a 512-point row: 255 + 255 + 2).
+//   0: 1 x 255   1: 8 x 31
+constexpr int kXTileVariants = 2;
+
 template <int SYS, int NDIM, int DIR>
 constexpr bool has_tile_variants()
 {
-    return SYS == SYS_EULER && NDIM > 1 && DIR > 0;
+    return SYS == SYS_EULER && NDIM > 1;
 }
 
 template <int SYS, int NDIM, int DIR, int MODE, int PREC, int TX, int TN>
@@ -585,7 +610,7 @@ hipError_t launch_tile(const SweepArgs &A, hipStream_t s)
     const int64_t nd = A.n[DIR];
     const int64_t nseg = (nd + TN - 1) / TN;
     int64_t blocks;
-    if (DIR == 0) blocks = nseg * A.n[1] * A.n[2];
+    if (DIR == 0) blocks = nseg * ((A.n[1] * A.n[2] + TX - 1) / TX);
     else if (DIR == 1) blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[2];
     else blocks = ((A.n[0] + TX - 1) / TX) * nseg * A.n[1];
     SweepArgs B = A;
@@ -608,6 +633,9 @@ hipError_t launch_sweep(const SweepArgs &A, int tile, hipStream_t s)
         constexpr int TX = DIR == 0 ? 1 : 8;
         constexpr int TN = DIR != 0 ? 31 : (split_fields<SYS, NDIM, PREC>() ? kThreads / Ncomp<SYS, NDIM>::value - 1 : 255);
         return launch_tile<SYS, NDIM, DIR, MODE, PREC, TX, TN>(A, s);
+    } else if constexpr (DIR == 0) {
+        if (tile == 1) return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<0>::TX, TileYZ<0>::TN>(A, s);
+        return launch_tile<SYS, NDIM, DIR, MODE, PREC, 1, 255>(A, s);
     } else {
         switch (tile) {
             case 1: return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<1>::TX, TileYZ<1>::TN>(A, s);
@@ -944,7 +972,7 @@ wt_status ensure_step_graph(wt_ctx *c, const Shape &S, const wt_params *P, doubl
     uint64_t key = plan_key(S, P);
     for (uint64_t v : {(uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)c->U1, (uint64_t)(uintptr_t)c->U2,
                        (uint64_t)(uintptr_t)c->D, (uint64_t)(uintptr_t)c->st, (uint64_t)(c->g % kSlots),
-                       (uint64_t)plan_tile(c, S, P, 1), (uint64_t)plan_tile(c, S, P, 2), bits(P->a),
+                       (uint64_t)plan_tile(c, S, P, 0), (uint64_t)plan_tile(c, S, P, 1), (uint64_t)plan_tile(c, S, P, 2), bits(P->a),
                        bits(P->gamma), bits(P->cfl), bits(P->eps), bits(P->alpha_R),
                        bits(P->gravity[0]), bits(P->gravity[1]), bits(P->gravity[2]), bits(S.dx[0]),
                        bits(S.dx[1]), bits(S.dx[2]), (uint64_t)S.bc[0], (uint64_t)S.bc[1], (uint64_t)S.bc[2]})
@@ -1238,7 +1266,7 @@ wt_status wenotheta_set_tiles(wt_ctx *c, const wt_grid *G, const wt_params *P, c
     if (r) return r;
     int t[3] = {0, 0, 0};
     for (int d = 0; d < S.ndim; ++d) {
-        if (tile[d] < 0 || tile[d] >= kTileVariants) return WT_ERR_ARG;
+        if (tile[d] < 0 || tile[d] >= (d == 0 ? kXTileVariants : kTileVariants)) return WT_ERR_ARG;
         t[d] = tile[d];
     }
     set_plan(c, S, P, t);
@@ -1292,7 +1320,8 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
             (void)hipEventDestroy(e0);
             return WT_ERR_DEVICE;
         }
-        for (int d = 1; d < S.ndim && r == WT_OK; ++d) {
+        for (int d = 0; d < S.ndim && r == WT_OK; ++d) {
+            const int nvar = d == 0 ? kXTileVariants : kTileVariants;
             // the divergence of the directions before d, as the stage forms it
             // (an accumulating sweep timed for an earlier direction added to it
             // several times)
@@ -1307,7 +1336,7 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
                 float ms_best[kTileVariants];
                 for (int v = 0; v < kTileVariants; ++v) ms_best[v] = 1e30f;
                 for (int round = 0; round < 4 && r == WT_OK; ++round)
-                    for (int v = 0; v < kTileVariants && r == WT_OK; ++v) {
+                    for (int v = 0; v < nvar && r == WT_OK; ++v) {
                         float ms = 0.0f;
                         if (hipEventRecord(e0, s) != hipSuccess ||
                             launch_sweep_any(P->system, S.ndim, P->precision, d, mode, A, v, s) != hipSuccess ||
@@ -1319,7 +1348,7 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
                         if (round > 0 && ms < ms_best[v]) ms_best[v] = ms;   // round 0 warms up
                     }
                 // another shape replaces the default only if clearly faster
-                for (int v = 1; v < kTileVariants; ++v)
+                for (int v = 1; v < nvar; ++v)
                     if (ms_best[v] < 0.98f * ms_best[0] && ms_best[v] < ms_best[best[d]]) best[d] = v;
             }
         }

@@ -189,14 +189,22 @@ def test_graph_follows_a_new_side_table(ctx):
     assert np.array_equal(ud.cpu().numpy(), ref)
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
-def test_every_y_tile_shape(ctx, tile):
+@pytest.mark.parametrize("tiles", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 2)])
+def test_every_tile_shape(ctx, tiles):
+    """2D: every y shape, and the 8-row x tile (each lane its own row, so its own side
+    part along y); 3D with the 8-row x tile."""
     c = _random_case(4, (77, 50), (0.0, 0.0), (1.0, 0.7))
     g, p = grid_params(c)
     wt.wenotheta_set_sides(ctx, _wt_sides(c.sides), 0.3)
-    wt.wenotheta_set_tiles(ctx, g, p, (0, tile))
+    wt.wenotheta_set_tiles(ctx, g, p, tiles)
     got = _gpu_rhs(ctx, c, 0.3)
     assert np.array_equal(got, oracle.rhs(oracle_problem(c, t=0.3), c.u))
+    if tiles[0] == 1:
+        c3 = _random_case(5, (20, 13, 11), (0.0, 0.0, 0.0), (1.0, 0.9, 0.8))
+        g3, p3 = grid_params(c3)
+        wt.wenotheta_set_sides(ctx, _wt_sides(c3.sides), 0.4)
+        wt.wenotheta_set_tiles(ctx, g3, p3, (1, tiles[1], tiles[1]))
+        assert np.array_equal(_gpu_rhs(ctx, c3, 0.4), oracle.rhs(oracle_problem(c3, t=0.4), c3.u))
 
 
 def test_tuner_on_a_sides_grid(ctx):

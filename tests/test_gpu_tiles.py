@@ -1,7 +1,7 @@
-"""GPU tests of the y/z-sweep tile shapes and their tuner: every shape computes the
-same fluxes with the same operations, so RHS and steps are bit-identical across
-shapes (and to the oracle in FP64), on grids whose sizes are not multiples of
-the tile widths."""
+"""GPU tests of the sweep tile shapes (x: one row segment or 8 rows x 31 points; y/z:
+four shapes) and their tuner: every shape computes the same fluxes with the same
+operations, so RHS and steps are bit-identical across shapes (and to the oracle in
+FP64), on grids whose sizes are not multiples of the tile widths or heights."""
 import math
 
 import numpy as np
@@ -52,19 +52,20 @@ def _steps(ctx, case, tiles, k, precision=wt.WT_FP64):
     return u.cpu().numpy()
 
 
+@pytest.mark.parametrize("xv", range(2))
 @pytest.mark.parametrize("v", range(4))
-def test_every_tile_shape_matches_oracle_rhs(ctx, v):
+def test_every_tile_shape_matches_oracle_rhs(ctx, xv, v):
     for case in _cases():
         ref = oracle.rhs(oracle_problem(case), case.u)
-        got = _rhs(ctx, case, [0, v, v])
-        assert np.array_equal(got, ref), (case.name, v)
+        got = _rhs(ctx, case, [xv, v, v])
+        assert np.array_equal(got, ref), (case.name, xv, v)
 
 
 def test_tile_shapes_give_identical_steps(ctx):
     for case in _cases():
         for prec in (wt.WT_FP64, wt.WT_FP32_RECON):
             ref = _steps(ctx, case, [0, 0, 0], 3, prec)
-            for tiles in ([0, 1, 2], [0, 2, 3], [0, 3, 1], [0, 1, 1]):
+            for tiles in ([0, 1, 2], [0, 2, 3], [0, 3, 1], [0, 1, 1], [1, 0, 0], [1, 2, 3]):
                 assert np.array_equal(_steps(ctx, case, tiles, 3, prec), ref), (case.name, prec, tiles)
 
 
@@ -74,7 +75,7 @@ def test_tune_picks_a_shape_and_keeps_results(ctx):
     g, p = grid_params(case)
     u = to_dev(case.u)
     choice = wt.wenotheta_tune(ctx, g, p, u)
-    assert len(choice) == 2 and choice[0] == 0 and 0 <= choice[1] < 4
+    assert len(choice) == 2 and 0 <= choice[0] < 2 and 0 <= choice[1] < 4
     assert np.array_equal(u.cpu().numpy(), case.u)         # tuning only reads u
     L = torch.empty_like(u)
     wt.wenotheta_rhs(ctx, g, p, u, L)
@@ -85,7 +86,7 @@ def test_tune_picks_a_shape_and_keeps_results(ctx):
 def test_set_tiles_rejects_bad_variants(ctx):
     case = W.euler2d_seeded(0, 16)
     g, p = grid_params(case)
-    for bad in ([0, 4], [0, -1]):
+    for bad in ([0, 4], [0, -1], [2, 0], [-1, 0]):
         with pytest.raises(wt.WenoThetaError) as e:
             wt.wenotheta_set_tiles(ctx, g, p, bad)
         assert e.value.code == 1

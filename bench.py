@@ -19,6 +19,9 @@ Prints ONE JSON line (rank 0):
            ALU-bound), from HIP events recorded around every kernel launch of
            the timed region on the launch stream;
   hbm    = algorithmic state traffic per step against the HBM peak;
+  graph  = the same steps replayed from the solver's captured graph without the
+           per-sweep events of the timed region (the production path; on short
+           grids noticeably faster), checked to give the same state bit for bit;
   cpu_baseline = the oracle (plain C, OpenMP over pencils) on the host cores,
            timed on a bounded sample of the same workload.
 """
@@ -245,7 +248,20 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None)
         wt.wenotheta_profile(ctx, False)
     assert k == steps, (k, steps)
     assert bool(torch.isfinite(u).all()), "non-finite state after the timed steps"
-    return {"ms": ms, "wall": wall, "t_sim": t_sim, "u": u, "prof": prof,
+    # The profiled region queues the sweeps one by one with an event pair around each;
+    # the solver itself replays them from a captured graph.  The same steps once more
+    # that way (after one untimed solve that captures the graph), for the production
+    # path's rate; the state must come out the same.
+    ms_graph = None
+    if profile:
+        ug = u_init.clone()            # the graph is captured for this state's address
+        wt.wenotheta_solve(ctx, g, p, ug, float("inf"), max_steps=min(steps, 8))
+        ug.copy_(u_init)
+        ms_graph, (_, kg) = timed(stream, lambda: wt.wenotheta_solve(ctx, g, p, ug, float("inf"),
+                                                                   max_steps=steps))
+        assert kg == steps and torch.equal(ug, u), "graph replay differs from the queued steps"
+        del ug
+    return {"ms": ms, "ms_graph": ms_graph, "wall": wall, "t_sim": t_sim, "u": u, "prof": prof,
             "tiles": [list(wt.TILE_SHAPES[v]) if d > 0 else
                       (list(wt.X_TILE_SHAPES[v]) if case.system == wt.WT_EULER and case.ndim > 1
                        else [1, 255]) for d, v in enumerate(tiles)]}
@@ -505,6 +521,10 @@ def main():
                 "bytes_per_cell_update": bytes_per_step // cells,
                 "achievable_copy": achievable_copy_bandwidth()},
         "kernel_ms": {kk: {"total": v[0], "launches": v[1]} for kk, v in prof.items() if v[1]},
+        "graph": {"value": cells * args.steps / (r["ms_graph"] / 1e3),
+                  "ms_per_step": r["ms_graph"] / args.steps,
+                  "note": "the same steps replayed from the solver's captured graph without "
+                          "the per-sweep events of the timed region"},
         "wall_s": r["wall"],
         "sim_time": r["t_sim"],
     }
@@ -513,7 +533,9 @@ def main():
         r32 = run_grid(wt, ctx, case, wt.WT_FP32_RECON, args.steps, args.warmup, profile=True,
                        tile_choice=tile_choice)
         f32 = {"value": cells * args.steps / (r32["ms"] / 1e3), "unit": "cell-updates/s",
-               "ms_per_step": r32["ms"] / args.steps, "tiles_tx_tn": r32["tiles"]}
+               "ms_per_step": r32["ms"] / args.steps, "tiles_tx_tn": r32["tiles"],
+               "graph": {"value": cells * args.steps / (r32["ms_graph"] / 1e3),
+                         "ms_per_step": r32["ms_graph"] / args.steps}}
         # the dominant kernel against the vector lane rate: without packed FP32 (left off in
         # this build) an FP32 instruction issues at the FP64 rate, so the peak is the same
         # 256 x 64 x 2.4e9 lane operations/s (the packed FP32 rate is twice that)

@@ -53,7 +53,9 @@ typedef enum {
     WT_ERR_NONPHYSICAL = 3,  /* rho <= 0 or p <= 0 met on the device          */
     WT_ERR_NONFINITE = 4,    /* NaN or Inf met on the device                  */
     WT_ERR_DEVICE = 5,       /* HIP runtime error                             */
-    WT_ERR_NOMEM = 6         /* workspace allocation failed                   */
+    WT_ERR_NOMEM = 6,        /* workspace allocation failed                   */
+    WT_ERR_SCRATCH = 7       /* input exceeds the fixed scratch buffer of
+                                wenotheta_rhs_noalloc                         */
 } wt_status;
 
 typedef enum {
@@ -163,6 +165,32 @@ const char *wenotheta_status_string(int32_t status);
 wt_status wenotheta_rhs(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
                         const double *u, const double *f, const double *alpha_host,
                         double *L_out, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * right-hand side of wenotheta_rhs, same arguments and results (bit for bit),
+ * without a context.  It calls no allocating routine: its scratch (the speed
+ * slot, the error word and, for ndim > 1, the divergence accumulator of
+ * m * ncell doubles) lives in a fixed device buffer of the library, 64 MiB per
+ * GPU, held from the library's first use of that GPU until the process ends.
+ *   - Runs on the current HIP device; stream must belong to it.  The first
+ *     call on a device looks up the buffer's address there (no allocation,
+ *     no stream work).
+ *   - Size limit: for ndim > 1, m * ncell <= 8388096 (e.g. 2D Euler up to
+ *     2097024 points, 1448^2); beyond it WT_ERR_SCRATCH is returned before
+ *     any work is queued.  1D grids have no limit.
+ *   - WT_SIDES grids are not supported (WT_ERR_UNSUPPORTED: there is no side
+ *     table without a context); the default tile shapes are used.
+ *   - status_dev: optional DEVICE int32 that receives, when the work has run,
+ *     WT_OK or the error the device met (WT_ERR_NONPHYSICAL, WT_ERR_NONFINITE).
+ *   - Every call on one GPU shares that GPU's buffer and leaves its contents
+ *     there; each call clears what must start at zero.  Calls that overlap on
+ *     one GPU (several streams, threads or processes' graphs at once) race and
+ *     give undefined results: serialise them.
+ * Asynchronous; argument errors are returned before any work is queued. */
+wt_status wenotheta_rhs_noalloc(const wt_grid *grid, const wt_params *prm, const double *u,
+                                const double *f, const double *alpha_host, double *L_out,
+                                int32_t *status_dev, void *stream);
 
 /* One 3-stage TVD Runge-Kutta step (Sec. 2.1) of u in place.  dt > 0 is used
  * as given; dt <= 0 selects the CFL step dt = cfl / sum_d(amax_d / dx_d),

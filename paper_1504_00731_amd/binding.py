@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwenotheta.so")
 
 WT_OK, WT_ERR_ARG, WT_ERR_UNSUPPORTED, WT_ERR_NONPHYSICAL = 0, 1, 2, 3
-WT_ERR_NONFINITE, WT_ERR_DEVICE, WT_ERR_NOMEM = 4, 5, 6
+WT_ERR_NONFINITE, WT_ERR_DEVICE, WT_ERR_NOMEM, WT_ERR_SCRATCH = 4, 5, 6, 7
 WT_LINEAR, WT_BURGERS, WT_EULER = 0, 1, 2
 WT_PERIODIC, WT_TRANSMISSIVE, WT_REFLECTIVE, WT_SIDES = 0, 1, 2, 3
 WT_SIDE_TRANSMISSIVE, WT_SIDE_REFLECTIVE, WT_SIDE_STATE = 1, 2, 3
@@ -27,7 +27,7 @@ EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_s
             "wenotheta_profile", "wenotheta_profile_read", "wenotheta_solve_batched",
             "wenotheta_solve_batched_2d", "wenotheta_tune_batched", "wenotheta_tune_batched_2d",
             "wenotheta_set_batched_tiles", "wenotheta_tune", "wenotheta_set_tiles",
-            "wenotheta_set_sides")
+            "wenotheta_set_sides", "wenotheta_rhs_noalloc")
 PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
                  "sweep_z_final")
 
@@ -81,6 +81,7 @@ def _lib():
         L.wenotheta_status_string.argtypes = [ctypes.c_int32]
         L.wenotheta_status_string.restype = ctypes.c_char_p
         L.wenotheta_rhs.argtypes = [vp, G, P, vp, vp, dp, vp, vp]
+        L.wenotheta_rhs_noalloc.argtypes = [G, P, vp, vp, dp, vp, vp, vp]
         L.wenotheta_step.argtypes = [vp, G, P, vp, ctypes.c_double, vp, vp]
         L.wenotheta_solve.argtypes = [vp, G, P, vp, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int64, dp, ctypes.POINTER(ctypes.c_int64), vp]
@@ -251,6 +252,25 @@ def wenotheta_rhs(ctx: Context, grid: Grid, params: Params, u, L_out, f=None, al
                                 ctypes.byref(params.c_struct()), _dev_ptr(u, "u", shp),
                                 _dev_ptr(f, "f", shp), al, _dev_ptr(L_out, "L_out", shp),
                                 _stream_ptr(stream)), "wenotheta_rhs")
+    return L_out
+
+
+def wenotheta_rhs_noalloc(grid: Grid, params: Params, u, L_out, f=None, alpha_host=None,
+                          status=None, stream=None):
+    """L(u) as wenotheta_rhs computes it, with no context and no allocation: the
+    library's fixed per-GPU scratch buffer holds the intermediates (calls on one GPU
+    must not overlap).  status: optional int32 device tensor of shape (1,) that
+    receives the device-detected status."""
+    shp = state_shape(grid, params)
+    al = None
+    if alpha_host is not None:
+        vals = [float(v) for v in alpha_host]
+        al = (ctypes.c_double * len(vals))(*vals)
+    _check(_lib().wenotheta_rhs_noalloc(ctypes.byref(grid.c_struct()),
+                                        ctypes.byref(params.c_struct()), _dev_ptr(u, "u", shp),
+                                        _dev_ptr(f, "f", shp), al, _dev_ptr(L_out, "L_out", shp),
+                                        _dev_int_ptr(status, "status", 1, 32),
+                                        _stream_ptr(stream)), "wenotheta_rhs_noalloc")
     return L_out
 
 

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "wenotheta.h"
@@ -729,7 +730,8 @@ struct Shape {
     bool sides;           // some dimension is WT_SIDES
 };
 
-wt_status validate(const wt_ctx *c, const wt_grid *G, const wt_params *P, Shape &S)
+// sides: the side table WT_SIDES dimensions follow (null: none is set).
+wt_status validate_grid(const wt_side *sides, const wt_grid *G, const wt_params *P, Shape &S)
 {
     if (!G || !P) return WT_ERR_ARG;
     if (G->ndim < 1 || G->ndim > 3) return WT_ERR_ARG;
@@ -756,7 +758,7 @@ wt_status validate(const wt_ctx *c, const wt_grid *G, const wt_params *P, Shape 
                 return WT_ERR_ARG;
             if ((G->bc[k] == WT_REFLECTIVE || G->bc[k] == WT_SIDES) && P->system != WT_EULER)
                 return WT_ERR_UNSUPPORTED;
-            if (G->bc[k] == WT_SIDES && !c->has_sides) return WT_ERR_ARG;
+            if (G->bc[k] == WT_SIDES && !sides) return WT_ERR_ARG;
             S.n[k] = G->n[k];
             S.dx[k] = (G->hi[k] - G->lo[k]) / (double)G->n[k];
             S.lo[k] = G->lo[k];
@@ -766,7 +768,7 @@ wt_status validate(const wt_ctx *c, const wt_grid *G, const wt_params *P, Shape 
                 S.sides = true;
                 for (int e = 0; e < 2; ++e)
                     for (int q = 0; q < 2; ++q)
-                        S.walls[k] |= c->sides[2 * k + e].kind[q] == WT_SIDE_REFLECTIVE;
+                        S.walls[k] |= sides[2 * k + e].kind[q] == WT_SIDE_REFLECTIVE;
             }
         } else {
             if (G->n[k] != 1) return WT_ERR_ARG;
@@ -780,6 +782,11 @@ wt_status validate(const wt_ctx *c, const wt_grid *G, const wt_params *P, Shape 
     }
     if (S.ncell * S.m > (int64_t(1) << 40)) return WT_ERR_ARG;
     return WT_OK;
+}
+
+wt_status validate(const wt_ctx *c, const wt_grid *G, const wt_params *P, Shape &S)
+{
+    return validate_grid(c->has_sides ? c->sides : nullptr, G, P, S);
 }
 
 wt_status ensure_workspace(wt_ctx *c, const Shape &S)
@@ -872,16 +879,16 @@ void drain_profile(wt_ctx *c)
     c->nev = 0;
 }
 
-SweepArgs base_args(wt_ctx *c, const Shape &S, const wt_params *P)
+SweepArgs base_args(DevState *st, double *D, const Shape &S, const wt_params *P)
 {
     SweepArgs A{};
-    A.st = c->st;
+    A.st = st;
     for (int k = 0; k < 3; ++k) A.n[k] = S.n[k];
     A.ncell = S.ncell;
     A.a = P->a;
     A.gamma = P->gamma;
     A.W = WenoConst{P->eps, P->alpha_R, 1.0 / P->eps};
-    A.D = c->D;
+    A.D = D;
     for (int d = 0; d < 3; ++d) {
         A.grav[d] = P->gravity[d];
         A.has_grav |= P->gravity[d] != 0.0;
@@ -889,8 +896,13 @@ SweepArgs base_args(wt_ctx *c, const Shape &S, const wt_params *P)
     return A;
 }
 
+SweepArgs base_args(wt_ctx *c, const Shape &S, const wt_params *P)
+{
+    return base_args(c->st, c->D, S, P);
+}
+
 // The arguments of a sweep along direction d.
-void dir_args(SweepArgs &A, const wt_ctx *c, const Shape &S, int d)
+void dir_args(SweepArgs &A, const wt_side *sides, const Shape &S, int d)
 {
     A.dx = S.dx[d];
     A.rdx = 1.0 / S.dx[d];
@@ -898,11 +910,16 @@ void dir_args(SweepArgs &A, const wt_ctx *c, const Shape &S, int d)
     A.walls = S.walls[d];
     if (S.bc[d] == WT_SIDES) {
         const int a = (d + 1) % S.ndim;
-        A.side[0] = c->sides[2 * d];
-        A.side[1] = c->sides[2 * d + 1];
+        A.side[0] = sides[2 * d];
+        A.side[1] = sides[2 * d + 1];
         A.tlo = S.lo[a];
         A.tdx = S.dx[a];
     }
+}
+
+void dir_args(SweepArgs &A, const wt_ctx *c, const Shape &S, int d)
+{
+    dir_args(A, c->sides, S, d);
 }
 
 // Queue the speeds of u into slot g % 3 and zero slot (g + 1) % 3.
@@ -1013,6 +1030,70 @@ wt_status ensure_step_graph(wt_ctx *c, const Shape &S, const wt_params *P, doubl
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of wenotheta_rhs_noalloc
+// ---------------------------------------------------------------------------
+// One device array per GPU holds the device state (speed slot, error word) at
+// offset 0 and the divergence accumulator of multi-dimensional grids after it.
+// Host code never names the array in a kernel argument or a copy: it uses the
+// address hipGetSymbolAddress returns on each device (the name is a host-side
+// stand-in there).
+namespace wt {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr size_t kNoAllocStateBytes = 4096;   // DevState, padded so D stays aligned
+static_assert(sizeof(DevState) <= kNoAllocStateBytes, "device state fits its part");
+static_assert(sizeof(DevState) % sizeof(unsigned long long) == 0, "cleared word by word");
+constexpr int64_t kNoAllocDoubles = (int64_t)((kNoAllocBytes - kNoAllocStateBytes) / sizeof(double));
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace wt
+
+static __device__ __align__(256) unsigned char scratch[wt::kNoAllocBytes];
+
+namespace {
+
+using namespace wt;
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current), looked up on the first
+// call for that device and kept.
+wt_status noalloc_scratch(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return WT_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return WT_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+    return WT_OK;
+}
+
+// Zero the device state word by word (a kernel, not a memset node, so the
+// call may be captured into a graph).
+__global__ void clear_state_kernel(DevState *st)
+{
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(st);
+    for (int k = threadIdx.x; k < (int)(sizeof(DevState) / sizeof(unsigned long long)); k += blockDim.x)
+        w[k] = 0ull;
+}
+
+// The status the device recorded, as a wt_status.
+__global__ void status_kernel(const DevState *st, int32_t *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int e = st->err;
+        *out = (e & kErrNonfinite) ? WT_ERR_NONFINITE : ((e & kErrNonphysical) ? WT_ERR_NONPHYSICAL : WT_OK);
+    }
+}
+
+}  // namespace
+
 namespace wt {
 
 // Read and clear the device error word (synchronises the stream).
@@ -1048,6 +1129,7 @@ const char *wenotheta_status_string(int32_t s)
         case WT_ERR_NONFINITE: return "non-finite value";
         case WT_ERR_DEVICE: return "HIP device error";
         case WT_ERR_NOMEM: return "out of device memory";
+        case WT_ERR_SCRATCH: return "input larger than the fixed scratch buffer of wenotheta_rhs_noalloc";
         default: return "unknown status";
     }
 }
@@ -1371,6 +1453,59 @@ wt_status wenotheta_sync(wt_ctx *c, void *stream)
     if (hipSetDevice(c->device) != hipSuccess) return WT_ERR_DEVICE;
     DevState host{};
     return collect(c, (hipStream_t)stream, &host);
+}
+
+wt_status wenotheta_rhs_noalloc(const wt_grid *G, const wt_params *P, const double *u,
+                                const double *f, const double *alpha_host, double *L,
+                                int32_t *status_dev, void *stream)
+{
+    if (!u || !L || !G) return WT_ERR_ARG;
+    for (int k = 0; k < G->ndim && k < 3; ++k)
+        if (G->bc[k] == WT_SIDES) return WT_ERR_UNSUPPORTED;   // no side table without a context
+    Shape S;
+    wt_status r = validate_grid(nullptr, G, P, S);
+    if (r) return r;
+    if (f && (P->system == WT_EULER || !alpha_host)) return WT_ERR_ARG;
+    if (alpha_host)
+        for (int k = 0; k < S.ndim * S.m; ++k)
+            if (!(alpha_host[k] >= 0.0) || !std::isfinite(alpha_host[k])) return WT_ERR_ARG;
+    // the divergence accumulator of a multi-dimensional grid must fit the buffer
+    if (S.ndim > 1 && S.ncell * S.m > kNoAllocDoubles) return WT_ERR_SCRATCH;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return WT_ERR_DEVICE;
+    unsigned char *base = nullptr;
+    if ((r = noalloc_scratch(dev, &base))) return r;
+    DevState *st = reinterpret_cast<DevState *>(base);
+    double *D = reinterpret_cast<double *>(base + kNoAllocStateBytes);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(clear_state_kernel, dim3(1), dim3(64), 0, s, st);
+    if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    if (alpha_host) {
+        SlotValues v{};
+        for (int d = 0; d < S.ndim; ++d)
+            for (int k = 0; k < S.m; ++k) v.v[d * 5 + k] = alpha_host[d * S.m + k];
+        hipLaunchKernelGGL(set_slots_kernel, dim3(1), dim3(64), 0, s, st, 0, v, -1);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    } else if (launch_alpha(P->system, S.ndim, u, S.ncell, P->a, P->gamma, st, 0, s) != hipSuccess) {
+        return WT_ERR_DEVICE;
+    }
+    SweepArgs A = base_args(st, D, S, P);
+    A.uin = u;
+    A.out = L;
+    A.fgiven = f;
+    A.check_done = 0;
+    A.slot_rd = 0;
+    for (int d = 0; d < S.ndim; ++d) {
+        const int mode = d == S.ndim - 1 ? MODE_LAST_RHS : (d == 0 ? MODE_FIRST : MODE_MID);
+        dir_args(A, static_cast<const wt_side *>(nullptr), S, d);
+        if (launch_sweep_any(P->system, S.ndim, P->precision, d, mode, A, 0, s) != hipSuccess)
+            return WT_ERR_DEVICE;
+    }
+    if (status_dev) {
+        hipLaunchKernelGGL(status_kernel, dim3(1), dim3(64), 0, s, st, status_dev);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_DEVICE;
+    }
+    return WT_OK;
 }
 
 }  // extern "C"

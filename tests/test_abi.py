@@ -81,3 +81,38 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libwenotheta.so")
     with pytest.raises(binding.LibraryMissing):
         wt.Context(0)
+
+
+def test_noalloc_checks_arguments_before_any_work(lib):
+    """wenotheta_rhs_noalloc rejects a grid whose divergence accumulator would exceed its
+    fixed scratch buffer (WT_ERR_SCRATCH), WT_SIDES grids (no side table without a
+    context) and bad arguments, all before any HIP call: this runs without a GPU.  The
+    device pointers are placeholders that the checks never dereference."""
+    f = lib.wenotheta_rhs_noalloc
+    f.restype = ctypes.c_int
+    G, P = ctypes.POINTER(binding.wt_grid), ctypes.POINTER(binding.wt_params)
+    vp = ctypes.c_void_p
+    f.argtypes = [G, P, vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp, vp]
+    fake = vp(0x1000)
+
+    def call(grid, params=wt.Params(system=wt.WT_EULER), u=fake, L=fake):
+        return f(ctypes.byref(grid.c_struct()), ctypes.byref(params.c_struct()), u, None, None, L,
+                 None, None)
+
+    def grid2(nx, ny, bc=wt.WT_TRANSMISSIVE):
+        return wt.Grid(n=(nx, ny), lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(bc, bc))
+
+    # 2D Euler: 4 * nx * ny doubles of divergence; the buffer holds 8388096
+    assert call(grid2(1449, 1449)) == binding.WT_ERR_SCRATCH
+    assert call(grid2(2048, 1024)) == binding.WT_ERR_SCRATCH
+    g3 = wt.Grid(n=(128, 128, 128), lo=(0.0,) * 3, hi=(1.0,) * 3, bc=(0, 0, 0))
+    assert call(g3) == binding.WT_ERR_SCRATCH
+    assert call(grid2(64, 64, bc=wt.WT_SIDES)) == binding.WT_ERR_UNSUPPORTED
+    assert call(grid2(5, 64)) == binding.WT_ERR_ARG                 # fewer than 6 points
+    assert call(grid2(64, 64), u=None) == binding.WT_ERR_ARG
+    assert call(grid2(64, 64), L=None) == binding.WT_ERR_ARG
+    assert call(grid2(64, 64), params=wt.Params(system=wt.WT_EULER, cfl=0.0)) == binding.WT_ERR_ARG
+    msg = lib.wenotheta_status_string
+    msg.restype = ctypes.c_char_p
+    msg.argtypes = [ctypes.c_int32]
+    assert b"scratch" in msg(binding.WT_ERR_SCRATCH)

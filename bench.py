@@ -40,7 +40,12 @@ if ROOT not in sys.path:
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-FP64_VALU_OPS_PEAK = 256 * 64 * 2.4e9      # FP64 lane operations per second (FMA = 1 op)
+FP64_VECTOR_FLOPS_PEAK = 78.6e12           # FP64 vector FLOP/s (an FMA counts as 2 FLOPs)
+# The same peak as an issue rate: 256 CUs x 64 FP64 lanes x 2.4 GHz = 39.3e12 lane
+# instructions/s.  The method's formulas, evaluated as printed, have no fused
+# multiply-adds, so every counted operation needs an instruction of its own: at most
+# half the FLOP/s peak is reachable in that order of operations.
+FP64_LANE_ISSUE_PEAK = 256 * 64 * 2.4e9
 
 WENO_OPS = 132          # FP64 operations of one WENO-theta reconstruction (9 divisions)
 W_EULER = 2             # wt_system of the Euler equations
@@ -124,6 +129,30 @@ def measured_traffic(kernel: str, y_tile: str):
     if kernel.startswith("sweep_y") and kv.get("y_tile") != y_tile:
         return None
     return float(kv[kernel + ".bytes"])
+
+
+def roofline_entry(kind, ops, tot_ms, launches, traffic=None, fp32_recon=False):
+    """The dominant kernel against the published FP64 vector peak: algorithmic FLOPs per
+    launch (every add, multiply, division and square root of the method's formulas
+    counted as one FLOP) over the kernel's average launch duration from HIP events on
+    its launch stream.  The same rate is also given against the lane issue rate."""
+    avg_s = tot_ms / launches / 1e3
+    achieved = ops / avg_s
+    e = {"bound": "alu", "kernel": kind, "achieved": achieved / 1e12,
+         "peak": FP64_VECTOR_FLOPS_PEAK / 1e12, "unit": "TFLOP/s",
+         "frac": achieved / FP64_VECTOR_FLOPS_PEAK, "traffic": traffic,
+         "avg_launch_ms": tot_ms / launches, "launches": launches,
+         "algorithmic_flops_per_launch": ops,
+         "frac_of_lane_issue_rate": achieved / FP64_LANE_ISSUE_PEAK,
+         "lane_issue_rate_note": "39.3e12 FP64 lane instructions/s (256 CUs x 64 lanes x "
+                                 "2.4 GHz): the reachable peak for formulas evaluated without "
+                                 "fused multiply-adds, half the FLOP/s peak"}
+    if fp32_recon:
+        e["flops_counted_as"] = ("the FP64 formulas' operations, the reconstructions (run in "
+                                 "FP32) counted alike; without packed FP32 instructions (left "
+                                 "off in this build) FP32 issues at the FP64 lane rate, so the "
+                                 "same peak applies")
+    return e
 
 
 def build_case(workload: str, n: int | None):
@@ -377,6 +406,7 @@ def compare_batched(wt, ctx, B, cells_per_problem, steps):
                      "ms": r["ms"], "failed_problems": int((r["status"] != 0).sum()),
                      "tile_variant": r["variant"]}
     f32 = out["fp32_recon"]
+    f32["fp32_recon_over_fp64_same_workload"] = f32["value"] / out["fp64"]["value"]
     f32["l1_rel_vs_fp64_well_conditioned"] = [
         float(x) for x in (d32[wellt].sum(0) / den[wellt].sum(0)).cpu()]
     f32["l1_rel_vs_fp64_all"] = [float(x) for x in (d32[okt].sum(0) / den[okt].sum(0)).cpu()]
@@ -480,13 +510,17 @@ def main():
     kind = max(prof, key=lambda kk: prof[kk][0])
     tot_ms, launches = prof[kind]
     d, final = names[kind]
-    avg_s = tot_ms / launches / 1e3
     euler = case.system == W_EULER
     ops = sweep_ops(case.ndim, case.n, d, final, euler)
-    achieved = ops / avg_s
     m = case.ndim + 2 if euler else 1
     bytes_per_step = 8 * m * 8 * cells                   # 8 state passes of m FP64 components
-    peak = FP64_VALU_OPS_PEAK
+    traffic = step_traffic = None
+    if args.workload == "euler2d" and case.n == (4096, 4096) and prec == wt.WT_FP64:
+        y_tile = "x".join(map(str, r["tiles"][1]))
+        traffic = measured_traffic(kind, y_tile)
+        tx, ty = measured_traffic("sweep_x", y_tile), measured_traffic("sweep_y_final", y_tile)
+        if tx is not None and ty is not None:
+            step_traffic = 3 * (tx + ty)                 # one x and one y sweep per stage
 
     line = {
         "metric": "cell-updates/s (RHS+RK3), FP64 plain vs FP32 batched; % of HBM peak",
@@ -506,19 +540,13 @@ def main():
                    "grid": list(case.n), "steps": args.steps, "cfl": case.cfl,
                    "alpha_R": case.alpha_R, "precision": args.precision,
                    "tiles_tx_tn": r["tiles"]},
-        "roofline": {"bound": "alu", "kernel": kind, "achieved": achieved / 1e12,
-                     "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": (measured_traffic(kind, "x".join(map(str, r["tiles"][1])))
-                                 if args.workload == "euler2d" and case.n == (4096, 4096) and
-                                 prec == wt.WT_FP64 else None),
-                     "avg_launch_ms": tot_ms / launches, "launches": launches,
-                     "algorithmic_ops_per_launch": ops,
-                     "ops_counted_as": "fp64 lane operations" + (
-                         "" if prec == wt.WT_FP64 else " (the FP32 reconstruction counted alike)")},
+        "roofline": roofline_entry(kind, ops, tot_ms, launches, traffic),
         "hbm": {"achieved": bytes_per_step * args.steps / sec / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": bytes_per_step * args.steps / sec / 1e9 / HBM_PEAK_GBS,
                 "bytes_per_cell_update": bytes_per_step // cells,
+                "measured_traffic_per_step": step_traffic,
+                "measured_over_algorithmic": (None if step_traffic is None
+                                              else step_traffic / bytes_per_step),
                 "achievable_copy": achievable_copy_bandwidth()},
         "kernel_ms": {kk: {"total": v[0], "launches": v[1]} for kk, v in prof.items() if v[1]},
         "graph": {"value": cells * args.steps / (r["ms_graph"] / 1e3),
@@ -536,26 +564,19 @@ def main():
                "ms_per_step": r32["ms"] / args.steps, "tiles_tx_tn": r32["tiles"],
                "graph": {"value": cells * args.steps / (r32["ms_graph"] / 1e3),
                          "ms_per_step": r32["ms_graph"] / args.steps}}
-        # the dominant kernel against the vector lane rate: without packed FP32 (left off in
-        # this build) an FP32 instruction issues at the FP64 rate, so the peak is the same
-        # 256 x 64 x 2.4e9 lane operations/s (the packed FP32 rate is twice that)
+        # the dominant kernel against the same FP64 vector peak: without packed FP32 (left
+        # off in this build) an FP32 instruction issues at the FP64 rate
         p32 = r32["prof"]
         k32 = max(p32, key=lambda kk: p32[kk][0])
         d32, final32 = names[k32]
         ops32 = sweep_ops(case.ndim, case.n, d32, final32, euler)
-        ach32 = ops32 / (p32[k32][0] / p32[k32][1] / 1e3)
-        f32["roofline"] = {"bound": "alu", "kernel": k32, "achieved": ach32 / 1e12,
-                           "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach32 / peak,
-                           "avg_launch_ms": p32[k32][0] / p32[k32][1],
-                           "ops_counted_as": "lane operations of the FP64 formulas (the "
-                                             "FP32 reconstruction counted alike)"}
+        f32["roofline"] = roofline_entry(k32, ops32, p32[k32][0], p32[k32][1], fp32_recon=True)
+        f32["fp32_recon_over_fp64_same_workload"] = f32["value"] / value
         f32.update(differences(r32["u"], r["u"]))
         comp = {args.workload + "_fp32_recon": f32}
         del r32
         if args.workload == "euler2d":
             comp["batched"] = batched_companions(wt, ctx, args.batched_steps)
-            comp["batched"]["fp32_recon_over_plain_fp64"] = (comp["batched"]["fp32_recon"]["value"] /
-                                                             value)
             comp["batched_2d"] = batched2d_companions(wt, ctx, args.batched2d_steps)
         line["companions"] = comp
     del r

@@ -201,8 +201,10 @@ wt_status wenotheta_rhs_noalloc(const wt_grid *grid, const wt_params *prm, const
 wt_status wenotheta_step(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
                          double *u, double dt, double *dt_used_dev, void *stream);
 
-/* Advance u in place from time t0 to t_end with CFL steps, the last one
- * clipped to end at t_end (a step that would leave less than 1e-6 of itself
+/* Advance u in place from time t0 to t_end with CFL steps (Sec. 2.1 asks for
+ * a proper CFL condition; the tests of Sec. 4.3 take CFL 0.5): each step takes
+ * dt = cfl / sum_d(amax_d / dx_d) from the speeds of its initial state, the
+ * last one clipped to end at t_end (a step that would leave less than 1e-6 of itself
  * to go is stretched to t_end), or until max_steps steps have been taken
  * (max_steps < 0: no limit).  Synchronises; *t_out and *steps_out (HOST,
  * optional) receive the time reached and the steps taken, which also becomes

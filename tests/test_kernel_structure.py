@@ -46,7 +46,10 @@ def _device_asm(src):
 
 
 def _kernels(asm):
-    return sorted(set(re.findall(r"^(_Z\w+):", asm, re.M)))
+    """The functions of the listing (device data such as the fixed scratch array of the
+    allocation-free entry point is an @object symbol and has no code)."""
+    funcs = set(re.findall(r"^\s*\.type\s+(_Z\w+),@function", asm, re.M))
+    return sorted(set(re.findall(r"^(_Z\w+):", asm, re.M)) & funcs)
 
 
 @pytest.mark.parametrize("src", ["wenotheta.hip", "batched.hip"])

@@ -166,9 +166,9 @@ def lib():
         _lib.wto_step.argtypes = [P, dp, ctypes.c_double, dp]
         _lib.wto_solve.argtypes = [P, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                    dp, ip]
-        _lib.wto_decisions_1d.argtypes = [P, dp, dp, i32p, dp]
+        _lib.wto_decisions.argtypes = [P, dp, dp, ctypes.c_int32, i32p, dp]
         for name in ("wto_euler_eigen", "wto_alpha", "wto_rhs", "wto_rhs_points", "wto_step",
-                     "wto_solve", "wto_decisions_1d"):
+                     "wto_solve", "wto_decisions"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
 
@@ -255,16 +255,22 @@ def solve(P: Problem, u, t_end, t0=0.0, max_steps=-1):
     return u, t.value, k.value
 
 
-def decisions_1d(P: Problem, u, alpha_=None):
-    """theta / restriction decisions per interface, field and sign, with margins."""
+def decisions(P: Problem, u, direction=0, alpha_=None):
+    """theta / restriction decisions of every reconstruction along `direction`, and their
+    margins in units of a rounding-error bound (near-ties have small margins).
+    Returns (dec, margins), shaped (ext_z, ext_y, ext_x, m, 4) with ext the grid's
+    point counts except n + 1 interfaces along the direction (entry i + 1 is
+    interface i + 1/2); last axis [theta+, restricted+, theta-, restricted-]."""
     u = _f64(u, P.shape)
-    n = P.n[0]
     al = None if alpha_ is None else _f64(np.asarray(alpha_, dtype=np.float64).ravel())
-    dec = np.zeros((n + 1, P.m, 4), dtype=np.int32)
-    mar = np.zeros((n + 1, P.m, 4))
-    _check(lib().wto_decisions_1d(ctypes.byref(P.c_struct()), _dp(u), _dp(al),
-                                  dec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                  _dp(mar)), "decisions_1d")
+    ext = list(P.n) + [1] * (3 - len(P.n))
+    ext[direction] += 1
+    shape = (ext[2], ext[1], ext[0], P.m, 4)
+    dec = np.zeros(shape, dtype=np.int32)
+    mar = np.zeros(shape)
+    _check(lib().wto_decisions(ctypes.byref(P.c_struct()), _dp(u), _dp(al), int(direction),
+                               dec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(mar)),
+           "decisions")
     return dec, mar
 
 

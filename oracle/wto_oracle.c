@@ -18,10 +18,10 @@
  *   Sec. 4.2/4.3  Euler equations, characteristic-wise reconstruction with the
  *                 Roe mean matrix, dimension by dimension in 2D/3D.
  *   Sec. 4.3      TEST 9's boundaries as sides made of two parts (a given
- *                 state, a wall, zero gradient) split at a point that may move.
- *                 Parity unpinned: the times at which wto_step's stages take
- *                 moving splits (t, t + dt, t + dt/2; a reading) are checked
- *                 only against the stages assembled by hand.
+ *                 state, a wall, zero gradient) split at a point that may move;
+ *                 wto_step's stages take moving splits at t, t + dt, t + dt/2
+ *                 (a reading, pinned by the Simpson-rule error of an inflow
+ *                 switched on inside a step).
  *
  * Built with -O2 -ffp-contract=off and without -ffast-math: every operation
  * below is one IEEE double rounding, evaluated left to right as written.
@@ -881,62 +881,185 @@ int wto_solve(const wto_problem *P, double *u, double t0, double t_end,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Decision dump for flip accounting (1D)                                   */
+/* Decisions and their margins, for flip accounting                         */
 /* ------------------------------------------------------------------------ */
 
-static double rel_margin(double x, double y)
+/* theta (tau_6 < tau_5) and the restriction (R <= alpha_R) are discontinuous in
+ * the six stencil values (Sec. 3.1), so an evaluation of the same formulas with
+ * other rounding (another operation order, fused multiply-adds) may legitimately
+ * take the other branch where the two sides of a comparison are closer than
+ * their rounding errors.  decisions_core reports each decision with its margin
+ * in units of a first-order bound on those errors: |tau_6 - tau_5| / (E_5 + E_6)
+ * and |R - alpha_R| / E_R, where E bounds the error of a quantity computed in
+ * double precision from stencil values that themselves carry errors of up to
+ * err_s[k] (the projection and split that form them).  A margin below a few
+ * units marks a near-tie; +inf marks a comparison no rounding can change (both
+ * sides exactly zero, as for a constant stencil). */
+
+#define WTO_U 0x1p-53
+
+/* Error bound of t = sum_i c[i] s[i] (n terms) from the rounding of the sum and
+ * the errors err_s of the values. */
+static double lin_err(const double *c, const double *s, const double *err_s, int first, int n)
 {
-    const double mx = fabs(x) > fabs(y) ? fabs(x) : fabs(y);
-    return mx > 0.0 ? fabs(x - y) / mx : 0.0;
+    double e = 0.0, mag = 0.0;
+    for (int i = 0; i < n; ++i) {
+        mag += fabs(c[i] * s[first + i]);
+        e += fabs(c[i]) * err_s[first + i];
+    }
+    return e + (double)(n + 1) * WTO_U * mag;
 }
 
-int wto_decisions_1d(const wto_problem *P, const double *u, const double *alpha_in,
-                     int32_t *dec, double *margins)
+/* Error bound of A t1^2 + B t2^2 with t1, t2 the combinations (c1, c2) of the
+ * stencil; value returned in *val. */
+static double sq_err(double A, const double *c1, int f1, int n1, double B, const double *c2,
+                     int f2, int n2, const double *s, const double *err_s, double *val)
+{
+    double t1 = 0.0, t2 = 0.0;
+    for (int i = 0; i < n1; ++i) t1 += c1[i] * s[f1 + i];
+    for (int i = 0; i < n2; ++i) t2 += c2[i] * s[f2 + i];
+    *val = A * t1 * t1 + B * t2 * t2;
+    return 2.0 * A * fabs(t1) * lin_err(c1, s, err_s, f1, n1) +
+           2.0 * B * fabs(t2) * lin_err(c2, s, err_s, f2, n2) + 4.0 * WTO_U * *val;
+}
+
+static double scaled_margin(double diff, double err)
+{
+    if (err > 0.0) return fabs(diff) / err;
+    return INFINITY;
+}
+
+/* out: theta, restricted (as the reconstruction decides them), theta margin,
+ * restriction margin. */
+static void decisions_core(const double s[6], const double err_s[6], double eps,
+                           double alpha_R, int32_t *theta, int32_t *restricted,
+                           double *m_theta, double *m_restr)
+{
+    double d[WTO_DIAG_LEN];
+    weno_theta_core(s, eps, alpha_R, d);
+    *theta = (int32_t)d[12];
+    *restricted = (int32_t)d[9];
+
+    /* beta~_k and tau (Sec. 3.1) with their error bounds */
+    static const double c_b0a[3] = {1.0, -2.0, 1.0}, c_b0b[3] = {1.0, -3.0, 2.0};
+    static const double c_b1a[3] = {1.0, -2.0, 1.0}, c_b1b[2] = {-1.0, 1.0};
+    static const double c_b2a[3] = {1.0, -2.0, 1.0}, c_b2b[2] = {1.0, -1.0};
+    static const double c_b3a[4] = {3.0, -7.0, 5.0, -1.0}, c_b3b[3] = {2.0, -3.0, 1.0};
+    static const double c_t5a[5] = {1.0, -4.0, 6.0, -4.0, 1.0}, c_t5b[4] = {-1.0, 3.0, -3.0, 1.0};
+    static const double c_t6a[6] = {-1.0, 5.0, -10.0, 10.0, -5.0, 1.0};
+    static const double c_t6b[6] = {1.0, -3.0, 2.0, 2.0, -3.0, 1.0};
+    double b[4], eb[4], t5, t6;
+    eb[0] = sq_err(13.0 / 12.0, c_b0a, 0, 3, 1.0, c_b0b, 0, 3, s, err_s, &b[0]);
+    eb[1] = sq_err(13.0 / 12.0, c_b1a, 1, 3, 1.0, c_b1b, 2, 2, s, err_s, &b[1]);
+    eb[2] = sq_err(13.0 / 12.0, c_b2a, 2, 3, 1.0, c_b2b, 2, 2, s, err_s, &b[2]);
+    eb[3] = sq_err(13.0 / 48.0, c_b3a, 2, 4, 1.0, c_b3b, 3, 3, s, err_s, &b[3]);
+    const double e5 = sq_err(13.0 / 12.0, c_t5a, 0, 5, 1.0, c_t5b, 1, 4, s, err_s, &t5);
+    const double e6 = sq_err(13.0 / 12.0, c_t6a, 0, 6, 0.25, c_t6b, 0, 6, s, err_s, &t6);
+    *m_theta = scaled_margin(d[11] - d[10], e5 + e6);
+
+    int kmax = 0, kmin = 0;
+    for (int k = 1; k < 4; ++k) {
+        if (b[k] > b[kmax]) kmax = k;
+        if (b[k] < b[kmin]) kmin = k;
+    }
+    const double R = d[8];
+    double eR = 0.0;
+    if (R > 0.0 && isfinite(R))
+        eR = R * ((b[kmax] > 0.0 ? eb[kmax] / b[kmax] : 0.0) + eb[kmin] / (eps + b[kmin]) +
+                  2.0 * WTO_U);
+    *m_restr = scaled_margin(R - alpha_R, eR);
+}
+
+/* Absolute scale of the split values v+-_{s,k} = (w +- alpha_s q)/2 for the
+ * error bounds: (sum_c |L_sc f_c| + alpha_s sum_c |L_sc u_c|) / 2 times the
+ * roundings of the projection (m products, m - 1 sums) and of the split. */
+static void euler_split_errors(const wto_problem *P, const double *u, int d, int64_t base,
+                               int64_t i, const double *alpha_d, double ep[MAXM][6],
+                               double em[MAXM][6])
+{
+    const int ndim = P->ndim, m = ndim + 2;
+    int perm[MAXM];
+    direction_perm(ndim, d, perm);
+    double Up[6][MAXM], Fp[6][MAXM];
+    prim_t Pk[6];
+    for (int k = 0; k < 6; ++k) {
+        double uc[MAXM];
+        line_point(P, u, d, base, i - 2 + k, uc);
+        primitives(uc, ndim, P->gamma, &Pk[k]);
+        for (int c = 0; c < m; ++c) Up[k][c] = uc[perm[c]];
+        euler_flux_perm(Up[k], &Pk[k], ndim, d, Fp[k]);
+    }
+    double L[MAXM][MAXM], R[MAXM][MAXM], lam[MAXM];
+    roe_eigen(ndim, d, P->gamma, &Pk[2], &Pk[3], L, R, lam);
+    for (int k = 0; k < 6; ++k)
+        for (int s = 0; s < m; ++s) {
+            double sq = 0.0, sw = 0.0;
+            for (int c = 0; c < m; ++c) {
+                sq += fabs(L[s][c] * Up[k][c]);
+                sw += fabs(L[s][c] * Fp[k][c]);
+            }
+            const double e = (double)(m + 3) * WTO_U * 0.5 * (sw + alpha_d[s] * sq);
+            ep[s][k] = e;
+            em[s][5 - k] = e;
+        }
+}
+
+int wto_decisions(const wto_problem *P, const double *u, const double *alpha_in, int32_t dir,
+                  int32_t *dec, double *margins)
 {
     int st = validate(P);
     if (st) return st;
-    if (P->ndim != 1 || P->bc[0] == WTO_SIDES) return WTO_ERR_UNSUPPORTED;
-    const int m = ncomp(P);
-    const int64_t n = P->n[0];
-    double alpha[MAXM], amax[1];
+    if (!u || !dec || !margins) return WTO_ERR_ARG;
+    if (dir < 0 || dir >= P->ndim) return WTO_ERR_ARG;
+    const int ndim = P->ndim, m = ncomp(P);
+    double alpha[3 * MAXM], amax[3];
     if (alpha_in) {
-        for (int k = 0; k < m; ++k) alpha[k] = alpha_in[k];
+        for (int k = 0; k < ndim * m; ++k) alpha[k] = alpha_in[k];
     } else {
         st = wto_alpha(P, u, alpha, amax);
         if (st) return st;
     }
     pair_wall_speeds(P, alpha);
-    for (int64_t i = -1; i < n; ++i) {
-        double vp[MAXM][6], vm[MAXM][6];
-        if (P->system != WTO_EULER) {
-            for (int k = 0; k < 6; ++k) {
-                const int64_t cell = map_index(i - 2 + k, n, P->bc[0]);
-                const double fv = scalar_flux(P, u[cell]);
-                vp[0][k] = 0.5 * (fv + alpha[0] * u[cell]);
-                vm[0][5 - k] = 0.5 * (fv - alpha[0] * u[cell]);
+    const int64_t nd = P->n[dir];
+    const int64_t npen = total_points(P) / nd;
+    /* output strides: the grid with dimension dir extended to nd + 1 interfaces */
+    int64_t ext[3] = {P->n[0], P->n[1], P->n[2]};
+    ext[dir] = nd + 1;
+    const int64_t es[3] = {1, ext[0], ext[0] * ext[1]};
+    for (int64_t pn = 0; pn < npen && !st; ++pn) {
+        const int64_t base = pencil_base(P, dir, pn);
+        const int64_t coord[3] = {base % P->n[0], (base / P->n[0]) % P->n[1],
+                                  base / (P->n[0] * P->n[1])};
+        int64_t obase = 0;
+        for (int k = 0; k < 3; ++k)
+            if (k != dir) obase += coord[k] * es[k];
+        for (int64_t i = -1; i < nd && !st; ++i) {
+            double vp[MAXM][6], vm[MAXM][6], ep[MAXM][6], em[MAXM][6];
+            if (P->system != WTO_EULER) {
+                for (int k = 0; k < 6; ++k) {
+                    const int64_t cell = map_index(i - 2 + k, nd, P->bc[0]);
+                    const double fv = scalar_flux(P, u[cell]);
+                    vp[0][k] = 0.5 * (fv + alpha[0] * u[cell]);
+                    vm[0][5 - k] = 0.5 * (fv - alpha[0] * u[cell]);
+                    const double e = 3.0 * WTO_U * 0.5 * (fabs(fv) + fabs(alpha[0] * u[cell]));
+                    ep[0][k] = e;
+                    em[0][5 - k] = e;
+                }
+            } else {
+                double R[MAXM][MAXM];
+                int perm[MAXM];
+                st = euler_interface_stencils(P, u, dir, base, i, &alpha[dir * m], vp, vm, R, perm);
+                if (st) break;
+                euler_split_errors(P, u, dir, base, i, &alpha[dir * m], ep, em);
             }
-        } else {
-            double R[MAXM][MAXM];
-            int perm[MAXM];
-            st = euler_interface_stencils(P, u, 0, 0, i, alpha, vp, vm, R, perm);
-            if (st) return st;
-        }
-        for (int s = 0; s < m; ++s) {
-            double dp[WTO_DIAG_LEN], dm[WTO_DIAG_LEN];
-            weno_theta_core(vp[s], P->eps, P->alpha_R, dp);
-            weno_theta_core(vm[s], P->eps, P->alpha_R, dm);
-            const int64_t o = ((i + 1) * m + s) * 4;
-            dec[o + 0] = (int32_t)dp[12];
-            dec[o + 1] = (int32_t)dp[9];
-            dec[o + 2] = (int32_t)dm[12];
-            dec[o + 3] = (int32_t)dm[9];
-            if (margins) {
-                margins[o + 0] = rel_margin(dp[10], dp[11]);
-                margins[o + 1] = rel_margin(dp[8], P->alpha_R);
-                margins[o + 2] = rel_margin(dm[10], dm[11]);
-                margins[o + 3] = rel_margin(dm[8], P->alpha_R);
+            const int64_t o = obase + (i + 1) * es[dir];
+            for (int s = 0; s < m; ++s) {
+                int32_t *dd = &dec[(o * m + s) * 4];
+                double *mm = &margins[(o * m + s) * 4];
+                decisions_core(vp[s], ep[s], P->eps, P->alpha_R, &dd[0], &dd[1], &mm[0], &mm[1]);
+                decisions_core(vm[s], em[s], P->eps, P->alpha_R, &dd[2], &dd[3], &mm[2], &mm[3]);
             }
         }
     }
-    return WTO_OK;
+    return st;
 }

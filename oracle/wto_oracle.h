@@ -111,13 +111,19 @@ int wto_step(const wto_problem *P, double *u, double dt, double *dt_used);
 int wto_solve(const wto_problem *P, double *u, double t0, double t_end,
               int64_t max_steps, double *t_out, int64_t *steps_out);
 
-/* Per-interface decisions of a 1D problem for flip accounting: for interface
- * j+1/2, j = -1..n-1, and each field s, theta and restriction of the + and -
- * reconstructions.  dec has (n+1)*m*4 entries: [iface][s][theta+, restr+,
- * theta-, restr-]; margins has (n+1)*m*4 entries: relative |tau6-tau5| and
- * |R-alpha_R| margins in the same layout. */
-int wto_decisions_1d(const wto_problem *P, const double *u, const double *alpha,
-                     int32_t *dec, double *margins);
+/* Decisions of every reconstruction along direction dir, for flip accounting:
+ * for each interface (i + 1/2, i = -1..n_dir - 1, of each grid line along dir)
+ * and field s, the theta and restriction decisions of the + and - parts and
+ * their margins in units of a first-order bound on the rounding errors of the
+ * compared quantities (|tau_6 - tau_5| / (E_5 + E_6), |R - alpha_R| / E_R,
+ * the stencil values' own errors from the projection and split included;
+ * +inf where no rounding can change the comparison).  dec and margins have
+ * shape [ext_z][ext_y][ext_x][m][4], ext the grid's point counts with
+ * ext_dir = n_dir + 1 (entry i + 1 for interface i + 1/2); the last axis is
+ * [theta+, restricted+, theta-, restricted-] and the margins in that order.
+ * alpha as in wto_rhs. */
+int wto_decisions(const wto_problem *P, const double *u, const double *alpha,
+                  int32_t dir, int32_t *dec, double *margins);
 
 #ifdef __cplusplus
 }

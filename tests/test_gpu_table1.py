@@ -2,8 +2,8 @@
 t = 1, WENO-theta6 with alpha_R = 50.  The errors of the library's own run are compared
 with the values the paper prints (tests/golden/table1_weno_theta6.txt), by the same rules
 as the oracle's pins (two printed digits for the sine rows up to N = 160, 6% for the rows
-with vanishing derivatives, a round-off bound for the sine row at N = 320), and for
-N <= 160 the final states equal the oracle's bit for bit."""
+with vanishing derivatives, the truncation error plus a round-off band for the sine row at
+N = 320), and the final states equal the oracle's bit for bit."""
 import os
 
 import numpy as np
@@ -61,14 +61,16 @@ def test_table1_on_the_gpu(ctx, row):
     e = np.abs(got[0] - _u0((x - 1.0 + 1.0) % 2.0 - 1.0, kind))
     l1, linf = (2.0 / N) * (e.sum() + e[0]), e.max()
     if kind == "sin" and N == 320:
-        assert l1 < 5e-12 and linf < 5e-12, (l1, linf)
+        # the printed 4.1e-13 lies below the scheme's own truncation error (1.67e-12 in
+        # extended precision, the 6th-order continuation of the N = 160 entry); the run
+        # equals the oracle's bit for bit below, whose value the CPU pins tie to it
+        assert abs(l1 - 1.67e-12) < 1.5e-12 and abs(linf - 1.31e-12) < 1.5e-12, (l1, linf)
     elif kind == "sin":
         assert float("%.1e" % l1) == l1_ref and float("%.1e" % linf) == linf_ref, (l1, linf)
     else:
         assert abs(l1 / l1_ref - 1) < 0.06 and abs(linf / linf_ref - 1) < 0.06, (l1, linf)
-    if N <= 160:
-        P = oracle.linear_problem(N, alpha_R=50.0)
-        ref = u0
-        for _ in range(N * N // 4):
-            ref, _ = oracle.step(P, ref, dt)
-        assert np.array_equal(got, ref)
+    P = oracle.linear_problem(N, alpha_R=50.0)
+    ref = u0
+    for _ in range(N * N // 4):
+        ref, _ = oracle.step(P, ref, dt)
+    assert np.array_equal(got, ref)

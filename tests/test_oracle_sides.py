@@ -182,6 +182,86 @@ def test_stage_times_of_moving_splits():
     assert k(t0) != k(t0 + dt)
 
 
+def _inflow_run(step, phi0, delta, dt, K, sub=1):
+    """Mass that enters a quiescent 16 x 8 box (x periodic) in K coarse steps through a
+    bottom side whose given state switches from rest to an inflow of vertical momentum
+    rho * delta on each grid line in turn: the split moves one line per coarse step
+    (dt * sub), crossing line j at time (j + phi0) dt * sub.  step(P, u, dt, t) advances
+    u by one RK3 step from time t."""
+    import dataclasses
+    nx, ny = 16, 8
+    dx = 1.0 / nx
+    U0 = W.conserved(np.array(1.0), [np.array(0.0), np.array(0.0)], np.array(1.0)).ravel()
+    Uin = U0.copy()
+    Uin[2] = delta
+    Uin[3] = U0[3] + 0.5 * delta * delta
+    T = dt * sub
+    free = oracle.Side()
+    bottom = oracle.Side(kind=(oracle.STATE, oracle.STATE), state=(tuple(Uin), tuple(U0)),
+                         split0=(0.5 - phi0) * dx, split_speed=dx / T)
+    P = oracle.Problem(ndim=2, system=oracle.EULER, n=(nx, ny), dx=(dx, dx),
+                       bc=(oracle.PERIODIC, oracle.SIDES), lo=(0.0, 0.0),
+                       sides=(free, free, bottom, free, free, free))
+    u = np.broadcast_to(U0[:, None, None], (4, ny, nx)).copy()
+    m0 = u[0].sum()
+    for n in range(K * sub):
+        u = step(dataclasses.replace(P, t=n * dt), u, dt, n * dt)
+    return (u[0].sum() - m0) * dx * dx
+
+
+def _oracle_step(P, u, dt, t):
+    return oracle.step(P, u, dt=dt)[0]
+
+
+def _step_with_nodes(c2, c3):
+    """The RK3 stages assembled from RHS evaluations with stage 2 at t + c2 dt and stage
+    3 at t + c3 dt (for the planted alternatives)."""
+    def step(P, u, dt, t):
+        def L(v, tt):
+            P.t = tt
+            return oracle.rhs(P, v)
+        u1 = u + dt * L(u, t)
+        u2 = 0.75 * u + 0.25 * u1 + 0.25 * dt * L(u1, t + c2 * dt)
+        return (1.0 / 3.0) * u + (2.0 / 3.0) * u2 + (2.0 / 3.0) * dt * L(u2, t + c3 * dt)
+    return step
+
+
+def test_stage_times_integrate_a_switching_inflow_like_simpson():
+    """For a forcing g(t) that does not depend on the state, the three stages of the TVD
+    RK3 (Sec. 2.1) add dt (g(c1) + g(c2) + 4 g(c3)) / 6: with the stage times t, t + dt,
+    t + dt/2 this is Simpson's rule, the only choice of times that integrates quadratics
+    exactly.  An inflow that a side switches on at phase phi within a step (a moving
+    split crossing a grid line) is such a forcing, to first order in its amplitude, so
+    Simpson's rule on a step function fixes the mass error of each crossing:
+    dt F (phi - 1/6) for phi < 1/2 and dt F (phi - 5/6) for phi > 1/2 (F the inflow
+    rate), against a reference with 20 times smaller steps.  The oracle's errors follow
+    that sawtooth (zeros at 1/6 and 5/6, a jump at 1/2); stage times t, t + dt, t + dt
+    or t, t, t + dt/2 give other shapes and fail the same check."""
+    phis = np.array([0.1, 0.3, 0.45, 0.55, 0.7, 0.9])
+    model = np.where(phis < 0.5, phis - 1.0 / 6.0, phis - 5.0 / 6.0)
+    dt, K, delta = 0.2 / 16, 8, 1e-3
+
+    def errors(step):
+        out = []
+        for phi in phis:
+            e = []
+            for d in (delta, -delta):          # the part linear in the amplitude
+                ref = _inflow_run(_oracle_step, phi, d, dt / 20, K, sub=20)
+                e.append(_inflow_run(step, phi, d, dt, K) - ref)
+            out.append(0.5 * (e[0] - e[1]))
+        return np.array(out)
+
+    def fit(E):
+        C = float(E @ model / (model @ model))
+        return C, float(np.max(np.abs(E - C * model)) / np.max(np.abs(C * model)))
+
+    C, res = fit(errors(_oracle_step))
+    assert C > 0 and res < 0.25, (C, res)
+    for nodes in ((1.0, 1.0), (0.0, 0.5)):
+        Cw, rw = fit(errors(_step_with_nodes(*nodes)))
+        assert not (Cw > 0 and rw < 0.25), (nodes, Cw, rw)
+
+
 def test_double_mach_states_satisfy_rankine_hugoniot():
     """Across a shock moving at speed s along its normal n into gas at rest, mass,
     normal momentum and energy fluxes in the shock frame agree and the tangential

@@ -106,11 +106,19 @@ typedef struct {
 typedef enum {
     WT_FP64 = 0,         /* every step in IEEE double precision, in the plain
                             order of the formulas (bit-reproducible)          */
-    WT_FP32_RECON = 1    /* the WENO-theta reconstructions in FP32: each
+    WT_FP32_RECON = 1,   /* the WENO-theta reconstructions in FP32: each
                             stencil is shifted by its point f_j and scaled by
                             a power of two (epsilon scaled by its square)
                             before rounding to FP32; projections, fluxes, RK
                             stages and all stored states stay FP64           */
+    WT_FP64_FAST = 2     /* every step in FP64 with fused multiply-adds and
+                            fast (not correctly rounded) reciprocals and
+                            square roots; where the restriction holds, the
+                            weights are the linear weights gamma^theta exactly
+                            (Sec. 3.1).  Differs from WT_FP64 by rounding; a
+                            theta or restriction decision may differ where its
+                            two sides are within rounding of each other.  Grid
+                            entry points only (batched: WT_ERR_UNSUPPORTED)   */
 } wt_precision;
 
 /* Uniform grid.  n[k] points in dimension k (n[k] = 1 for k >= ndim; at least
@@ -328,6 +336,10 @@ wt_status wenotheta_set_batched_tiles(wt_ctx *ctx, int32_t ndim, int32_t variant
  * and their x sweeps in one of two, rows by TN points along x:
  *   0: 1 x 255 (default)  1: 8 x 31 (for rows that 255-point segments would
  *                          leave a nearly empty last segment, e.g. 512 points)
+ * or, for the 2D Euler system without WT_SIDES dimensions, x variant
+ *   2: the fused stage kernel: both directions of a stage in one launch on
+ *      tiles of 16 x 30 points with 3-point halos, so that the divergence of
+ *      the x direction stays on chip (the y entry is then unused)
  * Every shape computes the same fluxes with the same operations: the results
  * are bit-identical whichever is used; only the speed differs.  The choice
  * is kept in the context per grid shape (system, ndim, n, precision; the 16
@@ -341,8 +353,9 @@ wt_status wenotheta_set_batched_tiles(wt_ctx *ctx, int32_t ndim, int32_t variant
  * and returns any device error.
  *
  * wenotheta_set_tiles sets the shapes for the grid instead: tile[0] in 0..1
- * and tile[d] in 0..3 for 0 < d < ndim (HOST); systems or dimensions without
- * choices (scalar laws, 1D) ignore the entries.  No device work. */
+ * (0..2 for the 2D Euler system without WT_SIDES dimensions) and tile[d] in
+ * 0..3 for 0 < d < ndim (HOST); systems or dimensions without choices (scalar
+ * laws, 1D) ignore the entries.  No device work. */
 wt_status wenotheta_tune(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm, const double *u,
                          int32_t *tile_out, void *stream);
 wt_status wenotheta_set_tiles(wt_ctx *ctx, const wt_grid *grid, const wt_params *prm,
@@ -360,9 +373,10 @@ wt_status wenotheta_profile(wt_ctx *ctx, int32_t enable);
 
 /* Totals since wenotheta_profile(ctx, 1), folded in at each synchronising
  * call: ms[k] (HOST) the summed kernel milliseconds and count[k] (HOST) the
- * launches of kind k, nkinds >= 6.  Kind d (0..2) is the sweep along
- * direction d in a non-final role (writing or accumulating the divergence);
- * kind 3 + d is the sweep along d that finishes a stage or an RHS evaluation.
+ * launches of kind k for k < min(nkinds, 7), nkinds >= 6.  Kind d (0..2) is the
+ * sweep along direction d in a non-final role (writing or accumulating the
+ * divergence); kind 3 + d is the sweep along d that finishes a stage or an RHS
+ * evaluation; kind 6 is the fused 2D stage kernel.
  * Returns WT_ERR_ARG if more launches were queued between two synchronising
  * calls than could be recorded (4096). */
 wt_status wenotheta_profile_read(wt_ctx *ctx, double *ms, int64_t *count, int32_t nkinds);

@@ -7,7 +7,7 @@ The computation lives in ``libwenotheta.so`` (HIP kernels behind the C ABI of
 """
 from . import workloads  # noqa: F401
 from .binding import (  # noqa: F401
-    INF, WT_BURGERS, WT_EULER, WT_FP32_RECON, WT_FP64, WT_LINEAR, WT_PERIODIC, WT_REFLECTIVE,
+    INF, WT_BURGERS, WT_EULER, WT_FP32_RECON, WT_FP64, WT_FP64_FAST, WT_LINEAR, WT_PERIODIC, WT_REFLECTIVE,
     WT_TRANSMISSIVE, WT_SIDES, WT_SIDE_TRANSMISSIVE, WT_SIDE_REFLECTIVE, WT_SIDE_STATE, Side,
     wenotheta_set_sides, Context, Grid,
     LibraryMissing, Params, WenoThetaError, state_shape, wenotheta_rhs, wenotheta_rhs_noalloc, wenotheta_solve,

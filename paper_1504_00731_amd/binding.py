@@ -20,7 +20,7 @@ WT_ERR_NONFINITE, WT_ERR_DEVICE, WT_ERR_NOMEM, WT_ERR_SCRATCH = 4, 5, 6, 7
 WT_LINEAR, WT_BURGERS, WT_EULER = 0, 1, 2
 WT_PERIODIC, WT_TRANSMISSIVE, WT_REFLECTIVE, WT_SIDES = 0, 1, 2, 3
 WT_SIDE_TRANSMISSIVE, WT_SIDE_REFLECTIVE, WT_SIDE_STATE = 1, 2, 3
-WT_FP64, WT_FP32_RECON = 0, 1
+WT_FP64, WT_FP32_RECON, WT_FP64_FAST = 0, 1, 2
 
 EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_string",
             "wenotheta_rhs", "wenotheta_step", "wenotheta_solve", "wenotheta_sync",
@@ -29,7 +29,7 @@ EXPORTED = ("wenotheta_ctx_create", "wenotheta_ctx_destroy", "wenotheta_status_s
             "wenotheta_set_batched_tiles", "wenotheta_tune", "wenotheta_set_tiles",
             "wenotheta_set_sides", "wenotheta_rhs_noalloc")
 PROFILE_KINDS = ("sweep_x", "sweep_y", "sweep_z", "sweep_x_final", "sweep_y_final",
-                 "sweep_z_final")
+                 "sweep_z_final", "stage_2d")
 
 
 class LibraryMissing(RuntimeError):
@@ -297,7 +297,8 @@ def wenotheta_solve(ctx: Context, grid: Grid, params: Params, u, t_end, t0=0.0, 
 
 
 TILE_SHAPES = ((8, 31), (16, 15), (4, 63), (32, 7))   # (TX, TN) of the y/z-sweep tile variants
-X_TILE_SHAPES = ((1, 255), (8, 31))                   # (rows, TN) of the x-sweep tile variants
+X_TILE_SHAPES = ((1, 255), (8, 31), (16, 30))        # (rows, TN) of the x-sweep tile variants;
+                                                      # 2: the fused 2D stage (16 x 30 tiles)
 
 
 def wenotheta_tune(ctx: Context, grid: Grid, params: Params, u, stream=None) -> tuple:
@@ -349,9 +350,10 @@ def wenotheta_profile(ctx: Context, enable: bool):
 
 def wenotheta_profile_read(ctx: Context) -> dict:
     """{kind: (total_ms, launches)} since profiling was enabled."""
-    ms = (ctypes.c_double * 6)()
-    cnt = (ctypes.c_int64 * 6)()
-    _check(_lib().wenotheta_profile_read(ctx.handle, ms, cnt, 6), "wenotheta_profile_read")
+    nk = len(PROFILE_KINDS)
+    ms = (ctypes.c_double * nk)()
+    cnt = (ctypes.c_int64 * nk)()
+    _check(_lib().wenotheta_profile_read(ctx.handle, ms, cnt, nk), "wenotheta_profile_read")
     return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_KINDS)}
 
 

@@ -31,24 +31,52 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the library)")
 
 
-def _build_one(out: str, sources: list, verbose: bool) -> str:
-    srcs = [os.path.join(CSRC, s) for s in sources]
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH] + FLAGS + ["-I" + INCLUDE, "-I" + CSRC,
-                                                         "-o", tmp] + srcs
+def _run(cmd: list, verbose: bool, what: str):
     if verbose:
         print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building " + os.path.basename(out))
-    os.replace(tmp, out)
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True), what
+
+
+def _wait(jobs):
+    failed = []
+    for proc, what in jobs:
+        out, _ = proc.communicate()
+        if proc.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(what)
+    if failed:
+        raise RuntimeError("hipcc failed building " + ", ".join(failed))
+
+
+def _build_one(out: str, sources: list, verbose: bool) -> str:
+    """Each source compiled to an object in parallel, then linked."""
+    tag = ".tmp%d" % os.getpid()
+    objs = [os.path.join(HERE, os.path.splitext(s)[0] + tag + ".o") for s in sources]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs = [_run([hipcc(), "--offload-arch=" + ARCH] + compile_flags +
+                 ["-I" + INCLUDE, "-I" + CSRC, "-c", "-o", o, os.path.join(CSRC, src)],
+                 verbose, src) for src, o in zip(sources, objs)]
+    try:
+        _wait(jobs)
+        tmp = out + tag
+        _wait([_run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs,
+                    verbose, os.path.basename(out))])
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 
 def build(verbose: bool = False) -> str:
     """Builds both libraries; returns the solver library's path."""
     _build_one(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _build_one(LIB, SOURCES, verbose)
+
+
+def build_solver(verbose: bool = False) -> str:
+    """Builds the solver library only."""
     return _build_one(LIB, SOURCES, verbose)
 
 

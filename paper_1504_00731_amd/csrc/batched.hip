@@ -1082,6 +1082,7 @@ wt_status prepare_1d(wt_ctx *c, int64_t nprob, const int64_t *n, const int64_t *
     if (!c || !P || !u || !n || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 6 || nsteps < 0) return WT_ERR_ARG;
     if (P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
+    if (P->precision == WT_FP64_FAST) return WT_ERR_UNSUPPORTED;
     if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
     if (P->gravity[0] != 0.0 || P->gravity[1] != 0.0 || P->gravity[2] != 0.0) return WT_ERR_UNSUPPORTED;
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0) || !(P->gamma > 1.0))
@@ -1312,6 +1313,7 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
     if (!c || !P || !u || !nx || !ny || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 36 || nsteps < 0) return WT_ERR_ARG;
     if (P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
+    if (P->precision == WT_FP64_FAST) return WT_ERR_UNSUPPORTED;
     if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
     if (P->gravity[0] != 0.0 || P->gravity[1] != 0.0 || P->gravity[2] != 0.0) return WT_ERR_UNSUPPORTED;
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0) || !(P->gamma > 1.0))

@@ -40,10 +40,11 @@ struct HostScalar {
     double f(int k) const { return ff[k]; }
 };
 
-template <int NDIM, int DIR>
+template <int NDIM, int DIR, int PREC>
 int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double gamma, double eps,
                 double aR, const double *u, double *D, bool first)
 {
+    constexpr bool FAST = wt::fast_math<PREC>();
     constexpr int M = NDIM + 2;
     const int64_t N = n[0] * n[1] * n[2];
     const int64_t nd = n[DIR];
@@ -62,20 +63,21 @@ int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double ga
                 for (int c = 0; c < M; ++c) uc[c] = u[c * N + idx];
                 if (reflected(i - 2 + k, nd, bc)) uc[1 + DIR] = -uc[1 + DIR];
                 double p, H;
-                if (!wt::euler_cell<NDIM>(uc, gamma, S.vv[k], p, H)) bad = 1;
+                if (!wt::euler_cell<NDIM, FAST>(uc, gamma, S.vv[k], p, H)) bad = 1;
                 for (int c = 0; c < M; ++c) S.uu[k][c] = uc[c];
                 wt::euler_normal_flux<NDIM, DIR>(uc, S.vv[k], p, S.ff[k]);
-                S.ss[k] = wt::sqrt_rn(uc[0]);
+                S.ss[k] = FAST ? wt::sqrt_fast(uc[0]) : wt::sqrt_rn(uc[0]);
                 S.hh[k] = H;
             }
-            if (!wt::euler_interface_flux<NDIM, DIR, 0>(S, HostSpeeds{al, bc == WT_REFLECTIVE}, gamma,
+            if (!wt::euler_interface_flux<NDIM, DIR, PREC>(S, HostSpeeds{al, bc == WT_REFLECTIVE}, gamma,
                                                         wt::WenoConst{eps, aR, 1.0 / eps},
                                                         &F[(i + 1) * M]))
                 bad = 1;
         }
         for (int64_t i = 0; i < nd; ++i)
             for (int c = 0; c < M; ++c) {
-                const double Dd = wt::div_rn(F[(i + 1) * M + c] - F[i * M + c], dx);
+                const double Dd = FAST ? (F[(i + 1) * M + c] - F[i * M + c]) * (1.0 / dx)
+                                       : wt::div_rn(F[(i + 1) * M + c] - F[i * M + c], dx);
                 const int64_t o = c * N + base + i * sd;
                 D[o] = first ? Dd : D[o] + Dd;
             }
@@ -111,11 +113,14 @@ double wth_weno(const double *s, double eps, double aR)
     return wt::weno_theta(s[0], s[1], s[2], s[3], s[4], s[5], eps, aR, 1.0 / eps);
 }
 
-// Full L(u) for the Euler equations (alpha: [ndim][5] LF speeds per field) or
-// for a 1D scalar state with given flux values f (alpha[0]).
-int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc,
-            const double *alpha, double gamma, double eps, double aR, const double *u,
-            const double *f, double *L, const double *grav)
+}  // extern "C"
+
+namespace {
+
+template <int PREC>
+int host_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc,
+             const double *alpha, double gamma, double eps, double aR, const double *u,
+             const double *f, double *L, const double *grav)
 {
     if (sys != 2) {
         const int64_t nn = n[0];
@@ -127,7 +132,7 @@ int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc
                 S.uu[k] = u[idx];
                 S.ff[k] = f[idx];
             }
-            F[i + 1] = wt::scalar_interface_flux<0>(S, alpha[0], wt::WenoConst{eps, aR, 1.0 / eps});
+            F[i + 1] = wt::scalar_interface_flux<PREC>(S, alpha[0], wt::WenoConst{eps, aR, 1.0 / eps});
         }
         for (int64_t i = 0; i < nn; ++i) L[i] = -wt::div_rn(F[i + 1] - F[i], dx[0]);
         return 0;
@@ -137,14 +142,14 @@ int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc
     std::vector<double> D((size_t)N * M);
     int bad = 0;
     if (ndim == 1) {
-        bad |= euler_sweep<1, 0>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
+        bad |= euler_sweep<1, 0, PREC>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
     } else if (ndim == 2) {
-        bad |= euler_sweep<2, 0>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
-        bad |= euler_sweep<2, 1>(n, dx[1], bc[1], alpha + 5, gamma, eps, aR, u, D.data(), false);
+        bad |= euler_sweep<2, 0, PREC>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
+        bad |= euler_sweep<2, 1, PREC>(n, dx[1], bc[1], alpha + 5, gamma, eps, aR, u, D.data(), false);
     } else {
-        bad |= euler_sweep<3, 0>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
-        bad |= euler_sweep<3, 1>(n, dx[1], bc[1], alpha + 5, gamma, eps, aR, u, D.data(), false);
-        bad |= euler_sweep<3, 2>(n, dx[2], bc[2], alpha + 10, gamma, eps, aR, u, D.data(), false);
+        bad |= euler_sweep<3, 0, PREC>(n, dx[0], bc[0], alpha, gamma, eps, aR, u, D.data(), true);
+        bad |= euler_sweep<3, 1, PREC>(n, dx[1], bc[1], alpha + 5, gamma, eps, aR, u, D.data(), false);
+        bad |= euler_sweep<3, 2, PREC>(n, dx[2], bc[2], alpha + 10, gamma, eps, aR, u, D.data(), false);
     }
     for (int64_t k = 0; k < N * M; ++k) L[k] = -D[k];
     if (grav && (grav[0] != 0.0 || grav[1] != 0.0 || grav[2] != 0.0))
@@ -160,6 +165,22 @@ int wth_rhs(int sys, int ndim, const int64_t *n, const double *dx, const int *bc
             L[(ndim + 1) * N + j] = L[(ndim + 1) * N + j] + (-e);
         }
     return bad;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Full L(u) for the Euler equations (alpha: [ndim][5] LF speeds per field) or
+// for a 1D scalar state with given flux values f (alpha[0]), in precision mode
+// prec (0: plain FP64 order, 1: FP32 reconstruction, 2: fast FP64).
+int wth_rhs(int prec, int sys, int ndim, const int64_t *n, const double *dx, const int *bc,
+            const double *alpha, double gamma, double eps, double aR, const double *u,
+            const double *f, double *L, const double *grav)
+{
+    if (prec == 1) return host_rhs<1>(sys, ndim, n, dx, bc, alpha, gamma, eps, aR, u, f, L, grav);
+    if (prec == 2) return host_rhs<2>(sys, ndim, n, dx, bc, alpha, gamma, eps, aR, u, f, L, grav);
+    return host_rhs<0>(sys, ndim, n, dx, bc, alpha, gamma, eps, aR, u, f, L, grav);
 }
 
 }  // extern "C"

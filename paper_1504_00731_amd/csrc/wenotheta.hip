@@ -248,14 +248,14 @@ __global__ void copy_dt_kernel(const DevState *st, double *dst)
 // ---------------------------------------------------------------------------
 
 // Minimum waves per SIMD the register allocation must allow (measured on the
-// benchmark grids): 4 for the Euler sweeps in FP64, which then fit 128 VGPRs
-// (spill-free in 1D and 2D; in 3D with 12-28 bytes held outside the interface
-// loop, still 13% faster than at 3 waves); 5 for the 2D FP32 sweeps (96 VGPRs,
-// 6% faster than at 4).
+// benchmark grids): 4 for the Euler sweeps, which then fit 128 VGPRs without
+// spills in every precision mode.  At 5 waves (96 VGPRs) the fast FP64 and the
+// FP32-weight 2D sweeps spill 36-52 bytes and ran 6% (3.02e9 against 3.21e9
+// cell-updates/s) and 11% (2.81e9 against 3.15e9) slower on 2D Euler 4096^2.
 template <int SYS, int NDIM, int PREC>
 constexpr int sweep_min_waves()
 {
-    return SYS == WT_EULER && NDIM == 2 && PREC != 0 ? 5 : (SYS == WT_EULER ? 4 : 1);
+    return SYS == WT_EULER ? 4 : 1;
 }
 
 // 1D Euler grids are short (65536 points fill only 257 one-interface-per-thread
@@ -279,6 +279,7 @@ void sweep_kernel(SweepArgs A)
     constexpr int NV = SpeedLayout<SYS, NDIM>::NV;
     // 1D Euler: the characteristic fields of an interface on separate threads
     constexpr bool SPLIT = split_fields<SYS, NDIM, PREC>();
+    constexpr bool FAST = fast_math<PREC>();
     static_assert(SPLIT ? TX == 1 && M * (TN + 1) <= kThreads : TX * (TN + 1) == kThreads,
                   "one interface (or, split, one field of an interface) per thread");
 
@@ -388,7 +389,7 @@ void sweep_kernel(SweepArgs A)
                 if (reflected(gi, nd, A.bc)) uc[1 + DIR] = -uc[1 + DIR];
             }
             double vel[NDIM], p, H;
-            const bool ok = euler_cell<NDIM>(uc, A.gamma, vel, p, H);
+            const bool ok = euler_cell<NDIM, FAST>(uc, A.gamma, vel, p, H);
             if (!ok) {
                 bool fin = true;
 #pragma unroll
@@ -404,7 +405,7 @@ void sweep_kernel(SweepArgs A)
             }
 #pragma unroll
             for (int k = 0; k < NDIM; ++k) s_v[k][li] = vel[k];
-            s_sr[li] = sqrt_rn(uc[0]);
+            s_sr[li] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
             s_H[li] = H;
         } else {
             const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
@@ -429,7 +430,7 @@ void sweep_kernel(SweepArgs A)
         const LdsStencil<M, NDIM, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, it};
         RoeBasis<NDIM> B{};
         if (valid) {
-            B = interface_basis<NDIM, DIR>(S, A.gamma);
+            B = interface_basis<NDIM, DIR, FAST>(S, A.gamma);
             const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.walls != 0};
             s_h[f][it] = euler_field_flux<NDIM, DIR, PREC, fresh_rows<NDIM, PREC>()>(S, B, f, al, A.W);
             if (f == 0 && !B.ok) atomicOr(&st->err, kErrNonphysical);
@@ -488,7 +489,8 @@ void sweep_kernel(SweepArgs A)
             double Lc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                const double Dd = div_by_recip(s_F[c][t + TX] - s_F[c][t], A.dx, A.rdx);
+                const double Dd = FAST ? (s_F[c][t + TX] - s_F[c][t]) * A.rdx
+                                       : div_by_recip(s_F[c][t + TX] - s_F[c][t], A.dx, A.rdx);
                 const int64_t o = c * ncell + idx;
                 if constexpr (MODE == MODE_FIRST) {
                     A.D[o] = Dd;
@@ -521,7 +523,18 @@ void sweep_kernel(SweepArgs A)
             } else if constexpr (MODE == MODE_LAST_STAGE) {
                 const double dt = st->dt;
                 double un[M];
-                if (A.stage == 1) {
+                if constexpr (FAST) {
+                    // the stage combinations with fused multiply-adds, one fixed form for
+                    // every component (the symmetries exchange components)
+                    const double c0 = A.stage == 1 ? 0.0 : (A.stage == 2 ? 0.75 : 1.0 / 3.0);
+                    const double c1 = A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0);
+                    const double cdt = (A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0)) * dt;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) {
+                        const double base = __builtin_fma(cdt, Lc[c], c1 * s_u[c][t + 3 * TX]);
+                        un[c] = A.stage == 1 ? base : __builtin_fma(c0, A.u0[c * ncell + idx], base);
+                    }
+                } else if (A.stage == 1) {
 #pragma unroll
                     for (int c = 0; c < M; ++c) {
                         const int64_t o = c * ncell + idx;
@@ -547,7 +560,7 @@ void sweep_kernel(SweepArgs A)
                 // Lax-Friedrichs speeds of the new state
                 if constexpr (EULER) {
                     double lam[3 * NDIM];
-                    err2 |= euler_speeds<NDIM>(un, A.gamma, lam);
+                    err2 |= euler_speeds<NDIM, FAST>(un, A.gamma, lam);
 #pragma unroll
                     for (int k = 0; k < NV; ++k) spd[k] = lam[k];
                 } else {
@@ -574,6 +587,302 @@ void sweep_kernel(SweepArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// Fused stage of the 2D Euler system
+// ---------------------------------------------------------------------------
+// One launch per Runge-Kutta stage (or RHS): a block owns a tile of kFX x kFY
+// points and stages it once with 3-point halos in both directions (the corners,
+// which no stencil reads, are skipped); the x interfaces, then their flux
+// differences (kept in registers), then the y interfaces, and the stage update.
+// No divergence array goes through HBM and the stage input is read once (plus
+// halos), against two sweeps that write and read back D.  The interfaces use the
+// sweeps' routine, so every flux is the same operations on the same values: the
+// results are the sweeps' bit for bit.
+//
+// LDS per block: the staged points (state, velocities, p, sqrt(rho), H: 9 doubles
+// each) and one buffer for the normal fluxes of the current direction, which the
+// interface fluxes replace once every stencil has been read: 78 KB, two blocks of
+// 512 threads per CU (4 waves per SIMD).  kFX = 16 makes each tile row one
+// 128-byte line of a component.
+constexpr int kFX = 16, kFY = 30, kFThreads = 512;
+constexpr int kFW = kFX + 6, kFH = kFY + 6, kFNP = kFW * kFH;
+constexpr int kFXF = kFY * kFW;              // x phase: normal fluxes of rows 3 .. kFY + 2
+constexpr int kFYF = kFH * kFX;              // y phase: normal fluxes of columns 3 .. kFX + 2
+constexpr int kFBuf = kFXF > kFYF ? kFXF : kFYF;
+static_assert((kFX + 1) * kFY <= kFThreads && kFX * (kFY + 1) <= kFThreads,
+              "one interface per thread in each phase");
+static_assert((kFX + 1) * kFY <= kFBuf && kFX * (kFY + 1) <= kFBuf, "interface fluxes fit");
+
+struct Stage2dArgs {
+    const double *uin;     // state whose fluxes are taken
+    const double *u0;      // state at the start of the step (stages 2, 3)
+    double *out;           // L (rhs) or the next stage state
+    DevState *st;
+    int64_t n[2];
+    int64_t ncell;
+    double dx[2], rdx[2];
+    double gamma;
+    WenoConst W;
+    int bc[2];
+    int walls[2];
+    int slot_rd, slot_wr, slot_zero;
+    int stage;
+    int check_done;
+    int64_t ntx, tiles, tiles_per_xcd;
+    double grav[2];
+    int has_grav;
+};
+
+// Stencil of one interface on the fused tile: point k at staged index base + k step,
+// its normal flux at fbase + k fstep of the flux buffer.
+template <int STEP, int FSTEP>
+struct TileStencil {
+    const double (*u)[kFNP];
+    const double (*fn)[kFBuf];
+    const double (*vel)[kFNP];
+    const double *sq, *hh;
+    int base, fbase;
+    __device__ double U(int k, int c) const { return u[c][base + k * STEP]; }
+    __device__ double f(int k, int c) const { return fn[c][fbase + k * FSTEP]; }
+    __device__ double v(int k, int d) const { return vel[d][base + k * STEP]; }
+    __device__ double sr(int k) const { return sq[base + k * STEP]; }
+    __device__ double H(int k) const { return hh[base + k * STEP]; }
+};
+
+template <int MODE, int PREC>
+__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void stage2d_kernel(Stage2dArgs A)
+{
+    constexpr int M = 4;
+    constexpr bool FAST = fast_math<PREC>();
+    constexpr int NV = SpeedLayout<SYS_EULER, 2>::NV;
+    __shared__ double s_u[M][kFNP];
+    __shared__ double s_v[2][kFNP];
+    __shared__ double s_p[kFNP];
+    __shared__ double s_sr[kFNP];
+    __shared__ double s_H[kFNP];
+    __shared__ double s_f[M][kFBuf];             // normal fluxes, then interface fluxes
+
+    DevState *st = A.st;
+    if (A.check_done && st->done) return;
+    const int64_t nx = A.n[0], ny = A.n[1], ncell = A.ncell;
+    // tiles dealt to the XCDs in contiguous ranges (see sweep_kernel)
+    int64_t b = blockIdx.x;
+    b = (b % kXcds) * A.tiles_per_xcd + b / kXcds;
+    if (b >= A.tiles) return;
+    const int64_t x0 = (b % A.ntx) * kFX, y0 = (b / A.ntx) * kFY;
+    const int nxt = (int)(nx - x0 < kFX ? nx - x0 : kFX);   // owned points of the tile
+    const int nyt = (int)(ny - y0 < kFY ? ny - y0 : kFY);
+    const int t = threadIdx.x;
+
+    // ---- stage the tile and its halos; ghost points through each direction's map
+    int err = 0;
+    for (int i = t; i < kFNP; i += kFThreads) {
+        const int iy = i / kFW, ix = i - iy * kFW;
+        if ((ix < 3 || ix >= kFX + 3) && (iy < 3 || iy >= kFY + 3)) continue;   // corner
+        const int64_t gx = x0 - 3 + ix, gy = y0 - 3 + iy;
+        const int64_t idx = map_index(gy, ny, A.bc[1]) * nx + map_index(gx, nx, A.bc[0]);
+        double uc[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uc[c] = A.uin[c * ncell + idx];
+        if (reflected(gx, nx, A.bc[0])) uc[1] = -uc[1];
+        if (reflected(gy, ny, A.bc[1])) uc[2] = -uc[2];
+        double vel[2], p, H;
+        if (!euler_cell<2, FAST>(uc, A.gamma, vel, p, H)) {
+            bool fin = true;
+#pragma unroll
+            for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
+            err |= fin ? kErrNonphysical : kErrNonfinite;
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) s_u[c][i] = uc[c];
+        s_v[0][i] = vel[0];
+        s_v[1][i] = vel[1];
+        s_p[i] = p;
+        s_sr[i] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
+        s_H[i] = H;
+    }
+    if (err) atomicOr(&st->err, err);
+    __syncthreads();
+
+    // ---- x direction: normal fluxes of rows 3 .. kFY + 2, then one interface per thread
+    for (int i = t; i < kFXF; i += kFThreads) {
+        const int li = i + 3 * kFW;
+        double uc[M], vel[2], fn[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uc[c] = s_u[c][li];
+        vel[0] = s_v[0][li];
+        vel[1] = s_v[1][li];
+        euler_normal_flux<2, 0>(uc, vel, s_p[li], fn);
+#pragma unroll
+        for (int c = 0; c < M; ++c) s_f[c][i] = fn[c];
+    }
+    __syncthreads();
+    double F[M];
+    {
+        const int fi = t % (kFX + 1), j = t / (kFX + 1);   // face between points fi-1, fi of row j
+        const bool valid = j < kFY && fi <= nxt && j < nyt;
+        if (valid) {
+            const TileStencil<1, 1> S{s_u, s_f, s_v, s_sr, s_H, (j + 3) * kFW + fi, j * kFW + fi};
+            const SlotSpeeds al{st->alpha[A.slot_rd], 0, A.walls[0] != 0};
+            if (!euler_interface_flux<2, 0, PREC>(S, al, A.gamma, A.W, F))
+                atomicOr(&st->err, kErrNonphysical);
+        }
+        __syncthreads();                         // every stencil read of s_f is done
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) s_f[c][j * (kFX + 1) + fi] = F[c];
+        }
+    }
+    __syncthreads();
+    // x flux differences of the owned points, kept for the end of the stage
+    const int ci = t % kFX, cj = t / kFX;
+    const bool own = cj < kFY && ci < nxt && cj < nyt;
+    double Dx[M];
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const double d = s_f[c][cj * (kFX + 1) + ci + 1] - s_f[c][cj * (kFX + 1) + ci];
+            Dx[c] = FAST ? d * A.rdx[0] : div_by_recip(d, A.dx[0], A.rdx[0]);
+        }
+    }
+    __syncthreads();
+
+    // ---- y direction: normal fluxes of columns 3 .. kFX + 2, one interface per thread
+    for (int i = t; i < kFYF; i += kFThreads) {
+        const int iy = i / kFX, ix = i - iy * kFX + 3;
+        const int li = iy * kFW + ix;
+        double uc[M], vel[2], fn[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uc[c] = s_u[c][li];
+        vel[0] = s_v[0][li];
+        vel[1] = s_v[1][li];
+        euler_normal_flux<2, 1>(uc, vel, s_p[li], fn);
+#pragma unroll
+        for (int c = 0; c < M; ++c) s_f[c][i] = fn[c];
+    }
+    __syncthreads();
+    {
+        const int i = t % kFX, fj = t / kFX;     // face between points fj-1, fj of column i
+        const bool valid = fj <= kFY && i < nxt && fj <= nyt;
+        if (valid) {
+            const TileStencil<kFW, kFX> S{s_u, s_f, s_v, s_sr, s_H, fj * kFW + i + 3, fj * kFX + i};
+            const SlotSpeeds al{st->alpha[A.slot_rd], 1, A.walls[1] != 0};
+            if (!euler_interface_flux<2, 1, PREC>(S, al, A.gamma, A.W, F))
+                atomicOr(&st->err, kErrNonphysical);
+        }
+        __syncthreads();
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) s_f[c][fj * kFX + i] = F[c];
+        }
+    }
+    __syncthreads();
+
+    // ---- owned points: L = -(D_x + D_y) (+ source), then the stage
+    double spd[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) spd[k] = 0.0;
+    int err2 = 0;
+    if (own) {
+        const int64_t idx = (y0 + cj) * nx + x0 + ci;
+        const int li = (cj + 3) * kFW + ci + 3;
+        double Lc[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const double d = s_f[c][(cj + 1) * kFX + ci] - s_f[c][cj * kFX + ci];
+            const double Dy = FAST ? d * A.rdx[1] : div_by_recip(d, A.dx[1], A.rdx[1]);
+            Lc[c] = -(Dx[c] + Dy);
+        }
+        if (A.has_grav) {
+            // gravity source (Sec. 4.3, TEST 6) of the stage's input state
+            const double rho = s_u[0][li];
+            double e = 0.0;
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const double md = s_u[1 + d][li];
+                Lc[1 + d] = Lc[1 + d] + (-(A.grav[d] * rho));
+                e = d == 0 ? A.grav[0] * md : e + A.grav[d] * md;
+            }
+            Lc[3] = Lc[3] + (-e);
+        }
+        if constexpr (MODE == MODE_LAST_RHS) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = Lc[c];
+        } else {
+            const double dt = st->dt;
+            double un[M];
+            if constexpr (FAST) {
+                const double c0 = A.stage == 1 ? 0.0 : (A.stage == 2 ? 0.75 : 1.0 / 3.0);
+                const double c1 = A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0);
+                const double cdt = (A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0)) * dt;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    const double base = __builtin_fma(cdt, Lc[c], c1 * s_u[c][li]);
+                    un[c] = A.stage == 1 ? base : __builtin_fma(c0, A.u0[c * ncell + idx], base);
+                }
+            } else if (A.stage == 1) {
+#pragma unroll
+                for (int c = 0; c < M; ++c) un[c] = s_u[c][li] + dt * Lc[c];
+            } else if (A.stage == 2) {
+                const double cdt = 0.25 * dt;
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    un[c] = 0.75 * A.u0[c * ncell + idx] + 0.25 * s_u[c][li] + cdt * Lc[c];
+            } else {
+                const double cdt = (2.0 / 3.0) * dt;
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    un[c] = (1.0 / 3.0) * A.u0[c * ncell + idx] + (2.0 / 3.0) * s_u[c][li] +
+                            cdt * Lc[c];
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = un[c];
+            double lam[6];
+            err2 |= euler_speeds<2, FAST>(un, A.gamma, lam);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) spd[k] = lam[k];
+        }
+    }
+    if constexpr (MODE == MODE_LAST_STAGE) {
+        if (err2) atomicOr(&st->err, err2);
+        constexpr int NS = SpeedLayout<SYS_EULER, 2>::NS;
+        int src[NS], sidx[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            src[j] = SpeedLayout<SYS_EULER, 2>::value_of_slot(j);
+            sidx[j] = SpeedLayout<SYS_EULER, 2>::slot_index(j);
+        }
+        block_slot_max<NV, NS, kFThreads>(spd, st->alpha[A.slot_wr], src, sidx);
+        if (blockIdx.x == 0 && t < kSlotLen)
+            __hip_atomic_store(&st->alpha[A.slot_zero][t], 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+hipError_t launch_stage2d(int mode, int prec, const Stage2dArgs &A0, hipStream_t s)
+{
+    Stage2dArgs A = A0;
+    A.ntx = (A.n[0] + kFX - 1) / kFX;
+    A.tiles = A.ntx * ((A.n[1] + kFY - 1) / kFY);
+    A.tiles_per_xcd = (A.tiles + kXcds - 1) / kXcds;
+    const int64_t blocks = A.tiles_per_xcd * kXcds;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 g((unsigned)blocks), bl(kFThreads);
+    const bool rhs = mode == MODE_LAST_RHS;
+    if (prec == WT_FP32_RECON) {
+        if (rhs) hipLaunchKernelGGL((stage2d_kernel<MODE_LAST_RHS, 1>), g, bl, 0, s, A);
+        else hipLaunchKernelGGL((stage2d_kernel<MODE_LAST_STAGE, 1>), g, bl, 0, s, A);
+    } else if (prec == WT_FP64_FAST) {
+        if (rhs) hipLaunchKernelGGL((stage2d_kernel<MODE_LAST_RHS, 2>), g, bl, 0, s, A);
+        else hipLaunchKernelGGL((stage2d_kernel<MODE_LAST_STAGE, 2>), g, bl, 0, s, A);
+    } else {
+        if (rhs) hipLaunchKernelGGL((stage2d_kernel<MODE_LAST_RHS, 0>), g, bl, 0, s, A);
+        else hipLaunchKernelGGL((stage2d_kernel<MODE_LAST_STAGE, 0>), g, bl, 0, s, A);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
 // Tile shapes (TX columns x TN points along the sweep, TX (TN + 1) = 256
@@ -595,9 +904,11 @@ struct TileYZ<3> { static constexpr int TX = 32, TN = 7; };
 
 // x-sweeps of the Euler system in 2D/3D: 1 x 255 (one row segment; default) or
 // 8 rows x 31 points, for rows whose length leaves a nearly empty last segment of
-// 255 (a 512-point row: 255 + 255 + 2).
-//   0: 1 x 255   1: 8 x 31
-constexpr int kXTileVariants = 2;
+// 255 (a 512-point row: 255 + 255 + 2).  In 2D, variant 2 replaces the two sweeps
+// of a stage by the fused stage kernel (stage2d_kernel).
+//   0: 1 x 255   1: 8 x 31   2: fused 2D stage (2D only)
+constexpr int kXTileVariants = 3;
+constexpr int kXFused = 2;
 
 template <int SYS, int NDIM, int DIR>
 constexpr bool has_tile_variants()
@@ -636,7 +947,7 @@ hipError_t launch_sweep(const SweepArgs &A, int tile, hipStream_t s)
         return launch_tile<SYS, NDIM, DIR, MODE, PREC, TX, TN>(A, s);
     } else if constexpr (DIR == 0) {
         if (tile == 1) return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<0>::TX, TileYZ<0>::TN>(A, s);
-        return launch_tile<SYS, NDIM, DIR, MODE, PREC, 1, 255>(A, s);
+        return launch_tile<SYS, NDIM, DIR, MODE, PREC, 1, 255>(A, s);   // 0 (and the fused 2)
     } else {
         switch (tile) {
             case 1: return launch_tile<SYS, NDIM, DIR, MODE, PREC, TileYZ<1>::TX, TileYZ<1>::TN>(A, s);
@@ -684,6 +995,7 @@ hipError_t launch_sweep_any(int sys, int ndim, int prec, int dir, int mode, cons
                             int tile, hipStream_t s)
 {
     if (prec == WT_FP32_RECON) return launch_sweep_prec<1>(sys, ndim, dir, mode, A, tile, s);
+    if (prec == WT_FP64_FAST) return launch_sweep_prec<2>(sys, ndim, dir, mode, A, tile, s);
     return launch_sweep_prec<0>(sys, ndim, dir, mode, A, tile, s);
 }
 
@@ -737,7 +1049,8 @@ wt_status validate_grid(const wt_side *sides, const wt_grid *G, const wt_params 
     if (G->ndim < 1 || G->ndim > 3) return WT_ERR_ARG;
     S.sides = false;
     if (P->system < WT_LINEAR || P->system > WT_EULER) return WT_ERR_ARG;
-    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
+    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON && P->precision != WT_FP64_FAST)
+        return WT_ERR_ARG;
     if (P->system != WT_EULER && G->ndim != 1) return WT_ERR_UNSUPPORTED;
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0)) return WT_ERR_ARG;
     if (P->system == WT_EULER && !(P->gamma > 1.0)) return WT_ERR_ARG;
@@ -838,6 +1151,11 @@ int plan_tile(const wt_ctx *c, const Shape &S, const wt_params *P, int dir)
     return 0;
 }
 
+bool fused_stage(const wt_ctx *c, const Shape &S, const wt_params *P)
+{
+    return P->system == WT_EULER && S.ndim == 2 && !S.sides && plan_tile(c, S, P, 0) == kXFused;
+}
+
 void set_plan(wt_ctx *c, const Shape &S, const wt_params *P, const int *tile)
 {
     const uint64_t key = plan_key(S, P);
@@ -849,21 +1167,62 @@ void set_plan(wt_ctx *c, const Shape &S, const wt_params *P, const int *tile)
     for (int d = 0; d < 3; ++d) c->plans[0].tile[d] = (int8_t)tile[d];
 }
 
-// Launch one sweep, bracketed by profiling events when enabled.
-hipError_t timed_sweep(wt_ctx *c, int sys, int ndim, int prec, int dir, int mode,
-                       const SweepArgs &A, int tile, hipStream_t s)
+// Launch one kernel, bracketed by profiling events of the given kind when enabled.
+template <class Launch>
+hipError_t timed_launch(wt_ctx *c, int kind, hipStream_t s, Launch launch)
 {
     const bool rec = c->prof && c->nev < kProfPairs;
     if (c->prof && !rec) c->prof_dropped++;
     if (rec && hipEventRecord(c->ev[2 * c->nev], s) != hipSuccess) return hipErrorUnknown;
-    const hipError_t e = launch_sweep_any(sys, ndim, prec, dir, mode, A, tile, s);
+    const hipError_t e = launch();
     if (e != hipSuccess) return e;
     if (rec) {
         if (hipEventRecord(c->ev[2 * c->nev + 1], s) != hipSuccess) return hipErrorUnknown;
-        c->ev_kind[c->nev] = (mode == MODE_LAST_RHS || mode == MODE_LAST_STAGE ? 3 : 0) + dir;
+        c->ev_kind[c->nev] = kind;
         c->nev++;
     }
     return hipSuccess;
+}
+
+// Launch one sweep, bracketed by profiling events when enabled.
+hipError_t timed_sweep(wt_ctx *c, int sys, int ndim, int prec, int dir, int mode,
+                       const SweepArgs &A, int tile, hipStream_t s)
+{
+    const int kind = (mode == MODE_LAST_RHS || mode == MODE_LAST_STAGE ? 3 : 0) + dir;
+    return timed_launch(c, kind, s, [&] { return launch_sweep_any(sys, ndim, prec, dir, mode, A, tile, s); });
+}
+
+// Whether the stages of this grid run as the fused 2D stage kernel.
+bool fused_stage(const wt_ctx *c, const Shape &S, const wt_params *P);
+
+// The fused kernel's arguments from a sweep's (speed slots, stage, buffers).
+Stage2dArgs stage2d_args(const wt_ctx *c, const Shape &S, const wt_params *P, const SweepArgs &B)
+{
+    Stage2dArgs A{};
+    A.uin = B.uin;
+    A.u0 = B.u0;
+    A.out = B.out;
+    A.st = B.st;
+    A.n[0] = S.n[0];
+    A.n[1] = S.n[1];
+    A.ncell = S.ncell;
+    for (int d = 0; d < 2; ++d) {
+        A.dx[d] = S.dx[d];
+        A.rdx[d] = 1.0 / S.dx[d];
+        A.bc[d] = S.bc[d];
+        A.walls[d] = S.walls[d];
+        A.grav[d] = P->gravity[d];
+    }
+    A.gamma = P->gamma;
+    A.W = B.W;
+    A.slot_rd = B.slot_rd;
+    A.slot_wr = B.slot_wr;
+    A.slot_zero = B.slot_zero;
+    A.stage = B.stage;
+    A.check_done = B.check_done;
+    A.has_grav = B.has_grav;
+    (void)c;
+    return A;
 }
 
 // Fold the recorded (completed) event pairs into the per-kind totals.
@@ -949,6 +1308,14 @@ wt_status queue_stage(wt_ctx *c, const Shape &S, const wt_params *P, const doubl
     A.slot_rd = (int)(c->g % kSlots);
     A.slot_wr = (int)((c->g + 1) % kSlots);
     A.slot_zero = (int)((c->g + 2) % kSlots);
+    if (fused_stage(c, S, P)) {
+        const Stage2dArgs F = stage2d_args(c, S, P, A);
+        if (timed_launch(c, kProfFused, s, [&] { return launch_stage2d(MODE_LAST_STAGE, P->precision, F, s); }) !=
+            hipSuccess)
+            return WT_ERR_DEVICE;
+        c->g += 1;
+        return WT_OK;
+    }
     for (int d = 0; d < S.ndim; ++d) {
         const int mode = d == S.ndim - 1 ? MODE_LAST_STAGE : (d == 0 ? MODE_FIRST : MODE_MID);
         dir_args(A, c, S, d);
@@ -1195,8 +1562,8 @@ wt_status wenotheta_profile(wt_ctx *c, int32_t enable)
 
 wt_status wenotheta_profile_read(wt_ctx *c, double *ms, int64_t *count, int32_t nkinds)
 {
-    if (!c || !ms || !count || nkinds < kProfKinds) return WT_ERR_ARG;
-    for (int k = 0; k < kProfKinds; ++k) {
+    if (!c || !ms || !count || nkinds < 6) return WT_ERR_ARG;
+    for (int k = 0; k < kProfKinds && k < nkinds; ++k) {
         ms[k] = c->prof_ms[k];
         count[k] = c->prof_n[k];
     }
@@ -1232,6 +1599,13 @@ wt_status wenotheta_rhs(wt_ctx *c, const wt_grid *G, const wt_params *P, const d
     A.fgiven = f;
     A.check_done = 0;
     A.slot_rd = (int)(c->g % kSlots);
+    if (fused_stage(c, S, P)) {
+        const Stage2dArgs F = stage2d_args(c, S, P, A);
+        if (timed_launch(c, kProfFused, s, [&] { return launch_stage2d(MODE_LAST_RHS, P->precision, F, s); }) !=
+            hipSuccess)
+            return WT_ERR_DEVICE;
+        return WT_OK;
+    }
     for (int d = 0; d < S.ndim; ++d) {
         const int mode = d == S.ndim - 1 ? MODE_LAST_RHS : (d == 0 ? MODE_FIRST : MODE_MID);
         dir_args(A, c, S, d);
@@ -1349,6 +1723,8 @@ wt_status wenotheta_set_tiles(wt_ctx *c, const wt_grid *G, const wt_params *P, c
     int t[3] = {0, 0, 0};
     for (int d = 0; d < S.ndim; ++d) {
         if (tile[d] < 0 || tile[d] >= (d == 0 ? kXTileVariants : kTileVariants)) return WT_ERR_ARG;
+        if (d == 0 && tile[d] == kXFused && !(P->system == WT_EULER && S.ndim == 2 && !S.sides))
+            return WT_ERR_ARG;
         t[d] = tile[d];
     }
     set_plan(c, S, P, t);
@@ -1403,7 +1779,7 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
             return WT_ERR_DEVICE;
         }
         for (int d = 0; d < S.ndim && r == WT_OK; ++d) {
-            const int nvar = d == 0 ? kXTileVariants : kTileVariants;
+            const int nvar = d == 0 ? kXFused : kTileVariants;      // the sweep shapes
             // the divergence of the directions before d, as the stage forms it
             // (an accumulating sweep timed for an earlier direction added to it
             // several times)
@@ -1433,6 +1809,35 @@ wt_status wenotheta_tune(wt_ctx *c, const wt_grid *G, const wt_params *P, const 
                 for (int v = 1; v < nvar; ++v)
                     if (ms_best[v] < 0.98f * ms_best[0] && ms_best[v] < ms_best[best[d]]) best[d] = v;
             }
+        }
+        // 2D: a whole stage by the fused kernel against the two chosen sweeps queued
+        // back to back, rounds interleaved (it replaces the pair only if clearly faster)
+        if (r == WT_OK && S.ndim == 2 && !S.sides) {
+            SweepArgs Bx = A, By = A;
+            dir_args(Bx, c, S, 0);
+            dir_args(By, c, S, 1);
+            const Stage2dArgs F = stage2d_args(c, S, P, By);
+            float ms_pair = 1e30f, ms_f = 1e30f;
+            for (int round = 0; round < 5 && r == WT_OK; ++round)
+                for (int v = 0; v < 2 && r == WT_OK; ++v) {
+                    float ms = 0.0f;
+                    hipError_t e = hipEventRecord(e0, s);
+                    if (e == hipSuccess && v == 0) {
+                        e = launch_sweep_any(P->system, 2, P->precision, 0, MODE_FIRST, Bx, best[0], s);
+                        if (e == hipSuccess)
+                            e = launch_sweep_any(P->system, 2, P->precision, 1, MODE_LAST_STAGE, By, best[1], s);
+                    } else if (e == hipSuccess) {
+                        e = launch_stage2d(MODE_LAST_STAGE, P->precision, F, s);
+                    }
+                    if (e != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        r = WT_ERR_DEVICE;
+                        break;
+                    }
+                    float &m = v == 0 ? ms_pair : ms_f;
+                    if (round > 0 && ms < m) m = ms;          // round 0 warms up
+                }
+            if (ms_f < 0.98f * ms_pair) best[0] = kXFused;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

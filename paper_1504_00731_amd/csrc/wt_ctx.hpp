@@ -12,8 +12,10 @@
 
 // Per-kernel timing with HIP events recorded on the launch stream around each
 // sweep launch (enabled by wenotheta_profile).  Kinds: sweep direction d in
-// its non-final role (d) or as the final sweep of a stage or RHS (3 + d).
-constexpr int kProfKinds = 6;
+// its non-final role (d) or as the final sweep of a stage or RHS (3 + d); the
+// fused 2D stage kernel (6).
+constexpr int kProfKinds = 7;
+constexpr int kProfFused = 6;
 constexpr int kProfPairs = 4096;
 
 // Tile shape chosen for the y/z sweeps of one grid shape (see wenotheta_tune).

@@ -69,11 +69,11 @@ __device__ __forceinline__ void slot_max(unsigned long long *p, double v)
 // Block-wide max of NV values per thread, then one slot update per slot
 // entry: entry slot_idx[j] takes the block maximum of value src[j] (several
 // entries may share a value).
-template <int NV, int NS>
+template <int NV, int NS, int NT = kThreads>
 __device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long long *slot,
                                                const int (&src)[NS], const int (&slot_idx)[NS])
 {
-    __shared__ double red[NV][kThreads / 64];
+    __shared__ double red[NV][NT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -85,19 +85,21 @@ __device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long lo
         const int j = threadIdx.x;
         double m = red[src[j]][0];
 #pragma unroll
-        for (int w = 1; w < kThreads / 64; ++w) m = __builtin_fmax(m, red[src[j]][w]);
+        for (int w = 1; w < NT / 64; ++w) m = __builtin_fmax(m, red[src[j]][w]);
         slot_max(&slot[slot_idx[j]], m);
     }
 }
 
 // Wave speeds of one cell (canonical state): per direction |u_d - c|, |u_d|,
 // |u_d + c|, with c = sqrt(gamma p / rho).  Returns an error bit mask.
-template <int NDIM>
+template <int NDIM, bool FAST = false>
 __device__ __forceinline__ int euler_speeds(const double *uc, double gamma, double *lam)
 {
     double vel[NDIM], p, H;
-    const bool ok = euler_cell<NDIM>(uc, gamma, vel, p, H);
-    const double c = sqrt_rn(div_rn(gamma * p, uc[0]));
+    const bool ok = euler_cell<NDIM, FAST>(uc, gamma, vel, p, H);
+    double c;
+    if constexpr (FAST) c = sqrt_fast(gamma * p * rcp_fast(uc[0]));
+    else c = sqrt_rn(div_rn(gamma * p, uc[0]));
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
         lam[3 * d + 0] = __builtin_fabs(vel[d] - c);

@@ -32,14 +32,25 @@
 namespace wt {
 
 // One interface reconstruction of six split values in precision mode PREC
-// (0: FP64 with the plain operation order, 1: FP32 reconstruction).
+// (0: FP64 with the plain operation order, 1: FP32 reconstruction, 2: fast FP64).
 template <int PREC>
 WT_HD double reconstruct(const double *v, const WenoConst &W)
 {
     if constexpr (PREC == 0)
         return weno_theta(v[0], v[1], v[2], v[3], v[4], v[5], W.eps, W.alpha_R, W.reps);
+    else if constexpr (PREC == 2)
+        return weno_theta_fast(v[0], v[1], v[2], v[3], v[4], v[5], W.eps, W.alpha_R);
     else
         return weno_theta_fp32_recon(v, W.eps, (float)W.alpha_R);
+}
+
+// Precision modes 1 (WT_FP32_RECON) and 2 (WT_FP64_FAST) evaluate the FP64 parts of
+// an interface (cell quantities, Roe basis, projection, split) with fused
+// multiply-adds and fast reciprocals; mode 0 keeps the plain operation order.
+template <int PREC>
+constexpr bool fast_math()
+{
+    return PREC != 0;
 }
 
 // Normal flux of a cell in canonical component order for direction DIR:
@@ -62,7 +73,7 @@ WT_HD void euler_normal_flux(const double *uc, const double *vel, double p, doub
 template <int NDIM, int PREC>
 constexpr bool fresh_rows()
 {
-    return PREC != 0 || NDIM == 3;
+    return PREC == 1 || NDIM == 3;
 }
 
 // Characteristic field s of an interface (0: u_n - c, 1: u_n, 2: u_n + c, 3..:
@@ -87,6 +98,36 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
         for (int t = 0; t < NT; ++t) lt[t] = 0.0;
     }
     const double a = al(s);
+    double vp[6], vm[6];
+    if constexpr (fast_math<PREC>()) {
+        // fused multiply-adds written out, in one fixed form: the mirror image of an
+        // interface (its acoustic fields exchanged, the normal components negated) then
+        // forms exactly the negated split values, which a contraction left to the
+        // compiler does not guarantee (it may fuse either product of a sum)
+        const double ha = 0.5 * a;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double qq, ww;
+            if (shear < 0) {
+                qq = __builtin_fma(ln1, S.U(k, 1 + DIR), ln0 * S.U(k, 0));
+                ww = __builtin_fma(ln1, S.f(k, 1 + DIR), ln0 * S.f(k, 0));
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    qq = __builtin_fma(lt[t], S.U(k, 1 + tangential_axis<DIR>(t)), qq);
+                    ww = __builtin_fma(lt[t], S.f(k, 1 + tangential_axis<DIR>(t)), ww);
+                }
+                qq = __builtin_fma(lE, S.U(k, NDIM + 1), qq);
+                ww = __builtin_fma(lE, S.f(k, NDIM + 1), ww);
+            } else {
+                const int ax = 1 + (shear == 0 ? tangential_axis<DIR>(0) : tangential_axis<DIR>(NT - 1));
+                qq = __builtin_fma(ln0, S.U(k, 0), S.U(k, ax));
+                ww = __builtin_fma(ln0, S.f(k, 0), S.f(k, ax));
+            }
+            const double hw = 0.5 * ww;
+            vp[k] = __builtin_fma(ha, qq, hw);
+            vm[5 - k] = __builtin_fma(-ha, qq, hw);
+        }
+    } else {
     double w[6], q[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -107,12 +148,12 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
             w[k] = ln0 * S.f(k, 0) + S.f(k, ax);
         }
     }
-    double vp[6], vm[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const double aq = a * q[k];
         vp[k] = 0.5 * (w[k] + aq);
         vm[5 - k] = 0.5 * (w[k] - aq);
+    }
     }
     double h = 0.0;
 #pragma unroll
@@ -180,7 +221,7 @@ WT_HD void store_interface_flux(const double *acc, double *F)
 }
 
 // Roe basis of the interface between stencil points 2 and 3.
-template <int NDIM, int DIR, class Acc>
+template <int NDIM, int DIR, bool FAST = false, class Acc>
 WT_HD RoeBasis<NDIM> interface_basis(const Acc &S, double gamma)
 {
     double velL[NDIM], velR[NDIM];
@@ -189,7 +230,7 @@ WT_HD RoeBasis<NDIM> interface_basis(const Acc &S, double gamma)
         velL[k] = S.v(2, k);
         velR[k] = S.v(3, k);
     }
-    return roe_basis<NDIM, DIR>(S.sr(2), velL, S.H(2), S.sr(3), velR, S.H(3), gamma);
+    return roe_basis<NDIM, DIR, FAST>(S.sr(2), velL, S.H(2), S.sr(3), velR, S.H(3), gamma);
 }
 
 // al(s): Lax-Friedrichs speed of field s for this direction.  F receives the
@@ -200,7 +241,7 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, con
                                 double *F)
 {
     constexpr int M = NDIM + 2;
-    const RoeBasis<NDIM> B = interface_basis<NDIM, DIR>(S, gamma);
+    const RoeBasis<NDIM> B = interface_basis<NDIM, DIR, fast_math<PREC>()>(S, gamma);
     double acc[M];
 #pragma unroll 1
     for (int it = 0; it < M; ++it) {

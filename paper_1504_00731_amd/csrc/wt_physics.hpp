@@ -46,18 +46,31 @@ WT_HD double sum_sq_xyz(const double *v)
 // velocities, pressure p = (gamma-1)(E - rho |v|^2 / 2) and total enthalpy
 // H = (E + p) / rho (Sec. 4.2; the 2D form of Sec. 4.3 with the density
 // restored).  Returns false for a non-physical or non-finite state.
-template <int NDIM>
+// FAST (the fast FP64 and FP32-weight modes): the same quantities with the fast
+// reciprocal of rho and products by it.
+template <int NDIM, bool FAST = false>
 WT_HD bool euler_cell(const double *uc, double gamma, double *vel,
                                            double &p, double &H)
 {
     const double rho = uc[0];
     const double E = uc[NDIM + 1];
-    const double y = div_rn(1.0, rho);          // shared by the quotients by rho
+    if constexpr (FAST) {
+        // no contraction: a fused |v|^2 would round the axes differently, and a state with
+        // its velocity components exchanged would no longer give the same pressure
+        const double y = rcp_fast(rho);
 #pragma unroll
-    for (int k = 0; k < NDIM; ++k) vel[k] = div_by_recip(uc[1 + k], rho, y);
-    const double v2 = sum_sq_xyz<NDIM>(vel);
-    p = (gamma - 1.0) * (E - 0.5 * rho * v2);
-    H = div_by_recip(E + p, rho, y);
+        for (int k = 0; k < NDIM; ++k) vel[k] = uc[1 + k] * y;
+        const double v2 = sum_sq_xyz<NDIM>(vel);
+        p = (gamma - 1.0) * (E - 0.5 * rho * v2);
+        H = (E + p) * y;
+    } else {
+        const double y = div_rn(1.0, rho);      // shared by the quotients by rho
+#pragma unroll
+        for (int k = 0; k < NDIM; ++k) vel[k] = div_by_recip(uc[1 + k], rho, y);
+        const double v2 = sum_sq_xyz<NDIM>(vel);
+        p = (gamma - 1.0) * (E - 0.5 * rho * v2);
+        H = div_by_recip(E + p, rho, y);
+    }
     return rho > 0.0 && p > 0.0 && H == H && __builtin_fabs(H) < __builtin_huge_val();
 }
 
@@ -80,12 +93,37 @@ struct RoeBasis {
     bool ok;
 };
 
-template <int NDIM, int DIR>
+template <int NDIM, int DIR, bool FAST = false>
 WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
                                                     double srR, const double *velR, double HR,
                                                     double gamma)
 {
     RoeBasis<NDIM> B;
+    if constexpr (FAST) {
+        // fast reciprocal and square root, but no contraction: a fused srL vL + srR vR
+        // would round the two sides differently, and the mirror image of an interface
+        // (left and right exchanged) would no longer give the mirrored flux bit for bit
+        const double yd = rcp_fast(srL + srR);
+        double vt[3];
+#pragma unroll
+        for (int k = 0; k < NDIM; ++k) vt[k] = (srL * velL[k] + srR * velR[k]) * yd;
+        const double H = (srL * HL + srR * HR) * yd;
+        const double q2 = 0.5 * sum_sq_xyz<NDIM>(vt);
+        const double c2 = (gamma - 1.0) * (H - q2);
+        B.ok = c2 > 0.0;
+        const double c = sqrt_fast(c2);
+        const double ic = rcp_fast(c);
+#pragma unroll
+        for (int t = 0; t < NDIM - 1; ++t) B.ut[t] = vt[tangential_axis<DIR>(t)];
+        B.un = vt[DIR];
+        B.c = c;
+        B.H = H;
+        B.b1 = (gamma - 1.0) * (ic * ic);
+        B.b2 = B.b1 * q2;
+        B.uc = B.un * ic;
+        B.ic = ic;
+        return B;
+    }
     const double den = srL + srR;
     const double yd = div_rn(1.0, den);         // shared by the Roe averages
     double vt[3];

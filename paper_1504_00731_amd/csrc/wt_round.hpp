@@ -142,6 +142,26 @@ WT_HD double recip_rn(double b)
 #endif
 }
 
+// 1 / b for normal b (fast FP64 mode): the hardware estimate and two Newton steps,
+// within an ulp or so of the nearest reciprocal, no exact finishing.
+WT_HD double rcp_fast(double b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(b);
+    y = __builtin_fma(y, __builtin_fma(-b, y, 1.0), y);
+    return __builtin_fma(y, __builtin_fma(-b, y, 1.0), y);
+#else
+    return 1.0 / b;
+#endif
+}
+
+// Square root for the fast FP64 mode (the compiler's refined sequence, no exact
+// finishing step).
+WT_HD double sqrt_fast(double x)
+{
+    return __builtin_sqrt(x);
+}
+
 WT_HD double sqrt_rn(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)

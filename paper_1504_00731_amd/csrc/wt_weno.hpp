@@ -134,21 +134,103 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3, double s4, d
 }
 
 // ---------------------------------------------------------------------------
-// FP32 reconstruction (precision mode WT_FP32_RECON).
+// Fast FP64 reconstruction (precision mode WT_FP64_FAST).
 //
-// WENO-theta is invariant under adding a constant to the six values (each
-// candidate's coefficients sum to one; the indicators use differences only)
-// and, with epsilon scaled by S^2, under scaling them by S.  The FP64 stencil
-// is therefore shifted by its point f_j and scaled by an exact power of two
-// to magnitude <= 1 before it is rounded to FP32; the reconstruction runs in
-// FP32, and the result is scaled back and shifted in FP64.  A constant
-// stencil reconstructs to exactly f_j.
+// The same formulas and decisions, evaluated with fused multiply-adds and
+// without correctly rounded quotients:
+//   * where the restriction holds every beta~_k is zero, so the four alpha_k
+//     share the factor 1 + tau / eps and the weights are exactly gamma^theta:
+//     h = sum gamma_k q_k, no quotient at all;
+//   * elsewhere alpha_k = gamma_k + gamma_k tau / (eps + beta~_k) from fast
+//     reciprocals (hardware estimate and two Newton steps), and
+//     h = (sum alpha_k q_k) / (sum alpha_k) by one more.
+// The results differ from the plain evaluation by rounding only; the theta and
+// restriction decisions can differ only where their two sides are within the
+// rounding of the indicators (a legitimate flip).
 //
-// Every quotient is (nearly always) correctly rounded: the hardware
-// reciprocal is accurate to one ulp but not unbiased, and a bias that scales
-// all reconstructed deviations the same way accumulates over the time steps
-// instead of averaging out (about 20x the L1 difference to the FP64 path over
-// 500 steps of Riemann data, against round-to-nearest quotients).
+// Every fused multiply-add is written out, in one fixed form, and the compiler
+// contracts nothing: a reconstruction is inlined twice per field (the two split
+// halves), and the mirror image of an interface hands one copy's stencil, negated,
+// to the other.  Copies contracted differently would break the exact mirror
+// symmetry of symmetric flows; with a fixed form h(-v) = -h(v) bit for bit.
+// ---------------------------------------------------------------------------
+
+// Candidate fluxes, smoothness indicators and the two theta indicators of a
+// stencil, by fused multiply-adds.
+struct FastStencil {
+    double q0, q1, q2, q3;     // candidate fluxes
+    double b0, b1, b2, b3;     // beta~_k
+    double tau5, tau6;
+};
+
+WT_HD FastStencil fast_stencil(double s0, double s1, double s2, double s3, double s4, double s5)
+{
+    FastStencil F;
+    F.q0 = __builtin_fma(11.0 / 6.0, s2, __builtin_fma(-7.0 / 6.0, s1, (2.0 / 6.0) * s0));
+    F.q1 = __builtin_fma(2.0 / 6.0, s3, __builtin_fma(5.0 / 6.0, s2, (-1.0 / 6.0) * s1));
+    F.q2 = __builtin_fma(-1.0 / 6.0, s4, __builtin_fma(5.0 / 6.0, s3, (2.0 / 6.0) * s2));
+    F.q3 = __builtin_fma(2.0 / 6.0, s5, __builtin_fma(-7.0 / 6.0, s4, (11.0 / 6.0) * s3));
+    double t1, t2;
+    t1 = __builtin_fma(-2.0, s1, s0 + s2);
+    t2 = __builtin_fma(2.0, s2, __builtin_fma(-3.0, s1, s0));
+    F.b0 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
+    t1 = __builtin_fma(-2.0, s2, s1 + s3);
+    t2 = s3 - s2;
+    F.b1 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
+    t1 = __builtin_fma(-2.0, s3, s2 + s4);
+    t2 = s2 - s3;
+    F.b2 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
+    t1 = __builtin_fma(3.0, s2, __builtin_fma(-7.0, s3, __builtin_fma(5.0, s4, -s5)));
+    t2 = __builtin_fma(2.0, s3, __builtin_fma(-3.0, s4, s5));
+    F.b3 = __builtin_fma((13.0 / 48.0) * t1, t1, t2 * t2);
+    t1 = __builtin_fma(6.0, s2, __builtin_fma(-4.0, s1 + s3, s0 + s4));
+    t2 = __builtin_fma(3.0, s2 - s3, s4 - s1);
+    F.tau5 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
+    t1 = __builtin_fma(10.0, s3 - s2, __builtin_fma(5.0, s1 - s4, s5 - s0));
+    t2 = __builtin_fma(2.0, s2 + s3, __builtin_fma(-3.0, s1 + s4, s0 + s5));
+    F.tau6 = __builtin_fma((13.0 / 12.0) * t1, t1, (0.25 * t2) * t2);
+    return F;
+}
+
+WT_HD double weno_theta_fast(double s0, double s1, double s2, double s3, double s4, double s5,
+                             double eps, double alpha_R)
+{
+    const FastStencil F = fast_stencil(s0, s1, s2, s3, s4, s5);
+    const double bmax = __builtin_fmax(__builtin_fmax(F.b0, F.b1), __builtin_fmax(F.b2, F.b3));
+    const double bmin = __builtin_fmin(__builtin_fmin(F.b0, F.b1), __builtin_fmin(F.b2, F.b3));
+    const bool restricted = bmax <= alpha_R * (eps + bmin);
+    const bool central = F.tau6 < F.tau5;
+    const double g0 = central ? GammaTheta::g0_t0 : GammaTheta::g0_t1;
+    const double g1 = central ? GammaTheta::g1_t0 : GammaTheta::g1_t1;
+    const double g2 = central ? GammaTheta::g2_t0 : GammaTheta::g2_t1;
+    const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
+    if (restricted)
+        return __builtin_fma(g3, F.q3, __builtin_fma(g2, F.q2, __builtin_fma(g1, F.q1, g0 * F.q0)));
+    const double tau = central ? F.tau6 : F.tau5;
+    const double a0 = __builtin_fma(g0 * tau, rcp_fast(eps + F.b0), g0);
+    const double a1 = __builtin_fma(g1 * tau, rcp_fast(eps + F.b1), g1);
+    const double a2 = __builtin_fma(g2 * tau, rcp_fast(eps + F.b2), g2);
+    const double a3 = __builtin_fma(g3 * tau, rcp_fast(eps + F.b3), g3);
+    const double num = __builtin_fma(a3, F.q3, __builtin_fma(a2, F.q2, __builtin_fma(a1, F.q1, a0 * F.q0)));
+    return num * rcp_fast(a0 + a1 + a2 + a3);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 weights (precision mode WT_FP32_RECON).
+//
+// The candidate fluxes, the indicators and both decisions are those of the fast
+// FP64 form above (the same fused multiply-adds, so the decisions are FP64
+// decisions); where the restriction holds the weights are gamma^theta exactly.
+// Elsewhere the quotients tau / (eps + beta~_k) and the weights alpha_k are
+// FP32 (eps + beta~_k >= eps keeps them clear of FP32 underflow), and the
+// weighted sum and its normalisation are FP64.  The FP32 rounding of the
+// weights (about 6e-8 relative) moves the flux by that fraction of the spread
+// of the candidate fluxes.
+//
+// The FP32 reciprocals are refined to nearly always correctly rounded: the
+// hardware reciprocal is accurate to one ulp but not unbiased, and a bias that
+// moves the weights the same way at every interface accumulates over the time
+// steps instead of averaging out.
 // ---------------------------------------------------------------------------
 
 // 1/x for normal x > 0: the hardware estimate and one Newton step.
@@ -162,83 +244,28 @@ WT_HD float rcp_f32(float x)
 #endif
 }
 
-// a / b for normal b > 0 with the reciprocal r = rcp_f32(b): one residual
-// correction of the product.
-WT_HD float div_f32(float a, float b, float r)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    const float q = a * r;
-    return __builtin_fmaf(__builtin_fmaf(-b, q, a), r, q);
-#else
-    (void)r;
-    return a / b;
-#endif
-}
-
-WT_HD float weno_theta_f32(float s0, float s1, float s2, float s3, float s4, float s5, float eps,
-                           float alpha_R)
-{
-#pragma clang fp contract(fast)
-    const float q0 = (2.0f / 6.0f) * s0 - (7.0f / 6.0f) * s1 + (11.0f / 6.0f) * s2;
-    const float q1 = -(1.0f / 6.0f) * s1 + (5.0f / 6.0f) * s2 + (2.0f / 6.0f) * s3;
-    const float q2 = (2.0f / 6.0f) * s2 + (5.0f / 6.0f) * s3 - (1.0f / 6.0f) * s4;
-    const float q3 = (11.0f / 6.0f) * s3 - (7.0f / 6.0f) * s4 + (2.0f / 6.0f) * s5;
-    float t1, t2;
-    t1 = s0 - 2.0f * s1 + s2;
-    t2 = s0 - 3.0f * s1 + 2.0f * s2;
-    const float b0 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
-    t1 = s1 - 2.0f * s2 + s3;
-    t2 = s3 - s2;
-    const float b1 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
-    t1 = s2 - 2.0f * s3 + s4;
-    t2 = s2 - s3;
-    const float b2 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
-    t1 = 3.0f * s2 - 7.0f * s3 + 5.0f * s4 - s5;
-    t2 = 2.0f * s3 - 3.0f * s4 + s5;
-    const float b3 = (13.0f / 48.0f) * t1 * t1 + t2 * t2;
-    const float bmax = fmaxf(fmaxf(b0, b1), fmaxf(b2, b3));
-    const float bmin = fminf(fminf(b0, b1), fminf(b2, b3));
-    const bool restricted = bmax <= alpha_R * (eps + bmin);
-    t1 = s0 - 4.0f * s1 + 6.0f * s2 - 4.0f * s3 + s4;
-    t2 = -s1 + 3.0f * s2 - 3.0f * s3 + s4;
-    const float tau5 = (13.0f / 12.0f) * t1 * t1 + t2 * t2;
-    t1 = -s0 + 5.0f * s1 - 10.0f * s2 + 10.0f * s3 - 5.0f * s4 + s5;
-    t2 = s0 - 3.0f * s1 + 2.0f * s2 + 2.0f * s3 - 3.0f * s4 + s5;
-    const float tau6 = (13.0f / 12.0f) * t1 * t1 + 0.25f * t2 * t2;
-    const bool central = tau6 < tau5;
-    const float tau = central ? tau6 : tau5;
-    const float g0 = central ? 0.05f : 0.1f;
-    const float g1 = central ? 0.45f : 0.6f;
-    const float g2 = central ? 0.45f : 0.3f;
-    const float g3 = central ? 0.05f : 0.0f;
-    // restricted: all indicators are zero and the weights are gamma exactly
-    const float a0 = restricted ? g0 : g0 + g0 * tau * rcp_f32(eps + b0);
-    const float a1 = restricted ? g1 : g1 + g1 * tau * rcp_f32(eps + b1);
-    const float a2 = restricted ? g2 : g2 + g2 * tau * rcp_f32(eps + b2);
-    const float a3 = restricted ? g3 : g3 + g3 * tau * rcp_f32(eps + b3);
-    const float sum = a0 + a1 + a2 + a3;
-    return div_f32(a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3, sum, rcp_f32(sum));
-}
-
-// The reconstruction of six FP64 values through the FP32 routine.
 WT_HD double weno_theta_fp32_recon(const double *v, double eps, float alpha_R)
 {
-    const double c = v[2];
-    double m = 0.0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const double d = __builtin_fabs(v[k] - c);
-        m = d > m ? d : m;
-    }
-    int e;
-    (void)__builtin_frexp(m, &e);               // m < 2^e (e = 0 for m = 0)
-    float d[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) d[k] = (float)__builtin_ldexp(v[k] - c, -e);
-    double es = __builtin_ldexp(eps, -2 * e);
-    es = es < 0x1p-100 ? 0x1p-100 : (es > 0x1p+126 ? 0x1p+126 : es);
-    const float h = weno_theta_f32(d[0], d[1], d[2], d[3], d[4], d[5], (float)es, alpha_R);
-    return c + __builtin_ldexp((double)h, e);
+    const FastStencil F = fast_stencil(v[0], v[1], v[2], v[3], v[4], v[5]);
+    const double bmax = __builtin_fmax(__builtin_fmax(F.b0, F.b1), __builtin_fmax(F.b2, F.b3));
+    const double bmin = __builtin_fmin(__builtin_fmin(F.b0, F.b1), __builtin_fmin(F.b2, F.b3));
+    const bool restricted = bmax <= (double)alpha_R * (eps + bmin);
+    const bool central = F.tau6 < F.tau5;
+    const double g0 = central ? GammaTheta::g0_t0 : GammaTheta::g0_t1;
+    const double g1 = central ? GammaTheta::g1_t0 : GammaTheta::g1_t1;
+    const double g2 = central ? GammaTheta::g2_t0 : GammaTheta::g2_t1;
+    const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
+    if (restricted)
+        return __builtin_fma(g3, F.q3, __builtin_fma(g2, F.q2, __builtin_fma(g1, F.q1, g0 * F.q0)));
+    // the weights in FP32 (tau is at most about 1e30 for flux values up to 1e14)
+    const float tau = (float)__builtin_fmin(central ? F.tau6 : F.tau5, 0x1p+100);
+    const float a0 = __builtin_fmaf((float)g0 * tau, rcp_f32((float)__builtin_fmin(eps + F.b0, 0x1p+100)), (float)g0);
+    const float a1 = __builtin_fmaf((float)g1 * tau, rcp_f32((float)__builtin_fmin(eps + F.b1, 0x1p+100)), (float)g1);
+    const float a2 = __builtin_fmaf((float)g2 * tau, rcp_f32((float)__builtin_fmin(eps + F.b2, 0x1p+100)), (float)g2);
+    const float a3 = __builtin_fmaf((float)g3 * tau, rcp_f32((float)__builtin_fmin(eps + F.b3, 0x1p+100)), (float)g3);
+    const double w0 = a0, w1 = a1, w2 = a2, w3 = a3;
+    const double num = __builtin_fma(w3, F.q3, __builtin_fma(w2, F.q2, __builtin_fma(w1, F.q1, w0 * F.q0)));
+    return num * rcp_fast(w0 + w1 + w2 + w3);
 }
 
 }  // namespace wt

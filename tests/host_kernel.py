@@ -32,7 +32,7 @@ def lib():
         L.wth_weno.restype = ctypes.c_double
         L.wth_weno.argtypes = [dp, ctypes.c_double, ctypes.c_double]
         L.wth_rhs.restype = ctypes.c_int
-        L.wth_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), dp,
+        L.wth_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), dp,
                               ctypes.POINTER(ctypes.c_int), dp, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, dp, dp, dp, dp]
         _lib = L
@@ -48,9 +48,11 @@ def weno(s, eps=1e-10, alpha_R=50.0) -> float:
     return lib().wth_weno(_dp(s), eps, alpha_R)
 
 
-def rhs(P, u, alpha, f=None):
-    """L(u) with the device arithmetic; P is an oracle.Problem (grid description only),
-    alpha the [ndim][m] Lax-Friedrichs speeds."""
+def rhs(P, u, alpha, f=None, prec=0):
+    """L(u) with the device arithmetic in precision mode prec (0: plain FP64 order,
+    1: FP32 reconstruction, 2: fast FP64; the host's own rounding of the fast forms);
+    P is an oracle.Problem (grid description only), alpha the [ndim][m] Lax-Friedrichs
+    speeds."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     n = (ctypes.c_int64 * 3)(*([int(v) for v in P.n] + [1] * (3 - len(P.n))))
     dx = (ctypes.c_double * 3)(*([float(v) for v in P.dx] + [1.0] * (3 - len(P.dx))))
@@ -63,7 +65,7 @@ def rhs(P, u, alpha, f=None):
     f = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
     L = np.zeros_like(u)
     grav = np.ascontiguousarray(list(P.gravity) + [0.0] * (3 - len(P.gravity)), dtype=np.float64)
-    bad = lib().wth_rhs(P.system, P.ndim, n, dx, bc, _dp(al), P.gamma, P.eps, P.alpha_R,
+    bad = lib().wth_rhs(int(prec), P.system, P.ndim, n, dx, bc, _dp(al), P.gamma, P.eps, P.alpha_R,
                         _dp(u), _dp(f), _dp(L), _dp(grav))
     return L, bad
 

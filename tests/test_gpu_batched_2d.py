@@ -172,6 +172,23 @@ def test_batched_2d_fp32_reconstruction(ctx):
     assert np.array_equal(u32[:, o:o + n], u64[:, o:o + n])
 
 
+def test_batched_2d_fp32_full_size(ctx):
+    """The benchmark's batched 2D workload (4096 problems, 32..96 points per side, 100
+    steps) in FP32 weights against the FP64 batch (bit-identical to the oracle): the L1
+    difference summed over every problem that both complete is <= 1e-6 per component,
+    and the FP32 form completes every problem the FP64 path completes."""
+    B = W.batched_2d(seed=0)
+    u64, _, s64, _ = _run(ctx, B, 100)
+    u32, _, s32, _ = _run(ctx, B, 100, wt.WT_FP32_RECON)
+    assert not np.any((s32 != 0) & (s64 == 0)), np.flatnonzero((s32 != 0) & (s64 == 0))
+    ok = (s64 == 0) & (s32 == 0)
+    assert ok.sum() >= 0.97 * B.nprob
+    n32, pd = _per_problem_l1(B, u32, u64)
+    e_all = n32[ok].sum(axis=0) / pd[ok].sum(axis=0)
+    print(f"batched 2D FP32 vs FP64 L1 over all {int(ok.sum())} completed problems: {e_all}")
+    assert np.all(e_all <= 1e-6), e_all
+
+
 @pytest.mark.parametrize("variant", [0, 2])
 def test_batched_2d_full_size_sampled(variant):
     """The benchmark batch (4096 problems, 32..96 points per side, 100 steps), in the

@@ -195,6 +195,8 @@ def test_batched_fp32_l1_full_size(ctx):
     u32, _, st32, _ = _run_batched(ctx, B, 500, precision=wt.WT_FP32_RECON)
     ok = (st64 == 0) & (stp == 0) & (st32 == 0)
     assert ok.sum() >= 0.97 * B.nprob
+    # the FP32-weight form completes every problem the FP64 path completes
+    assert not np.any((st32 != 0) & (st64 == 0)), np.flatnonzero((st32 != 0) & (st64 == 0))
     pn, pd = _per_problem_l1(B, up, u64)
     ill = ok & ((pn / pd).max(axis=1) > ILL_CONDITIONED)
     well = ok & ~ill

@@ -75,7 +75,7 @@ def test_tune_picks_a_shape_and_keeps_results(ctx):
     g, p = grid_params(case)
     u = to_dev(case.u)
     choice = wt.wenotheta_tune(ctx, g, p, u)
-    assert len(choice) == 2 and 0 <= choice[0] < 2 and 0 <= choice[1] < 4
+    assert len(choice) == 2 and 0 <= choice[0] < 3 and 0 <= choice[1] < 4
     assert np.array_equal(u.cpu().numpy(), case.u)         # tuning only reads u
     L = torch.empty_like(u)
     wt.wenotheta_rhs(ctx, g, p, u, L)
@@ -86,7 +86,7 @@ def test_tune_picks_a_shape_and_keeps_results(ctx):
 def test_set_tiles_rejects_bad_variants(ctx):
     case = W.euler2d_seeded(0, 16)
     g, p = grid_params(case)
-    for bad in ([0, 4], [0, -1], [2, 0], [-1, 0]):
+    for bad in ([0, 4], [0, -1], [3, 0], [-1, 0]):
         with pytest.raises(wt.WenoThetaError) as e:
             wt.wenotheta_set_tiles(ctx, g, p, bad)
         assert e.value.code == 1

@@ -76,13 +76,13 @@ def test_steps_match_oracle(ctx, make):
 
 
 def test_rayleigh_taylor_symmetry_on_the_gpu(ctx):
-    """x-mirror symmetry of the Rayleigh-Taylor flow, FP64 and FP32 reconstruction.  The
+    """x-mirror symmetry of the Rayleigh-Taylor flow in every precision mode.  The
     grid spacings are powers of two, so the grid points, and with them the initial data,
     are exactly mirror-symmetric (on a 48-wide grid x and -x differ in the last bit)."""
     c = W.rayleigh_taylor(64, 192)
     nx = c.u.shape[2]
     idx = (-np.arange(nx)) % nx
-    for prec in (wt.WT_FP64, wt.WT_FP32_RECON):
+    for prec in (wt.WT_FP64, wt.WT_FP32_RECON, wt.WT_FP64_FAST):
         u = _steps(ctx, c, 30, prec)
         m = u[:, :, idx]
         assert np.array_equal(u[0], m[0]) and np.array_equal(u[2], m[2]) and np.array_equal(u[3], m[3])
@@ -91,7 +91,7 @@ def test_rayleigh_taylor_symmetry_on_the_gpu(ctx):
 
 def test_implosion_diagonal_symmetry_on_the_gpu(ctx):
     c = W.implosion(64)
-    for prec in (wt.WT_FP64, wt.WT_FP32_RECON):
+    for prec in (wt.WT_FP64, wt.WT_FP32_RECON, wt.WT_FP64_FAST):
         u = _steps(ctx, c, 25, prec)
         assert np.array_equal(u[0], u[0].T) and np.array_equal(u[1], u[2].T)
 

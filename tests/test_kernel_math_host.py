@@ -205,3 +205,37 @@ def test_boundary_maps_stay_inside_the_line():
                 else:
                     want = -1 - i if i < 0 else (2 * n - 1 - i if i >= n else i)
                     assert k == want and HK.reflected(i, n, bc) == (i < 0 or i >= n)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32_recon", "fp64_fast"])
+def test_fast_and_fp32_forms_close_to_oracle(prec):
+    """The fast FP64 form (fused multiply-adds, fast reciprocals, linear weights taken
+    exactly where the restriction holds) and the FP32-weight form, built for the host
+    (its own rounding of those forms): L(u) within 1e-11 (fast FP64) or 1e-8 (weights
+    from FP32: 1e-7 of the spread of the candidate fluxes where the restriction does not
+    hold) of the oracle per component on 1D, 2D and 3D data with shocks (a component
+    that vanishes in exact arithmetic is measured against 1e-3 of the largest), so the
+    forms compute the same scheme."""
+    tol = 1e-11 if prec == 2 else 1e-8
+    cases = [(W.euler1d_seeded(1, 300), oracle.TRANSMISSIVE), (W.sod(200), oracle.TRANSMISSIVE),
+             (W.euler2d_seeded(1, 40), oracle.TRANSMISSIVE),
+             (W.euler2d_smooth_periodic(3, 24), oracle.PERIODIC),
+             (W.euler3d_seeded(0, n=16), oracle.PERIODIC)]
+    for c, bc in cases:
+        P = oracle.euler_problem(c.n, c.lo, c.hi, bc=bc)
+        al, _ = oracle.alpha(P, c.u)
+        ref = oracle.rhs(P, c.u)
+        got, bad = HK.rhs(P, c.u, al, prec=prec)
+        assert bad == 0
+        m = ref.shape[0]
+        mx = np.abs(ref).reshape(m, -1).max(axis=1)
+        scale = np.maximum(mx, 1e-3 * mx.max())
+        err = (np.abs(got - ref).reshape(m, -1).max(axis=1) / scale).max()
+        assert err <= tol, (c.name, err)
+    # scalar law
+    c = W.scalar_modes(0, 200)
+    P = oracle.linear_problem(200)
+    al, _ = oracle.alpha(P, c.u)
+    got, _ = HK.rhs(P, c.u, al, prec=prec)
+    ref = oracle.rhs(P, c.u)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()

@@ -3,14 +3,17 @@
 A "step" is one full 3-stage TVD Runge-Kutta step (three RHS evaluations and
 three stage updates, all directions) over the whole grid.  The default
 workload is the 2D Euler one: 4096 x 4096 points, seeded four-quadrant Riemann
-data, transmissive boundaries, CFL 0.5, 200 steps, FP64.  Beside it the same
-line reports ("companions") the FP32-reconstruction form of that workload and
-the batched workloads (4096 independent 1D Euler problems, N log-uniform in
-[256, 16384], 500 steps; 4096 independent 2D problems, 32..96 points per side,
-100 steps), each solved as one captured graph in the form the batch tuner picks
-(the persistent kernel, or the flat form with one launch per stage over all
-problems), in FP64 and in FP32 reconstruction, each with its L1 difference to
-the FP64 result.
+data, transmissive boundaries, CFL 0.5, 200 steps, in the fast FP64 mode
+(fused multiply-adds, refined hardware reciprocals).  Beside it the same line
+reports ("companions"): that workload in the plain FP64 order (bit-identical
+to the oracle) and with FP32 weights, each with its difference to the plain
+run; the batched workloads (4096 independent 1D Euler problems, N log-uniform
+in [256, 16384], 500 steps; 4096 independent 2D problems, 32..96 points per
+side, 100 steps), each solved as one captured graph in the form the batch
+tuner picks, in FP64 and in FP32 weights, with L1, Linf and conservation
+drift against the FP64 result; the 1D Euler workload (65536 points to
+t = 0.2) and the 3D one (512^3, 100 steps) in all three modes, each with its
+own roofline entry and the oracle's CPU baseline.
 
 Prints ONE JSON line (rank 0):
   value  = grid points x timed steps / wall time of the timed region (inputs
@@ -33,6 +36,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -112,11 +117,12 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, y_tile: str):
+def measured_traffic(kernel: str, y_tile: str, precision: str = "fp64_fast"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary of the
-    2D Euler 4096^2 FP64 sweeps, or None when there is none, the kernel sources have
-    changed since the counters were taken, or the y sweep runs another tile shape."""
-    path = os.path.join(ROOT, "profiles", "traffic_euler2d_4096_fp64.txt")
+    2D Euler 4096^2 sweeps in that precision mode, or None when there is none, the kernel
+    sources have changed since the counters were taken, or the y sweep runs another tile
+    shape."""
+    path = os.path.join(ROOT, "profiles", f"traffic_euler2d_4096_{precision}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -176,9 +182,13 @@ def build_case(workload: str, n: int | None):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def cpu_baseline(case, workload):
-    """The oracle on the host: one full RK3 step of the workload (bounded sample)."""
+def cpu_baseline(case, workload, sample_n=None):
+    """The oracle on the host, timed on a bounded sample of the workload: whole RK3 steps
+    of its full grid, or with sample_n, of the same workload generated at sample_n points
+    per dimension (the oracle's per-cell work does not depend on the grid size)."""
     import oracle
+    if sample_n is not None:
+        case = build_case(workload, sample_n)[0]
     sides = None
     if case.sides is not None:
         sides = tuple(oracle.Side(kind=sd.kind, state=sd.state, split0=sd.split0,
@@ -202,9 +212,11 @@ def cpu_baseline(case, workload):
         wall = time.perf_counter() - t0
         if wall >= 10.0 or k >= 400:
             break
+    grid = "x".join(map(str, case.n))
+    what = (f"the full {workload} grid {grid}" if sample_n is None else
+            f"the {workload} workload generated on a {grid} grid")
     return {"value": cells * k / wall, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{k} RK3 step{'s' if k > 1 else ''} of the full {workload} grid "
-                      f"{'x'.join(map(str, case.n))} ({wall:.2f} s)"}
+            "sample": f"{k} RK3 step{'s' if k > 1 else ''} of {what} ({wall:.2f} s)"}
 
 
 def l1_rel(a, b):
@@ -241,8 +253,13 @@ def timed(stream, fn):
     return ev0.elapsed_time(ev1), r
 
 
-def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None):
+def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None, graph=True,
+             t_end=None):
+    """Times `steps` CFL steps (or, with t_end, the steps to that time) of the workload
+    from its initial state; returns the timing, the kernel profile and the final state."""
     import torch
+    t_stop = float("inf") if t_end is None else float(t_end)
+    max_steps = -1 if t_end is not None else steps
     g = wt.Grid(n=case.n, lo=case.lo, hi=case.hi, bc=case.bc)
     p = wt.Params(system=case.system, gamma=case.gamma, cfl=case.cfl, alpha_R=case.alpha_R,
                   precision=precision)
@@ -251,9 +268,10 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None)
         wt.wenotheta_set_sides(ctx, [wt.Side(kind=sd.kind, state=sd.state, split0=sd.split0,
                                              split_speed=sd.split_speed) for sd in case.sides], 0.0)
     if tile_choice is None:
-        tiles = wt.wenotheta_tune(ctx, g, p, u_init)      # untimed set-up: y/z tile shapes
+        tiles = wt.wenotheta_tune(ctx, g, p, u_init)      # untimed set-up: tile shapes
     else:
-        tiles = tuple([0] + [tile_choice] * (case.ndim - 1))
+        xv, yv = tile_choice
+        tiles = tuple([xv] + [yv] * (case.ndim - 1))
         wt.wenotheta_set_tiles(ctx, g, p, tiles)
     if warmup > 0:
         # single CFL steps, queued like the timed ones (the solver's graph would also
@@ -268,32 +286,126 @@ def run_grid(wt, ctx, case, precision, steps, warmup, profile, tile_choice=None)
         wt.wenotheta_profile(ctx, True)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    ms, (t_sim, k) = timed(stream, lambda: wt.wenotheta_solve(ctx, g, p, u, float("inf"),
-                                                              max_steps=steps))
+    ms, (t_sim, k) = timed(stream, lambda: wt.wenotheta_solve(ctx, g, p, u, t_stop,
+                                                              max_steps=max_steps))
     wall = time.perf_counter() - t0
     prof = None
     if profile:
         prof = wt.wenotheta_profile_read(ctx)
         wt.wenotheta_profile(ctx, False)
-    assert k == steps, (k, steps)
+    assert t_end is not None or k == steps, (k, steps)
+    steps = k
     assert bool(torch.isfinite(u).all()), "non-finite state after the timed steps"
     # The profiled region queues the sweeps one by one with an event pair around each;
     # the solver itself replays them from a captured graph.  The same steps once more
     # that way (after one untimed solve that captures the graph), for the production
     # path's rate; the state must come out the same.
     ms_graph = None
-    if profile:
+    if profile and graph:
         ug = u_init.clone()            # the graph is captured for this state's address
         wt.wenotheta_solve(ctx, g, p, ug, float("inf"), max_steps=min(steps, 8))
         ug.copy_(u_init)
-        ms_graph, (_, kg) = timed(stream, lambda: wt.wenotheta_solve(ctx, g, p, ug, float("inf"),
-                                                                   max_steps=steps))
+        ms_graph, (_, kg) = timed(stream, lambda: wt.wenotheta_solve(ctx, g, p, ug, t_stop,
+                                                                   max_steps=max_steps))
         assert kg == steps and torch.equal(ug, u), "graph replay differs from the queued steps"
         del ug
+    del u_init
     return {"ms": ms, "ms_graph": ms_graph, "wall": wall, "t_sim": t_sim, "u": u, "prof": prof,
+            "steps": steps,
             "tiles": [list(wt.TILE_SHAPES[v]) if d > 0 else
                       (list(wt.X_TILE_SHAPES[v]) if case.system == wt.WT_EULER and case.ndim > 1
                        else [1, 255]) for d, v in enumerate(tiles)]}
+
+
+PROFILE_NAMES = {"sweep_x": (0, False), "sweep_y": (1, False), "sweep_z": (2, False),
+                 "sweep_x_final": (0, True), "sweep_y_final": (1, True),
+                 "sweep_z_final": (2, True), "stage_2d": (None, True)}
+
+
+def kernel_ops(case, kind, euler):
+    """Algorithmic operations of one launch of a kernel kind: a sweep, or the fused 2D
+    stage (both directions' interfaces, the x cell phase and the stage-finishing one)."""
+    d, final = PROFILE_NAMES[kind]
+    if d is None:
+        return (sweep_ops(case.ndim, case.n, 0, False, euler) +
+                sweep_ops(case.ndim, case.n, 1, True, euler))
+    return sweep_ops(case.ndim, case.n, d, final, euler)
+PRECISIONS = {"fp64_fast": 2, "fp64": 0, "fp32": 1}     # wt_precision values
+
+
+def grid_block(wt, ctx, case, prec_name, steps, warmup, tile_choice=None, graph=True, t_end=None):
+    """One timed run of a grid workload in one precision mode: cell-updates/s, the
+    dominant kernel's roofline entry, the graph-replay rate, and the final state."""
+    prec = PRECISIONS[prec_name]
+    r = run_grid(wt, ctx, case, prec, steps, warmup, profile=True, tile_choice=tile_choice,
+                 graph=graph, t_end=t_end)
+    cells = int(np.prod(case.n))
+    prof = r["prof"]
+    kind = max(prof, key=lambda kk: prof[kk][0])
+    euler = case.system == W_EULER
+    ops = kernel_ops(case, kind, euler)
+    out = {"value": cells * r["steps"] / (r["ms"] / 1e3), "unit": "cell-updates/s",
+           "precision": prec_name, "steps": r["steps"], "ms_per_step": r["ms"] / r["steps"],
+           "tiles_tx_tn": r["tiles"],
+           "roofline": roofline_entry(kind, ops, prof[kind][0], prof[kind][1],
+                                      fp32_recon=prec == 1),
+           "kernel_ms": {kk: {"total": v[0], "launches": v[1]} for kk, v in prof.items() if v[1]}}
+    if r["ms_graph"] is not None:
+        out["graph"] = {"value": cells * r["steps"] / (r["ms_graph"] / 1e3),
+                        "ms_per_step": r["ms_graph"] / r["steps"]}
+    return out, r
+
+
+def rel_diff(a, b):
+    """Max-relative and L1-relative differences of a against b, per component."""
+    m = b.shape[0]
+    a2, b2 = a.reshape(m, -1), b.reshape(m, -1)
+    d = (a2 - b2).abs()
+    mx = b2.abs().amax(dim=1)
+    scale = torch_max(mx, 1e-3 * mx.max())
+    return {"max_rel": [float(x) for x in (d.amax(dim=1) / scale).cpu()],
+            "l1_rel": [float(x) for x in (d.sum(dim=1) / b2.abs().sum(dim=1)).cpu()]}
+
+
+def torch_max(a, floor):
+    import torch
+    return torch.maximum(a, torch.as_tensor(floor, dtype=a.dtype, device=a.device))
+
+
+def perturbation_response(wt, ctx, case, steps, t_end, u_plain):
+    """The conditioning of a run: the plain FP64 result's change when every initial value
+    is moved by about one unit in the last place (relative 2^-52, seeded random signs),
+    in the same measures as the differences of the fast and FP32 forms."""
+    rng = np.random.default_rng(2)
+    cp = dataclasses.replace(case, u=case.u * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0],
+                                                                               size=case.u.shape)))
+    r = run_grid(wt, ctx, cp, PRECISIONS["fp64"], steps, 0, profile=False, graph=False,
+                 t_end=t_end, tile_choice=None)
+    out = rel_diff(r["u"], u_plain)
+    del r
+    return out
+
+
+def grid_companion(wt, ctx, case, desc, steps, warmup, t_end=None, graph=True):
+    """The FP64 fast, FP64 plain and FP32-weight runs of one grid workload, with the
+    differences of the fast and FP32 forms to the plain FP64 run (bit-identical to the
+    oracle) and the oracle's CPU baseline."""
+    out = {"workload": desc}
+    res = {}
+    for name in ("fp64_fast", "fp64", "fp32"):
+        print(f"[bench] {desc}: {name}", file=sys.stderr, flush=True)
+        e, r = grid_block(wt, ctx, case, name, steps, warmup, graph=graph, t_end=t_end)
+        out[name] = e
+        res[name] = r["u"]
+        del r
+    out["fp64_fast"]["vs_fp64"] = rel_diff(res["fp64_fast"], res["fp64"])
+    out["fp32"].update(differences(res["fp32"], res["fp64"]))
+    out["fp64_response_to_1ulp_input_perturbation"] = perturbation_response(
+        wt, ctx, case, steps, t_end, res["fp64"])
+    out["fp64_fast_over_fp64"] = out["fp64_fast"]["value"] / out["fp64"]["value"]
+    out["fp32_over_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    del res
+    return out
 
 
 def run_batched(wt, ctx, B, precision, steps, warmup, tune=True):
@@ -463,13 +575,19 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="euler2d", choices=["euler2d", "euler1d", "euler3d", "double_mach", "scalar"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64_fast", choices=["fp64_fast", "fp64", "fp32"],
+                    help="fp64_fast: FP64 with fused multiply-adds and fast reciprocals (within "
+                         "1e-12 per RHS of the oracle); fp64: the plain operation order "
+                         "(bit-identical to the oracle); fp32: FP32 nonlinear weights")
     ap.add_argument("--n", type=int, default=None,
                     help="points per dimension (double_mach: in y, 4n in x; default: full size)")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--batched2d-steps", type=int, default=100)
+    ap.add_argument("--steps-3d", type=int, default=100)
     ap.add_argument("--tiles", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="y/z-sweep tile shape: tuned (auto) or forced variant")
+    ap.add_argument("--x-tile", default="0", choices=["0", "1", "2"],
+                    help="with a forced --tiles: the x variant (2: the fused 2D stage)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
@@ -485,40 +603,34 @@ def main():
         copy_calibration(args.copy_calibration)
         return
 
-    import numpy as np
     import torch
 
     import paper_1504_00731_amd as wt
+    from paper_1504_00731_amd import workloads as W
 
     case, desc = build_case(args.workload, args.n)
     cells = int(np.prod(case.n))
-    prec = wt.WT_FP64 if args.precision == "fp64" else wt.WT_FP32_RECON
     print(f"[bench] workload {args.workload} {case.n} {args.precision} steps={args.steps} "
           f"warmup={args.warmup}", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     ctx = wt.Context(0)
-    tile_choice = None if args.tiles == "auto" else int(args.tiles)
-    r = run_grid(wt, ctx, case, prec, args.steps, args.warmup, profile=True, tile_choice=tile_choice)
-    ms, prof = r["ms"], r["prof"]
-
+    tile_choice = None if args.tiles == "auto" else (int(args.x_tile), int(args.tiles))
+    head, r = grid_block(wt, ctx, case, args.precision, args.steps, args.warmup,
+                         tile_choice=tile_choice)
+    u_head = r["u"]
+    ms = r["ms"]
     sec = ms / 1e3
-    value = cells * args.steps / sec
-
-    # dominant kernel: largest total time
-    names = {"sweep_x": (0, False), "sweep_y": (1, False), "sweep_z": (2, False),
-             "sweep_x_final": (0, True), "sweep_y_final": (1, True), "sweep_z_final": (2, True)}
-    kind = max(prof, key=lambda kk: prof[kk][0])
-    tot_ms, launches = prof[kind]
-    d, final = names[kind]
+    value = head["value"]
     euler = case.system == W_EULER
-    ops = sweep_ops(case.ndim, case.n, d, final, euler)
     m = case.ndim + 2 if euler else 1
     bytes_per_step = 8 * m * 8 * cells                   # 8 state passes of m FP64 components
-    traffic = step_traffic = None
-    if args.workload == "euler2d" and case.n == (4096, 4096) and prec == wt.WT_FP64:
+    kind = head["roofline"]["kernel"]
+    step_traffic = None
+    if args.workload == "euler2d" and case.n == (4096, 4096):
         y_tile = "x".join(map(str, r["tiles"][1]))
-        traffic = measured_traffic(kind, y_tile)
-        tx, ty = measured_traffic("sweep_x", y_tile), measured_traffic("sweep_y_final", y_tile)
+        head["roofline"]["traffic"] = measured_traffic(kind, y_tile, args.precision)
+        tx = measured_traffic("sweep_x", y_tile, args.precision)
+        ty = measured_traffic("sweep_y_final", y_tile, args.precision)
         if tx is not None and ty is not None:
             step_traffic = 3 * (tx + ty)                 # one x and one y sweep per stage
 
@@ -533,14 +645,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == wt.WT_FP64 else "f32+f64",
+        "dtype": "f32+f64" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{desc}, {'x'.join(map(str, case.n))} points, "
                                f"{args.steps} RK3 steps, CFL {case.cfl}, {args.precision}",
                    "grid": list(case.n), "steps": args.steps, "cfl": case.cfl,
                    "alpha_R": case.alpha_R, "precision": args.precision,
                    "tiles_tx_tn": r["tiles"]},
-        "roofline": roofline_entry(kind, ops, tot_ms, launches, traffic),
+        "roofline": head["roofline"],
         "hbm": {"achieved": bytes_per_step * args.steps / sec / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": bytes_per_step * args.steps / sec / 1e9 / HBM_PEAK_GBS,
                 "bytes_per_cell_update": bytes_per_step // cells,
@@ -548,41 +660,60 @@ def main():
                 "measured_over_algorithmic": (None if step_traffic is None
                                               else step_traffic / bytes_per_step),
                 "achievable_copy": achievable_copy_bandwidth()},
-        "kernel_ms": {kk: {"total": v[0], "launches": v[1]} for kk, v in prof.items() if v[1]},
-        "graph": {"value": cells * args.steps / (r["ms_graph"] / 1e3),
-                  "ms_per_step": r["ms_graph"] / args.steps,
-                  "note": "the same steps replayed from the solver's captured graph without "
-                          "the per-sweep events of the timed region"},
+        "kernel_ms": head["kernel_ms"],
+        "graph": dict(head.get("graph", {}), note="the same steps replayed from the solver's "
+                      "captured graph without the per-sweep events of the timed region"),
         "wall_s": r["wall"],
         "sim_time": r["t_sim"],
     }
-    if not args.no_companions and prec == wt.WT_FP64:
-        print("[bench] companion: same workload, FP32 reconstruction", file=sys.stderr, flush=True)
-        r32 = run_grid(wt, ctx, case, wt.WT_FP32_RECON, args.steps, args.warmup, profile=True,
-                       tile_choice=tile_choice)
-        f32 = {"value": cells * args.steps / (r32["ms"] / 1e3), "unit": "cell-updates/s",
-               "ms_per_step": r32["ms"] / args.steps, "tiles_tx_tn": r32["tiles"],
-               "graph": {"value": cells * args.steps / (r32["ms_graph"] / 1e3),
-                         "ms_per_step": r32["ms_graph"] / args.steps}}
-        # the dominant kernel against the same FP64 vector peak: without packed FP32 (left
-        # off in this build) an FP32 instruction issues at the FP64 rate
-        p32 = r32["prof"]
-        k32 = max(p32, key=lambda kk: p32[kk][0])
-        d32, final32 = names[k32]
-        ops32 = sweep_ops(case.ndim, case.n, d32, final32, euler)
-        f32["roofline"] = roofline_entry(k32, ops32, p32[k32][0], p32[k32][1], fp32_recon=True)
-        f32["fp32_recon_over_fp64_same_workload"] = f32["value"] / value
-        f32.update(differences(r32["u"], r["u"]))
-        comp = {args.workload + "_fp32_recon": f32}
-        del r32
+    del r
+    if not args.no_companions and args.precision == "fp64_fast":
+        comp = {}
+        # the same workload in the plain FP64 order (bit-identical to the oracle) and with
+        # FP32 weights; the headline's difference to the plain run
+        for name in ("fp64", "fp32"):
+            print(f"[bench] companion: same workload, {name}", file=sys.stderr, flush=True)
+            e, rr = grid_block(wt, ctx, case, name, args.steps, args.warmup,
+                               tile_choice=tile_choice)
+            if name == "fp64":
+                u_plain = rr["u"]
+                e["note"] = "plain operation order, bit-identical to the oracle"
+                line["vs_fp64_plain"] = rel_diff(u_head, u_plain)
+                line["fp64_plain_response_to_1ulp_input_perturbation"] = perturbation_response(
+                    wt, ctx, case, args.steps, None, u_plain)
+                line["speedup_over_fp64_plain"] = value / e["value"]
+            else:
+                e.update(differences(rr["u"], u_plain))
+                e["fp32_over_fp64_plain"] = e["value"] / comp["euler2d_fp64_plain"]["value"]
+            comp[f"{args.workload}_{'fp64_plain' if name == 'fp64' else 'fp32_weights'}"] = e
+            del rr
+        del u_plain
         if args.workload == "euler2d":
             comp["batched"] = batched_companions(wt, ctx, args.batched_steps)
             comp["batched_2d"] = batched2d_companions(wt, ctx, args.batched2d_steps)
+            # the other grid workloads: 1D Euler to t = 0.2, 3D Euler 512^3
+            c1 = W.euler1d_seeded(0, 65536)
+            d1 = (f"1D Euler, seeded Riemann data with density wave, 65536 points, to t = "
+                  f"{c1.t_end} (CFL {c1.cfl})")
+            comp["euler1d"] = grid_companion(wt, ctx, c1, d1, None, args.warmup, t_end=c1.t_end)
+            if not args.no_cpu_baseline:
+                comp["euler1d"]["cpu_baseline"] = cpu_baseline(c1, "euler1d")
+            del c1
+            c3 = W.euler3d_seeded(0, 512)
+            d3 = (f"3D Euler, seeded vortex with density spheres, 512^3 points, "
+                  f"{args.steps_3d} RK3 steps (CFL {c3.cfl})")
+            comp["euler3d"] = grid_companion(wt, ctx, c3, d3, args.steps_3d, args.warmup,
+                                             graph=False)
+            if not args.no_cpu_baseline:
+                comp["euler3d"]["cpu_baseline"] = cpu_baseline(c3, "euler3d", sample_n=192)
+            del c3
         line["companions"] = comp
-    del r
+    del u_head
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(case, args.workload)
+        big = cells > 64 * 2 ** 20           # one oracle step would take over a minute
+        line["cpu_baseline"] = cpu_baseline(case, args.workload,
+                                            sample_n=192 if big and case.ndim == 3 else None)
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -10,8 +10,8 @@ to the oracle) and with FP32 weights, each with its difference to the plain
 run; the batched workloads (4096 independent 1D Euler problems, N log-uniform
 in [256, 16384], 500 steps; 4096 independent 2D problems, 32..96 points per
 side, 100 steps), each solved as one captured graph in the form the batch
-tuner picks, in FP64 and in FP32 weights, with L1, Linf and conservation
-drift against the FP64 result; the 1D Euler workload (65536 points to
+tuner picks, in plain FP64, fast FP64 and FP32 weights, with L1 (and for
+FP32 Linf and conservation drift) against the plain FP64 result; the 1D Euler workload (65536 points to
 t = 0.2) and the 3D one (512^3, 100 steps) in all three modes, each with its
 own roofline entry and the oracle's CPU baseline.
 
@@ -443,7 +443,7 @@ def run_batched(wt, ctx, B, precision, steps, warmup, tune=True):
 
 
 def batched_companions(wt, ctx, steps):
-    """FP64 and FP32-reconstruction runs of the batched workload.  L1 is taken over the
+    """Plain FP64, fast FP64 and FP32-weight runs of the batched workload.  L1 is taken over the
     problems that every run completes (the unlimited scheme drives about 2% of the
     seeded problems to a non-physical state; they are reported, not counted), over
     all of them and over the well-conditioned ones: a problem is ill-conditioned at
@@ -473,7 +473,8 @@ def batched2d_companions(wt, ctx, steps):
 
 
 def compare_batched(wt, ctx, B, cells_per_problem, steps):
-    """FP64 and FP32-reconstruction runs of a batch, timed, and their differences."""
+    """Plain FP64, fast FP64 and FP32-weight runs of a batch, timed, and their differences
+    to the plain FP64 run."""
     import numpy as np
     import torch
     from paper_1504_00731_amd import workloads as W
@@ -482,13 +483,14 @@ def compare_batched(wt, ctx, B, cells_per_problem, steps):
     print(f"[bench] batched {B.nprob} problems ({m} components), {cells} cells, {steps} steps",
           file=sys.stderr, flush=True)
     r64 = run_batched(wt, ctx, B, wt.WT_FP64, steps, 1)
+    rfast = run_batched(wt, ctx, B, wt.WT_FP64_FAST, steps, 1)
     r32 = run_batched(wt, ctx, B, wt.WT_FP32_RECON, steps, 1)
     # sensitivity of each problem at FP32 scale: the FP64 result's response to a 2^-24
     # perturbation of the initial data (untimed)
     rng = np.random.default_rng(1)
     Bp = dataclasses.replace(B, u=B.u * (1.0 + 2.0 ** -24 * rng.choice([-1.0, 1.0], size=B.u.shape)))
     rp = run_batched(wt, ctx, Bp, wt.WT_FP64, steps, 0, tune=False)
-    ok = (r64["status"] == 0) & (r32["status"] == 0) & (rp["status"] == 0)
+    ok = (r64["status"] == 0) & (r32["status"] == 0) & (rp["status"] == 0) & (rfast["status"] == 0)
     # problems are packed in order: per-problem sums as differences of a running sum at
     # the problems' ends (relative error ~1e-12 here, far below the figures reported).
     # The columns of problems that failed in any run (unspecified, possibly NaN or huge)
@@ -513,10 +515,16 @@ def compare_batched(wt, ctx, B, cells_per_problem, steps):
     s32 = per_problem(r32["u"] - r64["u"])
     okt, wellt = torch.from_numpy(ok).cuda(), torch.from_numpy(well).cuda()
     out = {}
-    for name, r in (("fp64", r64), ("fp32_recon", r32)):
+    for name, r in (("fp64", r64), ("fp64_fast", rfast), ("fp32_recon", r32)):
         out[name] = {"value": cells * steps / (r["ms"] / 1e3), "unit": "cell-updates/s",
                      "ms": r["ms"], "failed_problems": int((r["status"] != 0).sum()),
                      "tile_variant": r["variant"]}
+    dfast = per_problem((rfast["u"] - r64["u"]).abs())
+    ff = out["fp64_fast"]
+    ff["fp64_fast_over_fp64_same_workload"] = ff["value"] / out["fp64"]["value"]
+    ff["l1_rel_vs_fp64_well_conditioned"] = [
+        float(x) for x in (dfast[wellt].sum(0) / den[wellt].sum(0)).cpu()]
+    ff["l1_rel_vs_fp64_all"] = [float(x) for x in (dfast[okt].sum(0) / den[okt].sum(0)).cpu()]
     f32 = out["fp32_recon"]
     f32["fp32_recon_over_fp64_same_workload"] = f32["value"] / out["fp64"]["value"]
     f32["l1_rel_vs_fp64_well_conditioned"] = [

@@ -106,19 +106,19 @@ typedef struct {
 typedef enum {
     WT_FP64 = 0,         /* every step in IEEE double precision, in the plain
                             order of the formulas (bit-reproducible)          */
-    WT_FP32_RECON = 1,   /* the WENO-theta reconstructions in FP32: each
-                            stencil is shifted by its point f_j and scaled by
-                            a power of two (epsilon scaled by its square)
-                            before rounding to FP32; projections, fluxes, RK
-                            stages and all stored states stay FP64           */
+    WT_FP32_RECON = 1,   /* the nonlinear weights of the WENO-theta
+                            reconstructions (Sec. 3: alpha_k from tau and the
+                            beta~_k) in FP32; the candidate fluxes, the
+                            indicators, the theta and restriction decisions,
+                            the weighted sum, projections, fluxes, RK stages
+                            and all stored states stay FP64                  */
     WT_FP64_FAST = 2     /* every step in FP64 with fused multiply-adds and
                             fast (not correctly rounded) reciprocals and
                             square roots; where the restriction holds, the
                             weights are the linear weights gamma^theta exactly
                             (Sec. 3.1).  Differs from WT_FP64 by rounding; a
                             theta or restriction decision may differ where its
-                            two sides are within rounding of each other.  Grid
-                            entry points only (batched: WT_ERR_UNSUPPORTED)   */
+                            two sides are within rounding of each other       */
 } wt_precision;
 
 /* Uniform grid.  n[k] points in dimension k (n[k] = 1 for k >= ndim; at least
@@ -257,8 +257,8 @@ wt_status wenotheta_set_sides(wt_ctx *ctx, const wt_side *sides, double t, void 
  *              before a problem's state became non-physical (nsteps if it
  *              never did).
  * The WENO-theta step of each problem is the one wenotheta_step performs on
- * it alone (bit for bit in WT_FP64).  Asynchronous after the problem tables
- * are uploaded. */
+ * it alone (bit for bit in WT_FP64 and WT_FP64_FAST).  Asynchronous after the
+ * problem tables are uploaded. */
 wt_status wenotheta_solve_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
                                   const int64_t *offset, const double *lo, const double *hi,
                                   const int32_t *bc, const wt_params *prm, double *u,
@@ -286,8 +286,8 @@ wt_status wenotheta_solve_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
  *           (any wt_bc) per direction;
  *   t_out, status_out, steps_out   as for wenotheta_solve_batched.
  * The step of each problem is the one wenotheta_step performs on it alone
- * (bit for bit in WT_FP64).  Asynchronous after the problem tables are
- * uploaded.  Calls on one context share the stage buffers of
+ * (bit for bit in WT_FP64 and WT_FP64_FAST).  Asynchronous after the problem
+ * tables are uploaded.  Calls on one context share the stage buffers of
  * wenotheta_solve_batched: the two must not overlap. */
 wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *nx,
                                      const int64_t *ny, const int64_t *offset, const double *lo,

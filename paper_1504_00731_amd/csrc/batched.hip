@@ -110,6 +110,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(PREC == 0 ?
 void batched_kernel(BatchArgs A)
 {
     constexpr int M = 3, TN = TPB - 1, NC = TN + 6, NW = TPB / 64;
+    constexpr bool FAST = PREC == 2;        // the fast FP64 cell and stage forms
     __shared__ double s_u[M][NC];
     __shared__ double s_f[M][NC];
     __shared__ double s_v[1][NC];
@@ -180,7 +181,7 @@ void batched_kernel(BatchArgs A)
                         for (int c = 0; c < 3; ++c) uc[c] = uin[c * total + off + g];
                         if (reflected(g0 - 3 + i, n, bc)) uc[1] = -uc[1];
                         double vel[1], p, H;
-                        if (!euler_cell<1>(uc, A.gamma, vel, p, H)) {
+                        if (!euler_cell<1, FAST>(uc, A.gamma, vel, p, H)) {
                             const bool fin = __builtin_isfinite(uc[0]) && __builtin_isfinite(uc[1]) &&
                                              __builtin_isfinite(uc[2]);
                             err |= fin ? kErrNonphysical : kErrNonfinite;
@@ -193,7 +194,7 @@ void batched_kernel(BatchArgs A)
                             s_f[c][i] = fn[c];
                         }
                         s_v[0][i] = vel[0];
-                        s_sr[i] = sqrt_rn(uc[0]);
+                        s_sr[i] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
                         s_H[i] = H;
                     }
                     __syncthreads();
@@ -212,18 +213,13 @@ void batched_kernel(BatchArgs A)
                         double un[3];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            const double L = -div_by_recip(s_F[c][t + 1] - s_F[c][t], dx, rdx);
+                            const double L = -flux_quotient<FAST>(s_F[c][t + 1] - s_F[c][t], dx, rdx);
                             const int64_t o = c * total + idx;
-                            if (stage == 1)
-                                un[c] = uin[o] + dt * L;
-                            else if (stage == 2)
-                                un[c] = 0.75 * A.u[o] + 0.25 * uin[o] + (0.25 * dt) * L;
-                            else
-                                un[c] = (1.0 / 3.0) * A.u[o] + (2.0 / 3.0) * uin[o] + ((2.0 / 3.0) * dt) * L;
+                            un[c] = rk3_stage<FAST>(stage, uin[o], L, dt, [&] { return A.u[o]; });
                         }
 #pragma unroll
                         for (int c = 0; c < 3; ++c) out[c * total + idx] = un[c];
-                        err |= euler_speeds<1>(un, A.gamma, lam);
+                        err |= euler_speeds<1, FAST>(un, A.gamma, lam);
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
@@ -312,7 +308,7 @@ struct Batch2Args {
 // TN owned points along DIR and 3-point halos mapped through the boundary; entry
 // r * TX + l holds point g0 - 3 + r of line l0 + l (lines past the last repeat
 // it; their interfaces are never taken).  Returns error bits.
-template <int DIR, int TX, int TN, int NC>
+template <int DIR, int TX, int TN, int NC, bool FAST>
 __device__ __forceinline__ int stage_tile2(const double *uin, int64_t total, const Prob2 &P,
                                            int64_t l0, int64_t g0, double gamma,
                                            double (*s_u)[NC], double (*s_f)[NC],
@@ -332,7 +328,7 @@ __device__ __forceinline__ int stage_tile2(const double *uin, int64_t total, con
         for (int c = 0; c < M; ++c) uc[c] = uin[c * total + idx];
         if (reflected(g0 - 3 + r, nd, bc)) uc[1 + DIR] = -uc[1 + DIR];
         double vel[2], p, H;
-        if (!euler_cell<2>(uc, gamma, vel, p, H)) {
+        if (!euler_cell<2, FAST>(uc, gamma, vel, p, H)) {
             bool fin = true;
 #pragma unroll
             for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
@@ -347,7 +343,7 @@ __device__ __forceinline__ int stage_tile2(const double *uin, int64_t total, con
         }
         s_v[0][i] = vel[0];
         s_v[1][i] = vel[1];
-        s_sr[i] = sqrt_rn(uc[0]);
+        s_sr[i] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
         s_H[i] = H;
     }
     return err;
@@ -390,6 +386,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void batched2d_kernel(Batch2Args A)
 {
     constexpr int M = 4, XTX = XV == 0 ? 4 : 8, XTN = XV == 0 ? 63 : 31, YTX = 8, YTN = 31;
+    constexpr bool FAST = PREC == 2;        // the fast FP64 cell and stage forms
     constexpr int NC = (YTN + 6) * YTX > (XTN + 6) * XTX ? (YTN + 6) * YTX : (XTN + 6) * XTX;
     static_assert(XTX * (XTN + 1) == kThreads && YTX * (YTN + 1) == kThreads, "one interface per thread");
     __shared__ double s_u[M][NC];
@@ -460,7 +457,7 @@ void batched2d_kernel(Batch2Args A)
                 // x pass: D = x divergence
                 for (int64_t tile = 0; tile < xlines * xseg; ++tile) {
                     const int64_t l0 = (tile / xseg) * XTX, g0 = (tile % xseg) * XTN;
-                    err |= stage_tile2<0, XTX, XTN, NC>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+                    err |= stage_tile2<0, XTX, XTN, NC, FAST>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
                     __syncthreads();
                     err |= tile_fluxes2<0, XTX, XTN, NC, PREC>(P, l0, g0, s_al[0], A.gamma, A.W, s_u, s_f,
                                                                 s_v, s_sr, s_H, s_F);
@@ -472,7 +469,7 @@ void batched2d_kernel(Batch2Args A)
                             const int64_t idx = P.off + l * P.nx + g;
 #pragma unroll
                             for (int c = 0; c < M; ++c)
-                                A.D[c * total + idx] = div_by_recip(s_F[c][t + XTX] - s_F[c][t], P.dx, P.rdx);
+                                A.D[c * total + idx] = flux_quotient<FAST>(s_F[c][t + XTX] - s_F[c][t], P.dx, P.rdx);
                         }
                     }
                     __syncthreads();                // the tile is reused by the next one
@@ -484,7 +481,7 @@ void batched2d_kernel(Batch2Args A)
                 // y pass: L = -(D + y divergence), the stage, the new speeds
                 for (int64_t tile = 0; tile < ylines * yseg; ++tile) {
                     const int64_t l0 = (tile / yseg) * YTX, g0 = (tile % yseg) * YTN;
-                    err |= stage_tile2<1, YTX, YTN, NC>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+                    err |= stage_tile2<1, YTX, YTN, NC, FAST>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
                     __syncthreads();
                     err |= tile_fluxes2<1, YTX, YTN, NC, PREC>(P, l0, g0, s_al[1], A.gamma, A.W, s_u, s_f,
                                                                 s_v, s_sr, s_H, s_F);
@@ -499,18 +496,13 @@ void batched2d_kernel(Batch2Args A)
 #pragma unroll
                             for (int c = 0; c < M; ++c) {
                                 const int64_t o = c * total + idx;
-                                const double Dd = div_by_recip(s_F[c][t + YTX] - s_F[c][t], P.dy, P.rdy);
+                                const double Dd = flux_quotient<FAST>(s_F[c][t + YTX] - s_F[c][t], P.dy, P.rdy);
                                 const double L = -(A.D[o] + Dd);
-                                if (stage == 1)
-                                    un[c] = uin[o] + dt * L;
-                                else if (stage == 2)
-                                    un[c] = 0.75 * A.u[o] + 0.25 * uin[o] + (0.25 * dt) * L;
-                                else
-                                    un[c] = (1.0 / 3.0) * A.u[o] + (2.0 / 3.0) * uin[o] + ((2.0 / 3.0) * dt) * L;
+                                un[c] = rk3_stage<FAST>(stage, uin[o], L, dt, [&] { return A.u[o]; });
                             }
 #pragma unroll
                             for (int c = 0; c < M; ++c) out[c * total + idx] = un[c];
-                            err |= euler_speeds<2>(un, A.gamma, lam);
+                            err |= euler_speeds<2, FAST>(un, A.gamma, lam);
                         }
                     }
 #pragma unroll
@@ -678,6 +670,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
 void flat2_pass_kernel(Flat2Args A)
 {
     constexpr int M = 4, NC = (TN + 6) * TX;
+    constexpr bool FAST = PREC == 2;        // the fast FP64 cell and stage forms
     static_assert(TX * (TN + 1) == kThreads && NC >= kThreads, "one interface per thread");
     __shared__ double s_u[M][NC];
     __shared__ double s_f[M][NC];
@@ -715,7 +708,7 @@ void flat2_pass_kernel(Flat2Args A)
             s_al[f] = split_speed([sl](int k) { return bits_to_double(sl[3 * DIR + (k < 3 ? k : 1)]); },
                                   f, walls);
     }
-    int err = stage_tile2<DIR, TX, TN, NC>(A.uin, A.total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+    int err = stage_tile2<DIR, TX, TN, NC, FAST>(A.uin, A.total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
     __syncthreads();
     err |= tile_fluxes2<DIR, TX, TN, NC, PREC, ALIAS_F>(P, l0, g0, s_al, A.gamma, A.W, s_u, s_f, s_v, s_sr,
                                                          s_H, s_F);
@@ -727,7 +720,7 @@ void flat2_pass_kernel(Flat2Args A)
             const int64_t idx = P.off + l * P.nx + g;
 #pragma unroll
             for (int c = 0; c < M; ++c)
-                A.D[c * A.total + idx] = div_by_recip(s_F[c][t + TX] - s_F[c][t], P.dx, P.rdx);
+                A.D[c * A.total + idx] = flux_quotient<FAST>(s_F[c][t + TX] - s_F[c][t], P.dx, P.rdx);
         }
         if (err) atomicOr(&A.err[b], err);
     } else {
@@ -739,18 +732,13 @@ void flat2_pass_kernel(Flat2Args A)
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 const int64_t o = c * A.total + idx;
-                const double Dd = div_by_recip(s_F[c][t + TX] - s_F[c][t], P.dy, P.rdy);
+                const double Dd = flux_quotient<FAST>(s_F[c][t + TX] - s_F[c][t], P.dy, P.rdy);
                 const double L = -(A.D[o] + Dd);
-                if (A.stage == 1)
-                    un[c] = A.uin[o] + dt * L;
-                else if (A.stage == 2)
-                    un[c] = 0.75 * A.u0[o] + 0.25 * A.uin[o] + (0.25 * dt) * L;
-                else
-                    un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * A.uin[o] + ((2.0 / 3.0) * dt) * L;
+                un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, [&] { return A.u0[o]; });
             }
 #pragma unroll
             for (int c = 0; c < M; ++c) A.out[c * A.total + idx] = un[c];
-            err |= euler_speeds<2>(un, A.gamma, lam);
+            err |= euler_speeds<2, FAST>(un, A.gamma, lam);
         }
         if (err) atomicOr(&A.err[b], err);
         // the new state's speeds: block maxima, one slot update per value
@@ -869,6 +857,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void flat1_pass_kernel(Flat1Args A)
 {
     constexpr int M = 3, TN = kThreads - 1, NC = TN + 6;
+    constexpr bool FAST = PREC == 2;        // the fast FP64 cell and stage forms
     __shared__ double s_u[M][NC];
     __shared__ double s_f[M][NC];
     __shared__ double s_v[1][NC];
@@ -899,7 +888,7 @@ void flat1_pass_kernel(Flat1Args A)
         for (int c = 0; c < 3; ++c) uc[c] = A.uin[c * A.total + off + g];
         if (reflected(g0 - 3 + i, n, bc)) uc[1] = -uc[1];
         double vel[1], p, H;
-        if (!euler_cell<1>(uc, A.gamma, vel, p, H)) {
+        if (!euler_cell<1, FAST>(uc, A.gamma, vel, p, H)) {
             const bool fin = __builtin_isfinite(uc[0]) && __builtin_isfinite(uc[1]) && __builtin_isfinite(uc[2]);
             err |= fin ? kErrNonphysical : kErrNonfinite;
         }
@@ -911,7 +900,7 @@ void flat1_pass_kernel(Flat1Args A)
             s_f[c][i] = fn[c];
         }
         s_v[0][i] = vel[0];
-        s_sr[i] = sqrt_rn(uc[0]);
+        s_sr[i] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
         s_H[i] = H;
     }
     __syncthreads();
@@ -931,18 +920,13 @@ void flat1_pass_kernel(Flat1Args A)
         double un[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double L = -div_by_recip(s_F[c][t + 1] - s_F[c][t], dx, rdx);
+            const double L = -flux_quotient<FAST>(s_F[c][t + 1] - s_F[c][t], dx, rdx);
             const int64_t o = c * A.total + idx;
-            if (A.stage == 1)
-                un[c] = A.uin[o] + dt * L;
-            else if (A.stage == 2)
-                un[c] = 0.75 * A.u0[o] + 0.25 * A.uin[o] + (0.25 * dt) * L;
-            else
-                un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * A.uin[o] + ((2.0 / 3.0) * dt) * L;
+            un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, [&] { return A.u0[o]; });
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) A.out[c * A.total + idx] = un[c];
-        err |= euler_speeds<1>(un, A.gamma, lam);
+        err |= euler_speeds<1, FAST>(un, A.gamma, lam);
     }
     if (err) atomicOr(&A.err[b], err);
     const int src[3] = {0, 1, 2}, dst[3] = {0, 1, 2};
@@ -1082,8 +1066,8 @@ wt_status prepare_1d(wt_ctx *c, int64_t nprob, const int64_t *n, const int64_t *
     if (!c || !P || !u || !n || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 6 || nsteps < 0) return WT_ERR_ARG;
     if (P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
-    if (P->precision == WT_FP64_FAST) return WT_ERR_UNSUPPORTED;
-    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
+    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON && P->precision != WT_FP64_FAST)
+        return WT_ERR_ARG;
     if (P->gravity[0] != 0.0 || P->gravity[1] != 0.0 || P->gravity[2] != 0.0) return WT_ERR_UNSUPPORTED;
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0) || !(P->gamma > 1.0))
         return WT_ERR_ARG;
@@ -1263,6 +1247,7 @@ wt_status enqueue_1d_flat(const BatchArgs &B, int precision, hipStream_t s)
             F.wr = stage % 3;
             F.zero = (stage + 1) % 3;
             if (precision == WT_FP32_RECON) hipLaunchKernelGGL(flat1_pass_kernel<1>, grid, block, 0, s, F);
+            else if (precision == WT_FP64_FAST) hipLaunchKernelGGL(flat1_pass_kernel<2>, grid, block, 0, s, F);
             else hipLaunchKernelGGL(flat1_pass_kernel<0>, grid, block, 0, s, F);
         }
     }
@@ -1281,6 +1266,9 @@ wt_status enqueue_1d(wt_ctx *c, const BatchArgs &A, int precision, int v, hipStr
     if (precision == WT_FP32_RECON)
         r = v == 0 ? persistent_grid(c, batched_kernel<1, 256>, threads, A.nprob, &grid)
                    : persistent_grid(c, batched_kernel<1, 128>, threads, A.nprob, &grid);
+    else if (precision == WT_FP64_FAST)
+        r = v == 0 ? persistent_grid(c, batched_kernel<2, 256>, threads, A.nprob, &grid)
+                   : persistent_grid(c, batched_kernel<2, 128>, threads, A.nprob, &grid);
     else
         r = v == 0 ? persistent_grid(c, batched_kernel<0, 256>, threads, A.nprob, &grid)
                    : persistent_grid(c, batched_kernel<0, 128>, threads, A.nprob, &grid);
@@ -1290,6 +1278,9 @@ wt_status enqueue_1d(wt_ctx *c, const BatchArgs &A, int precision, int v, hipStr
     if (precision == WT_FP32_RECON) {
         if (v == 0) hipLaunchKernelGGL((batched_kernel<1, 256>), g, b, 0, s, A);
         else hipLaunchKernelGGL((batched_kernel<1, 128>), g, b, 0, s, A);
+    } else if (precision == WT_FP64_FAST) {
+        if (v == 0) hipLaunchKernelGGL((batched_kernel<2, 256>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((batched_kernel<2, 128>), g, b, 0, s, A);
     } else {
         if (v == 0) hipLaunchKernelGGL((batched_kernel<0, 256>), g, b, 0, s, A);
         else hipLaunchKernelGGL((batched_kernel<0, 128>), g, b, 0, s, A);
@@ -1313,8 +1304,8 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
     if (!c || !P || !u || !nx || !ny || !offset || !lo || !hi || !bc) return WT_ERR_ARG;
     if (nprob < 1 || nprob > (int64_t(1) << 30) || total < 36 || nsteps < 0) return WT_ERR_ARG;
     if (P->system != WT_EULER) return WT_ERR_UNSUPPORTED;
-    if (P->precision == WT_FP64_FAST) return WT_ERR_UNSUPPORTED;
-    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON) return WT_ERR_ARG;
+    if (P->precision != WT_FP64 && P->precision != WT_FP32_RECON && P->precision != WT_FP64_FAST)
+        return WT_ERR_ARG;
     if (P->gravity[0] != 0.0 || P->gravity[1] != 0.0 || P->gravity[2] != 0.0) return WT_ERR_UNSUPPORTED;
     if (!(P->cfl > 0.0) || !(P->eps > 0.0) || !(P->alpha_R >= 0.0) || !(P->gamma > 1.0))
         return WT_ERR_ARG;
@@ -1522,6 +1513,9 @@ wt_status enqueue_2d_flat(const Batch2Args &B, int precision, int xv, hipStream_
             if (precision == WT_FP32_RECON) {
                 if (xv == 0) hipLaunchKernelGGL((flat2_pass_kernel<0, 8, 31, 1>), grid, block, 0, s, G);
                 else hipLaunchKernelGGL((flat2_pass_kernel<0, 4, 63, 1>), grid, block, 0, s, G);
+            } else if (precision == WT_FP64_FAST) {
+                if (xv == 0) hipLaunchKernelGGL((flat2_pass_kernel<0, 8, 31, 2>), grid, block, 0, s, G);
+                else hipLaunchKernelGGL((flat2_pass_kernel<0, 4, 63, 2>), grid, block, 0, s, G);
             } else {
                 if (xv == 0) hipLaunchKernelGGL((flat2_pass_kernel<0, 8, 31, 0>), grid, block, 0, s, G);
                 else hipLaunchKernelGGL((flat2_pass_kernel<0, 4, 63, 0>), grid, block, 0, s, G);
@@ -1529,6 +1523,8 @@ wt_status enqueue_2d_flat(const Batch2Args &B, int precision, int xv, hipStream_
         } else {
             if (precision == WT_FP32_RECON)
                 hipLaunchKernelGGL((flat2_pass_kernel<1, 8, 31, 1>), grid, block, 0, s, G);
+            else if (precision == WT_FP64_FAST)
+                hipLaunchKernelGGL((flat2_pass_kernel<1, 8, 31, 2>), grid, block, 0, s, G);
             else
                 hipLaunchKernelGGL((flat2_pass_kernel<1, 8, 31, 0>), grid, block, 0, s, G);
         }
@@ -1562,6 +1558,9 @@ wt_status enqueue_2d(wt_ctx *c, const Batch2Args &A, int precision, int v, hipSt
     if (precision == WT_FP32_RECON)
         r = v == 0 ? persistent_grid(c, batched2d_kernel<1, 0>, kThreads, A.nprob, &grid)
                    : persistent_grid(c, batched2d_kernel<1, 1>, kThreads, A.nprob, &grid);
+    else if (precision == WT_FP64_FAST)
+        r = v == 0 ? persistent_grid(c, batched2d_kernel<2, 0>, kThreads, A.nprob, &grid)
+                   : persistent_grid(c, batched2d_kernel<2, 1>, kThreads, A.nprob, &grid);
     else
         r = v == 0 ? persistent_grid(c, batched2d_kernel<0, 0>, kThreads, A.nprob, &grid)
                    : persistent_grid(c, batched2d_kernel<0, 1>, kThreads, A.nprob, &grid);
@@ -1571,6 +1570,9 @@ wt_status enqueue_2d(wt_ctx *c, const Batch2Args &A, int precision, int v, hipSt
     if (precision == WT_FP32_RECON) {
         if (v == 0) hipLaunchKernelGGL((batched2d_kernel<1, 0>), g, b, 0, s, A);
         else hipLaunchKernelGGL((batched2d_kernel<1, 1>), g, b, 0, s, A);
+    } else if (precision == WT_FP64_FAST) {
+        if (v == 0) hipLaunchKernelGGL((batched2d_kernel<2, 0>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((batched2d_kernel<2, 1>), g, b, 0, s, A);
     } else {
         if (v == 0) hipLaunchKernelGGL((batched2d_kernel<0, 0>), g, b, 0, s, A);
         else hipLaunchKernelGGL((batched2d_kernel<0, 1>), g, b, 0, s, A);

@@ -489,8 +489,7 @@ void sweep_kernel(SweepArgs A)
             double Lc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                const double Dd = FAST ? (s_F[c][t + TX] - s_F[c][t]) * A.rdx
-                                       : div_by_recip(s_F[c][t + TX] - s_F[c][t], A.dx, A.rdx);
+                const double Dd = flux_quotient<FAST>(s_F[c][t + TX] - s_F[c][t], A.dx, A.rdx);
                 const int64_t o = c * ncell + idx;
                 if constexpr (MODE == MODE_FIRST) {
                     A.D[o] = Dd;
@@ -523,38 +522,10 @@ void sweep_kernel(SweepArgs A)
             } else if constexpr (MODE == MODE_LAST_STAGE) {
                 const double dt = st->dt;
                 double un[M];
-                if constexpr (FAST) {
-                    // the stage combinations with fused multiply-adds, one fixed form for
-                    // every component (the symmetries exchange components)
-                    const double c0 = A.stage == 1 ? 0.0 : (A.stage == 2 ? 0.75 : 1.0 / 3.0);
-                    const double c1 = A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0);
-                    const double cdt = (A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0)) * dt;
 #pragma unroll
-                    for (int c = 0; c < M; ++c) {
-                        const double base = __builtin_fma(cdt, Lc[c], c1 * s_u[c][t + 3 * TX]);
-                        un[c] = A.stage == 1 ? base : __builtin_fma(c0, A.u0[c * ncell + idx], base);
-                    }
-                } else if (A.stage == 1) {
-#pragma unroll
-                    for (int c = 0; c < M; ++c) {
-                        const int64_t o = c * ncell + idx;
-                        un[c] = s_u[c][t + 3 * TX] + dt * Lc[c];
-                    }
-                } else if (A.stage == 2) {
-                    const double cdt = 0.25 * dt;
-#pragma unroll
-                    for (int c = 0; c < M; ++c) {
-                        const int64_t o = c * ncell + idx;
-                        un[c] = 0.75 * A.u0[o] + 0.25 * s_u[c][t + 3 * TX] + cdt * Lc[c];
-                    }
-                } else {
-                    const double cdt = (2.0 / 3.0) * dt;
-#pragma unroll
-                    for (int c = 0; c < M; ++c) {
-                        const int64_t o = c * ncell + idx;
-                        un[c] = (1.0 / 3.0) * A.u0[o] + (2.0 / 3.0) * s_u[c][t + 3 * TX] + cdt * Lc[c];
-                    }
-                }
+                for (int c = 0; c < M; ++c)
+                    un[c] = rk3_stage<FAST>(A.stage, s_u[c][t + 3 * TX], Lc[c], dt,
+                                            [&] { return A.u0[c * ncell + idx]; });
 #pragma unroll
                 for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = un[c];
                 // Lax-Friedrichs speeds of the new state
@@ -724,7 +695,7 @@ void stage2d_kernel(Stage2dArgs A)
         if (valid) {
             const TileStencil<1, 1> S{s_u, s_f, s_v, s_sr, s_H, (j + 3) * kFW + fi, j * kFW + fi};
             const SlotSpeeds al{st->alpha[A.slot_rd], 0, A.walls[0] != 0};
-            if (!euler_interface_flux<2, 0, PREC>(S, al, A.gamma, A.W, F))
+            if (!euler_interface_flux<2, 0, PREC, true>(S, al, A.gamma, A.W, F))
                 atomicOr(&st->err, kErrNonphysical);
         }
         __syncthreads();                         // every stencil read of s_f is done
@@ -742,7 +713,7 @@ void stage2d_kernel(Stage2dArgs A)
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             const double d = s_f[c][cj * (kFX + 1) + ci + 1] - s_f[c][cj * (kFX + 1) + ci];
-            Dx[c] = FAST ? d * A.rdx[0] : div_by_recip(d, A.dx[0], A.rdx[0]);
+            Dx[c] = flux_quotient<FAST>(d, A.dx[0], A.rdx[0]);
         }
     }
     __syncthreads();
@@ -767,7 +738,7 @@ void stage2d_kernel(Stage2dArgs A)
         if (valid) {
             const TileStencil<kFW, kFX> S{s_u, s_f, s_v, s_sr, s_H, fj * kFW + i + 3, fj * kFX + i};
             const SlotSpeeds al{st->alpha[A.slot_rd], 1, A.walls[1] != 0};
-            if (!euler_interface_flux<2, 1, PREC>(S, al, A.gamma, A.W, F))
+            if (!euler_interface_flux<2, 1, PREC, true>(S, al, A.gamma, A.W, F))
                 atomicOr(&st->err, kErrNonphysical);
         }
         __syncthreads();
@@ -790,7 +761,7 @@ void stage2d_kernel(Stage2dArgs A)
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             const double d = s_f[c][(cj + 1) * kFX + ci] - s_f[c][cj * kFX + ci];
-            const double Dy = FAST ? d * A.rdx[1] : div_by_recip(d, A.dx[1], A.rdx[1]);
+            const double Dy = flux_quotient<FAST>(d, A.dx[1], A.rdx[1]);
             Lc[c] = -(Dx[c] + Dy);
         }
         if (A.has_grav) {
@@ -811,30 +782,10 @@ void stage2d_kernel(Stage2dArgs A)
         } else {
             const double dt = st->dt;
             double un[M];
-            if constexpr (FAST) {
-                const double c0 = A.stage == 1 ? 0.0 : (A.stage == 2 ? 0.75 : 1.0 / 3.0);
-                const double c1 = A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0);
-                const double cdt = (A.stage == 1 ? 1.0 : (A.stage == 2 ? 0.25 : 2.0 / 3.0)) * dt;
 #pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    const double base = __builtin_fma(cdt, Lc[c], c1 * s_u[c][li]);
-                    un[c] = A.stage == 1 ? base : __builtin_fma(c0, A.u0[c * ncell + idx], base);
-                }
-            } else if (A.stage == 1) {
-#pragma unroll
-                for (int c = 0; c < M; ++c) un[c] = s_u[c][li] + dt * Lc[c];
-            } else if (A.stage == 2) {
-                const double cdt = 0.25 * dt;
-#pragma unroll
-                for (int c = 0; c < M; ++c)
-                    un[c] = 0.75 * A.u0[c * ncell + idx] + 0.25 * s_u[c][li] + cdt * Lc[c];
-            } else {
-                const double cdt = (2.0 / 3.0) * dt;
-#pragma unroll
-                for (int c = 0; c < M; ++c)
-                    un[c] = (1.0 / 3.0) * A.u0[c * ncell + idx] + (2.0 / 3.0) * s_u[c][li] +
-                            cdt * Lc[c];
-            }
+            for (int c = 0; c < M; ++c)
+                un[c] = rk3_stage<FAST>(A.stage, s_u[c][li], Lc[c], dt,
+                                        [&] { return A.u0[c * ncell + idx]; });
 #pragma unroll
             for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = un[c];
             double lam[6];

@@ -113,6 +113,36 @@ __device__ __forceinline__ int euler_speeds(const double *uc, double gamma, doub
     return finite ? kErrNonphysical : kErrNonfinite;
 }
 
+// Flux-difference quotient of a cell, (F_{i+1/2} - F_{i-1/2}) / dx: correctly
+// rounded, or (fast forms) the product with the reciprocal of dx.
+template <bool FAST>
+WT_HD double flux_quotient(double dF, double dx, double rdx)
+{
+    if constexpr (FAST) return dF * rdx;
+    else return div_by_recip(dF, dx, rdx);
+}
+
+// One component of a TVD Runge-Kutta stage (Sec. 2.1): stage 1 u + dt L, stage 2
+// 3/4 u^n + 1/4 u^(1) + dt/4 L, stage 3 1/3 u^n + 2/3 u^(2) + 2 dt/3 L, from the
+// stage's input uin and u^n (u0(), read for stages 2 and 3 only).  The fast forms
+// use fused multiply-adds in one fixed form for every component (the symmetries
+// of a flow exchange components).
+template <bool FAST, class U0>
+WT_HD double rk3_stage(int stage, double uin, double L, double dt, const U0 &u0)
+{
+    if constexpr (FAST) {
+        const double c1 = stage == 1 ? 1.0 : (stage == 2 ? 0.25 : 2.0 / 3.0);
+        const double cdt = (stage == 1 ? 1.0 : (stage == 2 ? 0.25 : 2.0 / 3.0)) * dt;
+        const double base = __builtin_fma(cdt, L, c1 * uin);
+        if (stage == 1) return base;
+        return __builtin_fma(stage == 2 ? 0.75 : 1.0 / 3.0, u0(), base);
+    } else {
+        if (stage == 1) return uin + dt * L;
+        if (stage == 2) return 0.75 * u0() + 0.25 * uin + (0.25 * dt) * L;
+        return (1.0 / 3.0) * u0() + (2.0 / 3.0) * uin + ((2.0 / 3.0) * dt) * L;
+    }
+}
+
 // Lax-Friedrichs speeds: per direction d the distinct values |u_d - c|,
 // |u_d|, |u_d + c| (value 3 d + s, the order of euler_speeds), reduced once
 // each; slot entry d * 5 + s of field s takes value 3 d + s for s = 0, 1, 2

@@ -168,11 +168,68 @@ def test_fast_conserves_on_periodic_data(ctx):
     assert np.all(drift / np.abs(case.u).reshape(4, -1).sum(axis=1) <= 1e-13), drift
 
 
-def test_fast_rejected_by_batched_entry_points(ctx):
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_fast_batched_1d_equals_the_grid_path(ctx, variant):
+    """The batched kernels' fast form uses the grid path's fast cell, interface and stage
+    arithmetic: every problem of a batch equals its own fast grid solve bit for bit, in
+    each tile variant (persistent workgroups of 256 and 128 threads, flat form)."""
+    import math
     import torch
-    B = W.batched_1d(seed=2, nprob=3, nmin=20, nmax=40, steps=1)
-    u = torch.from_numpy(B.u).cuda()
-    p = wt.Params(system=wt.WT_EULER, precision=wt.WT_FP64_FAST)
-    with pytest.raises(wt.WenoThetaError) as e:
-        wt.wenotheta_solve_batched(ctx, p, u, B.n, B.offset, B.lo, B.hi, B.bc, 1)
-    assert e.value.code == wt.binding.WT_ERR_UNSUPPORTED
+    B = W.batched_1d(seed=4, nprob=12, nmin=100, nmax=3000)
+    p = wt.Params(system=wt.WT_EULER, alpha_R=B.alpha_R, cfl=B.cfl, precision=wt.WT_FP64_FAST)
+    wt.wenotheta_set_batched_tiles(ctx, 1, variant)
+    u = to_dev(B.u)
+    t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+    st = torch.full((B.nprob,), -1, dtype=torch.int32, device="cuda")
+    wt.wenotheta_solve_batched(ctx, p, u, B.n, B.offset, B.lo, B.hi, B.bc, 25, t_out=t, status_out=st)
+    wt.wenotheta_sync(ctx)
+    got, t, st = u.cpu().numpy(), t.cpu().numpy(), st.cpu().numpy()
+    done = 0
+    for b in range(B.nprob):
+        if st[b] != 0:
+            continue
+        o, n = int(B.offset[b]), int(B.n[b])
+        case = W.Case("p", W.EULER, B.u[:, o:o + n].copy(), (B.lo[b],), (B.hi[b],), (int(B.bc[b]),))
+        g, pg = _fast_params(case)
+        ud = to_dev(case.u)
+        tt, k = wt.wenotheta_solve(ctx, g, pg, ud, math.inf, max_steps=25)
+        assert k == 25 and tt == t[b], (b, tt, t[b])
+        assert np.array_equal(ud.cpu().numpy(), got[:, o:o + n]), f"problem {b} (n={n})"
+        done += 1
+    assert done >= B.nprob - 1
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_fast_batched_2d_equals_the_grid_path(ctx, variant):
+    """The same for the 2D batch in each tile variant (persistent kernel with x tiles
+    4 x 63 and 8 x 31, flat form with x tiles 8 x 31 and 4 x 63), on problems of uneven
+    sizes, including sizes below one tile and ragged edges."""
+    import math
+    import torch
+    B = W.batched_2d(seed=5, nprob=10, smin=8, smax=70, steps=12)
+    p = wt.Params(system=wt.WT_EULER, gamma=B.gamma, alpha_R=B.alpha_R, cfl=B.cfl,
+                  precision=wt.WT_FP64_FAST)
+    wt.wenotheta_set_batched_tiles(ctx, 2, variant)
+    u = to_dev(B.u)
+    t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+    st = torch.full((B.nprob,), -1, dtype=torch.int32, device="cuda")
+    wt.wenotheta_solve_batched_2d(ctx, p, u, B.nx, B.ny, B.offset, B.lo, B.hi, B.bc, 12,
+                                  t_out=t, status_out=st)
+    wt.wenotheta_sync(ctx)
+    got, t, st = u.cpu().numpy(), t.cpu().numpy(), st.cpu().numpy()
+    done = 0
+    for b in range(B.nprob):
+        if st[b] != 0:
+            continue
+        nx, ny = int(B.nx[b]), int(B.ny[b])
+        g = wt.Grid(n=(nx, ny), lo=tuple(B.lo[b]), hi=tuple(B.hi[b]),
+                    bc=tuple(int(k) for k in B.bc[b]))
+        pg = wt.Params(system=wt.WT_EULER, gamma=B.gamma, alpha_R=B.alpha_R, cfl=B.cfl,
+                       precision=wt.WT_FP64_FAST)
+        ud = to_dev(B.problem(b))
+        tt, k = wt.wenotheta_solve(ctx, g, pg, ud, math.inf, max_steps=12)
+        assert k == 12 and tt == t[b], (b, tt, t[b])
+        o = int(B.offset[b])
+        assert np.array_equal(got[:, o:o + nx * ny], ud.cpu().numpy().reshape(4, -1)), f"problem {b}"
+        done += 1
+    assert done >= B.nprob // 2

@@ -279,8 +279,8 @@ wt_status wenotheta_solve_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
  *           its points x fastest (column offset[b] + y nx[b] + x); advanced in
  *           place;
  *   nx, ny, offset   HOST arrays of nprob entries: points per direction
- *           (>= 6 each) and first column; the column ranges must be disjoint
- *           and inside [0, total);
+ *           (>= 6 each, (nx + 1) ny and nx (ny + 1) at most 2^30) and first
+ *           column; the column ranges must be disjoint and inside [0, total);
  *   lo, hi, bc       HOST arrays of 2 nprob entries, [problem][x, y]: domain
  *           ends (dx = (hi - lo) / n per direction) and boundary condition
  *           (any wt_bc) per direction;
@@ -306,7 +306,12 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
  *               points (0, default) or of 8 rows x 31 points (1), or the flat
  *               form (each pass one launch over the tiles of all problems, the
  *               problems' speeds, steps and errors in device arrays) with x tiles
- *               of 8 x 31 (2) or 4 x 63 (3); the y pass in 8 columns x 31.
+ *               of 8 x 31 (2) or 4 x 63 (3) and the y pass in 8 columns x 31, or
+ *               the flat form with packed chunks (4): each pass's interfaces of
+ *               a problem listed line after line (rows; groups of 8 columns) and
+ *               cut into chunks of 256 interfaces (x) or 32 interface rows of 8
+ *               columns (y) overlapping by one, so that nearly every thread has
+ *               an interface whatever the problem's size.
  * wenotheta_tune_batched / wenotheta_tune_batched_2d take the arguments of the
  * corresponding solve (u DEVICE, only read: each variant runs probe_steps >= 1
  * steps on a scratch copy, 3 rounds interleaved, the best launch kept), keep
@@ -314,7 +319,7 @@ wt_status wenotheta_solve_batched_2d(wt_ctx *ctx, int64_t nprob, const int64_t *
  * and precision (the default stays unless another is more than 2% faster) and
  * write it to *variant_out (HOST, optional).  Synchronises the stream;
  * allocates and frees its scratch copy.
- * wenotheta_set_batched_tiles forces variant (1D: 0 to 2; 2D: 0 to 3) for every
+ * wenotheta_set_batched_tiles forces variant (1D: 0 to 2; 2D: 0 to 4) for every
  * later batch of ndim (1 or 2) dimensions on this context. */
 wt_status wenotheta_tune_batched(wt_ctx *ctx, int64_t nprob, const int64_t *n,
                                  const int64_t *offset, const double *lo, const double *hi,

@@ -32,6 +32,7 @@
 #include "wenotheta.h"
 #include "wt_ctx.hpp"
 #include "wt_device.hpp"
+#include "wt_pack.hpp"
 
 namespace wt {
 
@@ -288,6 +289,10 @@ struct Batch2Args {
     // 8 x 31) and the per-problem state
     const int32_t *xt_prob[2], *xt_local[2], *yt_prob, *yt_local;
     int64_t ntx[2], nty;
+    // packed tiles (variant 4): per pass (x, y) the problem, first interface and
+    // interface count of each chunk
+    const int32_t *pk_prob[2], *pk_q0[2], *pk_n[2];
+    int64_t npk[2];
     unsigned long long *f_spd;
     double *f_dt, *f_time;
     int32_t *f_err;
@@ -566,7 +571,8 @@ struct Flat2Args {
     int64_t total;
     const Prob2 *prob;
     const int32_t *tile_prob;  // problem of each tile (tiles listed problem by problem)
-    const int32_t *tile_local; // index of the tile within its problem
+    const int32_t *tile_local; // index of the tile within its problem (packed: first interface)
+    const int32_t *tile_count; // packed tiles: interfaces of the chunk
     int64_t ntiles, tiles_per_xcd;
     unsigned long long *spd;   // [3][nprob][kFlatSpeeds] speed slots (bits of doubles >= 0)
     double *dt;                // [nprob] time step of the current step
@@ -750,6 +756,154 @@ void flat2_pass_kernel(Flat2Args A)
         }
         block_slot_max<6, 6>(lam, flat_slot(A, A.wr, b), src, idx6);
         if (local == 0 && t < kFlatSpeeds)
+            __hip_atomic_store(&flat_slot(A, A.zero, b)[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Packed tiles of the flat 2D form (variant 4, wt_pack.hpp): a tile is a chunk of a
+// problem's pass interfaces listed line after line, a line being a group of 8 rows (x
+// pass) or 8 columns (y pass): 8 lanes by 32 interface rows, so that nearly every
+// thread has an interface whatever the problem's size; the stretch of each line the
+// chunk touches is staged with its halos.  A wave covers 8 interfaces along the pass
+// in 8 lines, as the fixed 8 x 31 tiles do: near a jump across the lines only a few
+// waves mix restricted and unrestricted stencils (a wave along one line of 64
+// interfaces nearly always would, and pays for both).  The interface and cell
+// routines are those of the other tiles, so results are bit-identical to them.
+static_assert(kPackQt * kPackLanes == kThreads, "one interface per thread");
+
+template <int DIR, int PREC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC == 0 ? 4 : 5)))
+void flat2_packed_kernel(Flat2Args A)
+{
+    constexpr int M = 4, TX = kPackLanes;
+    constexpr int NR = kPackRows, NC = NR * TX;
+    constexpr bool FAST = PREC == 2;
+    static_assert(NC >= kThreads, "the interface fluxes may overlay the staged normal fluxes");
+    __shared__ double s_u[M][NC];
+    __shared__ double s_f[M][NC];
+    __shared__ double s_v[2][NC];
+    __shared__ double s_sr[NC];
+    __shared__ double s_H[NC];
+    constexpr bool ALIAS_F = PREC != 0;
+    __shared__ double s_Fown[ALIAS_F ? 1 : M][ALIAS_F ? 1 : kThreads];
+    double (*s_F)[kThreads];
+    if constexpr (ALIAS_F) s_F = reinterpret_cast<double (*)[kThreads]>(&s_f[0][0]);
+    else s_F = reinterpret_cast<double (*)[kThreads]>(&s_Fown[0][0]);
+    __shared__ double s_al[M];
+
+    int64_t tile = blockIdx.x;
+    tile = (tile % kXcds) * A.tiles_per_xcd + tile / kXcds;
+    if (tile >= A.ntiles) return;
+    const int b = A.tile_prob[tile];
+    const int q0 = A.tile_local[tile], nq = A.tile_count[tile];
+    const Prob2 P = A.prob[b];
+    const int t = threadIdx.x;
+    const int nd = (int)(DIR == 0 ? P.nx : P.ny);     // points along the pass
+    const int64_t nlanes = DIR == 0 ? P.ny : P.nx;     // rows (x) or columns (y)
+    const int W = nd + 1;                              // interfaces per line
+    const int bc = DIR == 0 ? P.bcx : P.bcy;
+    const int nrows = pack_rows(q0, nq, W);
+
+    if (t == 0) {
+        const unsigned long long *sl = flat_slot(A, A.rd, b);
+        const bool walls = bc == WT_REFLECTIVE;
+#pragma unroll
+        for (int f = 0; f < M; ++f)
+            s_al[f] = split_speed([sl](int k) { return bits_to_double(sl[3 * DIR + (k < 3 ? k : 1)]); },
+                                  f, walls);
+    }
+    int err = 0;
+    if (nrows > NR) {             // the host's chunk tables never ask for this
+        if (t == 0) atomicOr(&A.err[b], kErrNonfinite);
+        return;
+    }
+    // stage the lines' stretches: entry row * TX + lane
+    for (int e = t; e < nrows * TX; e += kThreads) {
+        const int row = e / TX, lane = e % TX;
+        int line, g;
+        pack_point(q0, row, W, &line, &g);
+        const int64_t gm = map_index(g, nd, bc);
+        int64_t l = (int64_t)line * TX + lane;
+        if (l >= nlanes) l = nlanes - 1;               // lanes past the last row/column repeat it
+        const int64_t idx = P.off + (DIR == 0 ? l * P.nx + gm : gm * P.nx + l);
+        double uc[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uc[c] = A.uin[c * A.total + idx];
+        if (reflected(g, nd, bc)) uc[1 + DIR] = -uc[1 + DIR];
+        double vel[2], p, H;
+        if (!euler_cell<2, FAST>(uc, A.gamma, vel, p, H)) {
+            bool fin = true;
+#pragma unroll
+            for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
+            err |= fin ? kErrNonphysical : kErrNonfinite;
+        }
+        double fn[M];
+        euler_normal_flux<2, DIR>(uc, vel, p, fn);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            s_u[c][e] = uc[c];
+            s_f[c][e] = fn[c];
+        }
+        s_v[0][e] = vel[0];
+        s_v[1][e] = vel[1];
+        s_sr[e] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
+        s_H[e] = H;
+    }
+    __syncthreads();
+    // one interface per thread: interface row ir of the chunk, lane
+    const int ir = t / TX, lane = t % TX;
+    const int q = q0 + ir;
+    const int line = q / W, i = q - line * W;
+    const bool lane_ok = (int64_t)line * TX + lane < nlanes;
+    double F[M];
+    const bool valid = ir < nq && lane_ok;
+    if (valid) {
+        const LdsStencil<M, 2, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, pack_base(q0, q, W) * TX + lane};
+        if (!euler_interface_flux<2, DIR, PREC, true>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
+            err |= kErrNonphysical;
+    }
+    if constexpr (ALIAS_F) __syncthreads();
+    if (valid) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) s_F[c][t] = F[c];
+    }
+    __syncthreads();
+    // cells whose left interface is this thread's (not a line's last interface)
+    const bool cell = ir < nq - 1 && i < nd && lane_ok;
+    if constexpr (DIR == 0) {
+        if (cell) {
+            const int64_t idx = P.off + ((int64_t)line * TX + lane) * P.nx + i;
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                A.D[c * A.total + idx] = flux_quotient<FAST>(s_F[c][t + TX] - s_F[c][t], P.dx, P.rdx);
+        }
+        if (err) atomicOr(&A.err[b], err);
+    } else {
+        double lam[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (cell) {
+            const int64_t idx = P.off + (int64_t)i * P.nx + (int64_t)line * TX + lane;
+            const double dt = A.dt[b];
+            double un[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const int64_t o = c * A.total + idx;
+                const double Dd = flux_quotient<FAST>(s_F[c][t + TX] - s_F[c][t], P.dy, P.rdy);
+                const double L = -(A.D[o] + Dd);
+                un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, [&] { return A.u0[o]; });
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) A.out[c * A.total + idx] = un[c];
+            err |= euler_speeds<2, FAST>(un, A.gamma, lam);
+        }
+        if (err) atomicOr(&A.err[b], err);
+        int src[6], idx6[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            src[k] = k;
+            idx6[k] = k;
+        }
+        block_slot_max<6, 6>(lam, flat_slot(A, A.wr, b), src, idx6);
+        if (q0 == 0 && t < kFlatSpeeds)
             __hip_atomic_store(&flat_slot(A, A.zero, b)[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -1023,7 +1177,7 @@ void release_batched(wt_ctx *c)
 namespace {
 
 constexpr int kBatchVariants1D = 3;   // 1D: persistent 256 / 128 threads, flat
-constexpr int kBatchVariants2D = 4;   // 2D: persistent 4x63 / 8x31 x tiles, flat 8x31 / 4x63
+constexpr int kBatchVariants2D = 5;   // 2D: persistent 4x63 / 8x31 x tiles, flat 8x31 / 4x63, packed
 constexpr uint64_t kAnyBatch = ~0ull; // variant key of wenotheta_set_batched_tiles: every batch
 
 // The variant of a batch: the tuned one for its signature, a forced one, else 0.
@@ -1314,6 +1468,9 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
     std::vector<int64_t> cells(nprob);
     for (int64_t b = 0; b < nprob; ++b) {
         if (nx[b] < 6 || ny[b] < 6 || nx[b] > total || ny[b] > total / nx[b] || offset[b] < 0) return WT_ERR_ARG;
+        // the packed chunks index a pass's interfaces of one problem in 32 bits
+        if ((nx[b] + 1) * ny[b] > (int64_t(1) << 30) || (ny[b] + 1) * nx[b] > (int64_t(1) << 30))
+            return WT_ERR_ARG;
         cells[b] = nx[b] * ny[b];
         if (offset[b] > total - cells[b]) return WT_ERR_ARG;
         for (int d = 0; d < 2; ++d) {
@@ -1428,9 +1585,34 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
     list(ntx[0], [&](int64_t b) { return pass_tiles(nx[b], ny[b], 8, 31); });
     list(ntx[1], [&](int64_t b) { return pass_tiles(nx[b], ny[b], 4, 63); });
     list(nty, [&](int64_t b) { return pass_tiles(ny[b], nx[b], 8, 31); });
+    // packed chunks (wt_pack.hpp): x over groups of 8 rows, y over groups of 8 columns
+    int64_t npk[2] = {0, 0};
+    std::vector<int32_t> pk[2];
+    for (int d = 0; d < 2; ++d) {
+        std::vector<int32_t> pb, pq, pn;
+        for (int64_t b = 0; b < nprob; ++b) {
+            const int Wd = (int)(d == 0 ? nx[b] : ny[b]) + 1;
+            const int nl = (int)((d == 0 ? ny[b] : nx[b]) + kPackLanes - 1) / kPackLanes;
+            pack_chunks(Wd, nl, kPackQt, kPackRows,
+                        [&](int q0, int nq) {
+                            pb.push_back((int32_t)b);
+                            pq.push_back(q0);
+                            pn.push_back(nq);
+                        });
+        }
+        npk[d] = (int64_t)pb.size();
+        pk[d].reserve(3 * pb.size());
+        pk[d].insert(pk[d].end(), pb.begin(), pb.end());
+        pk[d].insert(pk[d].end(), pq.begin(), pq.end());
+        pk[d].insert(pk[d].end(), pn.begin(), pn.end());
+    }
+    if (entries + 3 * (npk[0] + npk[1]) > (int64_t(1) << 31)) return WT_ERR_ARG;
+    ttab.insert(ttab.end(), pk[0].begin(), pk[0].end());
+    ttab.insert(ttab.end(), pk[1].begin(), pk[1].end());
+    const int64_t all_entries = (int64_t)ttab.size();
     const size_t state_bytes = (size_t)nprob * (3 * kFlatSpeeds * sizeof(unsigned long long) +
                                                 2 * sizeof(double) + sizeof(int32_t) + sizeof(int64_t));
-    if (nprob > c->f2_state_cap || entries > c->f2_tab_cap) {
+    if (nprob > c->f2_state_cap || all_entries > c->f2_tab_cap) {
         if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_DEVICE;
         if (c->b2_graph) (void)hipGraphExecDestroy(c->b2_graph);
         c->b2_graph = nullptr;
@@ -1440,7 +1622,7 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
         c->f2_tab = nullptr;
         c->f2_state_cap = c->f2_tab_cap = 0;
         if (hipMalloc(&c->f2_state, state_bytes) != hipSuccess ||
-            hipMalloc(&c->f2_tab, entries * sizeof(int32_t)) != hipSuccess) {
+            hipMalloc(&c->f2_tab, all_entries * sizeof(int32_t)) != hipSuccess) {
             (void)hipFree(c->f2_state);
             (void)hipFree(c->f2_tab);
             c->f2_state = nullptr;
@@ -1449,9 +1631,9 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
             return WT_ERR_NOMEM;
         }
         c->f2_state_cap = nprob;
-        c->f2_tab_cap = entries;
+        c->f2_tab_cap = all_entries;
     }
-    if (hipMemcpyAsync(c->f2_tab, ttab.data(), entries * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+    if (hipMemcpyAsync(c->f2_tab, ttab.data(), all_entries * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return WT_ERR_DEVICE;
     const int32_t *t0 = c->f2_tab;
@@ -1464,6 +1646,14 @@ wt_status prepare_2d(wt_ctx *c, int64_t nprob, const int64_t *nx, const int64_t 
     A->ntx[0] = ntx[0];
     A->ntx[1] = ntx[1];
     A->nty = nty;
+    const int32_t *pk0 = t0 + entries;
+    for (int d = 0; d < 2; ++d) {
+        A->pk_prob[d] = pk0;
+        A->pk_q0[d] = pk0 + npk[d];
+        A->pk_n[d] = pk0 + 2 * npk[d];
+        A->npk[d] = npk[d];
+        pk0 += 3 * npk[d];
+    }
     char *p = (char *)c->f2_state;
     A->f_spd = (unsigned long long *)p;
     p += (size_t)nprob * 3 * kFlatSpeeds * sizeof(unsigned long long);
@@ -1509,7 +1699,18 @@ wt_status enqueue_2d_flat(const Batch2Args &B, int precision, int xv, hipStream_
         G.ntiles = n;
         G.tiles_per_xcd = (n + kXcds - 1) / kXcds;
         const dim3 grid((unsigned)(G.tiles_per_xcd * kXcds)), block(kThreads);
-        if (dir == 0) {
+        if (xv == 2) {              // packed chunks of both passes
+            G.tile_count = B.pk_n[dir];
+            if (dir == 0) {
+                if (precision == WT_FP32_RECON) hipLaunchKernelGGL((flat2_packed_kernel<0, 1>), grid, block, 0, s, G);
+                else if (precision == WT_FP64_FAST) hipLaunchKernelGGL((flat2_packed_kernel<0, 2>), grid, block, 0, s, G);
+                else hipLaunchKernelGGL((flat2_packed_kernel<0, 0>), grid, block, 0, s, G);
+            } else {
+                if (precision == WT_FP32_RECON) hipLaunchKernelGGL((flat2_packed_kernel<1, 1>), grid, block, 0, s, G);
+                else if (precision == WT_FP64_FAST) hipLaunchKernelGGL((flat2_packed_kernel<1, 2>), grid, block, 0, s, G);
+                else hipLaunchKernelGGL((flat2_packed_kernel<1, 0>), grid, block, 0, s, G);
+            }
+        } else if (dir == 0) {
             if (precision == WT_FP32_RECON) {
                 if (xv == 0) hipLaunchKernelGGL((flat2_pass_kernel<0, 8, 31, 1>), grid, block, 0, s, G);
                 else hipLaunchKernelGGL((flat2_pass_kernel<0, 4, 63, 1>), grid, block, 0, s, G);
@@ -1540,8 +1741,13 @@ wt_status enqueue_2d_flat(const Batch2Args &B, int precision, int xv, hipStream_
             F.rd = stage - 1;
             F.wr = stage % 3;
             F.zero = (stage + 1) % 3;
-            pass(0, B.xt_prob[xv], B.xt_local[xv], B.ntx[xv]);
-            pass(1, B.yt_prob, B.yt_local, B.nty);
+            if (xv == 2) {
+                pass(0, B.pk_prob[0], B.pk_q0[0], B.npk[0]);
+                pass(1, B.pk_prob[1], B.pk_q0[1], B.npk[1]);
+            } else {
+                pass(0, B.xt_prob[xv], B.xt_local[xv], B.ntx[xv]);
+                pass(1, B.yt_prob, B.yt_local, B.nty);
+            }
         }
     }
     hipLaunchKernelGGL(flat2_finish_kernel, dim3(per_problem), dim3(256), 0, s, F);
@@ -1549,7 +1755,8 @@ wt_status enqueue_2d_flat(const Batch2Args &B, int precision, int xv, hipStream_
 }
 
 // The 2D batch in variant v on s: the persistent kernel with x tiles 4 x 63 (0)
-// or 8 x 31 (1), or the flat form with x tiles 8 x 31 (2) or 4 x 63 (3).
+// or 8 x 31 (1), or the flat form with x tiles 8 x 31 (2) or 4 x 63 (3), or with
+// packed chunks in both passes (4).
 wt_status enqueue_2d(wt_ctx *c, const Batch2Args &A, int precision, int v, hipStream_t s)
 {
     if (v >= 2) return enqueue_2d_flat(A, precision, v - 2, s);

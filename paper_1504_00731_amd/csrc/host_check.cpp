@@ -9,6 +9,7 @@
 
 #include "wt_bc.hpp"
 #include "wt_flux.hpp"
+#include "wt_pack.hpp"
 
 namespace {
 
@@ -112,6 +113,31 @@ double wth_weno(const double *s, double eps, double aR)
 {
     return wt::weno_theta(s[0], s[1], s[2], s[3], s[4], s[5], eps, aR, 1.0 / eps);
 }
+
+// The packed-chunk rules of the batched 2D passes, for CPU checks of their tables:
+// the chunks of nl lines of W interfaces (at most cap; returns their number), and
+// the staged rows, stencil base and staged point of a chunk.
+int wth_pack_chunks(int W, int nl, int qt, int rmax, int32_t *q0, int32_t *nq, int cap)
+{
+    int k = 0;
+    wt::pack_chunks(W, nl, qt, rmax, [&](int a, int n) {
+        if (k < cap) {
+            q0[k] = a;
+            nq[k] = n;
+        }
+        ++k;
+    });
+    return k;
+}
+void wth_pack_limits(int *lim)
+{
+    lim[0] = wt::kPackLanes;
+    lim[1] = wt::kPackQt;
+    lim[2] = wt::kPackRows;
+}
+int wth_pack_rows(int q0, int nq, int W) { return wt::pack_rows(q0, nq, W); }
+int wth_pack_base(int q0, int q, int W) { return wt::pack_base(q0, q, W); }
+void wth_pack_point(int q0, int row, int W, int *line, int *g) { wt::pack_point(q0, row, W, line, g); }
 
 }  // extern "C"
 

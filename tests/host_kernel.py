@@ -117,3 +117,50 @@ def reflected(i, n, bc) -> bool:
     f.restype = ctypes.c_int
     f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
     return bool(f(i, n, bc))
+
+
+def pack_chunks(W, nl, qt, rmax):
+    """(q0, nq) of the packed chunks of nl lines of W interfaces (batched 2D passes)."""
+    L = lib()
+    cap = nl * W + 1
+    q0 = (ctypes.c_int32 * cap)()
+    nq = (ctypes.c_int32 * cap)()
+    f = L.wth_pack_chunks
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_int32)] * 2 + [ctypes.c_int]
+    k = f(W, nl, qt, rmax, q0, nq, cap)
+    assert k <= cap
+    return [(q0[i], nq[i]) for i in range(k)]
+
+
+def pack_rows(q0, nq, W) -> int:
+    f = lib().wth_pack_rows
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] * 3
+    return f(q0, nq, W)
+
+
+def pack_base(q0, q, W) -> int:
+    f = lib().wth_pack_base
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] * 3
+    return f(q0, q, W)
+
+
+def pack_point(q0, row, W):
+    f = lib().wth_pack_point
+    f.restype = None
+    f.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_int)] * 2
+    line, g = ctypes.c_int(), ctypes.c_int()
+    f(q0, row, W, ctypes.byref(line), ctypes.byref(g))
+    return line.value, g.value
+
+
+def pack_limits():
+    """(lanes per line, interface rows per chunk, staged rows per chunk) of the packed chunks."""
+    lim = (ctypes.c_int * 3)()
+    f = lib().wth_pack_limits
+    f.restype = None
+    f.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    f(lim)
+    return lim[0], lim[1], lim[2]

@@ -71,13 +71,13 @@ def _equal_where_completed(B, a, b, status):
 def test_batch_variants_are_bit_identical(ctx, precision):
     """1D: the persistent kernel with either workgroup size and the flat form (one launch
     per stage over all problems' segments); 2D: the persistent kernel and the flat form,
-    each with either x tile."""
+    each with either x tile, and the flat form with packed chunks in both passes."""
     B1, B2 = _batch_1d(), _mixed_batch()
     res1, res2 = {}, {}
     for v in (0, 1, 2):
         wt.wenotheta_set_batched_tiles(ctx, 1, v)
         res1[v] = _run_1d(ctx, B1, 12, precision)
-    for v in (0, 1, 2, 3):
+    for v in (0, 1, 2, 3, 4):
         wt.wenotheta_set_batched_tiles(ctx, 2, v)
         res2[v] = _run_2d(ctx, B2, 10, precision)
     for B, res in ((B1, res1), (B2, res2)):
@@ -110,7 +110,7 @@ def test_batch_tuners_leave_the_state_and_are_used(ctx):
     v2 = wt.wenotheta_tune_batched_2d(ctx, p, u2, B2.nx, B2.ny, B2.offset, B2.lo, B2.hi, B2.bc,
                                       probe_steps=3)
     wt.wenotheta_sync(ctx)                      # no error left in the context
-    assert v1 in (0, 1, 2) and v2 in (0, 1, 2, 3)
+    assert v1 in (0, 1, 2) and v2 in (0, 1, 2, 3, 4)
     assert np.array_equal(u1.cpu().numpy(), B1.u) and np.array_equal(u2.cpu().numpy(), B2.u)
     tuned = (_run_1d(ctx, B1, 12, wt.WT_FP64), _run_2d(ctx, B2, 60, wt.WT_FP64))
     with wt.Context(0) as other:                # default variants on a fresh context
@@ -122,7 +122,7 @@ def test_batch_tuners_leave_the_state_and_are_used(ctx):
 
 
 def test_batch_tile_arguments(ctx):
-    for ndim, v in ((0, 0), (3, 0), (1, 3), (2, -1), (2, 4)):
+    for ndim, v in ((0, 0), (3, 0), (1, 3), (2, -1), (2, 5)):
         with pytest.raises(wt.WenoThetaError) as e:
             wt.wenotheta_set_batched_tiles(ctx, ndim, v)
         assert e.value.code == 1

@@ -189,11 +189,11 @@ def test_batched_2d_fp32_full_size(ctx):
     assert np.all(e_all <= 1e-6), e_all
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 4])
 def test_batched_2d_full_size_sampled(variant):
     """The benchmark batch (4096 problems, 32..96 points per side, 100 steps), in the
-    persistent form (0) and the flat form (2): the largest, the smallest and seeded
-    other problems against the oracle."""
+    persistent form (0), the flat form (2) and the flat form with packed chunks (4): the
+    largest, the smallest and seeded other problems against the oracle."""
     B = W.batched_2d(seed=0)
     with wt.Context(0) as ctx:
         wt.wenotheta_set_batched_tiles(ctx, 2, variant)

@@ -199,11 +199,11 @@ def test_fast_batched_1d_equals_the_grid_path(ctx, variant):
     assert done >= B.nprob - 1
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_fast_batched_2d_equals_the_grid_path(ctx, variant):
     """The same for the 2D batch in each tile variant (persistent kernel with x tiles
-    4 x 63 and 8 x 31, flat form with x tiles 8 x 31 and 4 x 63), on problems of uneven
-    sizes, including sizes below one tile and ragged edges."""
+    4 x 63 and 8 x 31, flat form with x tiles 8 x 31 and 4 x 63, flat form with packed
+    chunks), on problems of uneven sizes, including sizes below one tile and ragged edges."""
     import math
     import torch
     B = W.batched_2d(seed=5, nprob=10, smin=8, smax=70, steps=12)

@@ -68,7 +68,7 @@ def test_batched_job_fetch_is_in_the_job_loop():
     asm = _device_asm("batched.hip")
     syms1 = kernel_symbols(asm, "_ZN2wt14batched_kernel")
     syms2 = kernel_symbols(asm, "_ZN2wt16batched2d_kernel")
-    assert len(syms1) == 4 and len(syms2) == 4         # 2 precisions x 2 tile variants each
+    assert len(syms1) == 6 and len(syms2) == 6         # 3 precisions x 2 tile variants each
     syms = syms1 + syms2
     lines = asm.split("\n")
     for s in syms:

@@ -598,6 +598,8 @@ def main():
                     help="with a forced --tiles: the x variant (2: the fused 2D stage)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="of the companions, run only the two batched workloads (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
                     help="only run a plain 512 MiB device copy REPS times (counter scaling)")
     args = ap.parse_args()
@@ -679,7 +681,7 @@ def main():
         comp = {}
         # the same workload in the plain FP64 order (bit-identical to the oracle) and with
         # FP32 weights; the headline's difference to the plain run
-        for name in ("fp64", "fp32"):
+        for name in (() if args.batched_only else ("fp64", "fp32")):
             print(f"[bench] companion: same workload, {name}", file=sys.stderr, flush=True)
             e, rr = grid_block(wt, ctx, case, name, args.steps, args.warmup,
                                tile_choice=tile_choice)
@@ -695,10 +697,12 @@ def main():
                 e["fp32_over_fp64_plain"] = e["value"] / comp["euler2d_fp64_plain"]["value"]
             comp[f"{args.workload}_{'fp64_plain' if name == 'fp64' else 'fp32_weights'}"] = e
             del rr
-        del u_plain
+            if name == "fp32":
+                del u_plain
         if args.workload == "euler2d":
             comp["batched"] = batched_companions(wt, ctx, args.batched_steps)
             comp["batched_2d"] = batched2d_companions(wt, ctx, args.batched2d_steps)
+        if args.workload == "euler2d" and not args.batched_only:
             # the other grid workloads: 1D Euler to t = 0.2, 3D Euler 512^3
             c1 = W.euler1d_seeded(0, 65536)
             d1 = (f"1D Euler, seeded Riemann data with density wave, 65536 points, to t = "

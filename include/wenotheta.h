@@ -343,7 +343,7 @@ wt_status wenotheta_set_batched_tiles(wt_ctx *ctx, int32_t ndim, int32_t variant
  *                          leave a nearly empty last segment, e.g. 512 points)
  * or, for the 2D Euler system without WT_SIDES dimensions, x variant
  *   2: the fused stage kernel: both directions of a stage in one launch on
- *      tiles of 16 x 30 points with 3-point halos, so that the divergence of
+ *      tiles of 31 x 15 points with 3-point halos, so that the divergence of
  *      the x direction stays on chip (the y entry is then unused)
  * Every shape computes the same fluxes with the same operations: the results
  * are bit-identical whichever is used; only the speed differs.  The choice

@@ -297,8 +297,8 @@ def wenotheta_solve(ctx: Context, grid: Grid, params: Params, u, t_end, t0=0.0, 
 
 
 TILE_SHAPES = ((8, 31), (16, 15), (4, 63), (32, 7))   # (TX, TN) of the y/z-sweep tile variants
-X_TILE_SHAPES = ((1, 255), (8, 31), (16, 30))        # (rows, TN) of the x-sweep tile variants;
-                                                      # 2: the fused 2D stage (16 x 30 tiles)
+X_TILE_SHAPES = ((1, 255), (8, 31), (15, 31))        # (rows, TN) of the x-sweep tile variants;
+                                                      # 2: the fused 2D stage (31 x 15 tiles)
 
 
 def wenotheta_tune(ctx: Context, grid: Grid, params: Params, u, stream=None) -> tuple:

@@ -571,17 +571,23 @@ void sweep_kernel(SweepArgs A)
 //
 // LDS per block: the staged points (state, velocities, p, sqrt(rho), H: 9 doubles
 // each) and one buffer for the normal fluxes of the current direction, which the
-// interface fluxes replace once every stencil has been read: 78 KB, two blocks of
-// 512 threads per CU (4 waves per SIMD).  kFX = 16 makes each tile row one
-// 128-byte line of a component.
-constexpr int kFX = 16, kFY = 30, kFThreads = 512;
+// interface fluxes replace once every stencil has been read: 77 KB, two blocks of
+// 512 threads per CU (4 waves per SIMD).
+//
+// Lanes and LDS banks: the tile is kFX = 31 points wide, so a row has 32 x
+// interfaces and every group of 32 lanes takes one row, reading 32 consecutive LDS
+// words; the y interfaces, the y normal fluxes and the owned points run 32 lanes per
+// row as well (31 columns, the 32nd lane idle), on flux rows of 32 words.  No access
+// of a half-wave then straddles two rows, which would meet in the same banks.
+constexpr int kFX = 31, kFY = 15, kFThreads = 512;
+constexpr int kFL = 32;                      // lanes per tile row in every phase
 constexpr int kFW = kFX + 6, kFH = kFY + 6, kFNP = kFW * kFH;
 constexpr int kFXF = kFY * kFW;              // x phase: normal fluxes of rows 3 .. kFY + 2
-constexpr int kFYF = kFH * kFX;              // y phase: normal fluxes of columns 3 .. kFX + 2
+constexpr int kFYF = kFH * kFL;              // y phase: normal fluxes of columns 3 .. kFX + 2
 constexpr int kFBuf = kFXF > kFYF ? kFXF : kFYF;
-static_assert((kFX + 1) * kFY <= kFThreads && kFX * (kFY + 1) <= kFThreads,
-              "one interface per thread in each phase");
-static_assert((kFX + 1) * kFY <= kFBuf && kFX * (kFY + 1) <= kFBuf, "interface fluxes fit");
+static_assert(kFX + 1 == kFL && kFL * (kFY + 1) <= kFThreads,
+              "one interface per thread in each phase, one row per 32 lanes");
+static_assert(kFL * (kFY + 1) <= kFBuf, "interface fluxes fit");
 
 struct Stage2dArgs {
     const double *uin;     // state whose fluxes are taken
@@ -690,7 +696,7 @@ void stage2d_kernel(Stage2dArgs A)
     __syncthreads();
     double F[M];
     {
-        const int fi = t % (kFX + 1), j = t / (kFX + 1);   // face between points fi-1, fi of row j
+        const int fi = t % kFL, j = t / kFL;     // face between points fi-1, fi of row j
         const bool valid = j < kFY && fi <= nxt && j < nyt;
         if (valid) {
             const TileStencil<1, 1> S{s_u, s_f, s_v, s_sr, s_H, (j + 3) * kFW + fi, j * kFW + fi};
@@ -701,18 +707,18 @@ void stage2d_kernel(Stage2dArgs A)
         __syncthreads();                         // every stencil read of s_f is done
         if (valid) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) s_f[c][j * (kFX + 1) + fi] = F[c];
+            for (int c = 0; c < M; ++c) s_f[c][j * kFL + fi] = F[c];
         }
     }
     __syncthreads();
     // x flux differences of the owned points, kept for the end of the stage
-    const int ci = t % kFX, cj = t / kFX;
-    const bool own = cj < kFY && ci < nxt && cj < nyt;
+    const int ci = t % kFL, cj = t / kFL;
+    const bool own = cj < kFY && ci < kFX && ci < nxt && cj < nyt;
     double Dx[M];
     if (own) {
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            const double d = s_f[c][cj * (kFX + 1) + ci + 1] - s_f[c][cj * (kFX + 1) + ci];
+            const double d = s_f[c][cj * kFL + ci + 1] - s_f[c][cj * kFL + ci];
             Dx[c] = flux_quotient<FAST>(d, A.dx[0], A.rdx[0]);
         }
     }
@@ -720,8 +726,9 @@ void stage2d_kernel(Stage2dArgs A)
 
     // ---- y direction: normal fluxes of columns 3 .. kFX + 2, one interface per thread
     for (int i = t; i < kFYF; i += kFThreads) {
-        const int iy = i / kFX, ix = i - iy * kFX + 3;
-        const int li = iy * kFW + ix;
+        const int iy = i / kFL, cx = i - iy * kFL;
+        if (cx >= kFX) continue;                 // the idle 32nd lane of a row
+        const int li = iy * kFW + cx + 3;
         double uc[M], vel[2], fn[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) uc[c] = s_u[c][li];
@@ -733,10 +740,10 @@ void stage2d_kernel(Stage2dArgs A)
     }
     __syncthreads();
     {
-        const int i = t % kFX, fj = t / kFX;     // face between points fj-1, fj of column i
-        const bool valid = fj <= kFY && i < nxt && fj <= nyt;
+        const int i = t % kFL, fj = t / kFL;     // face between points fj-1, fj of column i
+        const bool valid = fj <= kFY && i < kFX && i < nxt && fj <= nyt;
         if (valid) {
-            const TileStencil<kFW, kFX> S{s_u, s_f, s_v, s_sr, s_H, fj * kFW + i + 3, fj * kFX + i};
+            const TileStencil<kFW, kFL> S{s_u, s_f, s_v, s_sr, s_H, fj * kFW + i + 3, fj * kFL + i};
             const SlotSpeeds al{st->alpha[A.slot_rd], 1, A.walls[1] != 0};
             if (!euler_interface_flux<2, 1, PREC, true>(S, al, A.gamma, A.W, F))
                 atomicOr(&st->err, kErrNonphysical);
@@ -744,7 +751,7 @@ void stage2d_kernel(Stage2dArgs A)
         __syncthreads();
         if (valid) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) s_f[c][fj * kFX + i] = F[c];
+            for (int c = 0; c < M; ++c) s_f[c][fj * kFL + i] = F[c];
         }
     }
     __syncthreads();
@@ -760,7 +767,7 @@ void stage2d_kernel(Stage2dArgs A)
         double Lc[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            const double d = s_f[c][(cj + 1) * kFX + ci] - s_f[c][cj * kFX + ci];
+            const double d = s_f[c][(cj + 1) * kFL + ci] - s_f[c][cj * kFL + ci];
             const double Dy = flux_quotient<FAST>(d, A.dx[1], A.rdx[1]);
             Lc[c] = -(Dx[c] + Dy);
         }

@@ -1,5 +1,5 @@
 """The fused 2D stage kernel (x tile variant 2: both directions of a stage in one launch
-on 16 x 30 tiles with 3-point halos, the x divergence kept on chip) against the oracle
+on 31 x 15 tiles with 3-point halos, the x divergence kept on chip) against the oracle
 and the two-sweep path: it runs the sweeps' interface routine on the same values in the
 same order, so RHS and steps are bit-identical to the oracle in FP64 (and to the sweeps'
 to rounding in the fast FP64 and FP32-weight modes), on grids that are not multiples of
@@ -39,7 +39,8 @@ def _cases():
             W.quadrants_2d(c2.extra["states"], 37, ny=45, name="q2d_37x45"),
             W.quadrants_2d(q, 300, ny=262, name="q2d_300x262"),
             W.quadrants_2d(q, 10, ny=7, name="q2d_10x7"),          # smaller than one tile
-            W.quadrants_2d(q, 16, ny=30, name="q2d_16x30"),        # exactly one tile
+            W.quadrants_2d(q, 31, ny=15, name="q2d_31x15"),        # exactly one tile
+            W.quadrants_2d(q, 62, ny=31, name="q2d_62x31"),        # two tiles and a row
             W.euler2d_smooth_periodic(3, 64),
             W.rayleigh_taylor(40, 120),                             # walls in y, gravity
             W.implosion(48)]                                        # walls all round

@@ -21,6 +21,9 @@ enum ProbeOp : int {
     kSqrt = 3,           // out = sqrt(a)                    (a: n values)
     kWeno = 4,           // FP64 WENO-theta, eps c0, alpha_R c1, RN(1/eps) c2 (a: 6 n values)
     kWenoFp32 = 5,       // FP32 reconstruction, eps c0, alpha_R c1 (a: 6 n values)
+    kRcpFast = 6,        // out = 1 / b, the fast modes' reciprocal (b: n values)
+    kRcpEstimate = 7,    // out = the hardware reciprocal estimate of b (b: n values)
+    kWenoFast = 8,       // fast FP64 WENO-theta, eps c0, alpha_R c1 (a: 6 n values)
 };
 
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(int op, const double *a,
@@ -41,6 +44,13 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(int op, const doub
         break;
     }
     case kWenoFp32: out[i] = wt::weno_theta_fp32_recon(a + 6 * i, c0, (float)c1); break;
+    case kRcpFast: out[i] = wt::rcp_fast(b[i]); break;
+    case kRcpEstimate: out[i] = __builtin_amdgcn_rcp(b[i]); break;
+    case kWenoFast: {
+        const double *s = a + 6 * i;
+        out[i] = wt::weno_theta_fast(s[0], s[1], s[2], s[3], s[4], s[5], c0, c1);
+        break;
+    }
     default: break;
     }
 }
@@ -48,14 +58,16 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(int op, const doub
 }  // namespace
 
 // Applies probe `op` to n elements on `stream` (device pointers; a holds 6 n
-// values for the WENO probes, n otherwise; b is read by kDiv and kRecip only).
+// values for the WENO probes, n otherwise; b is read by kDiv and the reciprocals,
+// which do not read a).
 // Returns 0, 1 for bad arguments, 5 if the launch failed.  Asynchronous.
 extern "C" int wt_probe(int op, const double *a, const double *b, double c0, double c1, double c2,
                         double *out, int64_t n, void *stream)
 {
-    if (op < kDiv || op > kWenoFp32 || n < 0 || !out) return 1;
-    if ((op == kDiv || op == kRecip) && !b) return 1;
-    if (op != kRecip && !a) return 1;
+    if (op < kDiv || op > kWenoFast || n < 0 || !out) return 1;
+    const bool reads_b = op == kDiv || op == kRecip || op == kRcpFast || op == kRcpEstimate;
+    if (reads_b && !b) return 1;
+    if (op != kRecip && op != kRcpFast && op != kRcpEstimate && !a) return 1;
     if (n == 0) return 0;
     const int64_t blocks = (n + kProbeThreads - 1) / kProbeThreads;
     if (blocks > 0x7fffffff) return 1;

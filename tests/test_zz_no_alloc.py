@@ -82,6 +82,26 @@ def test_noalloc_equals_rhs_on_two_calls(ctx, name, first, second):
     assert np.array_equal(got, oracle.rhs(P, second.u)), f"{name}: differs from the oracle"
 
 
+@pytest.mark.parametrize("precision", [wt.WT_FP64_FAST, wt.WT_FP32_RECON], ids=["fast", "fp32"])
+def test_noalloc_equals_rhs_in_the_other_precision_modes(ctx, precision):
+    """The fast FP64 and FP32-weight forms through the allocation-free entry point equal
+    wenotheta_rhs in the same mode bit for bit, two calls in a row (2D, then 3D smaller)."""
+    import torch
+    for case in (_quadrants(300, ny=260, seed=1), W.euler3d_seeded(6, 18)):
+        g, p = grid_params(case)
+        p.precision = precision
+        ud = to_dev(case.u)
+        L1 = torch.empty_like(ud)
+        wt.wenotheta_rhs(ctx, g, p, ud, L1)
+        wt.wenotheta_sync(ctx)
+        L2 = torch.full_like(ud, float("nan"))
+        st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        wt.wenotheta_rhs_noalloc(g, p, ud, L2, status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == wt.binding.WT_OK
+        assert torch.equal(L1, L2), case.u.shape
+
+
 def test_noalloc_caller_speeds_and_flux_values(ctx):
     """The scalar law with caller-evaluated flux values and speed (the paper's problem
     statement), as wenotheta_rhs takes them."""

@@ -69,8 +69,8 @@ __device__ __forceinline__ void block_max(double (&v)[K], double (*red)[NW])
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double w = wave_max(v[k]);
-        if (lane == 0) red[k][wid] = w;
+        const double w = wave_max_to_lane63(v[k]);
+        if (lane == 63) red[k][wid] = w;
     }
     __syncthreads();
 #pragma unroll
@@ -224,8 +224,8 @@ void batched_kernel(BatchArgs A)
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        const double w = wave_max(lam[k]);
-                        if ((t & 63) == 0) s_red[k][t >> 6] = w > s_red[k][t >> 6] ? w : s_red[k][t >> 6];
+                        const double w = wave_max_to_lane63(lam[k]);
+                        if ((t & 63) == 63) s_red[k][t >> 6] = w > s_red[k][t >> 6] ? w : s_red[k][t >> 6];
                     }
                     __syncthreads();                // the tile is reused by the next segment
                 }
@@ -512,8 +512,8 @@ void batched2d_kernel(Batch2Args A)
                     }
 #pragma unroll
                     for (int k = 0; k < 6; ++k) {
-                        const double w = wave_max(lam[k]);
-                        if ((t & 63) == 0) s_red[k][t >> 6] = w > s_red[k][t >> 6] ? w : s_red[k][t >> 6];
+                        const double w = wave_max_to_lane63(lam[k]);
+                        if ((t & 63) == 63) s_red[k][t >> 6] = w > s_red[k][t >> 6] ? w : s_red[k][t >> 6];
                     }
                     __syncthreads();                // the tile is reused by the next one
                 }

@@ -46,13 +46,35 @@ __device__ __forceinline__ unsigned long long double_to_bits(double d)
     return static_cast<unsigned long long>(__double_as_longlong(d));
 }
 
-// Maximum over the wave of non-negative speeds (the hardware max: one
-// instruction per step; a NaN speed, which the caller reports as an error
-// anyway, is dropped instead of taken).
-__device__ __forceinline__ double wave_max(double v)
+// One step of a wave reduction by data-parallel primitives: each lane of the rows in
+// ROW_MASK takes the maximum of its value and the value DPP control CTRL moves to it
+// (both 32-bit halves moved alike; lanes without a source keep their own value).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_max_step(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = __builtin_fmax(v, __shfl_xor(v, off, 64));
+    const unsigned long long b = double_to_bits(v);
+    const int lo = (int)(unsigned)(b & 0xffffffffull), hi = (int)(unsigned)(b >> 32);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    const double o = bits_to_double(((unsigned long long)(unsigned)hi2 << 32) | (unsigned)lo2);
+    return __builtin_fmax(v, o);
+}
+
+// Maximum over the wave of non-negative speeds, left in lane 63 (the other lanes hold
+// partial maxima): within quads, half rows and rows by permutations, then row 0's
+// maximum into row 1 and row 2's into row 3 (row_bcast:15), then rows 0-1 into rows
+// 2-3 (row_bcast:31).  Six VALU steps and no LDS round trips (a butterfly of lane
+// shuffles takes six through the LDS crossbar); the hardware max returns one of the
+// values, so any order gives the same bits, and a NaN speed, which the caller reports
+// as an error anyway, is dropped instead of taken.
+__device__ __forceinline__ double wave_max_to_lane63(double v)
+{
+    v = dpp_max_step<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x141, 0xf>(v);    // row_half_mirror
+    v = dpp_max_step<0x140, 0xf>(v);    // row_mirror
+    v = dpp_max_step<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -77,8 +99,8 @@ __device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long lo
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        const double w = wave_max(v[k]);
-        if (lane == 0) red[k][wid] = w;
+        const double w = wave_max_to_lane63(v[k]);
+        if (lane == 63) red[k][wid] = w;
     }
     __syncthreads();
     if (threadIdx.x < NS) {

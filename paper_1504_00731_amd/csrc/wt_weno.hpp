@@ -140,7 +140,9 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3, double s4, d
 // without correctly rounded quotients:
 //   * where the restriction holds every beta~_k is zero, so the four alpha_k
 //     share the factor 1 + tau / eps and the weights are exactly gamma^theta:
-//     h = sum gamma_k q_k, no quotient at all;
+//     h = sum gamma_k q_k, no quotient at all, which is the 5th-order upwind
+//     (theta = 1) or 6th-order central (theta = 0) linear reconstruction, formed
+//     from differences the indicators need anyway (fast_linear);
 //   * elsewhere alpha_k = gamma_k + gamma_k tau / (eps + beta~_k) from fast
 //     reciprocals (hardware estimate and two Newton steps), and
 //     h = (sum alpha_k q_k) / (sum alpha_k) by one more.
@@ -155,41 +157,70 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3, double s4, d
 // symmetry of symmetric flows; with a fixed form h(-v) = -h(v) bit for bit.
 // ---------------------------------------------------------------------------
 
-// Candidate fluxes, smoothness indicators and the two theta indicators of a
-// stencil, by fused multiply-adds.
+// Smoothness indicators and the two theta indicators of a stencil, by fused
+// multiply-adds, with the differences they are built from that the linear
+// reconstruction reuses.
 struct FastStencil {
-    double q0, q1, q2, q3;     // candidate fluxes
     double b0, b1, b2, b3;     // beta~_k
     double tau5, tau6;
+    double d0, d1, d2;         // second differences s_k - 2 s_{k+1} + s_{k+2}, k = 0, 1, 2
+    double d5;                 // fifth difference -s0 + 5 s1 - 10 s2 + 10 s3 - 5 s4 + s5
 };
 
 WT_HD FastStencil fast_stencil(double s0, double s1, double s2, double s3, double s4, double s5)
 {
     FastStencil F;
-    F.q0 = __builtin_fma(11.0 / 6.0, s2, __builtin_fma(-7.0 / 6.0, s1, (2.0 / 6.0) * s0));
-    F.q1 = __builtin_fma(2.0 / 6.0, s3, __builtin_fma(5.0 / 6.0, s2, (-1.0 / 6.0) * s1));
-    F.q2 = __builtin_fma(-1.0 / 6.0, s4, __builtin_fma(5.0 / 6.0, s3, (2.0 / 6.0) * s2));
-    F.q3 = __builtin_fma(2.0 / 6.0, s5, __builtin_fma(-7.0 / 6.0, s4, (11.0 / 6.0) * s3));
     double t1, t2;
-    t1 = __builtin_fma(-2.0, s1, s0 + s2);
+    F.d0 = __builtin_fma(-2.0, s1, s0 + s2);
     t2 = __builtin_fma(2.0, s2, __builtin_fma(-3.0, s1, s0));
-    F.b0 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
-    t1 = __builtin_fma(-2.0, s2, s1 + s3);
+    F.b0 = __builtin_fma((13.0 / 12.0) * F.d0, F.d0, t2 * t2);
+    F.d1 = __builtin_fma(-2.0, s2, s1 + s3);
     t2 = s3 - s2;
-    F.b1 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
-    t1 = __builtin_fma(-2.0, s3, s2 + s4);
+    F.b1 = __builtin_fma((13.0 / 12.0) * F.d1, F.d1, t2 * t2);
+    F.d2 = __builtin_fma(-2.0, s3, s2 + s4);
     t2 = s2 - s3;
-    F.b2 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
+    F.b2 = __builtin_fma((13.0 / 12.0) * F.d2, F.d2, t2 * t2);
     t1 = __builtin_fma(3.0, s2, __builtin_fma(-7.0, s3, __builtin_fma(5.0, s4, -s5)));
     t2 = __builtin_fma(2.0, s3, __builtin_fma(-3.0, s4, s5));
     F.b3 = __builtin_fma((13.0 / 48.0) * t1, t1, t2 * t2);
     t1 = __builtin_fma(6.0, s2, __builtin_fma(-4.0, s1 + s3, s0 + s4));
     t2 = __builtin_fma(3.0, s2 - s3, s4 - s1);
     F.tau5 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
-    t1 = __builtin_fma(10.0, s3 - s2, __builtin_fma(5.0, s1 - s4, s5 - s0));
+    F.d5 = __builtin_fma(10.0, s3 - s2, __builtin_fma(5.0, s1 - s4, s5 - s0));
     t2 = __builtin_fma(2.0, s2 + s3, __builtin_fma(-3.0, s1 + s4, s0 + s5));
-    F.tau6 = __builtin_fma((13.0 / 12.0) * t1, t1, (0.25 * t2) * t2);
+    F.tau6 = __builtin_fma((13.0 / 12.0) * F.d5, F.d5, (0.25 * t2) * t2);
     return F;
+}
+
+// The reconstruction with the linear weights gamma^theta (the restriction in
+// force).  Summed over the candidates, the weights give the 5th-order upwind form
+// (theta = 1)  (2 s0 - 13 s1 + 47 s2 + 27 s3 - 3 s4) / 60,  which equals
+// (s2 + s3) / 2 + (2 d0 - 9 d1 - 3 d2) / 60, and the 6th-order central form
+// (theta = 0)  (s0 - 8 s1 + 37 s2 + 37 s3 - 8 s4 + s5) / 60,  which is the upwind
+// one plus d5 / 60.  The differences come from the indicators, so this costs a
+// few operations beside them, and a constant stencil gives back its value exactly
+// (every difference is zero).
+WT_HD double fast_linear(const FastStencil &F, double s2, double s3, bool central)
+{
+    const double corr = __builtin_fma(-3.0, F.d2, __builtin_fma(-9.0, F.d1, 2.0 * F.d0));
+    const double up = __builtin_fma(1.0 / 60.0, corr, 0.5 * (s2 + s3));
+    const double ce = __builtin_fma(1.0 / 60.0, F.d5, up);
+    return central ? ce : up;
+}
+
+// The candidate fluxes q_0 .. q_3 of the four 3-point sub-stencils.
+struct FastCandidates {
+    double q0, q1, q2, q3;
+};
+
+WT_HD FastCandidates fast_candidates(double s0, double s1, double s2, double s3, double s4, double s5)
+{
+    FastCandidates Q;
+    Q.q0 = __builtin_fma(11.0 / 6.0, s2, __builtin_fma(-7.0 / 6.0, s1, (2.0 / 6.0) * s0));
+    Q.q1 = __builtin_fma(2.0 / 6.0, s3, __builtin_fma(5.0 / 6.0, s2, (-1.0 / 6.0) * s1));
+    Q.q2 = __builtin_fma(-1.0 / 6.0, s4, __builtin_fma(5.0 / 6.0, s3, (2.0 / 6.0) * s2));
+    Q.q3 = __builtin_fma(2.0 / 6.0, s5, __builtin_fma(-7.0 / 6.0, s4, (11.0 / 6.0) * s3));
+    return Q;
 }
 
 WT_HD double weno_theta_fast(double s0, double s1, double s2, double s3, double s4, double s5,
@@ -200,18 +231,18 @@ WT_HD double weno_theta_fast(double s0, double s1, double s2, double s3, double 
     const double bmin = __builtin_fmin(__builtin_fmin(F.b0, F.b1), __builtin_fmin(F.b2, F.b3));
     const bool restricted = bmax <= alpha_R * (eps + bmin);
     const bool central = F.tau6 < F.tau5;
+    if (restricted) return fast_linear(F, s2, s3, central);
+    const FastCandidates Q = fast_candidates(s0, s1, s2, s3, s4, s5);
     const double g0 = central ? GammaTheta::g0_t0 : GammaTheta::g0_t1;
     const double g1 = central ? GammaTheta::g1_t0 : GammaTheta::g1_t1;
     const double g2 = central ? GammaTheta::g2_t0 : GammaTheta::g2_t1;
     const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
-    if (restricted)
-        return __builtin_fma(g3, F.q3, __builtin_fma(g2, F.q2, __builtin_fma(g1, F.q1, g0 * F.q0)));
     const double tau = central ? F.tau6 : F.tau5;
     const double a0 = __builtin_fma(g0 * tau, rcp_fast(eps + F.b0), g0);
     const double a1 = __builtin_fma(g1 * tau, rcp_fast(eps + F.b1), g1);
     const double a2 = __builtin_fma(g2 * tau, rcp_fast(eps + F.b2), g2);
     const double a3 = __builtin_fma(g3 * tau, rcp_fast(eps + F.b3), g3);
-    const double num = __builtin_fma(a3, F.q3, __builtin_fma(a2, F.q2, __builtin_fma(a1, F.q1, a0 * F.q0)));
+    const double num = __builtin_fma(a3, Q.q3, __builtin_fma(a2, Q.q2, __builtin_fma(a1, Q.q1, a0 * Q.q0)));
     return num * rcp_fast(a0 + a1 + a2 + a3);
 }
 
@@ -251,12 +282,12 @@ WT_HD double weno_theta_fp32_recon(const double *v, double eps, float alpha_R)
     const double bmin = __builtin_fmin(__builtin_fmin(F.b0, F.b1), __builtin_fmin(F.b2, F.b3));
     const bool restricted = bmax <= (double)alpha_R * (eps + bmin);
     const bool central = F.tau6 < F.tau5;
+    if (restricted) return fast_linear(F, v[2], v[3], central);
+    const FastCandidates Q = fast_candidates(v[0], v[1], v[2], v[3], v[4], v[5]);
     const double g0 = central ? GammaTheta::g0_t0 : GammaTheta::g0_t1;
     const double g1 = central ? GammaTheta::g1_t0 : GammaTheta::g1_t1;
     const double g2 = central ? GammaTheta::g2_t0 : GammaTheta::g2_t1;
     const double g3 = central ? GammaTheta::g3_t0 : GammaTheta::g3_t1;
-    if (restricted)
-        return __builtin_fma(g3, F.q3, __builtin_fma(g2, F.q2, __builtin_fma(g1, F.q1, g0 * F.q0)));
     // the weights in FP32 (tau is at most about 1e30 for flux values up to 1e14)
     const float tau = (float)__builtin_fmin(central ? F.tau6 : F.tau5, 0x1p+100);
     const float a0 = __builtin_fmaf((float)g0 * tau, rcp_f32((float)__builtin_fmin(eps + F.b0, 0x1p+100)), (float)g0);
@@ -264,7 +295,7 @@ WT_HD double weno_theta_fp32_recon(const double *v, double eps, float alpha_R)
     const float a2 = __builtin_fmaf((float)g2 * tau, rcp_f32((float)__builtin_fmin(eps + F.b2, 0x1p+100)), (float)g2);
     const float a3 = __builtin_fmaf((float)g3 * tau, rcp_f32((float)__builtin_fmin(eps + F.b3, 0x1p+100)), (float)g3);
     const double w0 = a0, w1 = a1, w2 = a2, w3 = a3;
-    const double num = __builtin_fma(w3, F.q3, __builtin_fma(w2, F.q2, __builtin_fma(w1, F.q1, w0 * F.q0)));
+    const double num = __builtin_fma(w3, Q.q3, __builtin_fma(w2, Q.q2, __builtin_fma(w1, Q.q1, w0 * Q.q0)));
     return num * rcp_fast(w0 + w1 + w2 + w3);
 }
 

@@ -46,35 +46,52 @@ __device__ __forceinline__ unsigned long long double_to_bits(double d)
     return static_cast<unsigned long long>(__double_as_longlong(d));
 }
 
-// One step of a wave reduction by data-parallel primitives: each lane of the rows in
-// ROW_MASK takes the maximum of its value and the value DPP control CTRL moves to it
-// (both 32-bit halves moved alike; lanes without a source keep their own value).
-template <int CTRL, int ROW_MASK>
+// The hardware maximum of two doubles.  The compiler's maxnum would first quiet the
+// operand that comes out of a lane move (it cannot know it to be an arithmetic
+// result), one more instruction per step; in IEEE mode v_max_f64 already returns
+// the other operand for a quiet NaN.  The two wait states after it cover a DPP move
+// that reads the result next (a dependency the compiler does not track through an
+// asm statement).
+__device__ __forceinline__ double hw_max(double a, double b)
+{
+    double r;
+    __asm__("v_max_f64 %0, %1, %2\n\ts_nop 1" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// One step of a wave reduction of non-negative values by data-parallel primitives:
+// every lane takes the maximum of its value and the value DPP control CTRL moves to
+// it (both 32-bit halves moved alike).  Every row is written and a lane without a
+// source lane reads zero (bound_ctrl), which leaves its maximum unchanged, so the
+// move keeps no old value: no copy of the operand before it.
+template <int CTRL>
 __device__ __forceinline__ double dpp_max_step(double v)
 {
     const unsigned long long b = double_to_bits(v);
     const int lo = (int)(unsigned)(b & 0xffffffffull), hi = (int)(unsigned)(b >> 32);
-    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
-    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    const int lo2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, true);
+    const int hi2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, true);
     const double o = bits_to_double(((unsigned long long)(unsigned)hi2 << 32) | (unsigned)lo2);
-    return __builtin_fmax(v, o);
+    return hw_max(v, o);
 }
 
-// Maximum over the wave of non-negative speeds, left in lane 63 (the other lanes hold
-// partial maxima): within quads, half rows and rows by permutations, then row 0's
-// maximum into row 1 and row 2's into row 3 (row_bcast:15), then rows 0-1 into rows
-// 2-3 (row_bcast:31).  Six VALU steps and no LDS round trips (a butterfly of lane
-// shuffles takes six through the LDS crossbar); the hardware max returns one of the
-// values, so any order gives the same bits, and a NaN speed, which the caller reports
-// as an error anyway, is dropped instead of taken.
+// Maximum over the wave of non-negative speeds, left in lane 63 (other lanes hold
+// partial maxima or values of no use): within quads, half rows and rows by
+// permutations, then row 0's maximum into row 1 and row 2's into row 3
+// (row_bcast:15), then lane 31's, the maximum of rows 0-1, into rows 2-3
+// (row_bcast:31).  Lane 63 only ever combines values of the wave (or zero), whatever
+// the broadcasts leave in rows 0-2.  Six VALU steps and no LDS round trips (a
+// butterfly of lane shuffles takes six through the LDS crossbar); the hardware max
+// returns one of the values, so any order gives the same bits, and a NaN speed,
+// which the caller reports as an error anyway, is dropped instead of taken.
 __device__ __forceinline__ double wave_max_to_lane63(double v)
 {
-    v = dpp_max_step<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
-    v = dpp_max_step<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
-    v = dpp_max_step<0x141, 0xf>(v);    // row_half_mirror
-    v = dpp_max_step<0x140, 0xf>(v);    // row_mirror
-    v = dpp_max_step<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
-    v = dpp_max_step<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    v = dpp_max_step<0xb1>(v);      // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4e>(v);      // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x141>(v);     // row_half_mirror
+    v = dpp_max_step<0x140>(v);     // row_mirror
+    v = dpp_max_step<0x142>(v);     // row_bcast:15
+    v = dpp_max_step<0x143>(v);     // row_bcast:31
     return v;
 }
 

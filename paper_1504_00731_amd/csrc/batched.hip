@@ -93,10 +93,6 @@ __device__ __forceinline__ double uniform(double x)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-struct LdsSpeeds {
-    const double *a;
-    __device__ double operator()(int s) const { return a[s]; }
-};
 
 // The FP64 form is held to 3 waves per SIMD (at most 168 VGPRs): left to
 // itself it takes 174, and it fits 164 without spilling.  The FP32 form
@@ -211,12 +207,14 @@ void batched_kernel(BatchArgs A)
                     double lam[3] = {0.0, 0.0, 0.0};
                     if (t < TN && g0 + t < n) {
                         const int64_t idx = off + g0 + t;
+                        double u0v[3];
+                        stage_u0<3>(stage, A.u, total, idx, u0v);
                         double un[3];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             const double L = -flux_quotient<FAST>(s_F[c][t + 1] - s_F[c][t], dx, rdx);
                             const int64_t o = c * total + idx;
-                            un[c] = rk3_stage<FAST>(stage, uin[o], L, dt, [&] { return A.u[o]; });
+                            un[c] = rk3_stage<FAST>(stage, uin[o], L, dt, u0v[c]);
                         }
 #pragma unroll
                         for (int c = 0; c < 3; ++c) out[c * total + idx] = un[c];
@@ -497,13 +495,15 @@ void batched2d_kernel(Batch2Args A)
                         const int64_t g = g0 + it, l = l0 + cl;
                         if (l < P.nx && g < P.ny) {
                             const int64_t idx = P.off + g * P.nx + l;
+                            double u0v[M];
+                            stage_u0<M>(stage, A.u, total, idx, u0v);
                             double un[M];
 #pragma unroll
                             for (int c = 0; c < M; ++c) {
                                 const int64_t o = c * total + idx;
                                 const double Dd = flux_quotient<FAST>(s_F[c][t + YTX] - s_F[c][t], P.dy, P.rdy);
                                 const double L = -(A.D[o] + Dd);
-                                un[c] = rk3_stage<FAST>(stage, uin[o], L, dt, [&] { return A.u[o]; });
+                                un[c] = rk3_stage<FAST>(stage, uin[o], L, dt, u0v[c]);
                             }
 #pragma unroll
                             for (int c = 0; c < M; ++c) out[c * total + idx] = un[c];
@@ -734,13 +734,15 @@ void flat2_pass_kernel(Flat2Args A)
         if (t < TN * TX && l < P.nx && g < P.ny) {
             const int64_t idx = P.off + g * P.nx + l;
             const double dt = A.dt[b];
+            double u0v[M];
+            stage_u0<M>(A.stage, A.u0, A.total, idx, u0v);
             double un[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 const int64_t o = c * A.total + idx;
                 const double Dd = flux_quotient<FAST>(s_F[c][t + TX] - s_F[c][t], P.dy, P.rdy);
                 const double L = -(A.D[o] + Dd);
-                un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, [&] { return A.u0[o]; });
+                un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, u0v[c]);
             }
 #pragma unroll
             for (int c = 0; c < M; ++c) A.out[c * A.total + idx] = un[c];
@@ -883,13 +885,15 @@ void flat2_packed_kernel(Flat2Args A)
         if (cell) {
             const int64_t idx = P.off + (int64_t)i * P.nx + (int64_t)line * TX + lane;
             const double dt = A.dt[b];
+            double u0v[M];
+            stage_u0<M>(A.stage, A.u0, A.total, idx, u0v);
             double un[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 const int64_t o = c * A.total + idx;
                 const double Dd = flux_quotient<FAST>(s_F[c][t + TX] - s_F[c][t], P.dy, P.rdy);
                 const double L = -(A.D[o] + Dd);
-                un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, [&] { return A.u0[o]; });
+                un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, u0v[c]);
             }
 #pragma unroll
             for (int c = 0; c < M; ++c) A.out[c * A.total + idx] = un[c];
@@ -1071,12 +1075,14 @@ void flat1_pass_kernel(Flat1Args A)
     if (t < TN && g0 + t < n) {
         const int64_t idx = off + g0 + t;
         const double dt = A.dt[b], dx = A.dx[b], rdx = A.rdx[b];
+        double u0v[3];
+        stage_u0<3>(A.stage, A.u0, A.total, idx, u0v);
         double un[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double L = -flux_quotient<FAST>(s_F[c][t + 1] - s_F[c][t], dx, rdx);
             const int64_t o = c * A.total + idx;
-            un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, [&] { return A.u0[o]; });
+            un[c] = rk3_stage<FAST>(A.stage, A.uin[o], L, dt, u0v[c]);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) A.out[c * A.total + idx] = un[c];

@@ -299,6 +299,7 @@ void sweep_kernel(SweepArgs A)
     if constexpr (ALIAS_F) s_F = reinterpret_cast<double (*)[kThreads]>(&s_f[0][0]);
     else s_F = reinterpret_cast<double (*)[kThreads]>(&s_Fown[0][0]);
     __shared__ double s_h[SPLIT ? M : 1][SPLIT ? TN + 1 : 1];   // h_s per field and interface
+    __shared__ double s_al[EULER ? M : 1];       // Lax-Friedrichs speed per field
 
     DevState *st = A.st;
     if (A.check_done && st->done) return;
@@ -353,7 +354,11 @@ void sweep_kernel(SweepArgs A)
     const int64_t g0 = seg * TN;                 // first owned point along the sweep
     const int64_t ncell = A.ncell;
 
-    // ---- stage the tile (owned points + 3-point halos) ----
+    // ---- stage the tile (owned points + 3-point halos) and the fields' speeds ----
+    if constexpr (EULER) {
+        if (threadIdx.x < M)
+            s_al[threadIdx.x] = SlotSpeeds{st->alpha[A.slot_rd], DIR, A.walls != 0}(threadIdx.x);
+    }
     int err = 0;
     for (int i = threadIdx.x; i < NC; i += kThreads) {
         // point r along the sweep of lane cx, kept in LDS at r * TX + cx; x-tiles of
@@ -431,7 +436,7 @@ void sweep_kernel(SweepArgs A)
         RoeBasis<NDIM> B{};
         if (valid) {
             B = interface_basis<NDIM, DIR, FAST>(S, A.gamma);
-            const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.walls != 0};
+            const LdsSpeeds al{s_al};
             s_h[f][it] = euler_field_flux<NDIM, DIR, PREC, fresh_rows<NDIM, PREC>()>(S, B, f, al, A.W);
             if (f == 0 && !B.ok) atomicOr(&st->err, kErrNonphysical);
         }
@@ -459,7 +464,7 @@ void sweep_kernel(SweepArgs A)
         if (valid) {
             if constexpr (EULER) {
                 const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
-                const SlotSpeeds al{st->alpha[A.slot_rd], DIR, A.walls != 0};
+                const LdsSpeeds al{s_al};
                 if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.W, F))
                     atomicOr(&st->err, kErrNonphysical);
             } else {
@@ -486,6 +491,8 @@ void sweep_kernel(SweepArgs A)
         const int64_t g = g0 + it;
         if ((DIR == 0 ? row0 + cx < nrows : x0 + cx < nx) && g < nd) {
             const int64_t idx = base + g * sstride + (DIR == 0 ? cx * nx : cx);
+            double u0v[M];
+            if constexpr (MODE == MODE_LAST_STAGE) stage_u0<M>(A.stage, A.u0, ncell, idx, u0v);
             double Lc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
@@ -524,8 +531,7 @@ void sweep_kernel(SweepArgs A)
                 double un[M];
 #pragma unroll
                 for (int c = 0; c < M; ++c)
-                    un[c] = rk3_stage<FAST>(A.stage, s_u[c][t + 3 * TX], Lc[c], dt,
-                                            [&] { return A.u0[c * ncell + idx]; });
+                    un[c] = rk3_stage<FAST>(A.stage, s_u[c][t + 3 * TX], Lc[c], dt, u0v[c]);
 #pragma unroll
                 for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = un[c];
                 // Lax-Friedrichs speeds of the new state
@@ -638,6 +644,7 @@ void stage2d_kernel(Stage2dArgs A)
     __shared__ double s_sr[kFNP];
     __shared__ double s_H[kFNP];
     __shared__ double s_f[M][kFBuf];             // normal fluxes, then interface fluxes
+    __shared__ double s_al[2][M];                // Lax-Friedrichs speed per direction and field
 
     DevState *st = A.st;
     if (A.check_done && st->done) return;
@@ -651,7 +658,12 @@ void stage2d_kernel(Stage2dArgs A)
     const int nyt = (int)(ny - y0 < kFY ? ny - y0 : kFY);
     const int t = threadIdx.x;
 
-    // ---- stage the tile and its halos; ghost points through each direction's map
+    // ---- stage the tile and its halos (ghost points through each direction's map)
+    // and the fields' speeds
+    if (t < 2 * M) {
+        const int d = t / M;
+        s_al[d][t - d * M] = SlotSpeeds{st->alpha[A.slot_rd], d, A.walls[d] != 0}(t - d * M);
+    }
     int err = 0;
     for (int i = t; i < kFNP; i += kFThreads) {
         const int iy = i / kFW, ix = i - iy * kFW;
@@ -700,7 +712,7 @@ void stage2d_kernel(Stage2dArgs A)
         const bool valid = j < kFY && fi <= nxt && j < nyt;
         if (valid) {
             const TileStencil<1, 1> S{s_u, s_f, s_v, s_sr, s_H, (j + 3) * kFW + fi, j * kFW + fi};
-            const SlotSpeeds al{st->alpha[A.slot_rd], 0, A.walls[0] != 0};
+            const LdsSpeeds al{s_al[0]};
             if (!euler_interface_flux<2, 0, PREC, true>(S, al, A.gamma, A.W, F))
                 atomicOr(&st->err, kErrNonphysical);
         }
@@ -744,7 +756,7 @@ void stage2d_kernel(Stage2dArgs A)
         const bool valid = fj <= kFY && i < kFX && i < nxt && fj <= nyt;
         if (valid) {
             const TileStencil<kFW, kFL> S{s_u, s_f, s_v, s_sr, s_H, fj * kFW + i + 3, fj * kFL + i};
-            const SlotSpeeds al{st->alpha[A.slot_rd], 1, A.walls[1] != 0};
+            const LdsSpeeds al{s_al[1]};
             if (!euler_interface_flux<2, 1, PREC, true>(S, al, A.gamma, A.W, F))
                 atomicOr(&st->err, kErrNonphysical);
         }
@@ -764,6 +776,8 @@ void stage2d_kernel(Stage2dArgs A)
     if (own) {
         const int64_t idx = (y0 + cj) * nx + x0 + ci;
         const int li = (cj + 3) * kFW + ci + 3;
+        double u0v[M];
+        if constexpr (MODE == MODE_LAST_STAGE) stage_u0<M>(A.stage, A.u0, ncell, idx, u0v);
         double Lc[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
@@ -791,8 +805,7 @@ void stage2d_kernel(Stage2dArgs A)
             double un[M];
 #pragma unroll
             for (int c = 0; c < M; ++c)
-                un[c] = rk3_stage<FAST>(A.stage, s_u[c][li], Lc[c], dt,
-                                        [&] { return A.u0[c * ncell + idx]; });
+                un[c] = rk3_stage<FAST>(A.stage, s_u[c][li], Lc[c], dt, u0v[c]);
 #pragma unroll
             for (int c = 0; c < M; ++c) A.out[c * ncell + idx] = un[c];
             double lam[6];

@@ -163,22 +163,37 @@ WT_HD double flux_quotient(double dF, double dx, double rdx)
 
 // One component of a TVD Runge-Kutta stage (Sec. 2.1): stage 1 u + dt L, stage 2
 // 3/4 u^n + 1/4 u^(1) + dt/4 L, stage 3 1/3 u^n + 2/3 u^(2) + 2 dt/3 L, from the
-// stage's input uin and u^n (u0(), read for stages 2 and 3 only).  The fast forms
-// use fused multiply-adds in one fixed form for every component (the symmetries
-// of a flow exchange components).
-template <bool FAST, class U0>
-WT_HD double rk3_stage(int stage, double uin, double L, double dt, const U0 &u0)
+// stage's input uin and u^n (u0, unused in stage 1).  The fast forms use fused
+// multiply-adds in one fixed form for every component (the symmetries of a flow
+// exchange components).
+template <bool FAST>
+WT_HD double rk3_stage(int stage, double uin, double L, double dt, double u0)
 {
     if constexpr (FAST) {
         const double c1 = stage == 1 ? 1.0 : (stage == 2 ? 0.25 : 2.0 / 3.0);
         const double cdt = (stage == 1 ? 1.0 : (stage == 2 ? 0.25 : 2.0 / 3.0)) * dt;
         const double base = __builtin_fma(cdt, L, c1 * uin);
         if (stage == 1) return base;
-        return __builtin_fma(stage == 2 ? 0.75 : 1.0 / 3.0, u0(), base);
+        return __builtin_fma(stage == 2 ? 0.75 : 1.0 / 3.0, u0, base);
     } else {
         if (stage == 1) return uin + dt * L;
-        if (stage == 2) return 0.75 * u0() + 0.25 * uin + (0.25 * dt) * L;
-        return (1.0 / 3.0) * u0() + (2.0 / 3.0) * uin + ((2.0 / 3.0) * dt) * L;
+        if (stage == 2) return 0.75 * u0 + 0.25 * uin + (0.25 * dt) * L;
+        return (1.0 / 3.0) * u0 + (2.0 / 3.0) * uin + ((2.0 / 3.0) * dt) * L;
+    }
+}
+
+// u^n of one cell for a Runge-Kutta stage (components `stride` apart), every
+// component read under one branch, so the loads are in flight together instead of
+// each waiting in turn; stage 1 reads nothing.
+template <int M>
+WT_HD void stage_u0(int stage, const double *u0, int64_t stride, int64_t idx, double (&v)[M])
+{
+    if (stage != 1) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) v[c] = u0[c * stride + idx];
+    } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) v[c] = 0.0;
     }
 }
 
@@ -226,6 +241,14 @@ struct SlotSpeeds {
     {
         return split_speed([this](int k) { return raw(k); }, s, walls);
     }
+};
+
+// Lax-Friedrichs speeds of one direction's fields staged in LDS (a[s] for field s):
+// every lane reads the same word, a broadcast, instead of each field of each
+// interface waiting on a device-memory read.
+struct LdsSpeeds {
+    const double *a;
+    __device__ double operator()(int s) const { return a[s]; }
 };
 
 template <int NC, int TX>

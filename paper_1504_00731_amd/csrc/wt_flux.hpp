@@ -90,7 +90,8 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
     double ln0, ln1, lE, lt[NT > 0 ? NT : 1];
     int shear = -1;
     if (s < 3) {
-        left_row<NDIM, FRESH>(B, s, ln0, ln1, lt, lE);
+        if constexpr (fast_math<PREC>()) left_row_half<NDIM, FRESH>(B, s, ln0, ln1, lt, lE);
+        else left_row<NDIM, FRESH>(B, s, ln0, ln1, lt, lE);
     } else {
         shear = s - 3;
         ln0 = -(shear == 0 ? B.ut[0] : B.ut[NT > 1 ? 1 : 0]); ln1 = 0.0; lE = 0.0;
@@ -104,13 +105,13 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
         // interface (its acoustic fields exchanged, the normal components negated) then
         // forms exactly the negated split values, which a contraction left to the
         // compiler does not guarantee (it may fuse either product of a sum)
+        // (the acoustic and entropy rows are halved, so qq and ww are q / 2 and w / 2)
         const double ha = 0.5 * a;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            double qq, ww;
             if (shear < 0) {
-                qq = __builtin_fma(ln1, S.U(k, 1 + DIR), ln0 * S.U(k, 0));
-                ww = __builtin_fma(ln1, S.f(k, 1 + DIR), ln0 * S.f(k, 0));
+                double qq = __builtin_fma(ln1, S.U(k, 1 + DIR), ln0 * S.U(k, 0));
+                double ww = __builtin_fma(ln1, S.f(k, 1 + DIR), ln0 * S.f(k, 0));
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     qq = __builtin_fma(lt[t], S.U(k, 1 + tangential_axis<DIR>(t)), qq);
@@ -118,14 +119,15 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
                 }
                 qq = __builtin_fma(lE, S.U(k, NDIM + 1), qq);
                 ww = __builtin_fma(lE, S.f(k, NDIM + 1), ww);
+                vp[k] = __builtin_fma(a, qq, ww);
+                vm[5 - k] = __builtin_fma(-a, qq, ww);
             } else {
                 const int ax = 1 + (shear == 0 ? tangential_axis<DIR>(0) : tangential_axis<DIR>(NT - 1));
-                qq = __builtin_fma(ln0, S.U(k, 0), S.U(k, ax));
-                ww = __builtin_fma(ln0, S.f(k, 0), S.f(k, ax));
+                const double qq = __builtin_fma(ln0, S.U(k, 0), S.U(k, ax));
+                const double hw = 0.5 * __builtin_fma(ln0, S.f(k, 0), S.f(k, ax));
+                vp[k] = __builtin_fma(ha, qq, hw);
+                vm[5 - k] = __builtin_fma(-ha, qq, hw);
             }
-            const double hw = 0.5 * ww;
-            vp[k] = __builtin_fma(ha, qq, hw);
-            vm[5 - k] = __builtin_fma(-ha, qq, hw);
         }
     } else {
     double w[6], q[6];

@@ -192,6 +192,36 @@ WT_HD void left_row(const RoeBasis<NDIM> &B, int s, double &ln0, double &ln1, do
     }
 }
 
+// Half of row s of the left eigenvectors (fast forms): the split values are
+// (w +- a q) / 2, and projecting on the halved row gives w / 2 and q / 2 directly.
+// Halving is exact, so every product and sum below is the half of the one formed
+// from the full row (outside the subnormal range).
+template <int NDIM, bool FRESH>
+WT_HD void left_row_half(const RoeBasis<NDIM> &B, int s, double &ln0, double &ln1, double *lt, double &lE)
+{
+    const double b1 = opaque<FRESH>(B.b1), b2 = opaque<FRESH>(B.b2), un = opaque<FRESH>(B.un);
+    if (s == 0) {
+        ln0 = 0.25 * (b2 + opaque<FRESH>(B.uc));
+        ln1 = -0.25 * (b1 * un + opaque<FRESH>(B.ic));
+#pragma unroll
+        for (int t = 0; t < NDIM - 1; ++t) lt[t] = -0.25 * (b1 * opaque<FRESH>(B.ut[t]));
+        lE = 0.25 * b1;
+    } else if (s == 1) {
+        const double hb1 = 0.5 * b1;
+        ln0 = __builtin_fma(-0.5, b2, 0.5);
+        ln1 = hb1 * un;
+#pragma unroll
+        for (int t = 0; t < NDIM - 1; ++t) lt[t] = hb1 * opaque<FRESH>(B.ut[t]);
+        lE = -hb1;
+    } else {
+        ln0 = 0.25 * (b2 - opaque<FRESH>(B.uc));
+        ln1 = -0.25 * (b1 * un - opaque<FRESH>(B.ic));
+#pragma unroll
+        for (int t = 0; t < NDIM - 1; ++t) lt[t] = -0.25 * (b1 * opaque<FRESH>(B.ut[t]));
+        lE = 0.25 * b1;
+    }
+}
+
 // |v~|^2 / 2 of a Roe basis, recomputed from its velocities in canonical order
 // with the operations of roe_basis (so the same value) where the entropy
 // column of R needs it.  The velocities first pass through an empty asm, so

@@ -154,8 +154,9 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
 // With FRESH, a value the compiler must treat as new here: the expressions
 // formed from it stay where they are written instead of being hoisted out of
 // the field loop, where they would all be live at once (and, in 3D and in the
-// FP32 forms, cost a wave per SIMD or spill).  Without FRESH the compiler may
-// keep them across the loop, which the FP64 1D and 2D sweeps can afford.
+// fast and FP32-weight forms, cost a wave per SIMD or spill).  Without FRESH the
+// compiler may keep them across the loop, which the plain FP64 1D and 2D sweeps
+// can afford.
 template <bool FRESH>
 WT_HD double opaque(double x)
 {

@@ -556,7 +556,7 @@ void sweep_kernel(SweepArgs A)
             src[j] = SpeedLayout<SYS, NDIM>::value_of_slot(j);
             sidx[j] = SpeedLayout<SYS, NDIM>::slot_index(j);
         }
-        block_slot_max<NV, NS>(spd, st->alpha[A.slot_wr], src, sidx);
+        block_slot_max<NV, NS, kThreads, NDIM == 2>(spd, st->alpha[A.slot_wr], src, sidx);
         if (blockIdx.x == 0 && threadIdx.x < kSlotLen)
             __hip_atomic_store(&st->alpha[A.slot_zero][threadIdx.x], 0ull, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -823,7 +823,7 @@ void stage2d_kernel(Stage2dArgs A)
             src[j] = SpeedLayout<SYS_EULER, 2>::value_of_slot(j);
             sidx[j] = SpeedLayout<SYS_EULER, 2>::slot_index(j);
         }
-        block_slot_max<NV, NS, kFThreads>(spd, st->alpha[A.slot_wr], src, sidx);
+        block_slot_max<NV, NS, kFThreads, true>(spd, st->alpha[A.slot_wr], src, sidx);
         if (blockIdx.x == 0 && t < kSlotLen)
             __hip_atomic_store(&st->alpha[A.slot_zero][t], 0ull, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

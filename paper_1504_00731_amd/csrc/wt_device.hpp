@@ -105,26 +105,44 @@ __device__ __forceinline__ void slot_max(unsigned long long *p, double v)
     if (vb > cur) atomicMax(p, vb);
 }
 
-// Block-wide max of NV values per thread, then one slot update per slot
-// entry: entry slot_idx[j] takes the block maximum of value src[j] (several
-// entries may share a value).
-template <int NV, int NS, int NT = kThreads>
+// Maximum over each row of 16 lanes of non-negative speeds, in every lane of the
+// row: the first four steps of wave_max_to_lane63.
+__device__ __forceinline__ double row_max(double v)
+{
+    v = dpp_max_step<0xb1>(v);      // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4e>(v);      // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x141>(v);     // row_half_mirror
+    v = dpp_max_step<0x140>(v);     // row_mirror
+    return v;
+}
+
+// Block-wide max of NV non-negative values per thread, then one slot update per
+// slot entry: entry slot_idx[j] takes the block maximum of value src[j] (several
+// entries may share a value).  Each wave (ROWS: each row of 16 lanes) reduces its
+// values by lane moves and leaves one partial maximum per value in LDS, which the
+// slot threads combine.  ROWS saves two lane-move steps per value for a longer
+// loop in one wave and four times the partials' LDS, which is for kernels whose
+// workgroups per CU the larger table leaves unchanged (the 2D sweeps and the fused
+// 2D stage; the 3D sweep and the packed batched pass would lose a workgroup).
+template <int NV, int NS, int NT = kThreads, bool ROWS = false>
 __device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long long *slot,
                                                const int (&src)[NS], const int (&slot_idx)[NS])
 {
-    __shared__ double red[NV][NT / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int W = ROWS ? 16 : 64;            // lanes per partial
+    constexpr int NR = NT / W;
+    __shared__ double red[NV][NR];
+    const int lane = threadIdx.x & (W - 1), part = threadIdx.x / W;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        const double w = wave_max_to_lane63(v[k]);
-        if (lane == 63) red[k][wid] = w;
+        const double w = ROWS ? row_max(v[k]) : wave_max_to_lane63(v[k]);
+        if (lane == W - 1) red[k][part] = w;
     }
     __syncthreads();
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
         double m = red[src[j]][0];
 #pragma unroll
-        for (int w = 1; w < NT / 64; ++w) m = __builtin_fmax(m, red[src[j]][w]);
+        for (int r = 1; r < NR; ++r) m = __builtin_fmax(m, red[src[j]][r]);
         slot_max(&slot[slot_idx[j]], m);
     }
 }

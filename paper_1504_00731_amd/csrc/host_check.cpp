@@ -114,6 +114,11 @@ double wth_weno(const double *s, double eps, double aR)
     return wt::weno_theta(s[0], s[1], s[2], s[3], s[4], s[5], eps, aR, 1.0 / eps);
 }
 
+double wth_weno_fast(const double *s, double eps, double aR)
+{
+    return wt::weno_theta_fast(s[0], s[1], s[2], s[3], s[4], s[5], eps, aR);
+}
+
 // The packed-chunk rules of the batched 2D passes, for CPU checks of their tables:
 // the chunks of nl lines of W interfaces (at most cap; returns their number), and
 // the staged rows, stencil base and staged point of a chunk.

@@ -31,6 +31,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.wth_weno.restype = ctypes.c_double
         L.wth_weno.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        L.wth_weno_fast.restype = ctypes.c_double
+        L.wth_weno_fast.argtypes = [dp, ctypes.c_double, ctypes.c_double]
         L.wth_rhs.restype = ctypes.c_int
         L.wth_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), dp,
                               ctypes.POINTER(ctypes.c_int), dp, ctypes.c_double, ctypes.c_double,
@@ -46,6 +48,13 @@ def _dp(a):
 def weno(s, eps=1e-10, alpha_R=50.0) -> float:
     s = np.ascontiguousarray(s, dtype=np.float64)
     return lib().wth_weno(_dp(s), eps, alpha_R)
+
+
+def weno_fast(s, eps=1e-10, alpha_R=50.0) -> float:
+    """The fast FP64 reconstruction of the device headers (host rounding of its fused
+    multiply-adds, which are correctly rounded on both)."""
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    return lib().wth_weno_fast(_dp(s), eps, alpha_R)
 
 
 def rhs(P, u, alpha, f=None, prec=0):

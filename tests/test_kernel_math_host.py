@@ -239,3 +239,52 @@ def test_fast_and_fp32_forms_close_to_oracle(prec):
     got, _ = HK.rhs(P, c.u, al, prec=prec)
     ref = oracle.rhs(P, c.u)
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_fast_restricted_reconstruction_is_the_linear_one():
+    """Where the restriction holds, the weights are gamma^theta and the reconstruction is
+    the linear one (Sec. 2): the 5th-order upwind form (theta = 1)
+    (2 s0 - 13 s1 + 47 s2 + 27 s3 - 3 s4) / 60 or the 6th-order central form (theta = 0)
+    (s0 - 8 s1 + 37 s2 + 37 s3 - 8 s4 + s5) / 60, here the gamma^theta-weighted sum of
+    the four candidates in exact rational arithmetic.  The fast forms evaluate it from the
+    indicators' second and fifth differences; on the side of the theta switch the oracle
+    takes (decisions within 1e-9 of their threshold skipped), they must agree with the
+    exact value to a few units of rounding of max|s_k|, and give constant stencils back
+    exactly."""
+    from fractions import Fraction as Fr
+    cand = [[Fr(2, 6), Fr(-7, 6), Fr(11, 6), 0, 0, 0], [0, Fr(-1, 6), Fr(5, 6), Fr(2, 6), 0, 0],
+            [0, 0, Fr(2, 6), Fr(5, 6), Fr(-1, 6), 0], [0, 0, 0, Fr(11, 6), Fr(-7, 6), Fr(2, 6)]]
+    gamma = {0: [Fr(1, 20), Fr(9, 20), Fr(9, 20), Fr(1, 20)], 1: [Fr(2, 20), Fr(12, 20), Fr(6, 20), 0]}
+    coef = {th: [sum(g[k] * cand[k][j] for k in range(4)) for j in range(6)] for th, g in gamma.items()}
+    assert coef[1] == [Fr(2, 60), Fr(-13, 60), Fr(47, 60), Fr(27, 60), Fr(-3, 60), 0]
+    assert coef[0] == [Fr(1, 60), Fr(-8, 60), Fr(37, 60), Fr(37, 60), Fr(-8, 60), Fr(1, 60)]
+    rng = np.random.default_rng(31)
+    x = np.arange(6) - 2.5
+    seen = {0: 0, 1: 0}
+    worst = 0.0
+    for trial in range(3000):
+        kind = trial % 3
+        if kind == 0:       # smooth: polynomial plus a sine, of several scales and widths
+            c = rng.normal(size=4) * 10.0 ** rng.uniform(-3, 3)
+            h = math.exp(rng.uniform(-6, 0))
+            s = c[0] + c[1] * h * x + c[2] * (h * x) ** 2 + c[3] * np.sin(h * x)
+        elif kind == 1:     # near-constant
+            s = rng.normal() * (1 + 1e-6 * rng.normal(size=6))
+        else:               # constant
+            s = np.full(6, rng.normal() * 10.0 ** rng.uniform(-5, 5))
+        d = oracle.weno_theta_diag(s, 1e-10, 50.0)
+        if not d["restricted"] or abs(d["R"] - 50.0) < 1e-9 * 50.0:
+            continue
+        if abs(d["tau5"] - d["tau6"]) <= 1e-9 * max(d["tau5"], d["tau6"]) and kind != 2:
+            continue
+        th = int(d["theta"])
+        got = HK.weno_fast(s)
+        if kind == 2:
+            assert got == s[2], (s.tolist(), got)
+        exact = sum(cj * Fr(float(v)) for cj, v in zip(coef[th], s))
+        err = float(abs(Fr(got) - exact)) / (np.abs(s).max() * 2.0 ** -52)
+        worst = max(worst, err)
+        assert err <= 4.0, (th, s.tolist(), got, float(exact))
+        seen[th] += 1
+    print(f"restricted fast reconstructions: {seen}, worst {worst:.2f} x 2^-52 max|s|")
+    assert seen[0] > 100 and seen[1] > 100, seen

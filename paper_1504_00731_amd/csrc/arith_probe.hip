@@ -24,6 +24,8 @@ enum ProbeOp : int {
     kRcpFast = 6,        // out = 1 / b, the fast modes' reciprocal (b: n values)
     kRcpEstimate = 7,    // out = the hardware reciprocal estimate of b (b: n values)
     kWenoFast = 8,       // fast FP64 WENO-theta, eps c0, alpha_R c1 (a: 6 n values)
+    kRsqFast = 9,        // out = 1 / sqrt(b), the fast modes' reciprocal square root (b: n values)
+    kSqrtFast = 10,      // out = sqrt(b), the fast modes' square root (b: n values)
 };
 
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(int op, const double *a,
@@ -51,6 +53,8 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(int op, const doub
         out[i] = wt::weno_theta_fast(s[0], s[1], s[2], s[3], s[4], s[5], c0, c1);
         break;
     }
+    case kRsqFast: out[i] = wt::rsq_fast(b[i]); break;
+    case kSqrtFast: out[i] = wt::sqrt_fast(b[i]); break;
     default: break;
     }
 }
@@ -58,16 +62,17 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(int op, const doub
 }  // namespace
 
 // Applies probe `op` to n elements on `stream` (device pointers; a holds 6 n
-// values for the WENO probes, n otherwise; b is read by kDiv and the reciprocals,
-// which do not read a).
+// values for the WENO probes, n otherwise; b is read by kDiv, the reciprocals and
+// the fast roots, which do not read a).
 // Returns 0, 1 for bad arguments, 5 if the launch failed.  Asynchronous.
 extern "C" int wt_probe(int op, const double *a, const double *b, double c0, double c1, double c2,
                         double *out, int64_t n, void *stream)
 {
-    if (op < kDiv || op > kWenoFast || n < 0 || !out) return 1;
-    const bool reads_b = op == kDiv || op == kRecip || op == kRcpFast || op == kRcpEstimate;
-    if (reads_b && !b) return 1;
-    if (op != kRecip && op != kRcpFast && op != kRcpEstimate && !a) return 1;
+    if (op < kDiv || op > kSqrtFast || n < 0 || !out) return 1;
+    const bool b_only = op == kRecip || op == kRcpFast || op == kRcpEstimate || op == kRsqFast ||
+                        op == kSqrtFast;
+    if ((b_only || op == kDiv) && !b) return 1;
+    if (!b_only && !a) return 1;
     if (n == 0) return 0;
     const int64_t blocks = (n + kProbeThreads - 1) / kProbeThreads;
     if (blocks > 0x7fffffff) return 1;

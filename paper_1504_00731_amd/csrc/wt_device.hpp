@@ -155,7 +155,10 @@ __device__ __forceinline__ int euler_speeds(const double *uc, double gamma, doub
     double vel[NDIM], p, H;
     const bool ok = euler_cell<NDIM, FAST>(uc, gamma, vel, p, H);
     double c;
-    if constexpr (FAST) c = sqrt_fast(gamma * p * rcp_fast(uc[0]));
+    if constexpr (FAST) {
+        const double r = rsq_fast(uc[0]);       // the one euler_cell formed 1/rho from
+        c = sqrt_fast(gamma * p * (r * r));
+    }
     else c = sqrt_rn(div_rn(gamma * p, uc[0]));
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {

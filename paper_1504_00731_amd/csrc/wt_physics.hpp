@@ -46,8 +46,9 @@ WT_HD double sum_sq_xyz(const double *v)
 // velocities, pressure p = (gamma-1)(E - rho |v|^2 / 2) and total enthalpy
 // H = (E + p) / rho (Sec. 4.2; the 2D form of Sec. 4.3 with the density
 // restored).  Returns false for a non-physical or non-finite state.
-// FAST (the fast FP64 and FP32-weight modes): the same quantities with the fast
-// reciprocal of rho and products by it.
+// FAST (the fast FP64 and FP32-weight modes): the same quantities with 1/rho formed
+// as the square of the refined reciprocal square root (which the staged sqrt(rho)
+// shares) and products by it.
 template <int NDIM, bool FAST = false>
 WT_HD bool euler_cell(const double *uc, double gamma, double *vel,
                                            double &p, double &H)
@@ -57,7 +58,8 @@ WT_HD bool euler_cell(const double *uc, double gamma, double *vel,
     if constexpr (FAST) {
         // no contraction: a fused |v|^2 would round the axes differently, and a state with
         // its velocity components exchanged would no longer give the same pressure
-        const double y = rcp_fast(rho);
+        const double r = rsq_fast(rho);
+        const double y = r * r;
 #pragma unroll
         for (int k = 0; k < NDIM; ++k) vel[k] = uc[1 + k] * y;
         const double v2 = sum_sq_xyz<NDIM>(vel);
@@ -100,7 +102,7 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
 {
     RoeBasis<NDIM> B;
     if constexpr (FAST) {
-        // fast reciprocal and square root, but no contraction: a fused srL vL + srR vR
+        // fast reciprocals and roots, but no contraction: a fused srL vL + srR vR
         // would round the two sides differently, and the mirror image of an interface
         // (left and right exchanged) would no longer give the mirrored flux bit for bit
         const double yd = rcp_fast(srL + srR);
@@ -111,8 +113,8 @@ WT_HD RoeBasis<NDIM> roe_basis(double srL, const double *velL, double HL,
         const double q2 = 0.5 * sum_sq_xyz<NDIM>(vt);
         const double c2 = (gamma - 1.0) * (H - q2);
         B.ok = c2 > 0.0;
-        const double c = sqrt_fast(c2);
-        const double ic = rcp_fast(c);
+        const double ic = rsq_fast(c2);          // 1/c, and c from it
+        const double c = c2 * ic;
 #pragma unroll
         for (int t = 0; t < NDIM - 1; ++t) B.ut[t] = vt[tangential_axis<DIR>(t)];
         B.un = vt[DIR];

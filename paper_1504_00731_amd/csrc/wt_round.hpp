@@ -155,11 +155,31 @@ WT_HD double rcp_fast(double b)
 #endif
 }
 
-// Square root for the fast FP64 mode (the compiler's refined sequence, no exact
-// finishing step).
+// 1/sqrt(x) for the fast forms (normal positive x): the hardware estimate and two
+// Newton steps r <- r + (r / 2)(1 - (x r) r), the residual by a fused multiply-add.
+// One of these gives a square root (x r), its reciprocal (r) and 1/x (r^2) together,
+// where the compiler's square root takes range scaling, an iteration and a class
+// fix-up, and a reciprocal its own estimate and steps.  Zero, infinite and negative x
+// (states the kernels report as non-physical) give non-finite results.
+WT_HD double rsq_fast(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rsq(x);
+    double t = x * r;
+    r = __builtin_fma(0.5 * r, __builtin_fma(-t, r, 1.0), r);
+    t = x * r;
+    return __builtin_fma(0.5 * r, __builtin_fma(-t, r, 1.0), r);
+#else
+    return 1.0 / __builtin_sqrt(x);
+#endif
+}
+
+// Square root for the fast forms: x / sqrt(x) by the refined reciprocal square root
+// (no exact finishing step; the rsq of the same x elsewhere is the same value, so a
+// square root and a reciprocal of one quantity share it).
 WT_HD double sqrt_fast(double x)
 {
-    return __builtin_sqrt(x);
+    return x * rsq_fast(x);
 }
 
 WT_HD double sqrt_rn(double x)

@@ -15,7 +15,7 @@ from paper_1504_00731_amd import build as B
 
 pytestmark = pytest.mark.gpu
 
-DIV, RECIP, DIV_BY_RECIP, SQRT, WENO, WENO_FP32, RCP_FAST, RCP_ESTIMATE, WENO_FAST = range(9)
+DIV, RECIP, DIV_BY_RECIP, SQRT, WENO, WENO_FP32, RCP_FAST, RCP_ESTIMATE, WENO_FAST, RSQ_FAST, SQRT_FAST = range(11)
 
 
 @pytest.fixture(scope="module")
@@ -175,6 +175,25 @@ def test_fast_reciprocal_within_one_ulp(probe):
           f"(2^{math.log2(rel):.1f})", flush=True)
     assert ulps.max() <= 1.0, ulps.max()
     assert rel < 2.0 ** -13, rel
+
+
+def test_fast_roots_within_two_ulps(probe):
+    """The fast modes' reciprocal square root (hardware estimate refined by two Newton
+    steps) against 1/sqrt(x) evaluated in extended precision, and their square root
+    (x times it) against the IEEE square root: within two units in the last place over
+    positive normal inputs of exponents -500 .. 500 and hard significands (the kernels
+    take the roots of densities and squared sound speeds)."""
+    rng = np.random.default_rng(23)
+    b = _positive_normals(rng, 400_000)
+    want = (1.0 / np.sqrt(b.astype(np.longdouble)))
+    got = probe(RSQ_FAST, b=b)
+    ulps = np.abs(got.astype(np.longdouble) - want) / np.spacing(want.astype(np.float64))
+    sq = probe(SQRT_FAST, b=b)
+    sq_ulps = np.abs(sq - np.sqrt(b)) / np.spacing(np.sqrt(b))
+    print(f"rsq_fast: max {float(ulps.max()):.2f} ulp; sqrt_fast: max {sq_ulps.max():.2f} ulp, "
+          f"{(sq_ulps > 0).mean():.2e} of the values not correctly rounded", flush=True)
+    assert float(ulps.max()) <= 2.0, float(ulps.max())
+    assert sq_ulps.max() <= 2.0, sq_ulps.max()
 
 
 def test_weno_fast_matches_oracle_to_rounding(probe):

@@ -159,36 +159,43 @@ WT_HD double weno_theta(double s0, double s1, double s2, double s3, double s4, d
 
 // Smoothness indicators and the two theta indicators of a stencil, by fused
 // multiply-adds, with the differences they are built from that the linear
-// reconstruction reuses.
+// reconstruction reuses.  Everything is formed from six first differences of the
+// stencil: each second difference is the sum of two of them, the fourth difference
+// of tau5 comes from the second differences, and the second term of tau6 is the sum
+// of the second terms of beta~_0 and beta~_3.  (Differences of neighbouring values
+// are also the accurate order: they are exact when the values are within a factor of
+// two.)
 struct FastStencil {
     double b0, b1, b2, b3;     // beta~_k
     double tau5, tau6;
-    double d0, d1, d2;         // second differences s_k - 2 s_{k+1} + s_{k+2}, k = 0, 1, 2
+    double d0, d1;             // second differences s_k - 2 s_{k+1} + s_{k+2}, k = 0, 1
+    double n2;                 // the negated third one, -(s2 - 2 s3 + s4)
     double d5;                 // fifth difference -s0 + 5 s1 - 10 s2 + 10 s3 - 5 s4 + s5
+    double e;                  // s3 - s2
 };
 
 WT_HD FastStencil fast_stencil(double s0, double s1, double s2, double s3, double s4, double s5)
 {
     FastStencil F;
-    double t1, t2;
-    F.d0 = __builtin_fma(-2.0, s1, s0 + s2);
-    t2 = __builtin_fma(2.0, s2, __builtin_fma(-3.0, s1, s0));
-    F.b0 = __builtin_fma((13.0 / 12.0) * F.d0, F.d0, t2 * t2);
-    F.d1 = __builtin_fma(-2.0, s2, s1 + s3);
-    t2 = s3 - s2;
-    F.b1 = __builtin_fma((13.0 / 12.0) * F.d1, F.d1, t2 * t2);
-    F.d2 = __builtin_fma(-2.0, s3, s2 + s4);
-    t2 = s2 - s3;
-    F.b2 = __builtin_fma((13.0 / 12.0) * F.d2, F.d2, t2 * t2);
-    t1 = __builtin_fma(3.0, s2, __builtin_fma(-7.0, s3, __builtin_fma(5.0, s4, -s5)));
-    t2 = __builtin_fma(2.0, s3, __builtin_fma(-3.0, s4, s5));
-    F.b3 = __builtin_fma((13.0 / 48.0) * t1, t1, t2 * t2);
-    t1 = __builtin_fma(6.0, s2, __builtin_fma(-4.0, s1 + s3, s0 + s4));
-    t2 = __builtin_fma(3.0, s2 - s3, s4 - s1);
+    const double a = s0 - s1, b = s2 - s1, e = s3 - s2, c = s3 - s4, d = s5 - s4, g = s4 - s1;
+    F.e = e;
+    F.d0 = a + b;
+    F.d1 = e - b;
+    F.n2 = e + c;
+    const double e2 = e * e;
+    const double p0 = __builtin_fma(2.0, b, a);                  // s0 - 3 s1 + 2 s2
+    const double p3 = __builtin_fma(2.0, c, d);                  // 2 s3 - 3 s4 + s5
+    const double r3 = __builtin_fma(-3.0, e, __builtin_fma(-4.0, c, -d));   // 3 s2 - 7 s3 + 5 s4 - s5
+    F.b0 = __builtin_fma((13.0 / 12.0) * F.d0, F.d0, p0 * p0);
+    F.b1 = __builtin_fma((13.0 / 12.0) * F.d1, F.d1, e2);
+    F.b2 = __builtin_fma((13.0 / 12.0) * F.n2, F.n2, e2);
+    F.b3 = __builtin_fma((13.0 / 48.0) * r3, r3, p3 * p3);
+    const double t1 = __builtin_fma(-2.0, F.d1, F.d0 - F.n2);   // s0 - 4 s1 + 6 s2 - 4 s3 + s4
+    const double t2 = __builtin_fma(-3.0, e, g);                 // -s1 + 3 s2 - 3 s3 + s4
     F.tau5 = __builtin_fma((13.0 / 12.0) * t1, t1, t2 * t2);
-    F.d5 = __builtin_fma(10.0, s3 - s2, __builtin_fma(5.0, s1 - s4, s5 - s0));
-    t2 = __builtin_fma(2.0, s2 + s3, __builtin_fma(-3.0, s1 + s4, s0 + s5));
-    F.tau6 = __builtin_fma((13.0 / 12.0) * F.d5, F.d5, (0.25 * t2) * t2);
+    F.d5 = __builtin_fma(10.0, e, __builtin_fma(-5.0, g, s5 - s0));
+    const double h = p0 + p3;                                    // s0 - 3 s1 + 2 s2 + 2 s3 - 3 s4 + s5
+    F.tau6 = __builtin_fma((13.0 / 12.0) * F.d5, F.d5, (0.25 * h) * h);
     return F;
 }
 
@@ -200,10 +207,10 @@ WT_HD FastStencil fast_stencil(double s0, double s1, double s2, double s3, doubl
 // one plus d5 / 60.  The differences come from the indicators, so this costs a
 // few operations beside them, and a constant stencil gives back its value exactly
 // (every difference is zero).
-WT_HD double fast_linear(const FastStencil &F, double s2, double s3, bool central)
+WT_HD double fast_linear(const FastStencil &F, double s2, bool central)
 {
-    const double corr = __builtin_fma(-3.0, F.d2, __builtin_fma(-9.0, F.d1, 2.0 * F.d0));
-    const double up = __builtin_fma(1.0 / 60.0, corr, 0.5 * (s2 + s3));
+    const double corr = __builtin_fma(3.0, F.n2, __builtin_fma(-9.0, F.d1, 2.0 * F.d0));
+    const double up = __builtin_fma(1.0 / 60.0, corr, __builtin_fma(0.5, F.e, s2));
     const double ce = __builtin_fma(1.0 / 60.0, F.d5, up);
     return central ? ce : up;
 }
@@ -231,7 +238,7 @@ WT_HD double weno_theta_fast(double s0, double s1, double s2, double s3, double 
     const double bmin = __builtin_fmin(__builtin_fmin(F.b0, F.b1), __builtin_fmin(F.b2, F.b3));
     const bool restricted = bmax <= alpha_R * (eps + bmin);
     const bool central = F.tau6 < F.tau5;
-    if (restricted) return fast_linear(F, s2, s3, central);
+    if (restricted) return fast_linear(F, s2, central);
     const FastCandidates Q = fast_candidates(s0, s1, s2, s3, s4, s5);
     const double g0 = central ? GammaTheta::g0_t0 : GammaTheta::g0_t1;
     const double g1 = central ? GammaTheta::g1_t0 : GammaTheta::g1_t1;
@@ -282,7 +289,7 @@ WT_HD double weno_theta_fp32_recon(const double *v, double eps, float alpha_R)
     const double bmin = __builtin_fmin(__builtin_fmin(F.b0, F.b1), __builtin_fmin(F.b2, F.b3));
     const bool restricted = bmax <= (double)alpha_R * (eps + bmin);
     const bool central = F.tau6 < F.tau5;
-    if (restricted) return fast_linear(F, v[2], v[3], central);
+    if (restricted) return fast_linear(F, v[2], central);
     const FastCandidates Q = fast_candidates(v[0], v[1], v[2], v[3], v[4], v[5]);
     const double g0 = central ? GammaTheta::g0_t0 : GammaTheta::g0_t1;
     const double g1 = central ? GammaTheta::g1_t0 : GammaTheta::g1_t1;

@@ -183,12 +183,15 @@ void batched_kernel(BatchArgs A)
                                              __builtin_isfinite(uc[2]);
                             err |= fin ? kErrNonphysical : kErrNonfinite;
                         }
-                        double fn[3];
-                        euler_normal_flux<1, 0>(uc, vel, p, fn);
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            s_u[c][i] = uc[c];
-                            s_f[c][i] = fn[c];
+                        for (int c = 0; c < 3; ++c) s_u[c][i] = uc[c];
+                        if constexpr (fast_math<PREC>()) {
+                            s_f[0][i] = p;      // the fast forms project the flux from p
+                        } else {
+                            double fn[3];
+                            euler_normal_flux<1, 0>(uc, vel, p, fn);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) s_f[c][i] = fn[c];
                         }
                         s_v[0][i] = vel[0];
                         s_sr[i] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
@@ -196,7 +199,8 @@ void batched_kernel(BatchArgs A)
                     }
                     __syncthreads();
                     if (g0 + t <= n) {
-                        const LdsStencil<M, 1, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, t};
+                        const LdsStencil<M, 1, NC, 1, fast_math<PREC>()> S{s_u, s_f, s_v, s_sr, s_H, t,
+                                                                           &s_f[0][0]};
                         double F[3];
                         if (!euler_interface_flux<1, 0, PREC, PREC == 0>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
                             err |= kErrNonphysical;
@@ -311,7 +315,7 @@ struct Batch2Args {
 // TN owned points along DIR and 3-point halos mapped through the boundary; entry
 // r * TX + l holds point g0 - 3 + r of line l0 + l (lines past the last repeat
 // it; their interfaces are never taken).  Returns error bits.
-template <int DIR, int TX, int TN, int NC, bool FAST>
+template <int DIR, int TX, int TN, int NC, bool FAST, bool PRESS>
 __device__ __forceinline__ int stage_tile2(const double *uin, int64_t total, const Prob2 &P,
                                            int64_t l0, int64_t g0, double gamma,
                                            double (*s_u)[NC], double (*s_f)[NC],
@@ -337,12 +341,15 @@ __device__ __forceinline__ int stage_tile2(const double *uin, int64_t total, con
             for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
             err |= fin ? kErrNonphysical : kErrNonfinite;
         }
-        double fn[M];
-        euler_normal_flux<2, DIR>(uc, vel, p, fn);
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            s_u[c][i] = uc[c];
-            s_f[c][i] = fn[c];
+        for (int c = 0; c < M; ++c) s_u[c][i] = uc[c];
+        if constexpr (PRESS) {
+            s_f[0][i] = p;                  // the fast forms project the flux from p
+        } else {
+            double fn[M];
+            euler_normal_flux<2, DIR>(uc, vel, p, fn);
+#pragma unroll
+            for (int c = 0; c < M; ++c) s_f[c][i] = fn[c];
         }
         s_v[0][i] = vel[0];
         s_v[1][i] = vel[1];
@@ -369,7 +376,7 @@ __device__ __forceinline__ int tile_fluxes2(const Prob2 &P, int64_t l0, int64_t 
     const bool valid = l0 + cl < nl && g0 + it <= nd;
     double F[4];
     if (valid) {
-        const LdsStencil<4, 2, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
+        const LdsStencil<4, 2, NC, TX, fast_math<PREC>()> S{s_u, s_f, s_v, s_sr, s_H, t, &s_f[0][0]};
         if (!euler_interface_flux<2, DIR, PREC, true>(S, LdsSpeeds{al}, gamma, W, F)) err = kErrNonphysical;
     }
     if constexpr (ALIAS) __syncthreads();
@@ -460,7 +467,7 @@ void batched2d_kernel(Batch2Args A)
                 // x pass: D = x divergence
                 for (int64_t tile = 0; tile < xlines * xseg; ++tile) {
                     const int64_t l0 = (tile / xseg) * XTX, g0 = (tile % xseg) * XTN;
-                    err |= stage_tile2<0, XTX, XTN, NC, FAST>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+                    err |= stage_tile2<0, XTX, XTN, NC, FAST, fast_math<PREC>()>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
                     __syncthreads();
                     err |= tile_fluxes2<0, XTX, XTN, NC, PREC>(P, l0, g0, s_al[0], A.gamma, A.W, s_u, s_f,
                                                                 s_v, s_sr, s_H, s_F);
@@ -484,7 +491,7 @@ void batched2d_kernel(Batch2Args A)
                 // y pass: L = -(D + y divergence), the stage, the new speeds
                 for (int64_t tile = 0; tile < ylines * yseg; ++tile) {
                     const int64_t l0 = (tile / yseg) * YTX, g0 = (tile % yseg) * YTN;
-                    err |= stage_tile2<1, YTX, YTN, NC, FAST>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+                    err |= stage_tile2<1, YTX, YTN, NC, FAST, fast_math<PREC>()>(uin, total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
                     __syncthreads();
                     err |= tile_fluxes2<1, YTX, YTN, NC, PREC>(P, l0, g0, s_al[1], A.gamma, A.W, s_u, s_f,
                                                                 s_v, s_sr, s_H, s_F);
@@ -714,7 +721,7 @@ void flat2_pass_kernel(Flat2Args A)
             s_al[f] = split_speed([sl](int k) { return bits_to_double(sl[3 * DIR + (k < 3 ? k : 1)]); },
                                   f, walls);
     }
-    int err = stage_tile2<DIR, TX, TN, NC, FAST>(A.uin, A.total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+    int err = stage_tile2<DIR, TX, TN, NC, FAST, fast_math<PREC>()>(A.uin, A.total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
     __syncthreads();
     err |= tile_fluxes2<DIR, TX, TN, NC, PREC, ALIAS_F>(P, l0, g0, s_al, A.gamma, A.W, s_u, s_f, s_v, s_sr,
                                                          s_H, s_F);
@@ -839,12 +846,15 @@ void flat2_packed_kernel(Flat2Args A)
             for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
             err |= fin ? kErrNonphysical : kErrNonfinite;
         }
-        double fn[M];
-        euler_normal_flux<2, DIR>(uc, vel, p, fn);
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            s_u[c][e] = uc[c];
-            s_f[c][e] = fn[c];
+        for (int c = 0; c < M; ++c) s_u[c][e] = uc[c];
+        if constexpr (fast_math<PREC>()) {
+            s_f[0][e] = p;                      // the fast forms project the flux from p
+        } else {
+            double fn[M];
+            euler_normal_flux<2, DIR>(uc, vel, p, fn);
+#pragma unroll
+            for (int c = 0; c < M; ++c) s_f[c][e] = fn[c];
         }
         s_v[0][e] = vel[0];
         s_v[1][e] = vel[1];
@@ -860,7 +870,8 @@ void flat2_packed_kernel(Flat2Args A)
     double F[M];
     const bool valid = ir < nq && lane_ok;
     if (valid) {
-        const LdsStencil<M, 2, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, pack_base(q0, q, W) * TX + lane};
+        const LdsStencil<M, 2, NC, TX, fast_math<PREC>()> S{s_u, s_f, s_v, s_sr, s_H,
+                                                            pack_base(q0, q, W) * TX + lane, &s_f[0][0]};
         if (!euler_interface_flux<2, DIR, PREC, true>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
             err |= kErrNonphysical;
     }
@@ -1050,12 +1061,15 @@ void flat1_pass_kernel(Flat1Args A)
             const bool fin = __builtin_isfinite(uc[0]) && __builtin_isfinite(uc[1]) && __builtin_isfinite(uc[2]);
             err |= fin ? kErrNonphysical : kErrNonfinite;
         }
-        double fn[3];
-        euler_normal_flux<1, 0>(uc, vel, p, fn);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            s_u[c][i] = uc[c];
-            s_f[c][i] = fn[c];
+        for (int c = 0; c < 3; ++c) s_u[c][i] = uc[c];
+        if constexpr (fast_math<PREC>()) {
+            s_f[0][i] = p;                      // the fast forms project the flux from p
+        } else {
+            double fn[3];
+            euler_normal_flux<1, 0>(uc, vel, p, fn);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_f[c][i] = fn[c];
         }
         s_v[0][i] = vel[0];
         s_sr[i] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
@@ -1063,7 +1077,7 @@ void flat1_pass_kernel(Flat1Args A)
     }
     __syncthreads();
     if (g0 + t <= n) {
-        const LdsStencil<M, 1, NC, 1> S{s_u, s_f, s_v, s_sr, s_H, t};
+        const LdsStencil<M, 1, NC, 1, fast_math<PREC>()> S{s_u, s_f, s_v, s_sr, s_H, t, &s_f[0][0]};
         double F[3];
         if (!euler_interface_flux<1, 0, PREC, PREC == 0>(S, LdsSpeeds{s_al}, A.gamma, A.W, F))
             err |= kErrNonphysical;

@@ -18,9 +18,11 @@ using wt::reflected;
 
 template <int NDIM>
 struct HostStencil {
-    double uu[6][NDIM + 2], ff[6][NDIM + 2], vv[6][NDIM], ss[6], hh[6];
+    double uu[6][NDIM + 2], ff[6][NDIM + 2], vv[6][NDIM], ss[6], hh[6], pp[6];
+    static constexpr bool kPressure = true;
     double U(int k, int c) const { return uu[k][c]; }
     double f(int k, int c) const { return ff[k][c]; }
+    double p(int k) const { return pp[k]; }
     double v(int k, int d) const { return vv[k][d]; }
     double sr(int k) const { return ss[k]; }
     double H(int k) const { return hh[k]; }
@@ -69,6 +71,7 @@ int euler_sweep(const int64_t *n, double dx, int bc, const double *al, double ga
                 wt::euler_normal_flux<NDIM, DIR>(uc, S.vv[k], p, S.ff[k]);
                 S.ss[k] = FAST ? wt::sqrt_fast(uc[0]) : wt::sqrt_rn(uc[0]);
                 S.hh[k] = H;
+                S.pp[k] = p;
             }
             if (!wt::euler_interface_flux<NDIM, DIR, PREC>(S, HostSpeeds{al, bc == WT_REFLECTIVE}, gamma,
                                                         wt::WenoConst{eps, aR, 1.0 / eps},

@@ -300,6 +300,12 @@ void sweep_kernel(SweepArgs A)
     else s_F = reinterpret_cast<double (*)[kThreads]>(&s_Fown[0][0]);
     __shared__ double s_h[SPLIT ? M : 1][SPLIT ? TN + 1 : 1];   // h_s per field and interface
     __shared__ double s_al[EULER ? M : 1];       // Lax-Friedrichs speed per field
+    // Fast forms: each point's pressure, from which the normal flux is projected, in
+    // the first row of the normal-flux buffer (no flux is staged; the interface
+    // fluxes replace the row once every stencil has been read).
+    constexpr bool PRESS = EULER && FAST && !SPLIT;
+    static_assert(!PRESS || ALIAS_F, "the fast forms alias the interface fluxes too");
+    double *s_p = &s_f[0][0];
 
     DevState *st = A.st;
     if (A.check_done && st->done) return;
@@ -401,12 +407,15 @@ void sweep_kernel(SweepArgs A)
                 for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
                 err |= fin ? kErrNonphysical : kErrNonfinite;
             }
-            double fn[M];
-            euler_normal_flux<NDIM, DIR>(uc, vel, p, fn);
 #pragma unroll
-            for (int c = 0; c < M; ++c) {
-                s_u[c][li] = uc[c];
-                s_f[c][li] = fn[c];
+            for (int c = 0; c < M; ++c) s_u[c][li] = uc[c];
+            if constexpr (PRESS) {
+                s_p[li] = p;
+            } else {
+                double fn[M];
+                euler_normal_flux<NDIM, DIR>(uc, vel, p, fn);
+#pragma unroll
+                for (int c = 0; c < M; ++c) s_f[c][li] = fn[c];
             }
 #pragma unroll
             for (int k = 0; k < NDIM; ++k) s_v[k][li] = vel[k];
@@ -463,7 +472,7 @@ void sweep_kernel(SweepArgs A)
         double F[M];
         if (valid) {
             if constexpr (EULER) {
-                const LdsStencil<M, NDIM, NC, TX> S{s_u, s_f, s_v, s_sr, s_H, t};
+                const LdsStencil<M, NDIM, NC, TX, PRESS> S{s_u, s_f, s_v, s_sr, s_H, t, s_p};
                 const LdsSpeeds al{s_al};
                 if (!euler_interface_flux<NDIM, DIR, PREC>(S, al, A.gamma, A.W, F))
                     atomicOr(&st->err, kErrNonphysical);
@@ -624,8 +633,11 @@ struct TileStencil {
     const double (*vel)[kFNP];
     const double *sq, *hh;
     int base, fbase;
+    const double *pp;                            // pressures of the staged points
+    static constexpr bool kPressure = true;
     __device__ double U(int k, int c) const { return u[c][base + k * STEP]; }
     __device__ double f(int k, int c) const { return fn[c][fbase + k * FSTEP]; }
+    __device__ double p(int k) const { return pp[base + k * STEP]; }
     __device__ double v(int k, int d) const { return vel[d][base + k * STEP]; }
     __device__ double sr(int k) const { return sq[base + k * STEP]; }
     __device__ double H(int k) const { return hh[base + k * STEP]; }
@@ -694,24 +706,28 @@ void stage2d_kernel(Stage2dArgs A)
     __syncthreads();
 
     // ---- x direction: normal fluxes of rows 3 .. kFY + 2, then one interface per thread
-    for (int i = t; i < kFXF; i += kFThreads) {
-        const int li = i + 3 * kFW;
-        double uc[M], vel[2], fn[M];
+    // (the fast forms project the normal flux from the state and the pressure and
+    // stage none)
+    if constexpr (!FAST) {
+        for (int i = t; i < kFXF; i += kFThreads) {
+            const int li = i + 3 * kFW;
+            double uc[M], vel[2], fn[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) uc[c] = s_u[c][li];
-        vel[0] = s_v[0][li];
-        vel[1] = s_v[1][li];
-        euler_normal_flux<2, 0>(uc, vel, s_p[li], fn);
+            for (int c = 0; c < M; ++c) uc[c] = s_u[c][li];
+            vel[0] = s_v[0][li];
+            vel[1] = s_v[1][li];
+            euler_normal_flux<2, 0>(uc, vel, s_p[li], fn);
 #pragma unroll
-        for (int c = 0; c < M; ++c) s_f[c][i] = fn[c];
+            for (int c = 0; c < M; ++c) s_f[c][i] = fn[c];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     double F[M];
     {
         const int fi = t % kFL, j = t / kFL;     // face between points fi-1, fi of row j
         const bool valid = j < kFY && fi <= nxt && j < nyt;
         if (valid) {
-            const TileStencil<1, 1> S{s_u, s_f, s_v, s_sr, s_H, (j + 3) * kFW + fi, j * kFW + fi};
+            const TileStencil<1, 1> S{s_u, s_f, s_v, s_sr, s_H, (j + 3) * kFW + fi, j * kFW + fi, s_p};
             const LdsSpeeds al{s_al[0]};
             if (!euler_interface_flux<2, 0, PREC, true>(S, al, A.gamma, A.W, F))
                 atomicOr(&st->err, kErrNonphysical);
@@ -737,25 +753,27 @@ void stage2d_kernel(Stage2dArgs A)
     __syncthreads();
 
     // ---- y direction: normal fluxes of columns 3 .. kFX + 2, one interface per thread
-    for (int i = t; i < kFYF; i += kFThreads) {
-        const int iy = i / kFL, cx = i - iy * kFL;
-        if (cx >= kFX) continue;                 // the idle 32nd lane of a row
-        const int li = iy * kFW + cx + 3;
-        double uc[M], vel[2], fn[M];
+    if constexpr (!FAST) {
+        for (int i = t; i < kFYF; i += kFThreads) {
+            const int iy = i / kFL, cx = i - iy * kFL;
+            if (cx >= kFX) continue;             // the idle 32nd lane of a row
+            const int li = iy * kFW + cx + 3;
+            double uc[M], vel[2], fn[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) uc[c] = s_u[c][li];
-        vel[0] = s_v[0][li];
-        vel[1] = s_v[1][li];
-        euler_normal_flux<2, 1>(uc, vel, s_p[li], fn);
+            for (int c = 0; c < M; ++c) uc[c] = s_u[c][li];
+            vel[0] = s_v[0][li];
+            vel[1] = s_v[1][li];
+            euler_normal_flux<2, 1>(uc, vel, s_p[li], fn);
 #pragma unroll
-        for (int c = 0; c < M; ++c) s_f[c][i] = fn[c];
+            for (int c = 0; c < M; ++c) s_f[c][i] = fn[c];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     {
         const int i = t % kFL, fj = t / kFL;     // face between points fj-1, fj of column i
         const bool valid = fj <= kFY && i < kFX && i < nxt && fj <= nyt;
         if (valid) {
-            const TileStencil<kFW, kFL> S{s_u, s_f, s_v, s_sr, s_H, fj * kFW + i + 3, fj * kFL + i};
+            const TileStencil<kFW, kFL> S{s_u, s_f, s_v, s_sr, s_H, fj * kFW + i + 3, fj * kFL + i, s_p};
             const LdsSpeeds al{s_al[1]};
             if (!euler_interface_flux<2, 1, PREC, true>(S, al, A.gamma, A.W, F))
                 atomicOr(&st->err, kErrNonphysical);

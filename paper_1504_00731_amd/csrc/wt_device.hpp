@@ -235,16 +235,20 @@ struct SpeedLayout {
 };
 
 // Stencil accessors over the staged tile: point k of the interface owned by
-// thread t is tile entry t + k * TX.
-template <int M, int NDIM, int NC, int TX>
+// thread t is tile entry t + k * TX.  With P the tile also holds each point's
+// pressure, from which the fast forms project the normal flux (kPressure).
+template <int M, int NDIM, int NC, int TX, bool P = false>
 struct LdsStencil {
     const double (*u)[NC];
     const double (*fn)[NC];
     const double (*vel)[NC];
     const double *sq, *hh;
     int t;
+    const double *pp = nullptr;                 // pressures, where P
+    static constexpr bool kPressure = P;
     __device__ double U(int k, int c) const { return u[c][t + k * TX]; }
     __device__ double f(int k, int c) const { return fn[c][t + k * TX]; }
+    __device__ double p(int k) const { return pp[t + k * TX]; }
     __device__ double v(int k, int d) const { return vel[d][t + k * TX]; }
     __device__ double sr(int k) const { return sq[t + k * TX]; }
     __device__ double H(int k) const { return hh[t + k * TX]; }

@@ -261,13 +261,14 @@ WT_HD bool euler_interface_flux(const Acc &S, const Alpha &al, double gamma, con
                                 double *F)
 {
     constexpr int M = NDIM + 2;
-    const RoeBasis<NDIM> B = interface_basis<NDIM, DIR, fast_math<PREC>()>(S, gamma);
+    RoeBasis<NDIM> B = interface_basis<NDIM, DIR, fast_math<PREC>()>(S, gamma);
     double acc[M];
 #pragma unroll 1
     for (int it = 0; it < M; ++it) {
+        if constexpr (FRESH) refresh_basis(B);    // rows and columns formed per field
         const int s = field_order(it);
-        const double h = euler_field_flux<NDIM, DIR, PREC, FRESH>(S, B, s, al, W);
-        backproject_field<NDIM, DIR, FRESH>(B, s, h, acc);
+        const double h = euler_field_flux<NDIM, DIR, PREC, false>(S, B, s, al, W);
+        backproject_field<NDIM, DIR, false>(B, s, h, acc);
     }
     store_interface_flux<NDIM, DIR>(acc, F);
     return B.ok;

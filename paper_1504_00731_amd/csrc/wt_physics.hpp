@@ -168,6 +168,22 @@ WT_HD double opaque(double x)
     return x;
 }
 
+// The basis values as values the compiler must treat as new at this point (once per
+// field, at the top of the field loop): the rows of L and columns of R formed from
+// them then stay where they are written instead of being hoisted out of the loop,
+// where they would all be live at once.  The values are updated in place, so, unlike
+// passing each use through opaque(), no copies are needed to keep the originals.
+template <int NDIM>
+WT_HD void refresh_basis(RoeBasis<NDIM> &B)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __asm__ volatile("" : "+v"(B.un), "+v"(B.c), "+v"(B.H), "+v"(B.b1), "+v"(B.b2), "+v"(B.uc),
+                          "+v"(B.ic));
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) __asm__ volatile("" : "+v"(B.ut[t]));
+#endif
+}
+
 // Row s (0: u_n - c, 1: u_n, 2: u_n + c) of the left eigenvectors in permuted
 // order: coefficients of rho, m_n, the tangential momenta and E.
 template <int NDIM, bool FRESH>

@@ -11,7 +11,8 @@
 // The stencil is read through an accessor, so the kernels can serve it from
 // LDS and a host build can serve it from arrays:
 //   S.U(k, c)  conserved component c (canonical order) of point k = 0..5
-//   S.f(k, c)  normal flux component c (canonical order) of point k
+//   S.f(k, c)  normal flux component c (canonical order) of point k (plain FP64)
+//   S.p(k)     pressure of point k (fast and FP32-weight forms, kPressure)
 //   S.v(k, d)  velocity along axis d;  S.sr(k) sqrt(rho);  S.H(k) enthalpy
 //   S.u(k), S.f(k) state and flux value            (scalar)
 //
@@ -110,10 +111,10 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
         // forms exactly the negated split values, which a contraction left to the
         // compiler does not guarantee (it may fuse either product of a sum)
         // (the acoustic and entropy rows are halved, so qq and ww are q / 2 and w / 2).
-        // Where the tile holds the pressures (kPressure), the normal flux is not read:
-        // it is f = u_n U + p (0, e_n, u_n), so l.f = u_n (l.U) + p (l_n + l_E u_n),
-        // three operations from qq instead of a second dot product, and u_n and p
-        // instead of the flux components from LDS.
+        // The normal flux is not read: it is f = u_n U + p (0, e_n, u_n), so
+        // l.f = u_n (l.U) + p (l_n + l_E u_n), three operations from qq instead of a
+        // second dot product, and u_n and p instead of the flux components from LDS.
+        static_assert(Acc::kPressure, "the fast forms read the points' pressures");
         const double ha = 0.5 * a;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -123,26 +124,15 @@ WT_HD double euler_field_flux(const Acc &S, const RoeBasis<NDIM> &B, int s, cons
                 for (int t = 0; t < NT; ++t)
                     qq = __builtin_fma(lt[t], S.U(k, 1 + tangential_axis<DIR>(t)), qq);
                 qq = __builtin_fma(lE, S.U(k, NDIM + 1), qq);
-                double ww;
-                if constexpr (Acc::kPressure) {
-                    const double un = S.v(k, DIR);
-                    ww = __builtin_fma(un, qq, S.p(k) * __builtin_fma(lE, un, ln1));
-                } else {
-                    ww = __builtin_fma(ln1, S.f(k, 1 + DIR), ln0 * S.f(k, 0));
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        ww = __builtin_fma(lt[t], S.f(k, 1 + tangential_axis<DIR>(t)), ww);
-                    ww = __builtin_fma(lE, S.f(k, NDIM + 1), ww);
-                }
+                const double un = S.v(k, DIR);
+                const double ww = __builtin_fma(un, qq, S.p(k) * __builtin_fma(lE, un, ln1));
                 vp[k] = __builtin_fma(a, qq, ww);
                 vm[5 - k] = __builtin_fma(-a, qq, ww);
             } else {
                 // shear row (-u_t, 0, .., 1, .., 0): l_n = l_E = 0, so l.f = u_n (l.U)
                 const int ax = 1 + (shear == 0 ? tangential_axis<DIR>(0) : tangential_axis<DIR>(NT - 1));
                 const double qq = __builtin_fma(ln0, S.U(k, 0), S.U(k, ax));
-                double hw;
-                if constexpr (Acc::kPressure) hw = (0.5 * S.v(k, DIR)) * qq;
-                else hw = 0.5 * __builtin_fma(ln0, S.f(k, 0), S.f(k, ax));
+                const double hw = (0.5 * S.v(k, DIR)) * qq;
                 vp[k] = __builtin_fma(ha, qq, hw);
                 vm[5 - k] = __builtin_fma(-ha, qq, hw);
             }

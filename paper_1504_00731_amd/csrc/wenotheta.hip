@@ -312,8 +312,9 @@ void sweep_kernel(SweepArgs A)
 
     const int64_t nx = A.n[0], ny = A.n[1], nz = A.n[2];
     const int64_t nd = A.n[DIR];
-    const int64_t nseg = (nd + TN - 1) / TN;
-    const int64_t ngx = DIR == 0 ? 1 : (nx + TX - 1) / TX;
+    // sizes are non-negative: unsigned division by the tile constants
+    const int64_t nseg = (int64_t)((uint64_t)(nd + TN - 1) / TN);
+    const int64_t ngx = DIR == 0 ? 1 : (int64_t)((uint64_t)(nx + TX - 1) / TX);
 
     // block -> tile.  Workgroups are dealt to the 8 XCDs round-robin (block i to
     // XCD i mod 8), each with its own L2; the y/z tiles of neighbouring column
@@ -330,32 +331,35 @@ void sweep_kernel(SweepArgs A)
     // tile -> (x0, seg, base): base is the offset of sweep index 0 of column x0
     // x-sweeps: TX rows (row = y + z * ny) from row0, each a segment of TN points;
     // y/z-sweeps: TX columns from x0.
+    // The launch has fewer than 2^31 tiles (checked by the host), so the tile index
+    // and every factor of the tile count fit 32 bits: the decode divides in 32-bit
+    // unsigned arithmetic, which costs a few instructions where a 64-bit division
+    // takes a long scalar sequence and a dozen vector ones.
     int64_t seg, x0 = 0, row0 = 0, base;
     int64_t sstride;
     int64_t tline = 0;                           // line index along the split axis (WT_SIDES)
     const int64_t nrows = ny * nz;
+    const uint32_t ub = (uint32_t)b, useg = (uint32_t)nseg;
     if constexpr (DIR == 0) {
-        seg = b % nseg;
-        row0 = (b / nseg) * TX;
+        const uint32_t q = ub / useg;
+        seg = ub - q * useg;
+        row0 = (int64_t)q * TX;
         base = row0 * nx;
         sstride = 1;
-    } else if constexpr (DIR == 1) {
-        const int64_t gx = b % ngx;
-        const int64_t r = b / ngx;
-        seg = r % nseg;
-        const int64_t z = r / nseg;
-        x0 = gx * TX;
-        base = z * nx * ny + x0;
-        sstride = nx;
-        tline = z;
     } else {
-        const int64_t gx = b % ngx;
-        const int64_t r = b / ngx;
-        seg = r % nseg;
-        const int64_t y = r / nseg;
+        const uint32_t ugx = (uint32_t)ngx;
+        const uint32_t r = ub / ugx;
+        const int64_t gx = ub - r * ugx;
+        const uint32_t q = r / useg;
+        seg = r - q * useg;
         x0 = gx * TX;
-        base = y * nx + x0;
-        sstride = nx * ny;
+        sstride = DIR == 1 ? nx : nx * ny;
+        if constexpr (DIR == 1) {
+            base = (int64_t)q * nx * ny + x0;   // q = z
+            tline = q;
+        } else {
+            base = (int64_t)q * nx + x0;        // q = y
+        }
     }
     const int64_t g0 = seg * TN;                 // first owned point along the sweep
     const int64_t ncell = A.ncell;
@@ -665,7 +669,10 @@ void stage2d_kernel(Stage2dArgs A)
     int64_t b = blockIdx.x;
     b = (b % kXcds) * A.tiles_per_xcd + b / kXcds;
     if (b >= A.tiles) return;
-    const int64_t x0 = (b % A.ntx) * kFX, y0 = (b / A.ntx) * kFY;
+    // fewer than 2^31 tiles (checked by the host): 32-bit division
+    const uint32_t ty = (uint32_t)b / (uint32_t)A.ntx;
+    const int64_t x0 = ((uint32_t)b - ty * (uint32_t)A.ntx) * (int64_t)kFX;
+    const int64_t y0 = (int64_t)ty * kFY;
     const int nxt = (int)(nx - x0 < kFX ? nx - x0 : kFX);   // owned points of the tile
     const int nyt = (int)(ny - y0 < kFY ? ny - y0 : kFY);
     const int t = threadIdx.x;

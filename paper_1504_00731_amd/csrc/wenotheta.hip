@@ -569,7 +569,19 @@ void sweep_kernel(SweepArgs A)
             src[j] = SpeedLayout<SYS, NDIM>::value_of_slot(j);
             sidx[j] = SpeedLayout<SYS, NDIM>::slot_index(j);
         }
-        block_slot_max<NV, NS, kThreads, NDIM == 2>(spd, st->alpha[A.slot_wr], src, sidx);
+        // 2D/3D Euler: the speeds through the staged state and flux rows, free once
+        // every cell is updated (fewer instructions than lane moves); 1D grids,
+        // whose launches are latency-bound, keep the lane moves and one barrier.
+        // speed rows kept in s_u (as many as fit, at most NV), the rest in s_f
+        constexpr int KA = (M * NC) / kThreads < NV ? (M * NC) / kThreads : NV;
+        if constexpr (EULER && NDIM >= 2) {
+            static_assert((NV - KA) * kThreads + NV * 16 <= M * NC,
+                          "the speed rows and their partials fit in the staged rows");
+            block_slot_max_lds<NV, NS, kThreads, KA>(spd, st->alpha[A.slot_wr], src, sidx,
+                                                     &s_u[0][0], &s_f[0][0]);
+        } else {
+            block_slot_max<NV, NS, kThreads, NDIM == 2>(spd, st->alpha[A.slot_wr], src, sidx);
+        }
         if (blockIdx.x == 0 && threadIdx.x < kSlotLen)
             __hip_atomic_store(&st->alpha[A.slot_zero][threadIdx.x], 0ull, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

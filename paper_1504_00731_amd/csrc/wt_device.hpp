@@ -147,6 +147,59 @@ __device__ __forceinline__ void block_slot_max(double (&v)[NV], unsigned long lo
     }
 }
 
+// The hardware maximum of two doubles just read from LDS (no lane move follows, so
+// no wait states).
+__device__ __forceinline__ double lds_max(double a, double b)
+{
+    double r;
+    __asm__("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// The same block-wide maxima and slot updates as block_slot_max, through LDS
+// instead of lane moves, for kernels whose staged tile is free once every cell is
+// updated: every thread writes its NV values to the scratch rows (value k of thread
+// t at k * NT + t; the first KA values in buffer a, the rest in buffer b), then
+// NV x 16 threads each take the maximum of one value over 16 threads 16 apart
+// (consecutive threads read consecutive words) into the 16 partials of the value,
+// kept in b after its rows, and the slot threads combine the partials of their
+// value.  It takes no LDS of its own, so the kernel's workgroups per CU are
+// unchanged.  Per block this issues about 60 VALU instructions in three waves
+// instead of four to six lane-move steps per value in every wave; the maximum
+// returns one of its operands, so any order gives the same bits.  The leading
+// barrier orders the writes after every read of the tile.
+template <int NV, int NS, int NT, int KA>
+__device__ __forceinline__ void block_slot_max_lds(const double (&v)[NV], unsigned long long *slot,
+                                                   const int (&src)[NS], const int (&slot_idx)[NS],
+                                                   double *a, double *b)
+{
+    constexpr int G = 16;                        // partials per value
+    constexpr int R = NT / G;                    // threads per partial
+    static_assert(NT % G == 0 && NV * G <= NT && NS <= NT, "one partial per thread");
+    double *part = b + (NV - KA) * NT;
+    const int t = threadIdx.x;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) (k < KA ? a + k * NT : b + (k - KA) * NT)[t] = v[k];
+    __syncthreads();
+    if (t < NV * G) {
+        const int k = t / G, g = t - k * G;
+        const double *row = k < KA ? a + k * NT : b + (k - KA) * NT;
+        double m = row[g];
+#pragma unroll
+        for (int r = 1; r < R; ++r) m = lds_max(m, row[r * G + g]);
+        part[t] = m;
+    }
+    __syncthreads();
+    if (t < NS) {
+        const double *p = part + src[t] * G;
+        double m = p[0];
+#pragma unroll
+        for (int g = 1; g < G; ++g) m = lds_max(m, p[g]);
+        slot_max(&slot[slot_idx[t]], m);
+    }
+}
+
 // Wave speeds of one cell (canonical state): per direction |u_d - c|, |u_d|,
 // |u_d + c|, with c = sqrt(gamma p / rho).  Returns an error bit mask.
 template <int NDIM, bool FAST = false>

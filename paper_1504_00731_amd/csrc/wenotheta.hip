@@ -440,6 +440,34 @@ void sweep_kernel(SweepArgs A)
     if (err) atomicOr(&st->err, err);
     __syncthreads();
 
+    // The cell a thread updates after the interfaces (t < TN * TX), and its inputs that
+    // do not depend on the fluxes -- D of the earlier sweeps and u^n -- loaded before
+    // the barriers that close the interface phase, so that they are in flight while
+    // the block's last interfaces finish.
+    // (The first sweep of a stage reads neither and locates its cell afterwards.)
+    auto locate_cell = [&](int64_t &idx) -> bool {
+        const int t = threadIdx.x, it = t / TX, cx = t % TX;
+        idx = base + (g0 + it) * sstride + (DIR == 0 ? cx * nx : cx);
+        return t < TN * TX && (DIR == 0 ? row0 + cx < nrows : x0 + cx < nx) && g0 + it < nd;
+    };
+    constexpr bool PRE_D = NDIM > 1 && MODE != MODE_FIRST;
+    constexpr bool PREFETCH = PRE_D || MODE == MODE_LAST_STAGE;
+    bool pre_cell = false;
+    int64_t pre_idx = 0;
+    double preD[M], u0v[M];
+    auto prefetch_cell = [&]() {
+        if constexpr (PREFETCH) {
+            pre_cell = locate_cell(pre_idx);
+            if (pre_cell) {
+                if constexpr (PRE_D) {
+#pragma unroll
+                    for (int c = 0; c < M; ++c) preD[c] = A.D[c * ncell + pre_idx];
+                }
+                if constexpr (MODE == MODE_LAST_STAGE) stage_u0<M>(A.stage, A.u0, ncell, pre_idx, u0v);
+            }
+        }
+    };
+
     // ---- 1D Euler: one characteristic field of an interface per thread ----
     if constexpr (SPLIT) {
         const int t = threadIdx.x;
@@ -453,6 +481,7 @@ void sweep_kernel(SweepArgs A)
             s_h[f][it] = euler_field_flux<NDIM, DIR, PREC, fresh_rows<NDIM, PREC>()>(S, B, f, al, A.W);
             if (f == 0 && !B.ok) atomicOr(&st->err, kErrNonphysical);
         }
+        prefetch_cell();
         __syncthreads();
         // back-projection by the field-0 thread, fields in the order of the
         // one-thread form (so the same sums)
@@ -485,6 +514,7 @@ void sweep_kernel(SweepArgs A)
                 F[0] = scalar_interface_flux<PREC>(S, bits_to_double(st->alpha[A.slot_rd][0]), A.W);
             }
         }
+        prefetch_cell();
         if constexpr (ALIAS_F) __syncthreads();     // every stencil read of s_f is done
         if (valid) {
 #pragma unroll
@@ -498,14 +528,21 @@ void sweep_kernel(SweepArgs A)
 #pragma unroll
     for (int k = 0; k < NV; ++k) spd[k] = 0.0;
     int err2 = 0;
-    if (threadIdx.x < TN * TX) {
+    {
         const int t = threadIdx.x;
-        const int it = t / TX, cx = t % TX;
-        const int64_t g = g0 + it;
-        if ((DIR == 0 ? row0 + cx < nrows : x0 + cx < nx) && g < nd) {
-            const int64_t idx = base + g * sstride + (DIR == 0 ? cx * nx : cx);
-            double u0v[M];
-            if constexpr (MODE == MODE_LAST_STAGE) stage_u0<M>(A.stage, A.u0, ncell, idx, u0v);
+        int64_t idx = pre_idx;
+        bool cell = pre_cell;
+        if constexpr (!PREFETCH) {
+            if (t < TN * TX) {
+                const int it = t / TX, cx = t % TX;
+                const int64_t g = g0 + it;
+                if ((DIR == 0 ? row0 + cx < nrows : x0 + cx < nx) && g < nd) {
+                    idx = base + g * sstride + (DIR == 0 ? cx * nx : cx);
+                    cell = true;
+                }
+            }
+        }
+        if (cell) {
             double Lc[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
@@ -514,10 +551,10 @@ void sweep_kernel(SweepArgs A)
                 if constexpr (MODE == MODE_FIRST) {
                     A.D[o] = Dd;
                 } else if constexpr (MODE == MODE_MID) {
-                    A.D[o] = A.D[o] + Dd;
+                    A.D[o] = preD[c] + Dd;
                 } else {
                     if constexpr (NDIM == 1) Lc[c] = -Dd;
-                    else Lc[c] = -(A.D[o] + Dd);
+                    else Lc[c] = -(preD[c] + Dd);
                 }
             }
             // The stage's input state of an owned cell is tile entry t + 3 TX (owned

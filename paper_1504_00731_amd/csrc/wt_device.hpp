@@ -162,8 +162,8 @@ __device__ __forceinline__ double lds_max(double a, double b)
 // t at k * NT + t; the first KA values in buffer a, the rest in buffer b), then
 // NV x 16 threads each take the maximum of one value over 16 threads 16 apart
 // (consecutive threads read consecutive words) into the 16 partials of the value,
-// kept in b after its rows, and the slot threads combine the partials of their
-// value.  It takes no LDS of its own, so the kernel's workgroups per CU are
+// kept in b after its rows (partial g of value k at g * NV + k), and the slot
+// threads combine the partials of their value.  It takes no LDS of its own, so the kernel's workgroups per CU are
 // unchanged.  Per block this issues about 60 VALU instructions in three waves
 // instead of four to six lane-move steps per value in every wave; the maximum
 // returns one of its operands, so any order gives the same bits.  The leading
@@ -188,14 +188,15 @@ __device__ __forceinline__ void block_slot_max_lds(const double (&v)[NV], unsign
         double m = row[g];
 #pragma unroll
         for (int r = 1; r < R; ++r) m = lds_max(m, row[r * G + g]);
-        part[t] = m;
+        part[g * NV + k] = m;
     }
     __syncthreads();
     if (t < NS) {
-        const double *p = part + src[t] * G;
+        // partials value-fastest: the slot threads read neighbouring words
+        const double *p = part + src[t];
         double m = p[0];
 #pragma unroll
-        for (int g = 1; g < G; ++g) m = lds_max(m, p[g]);
+        for (int g = 1; g < G; ++g) m = lds_max(m, p[g * NV]);
         slot_max(&slot[slot_idx[t]], m);
     }
 }

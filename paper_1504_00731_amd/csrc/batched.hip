@@ -721,7 +721,9 @@ void flat2_pass_kernel(Flat2Args A)
             s_al[f] = split_speed([sl](int k) { return bits_to_double(sl[3 * DIR + (k < 3 ? k : 1)]); },
                                   f, walls);
     }
+    __builtin_amdgcn_s_setprio(2);      // staging at a raised issue priority (as the grid sweeps)
     int err = stage_tile2<DIR, TX, TN, NC, FAST, fast_math<PREC>()>(A.uin, A.total, P, l0, g0, A.gamma, s_u, s_f, s_v, s_sr, s_H);
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     err |= tile_fluxes2<DIR, TX, TN, NC, PREC, ALIAS_F>(P, l0, g0, s_al, A.gamma, A.W, s_u, s_f, s_v, s_sr,
                                                          s_H, s_F);
@@ -831,6 +833,7 @@ void flat2_packed_kernel(Flat2Args A)
         return;
     }
     // stage the lines' stretches: entry row * TX + lane
+    __builtin_amdgcn_s_setprio(2);      // staging at a raised issue priority (as the grid sweeps)
     for (int e = t; e < nrows * TX; e += kThreads) {
         const int row = e / TX, lane = e % TX;
         int line, g;
@@ -865,6 +868,7 @@ void flat2_packed_kernel(Flat2Args A)
         s_sr[e] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
         s_H[e] = H;
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     // one interface per thread: interface row ir of the chunk, lane
     const int ir = t / TX, lane = t % TX;
@@ -1058,6 +1062,7 @@ void flat1_pass_kernel(Flat1Args A)
             s_al[f] = split_speed([sl](int k) { return bits_to_double(sl[k]); }, f, bc == WT_REFLECTIVE);
     }
     int err = 0;
+    __builtin_amdgcn_s_setprio(2);      // staging at a raised issue priority (as the grid sweeps)
     for (int i = t; i < NC; i += kThreads) {
         const int64_t g = map_index(g0 - 3 + i, n, bc);
         double uc[3];
@@ -1083,6 +1088,7 @@ void flat1_pass_kernel(Flat1Args A)
         s_sr[i] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
         s_H[i] = H;
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     if (g0 + t <= n) {
         const LdsStencil<M, 1, NC, 1, fast_math<PREC>()> S{s_u, s_f, s_v, s_sr, s_H, t, &s_f[0][0]};

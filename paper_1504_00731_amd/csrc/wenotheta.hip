@@ -370,6 +370,10 @@ void sweep_kernel(SweepArgs A)
             s_al[threadIdx.x] = SlotSpeeds{st->alpha[A.slot_rd], DIR, A.walls != 0}(threadIdx.x);
     }
     int err = 0;
+    // A block's waves stage at a raised issue priority, so that a newly started block
+    // issues its loads ahead of the interface arithmetic of the CU's other blocks.
+    constexpr bool PRIO_STAGING = EULER && NDIM >= 2;
+    if constexpr (PRIO_STAGING) __builtin_amdgcn_s_setprio(2);
     for (int i = threadIdx.x; i < NC; i += kThreads) {
         // point r along the sweep of lane cx, kept in LDS at r * TX + cx; x-tiles of
         // several rows are read row by row (consecutive threads, consecutive x)
@@ -437,6 +441,7 @@ void sweep_kernel(SweepArgs A)
             s_f[0][li] = f;
         }
     }
+    if constexpr (PRIO_STAGING) __builtin_amdgcn_s_setprio(0);
     if (err) atomicOr(&st->err, err);
     __syncthreads();
 

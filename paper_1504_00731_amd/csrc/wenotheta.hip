@@ -374,9 +374,10 @@ void sweep_kernel(SweepArgs A)
     // issues its loads ahead of the interface arithmetic of the CU's other blocks.
     constexpr bool PRIO_STAGING = EULER && NDIM >= 2;
     if constexpr (PRIO_STAGING) __builtin_amdgcn_s_setprio(2);
-    for (int i = threadIdx.x; i < NC; i += kThreads) {
-        // point r along the sweep of lane cx, kept in LDS at r * TX + cx; x-tiles of
-        // several rows are read row by row (consecutive threads, consecutive x)
+    // Point i of the tile (i < NC): its LDS entry li = r * TX + cx for point r along the
+    // sweep of lane cx (x-tiles of several rows are read row by row: consecutive threads,
+    // consecutive x), its index gi along the sweep and its line's offset xo from base.
+    auto tile_point = [&](int i, int &li, int64_t &gi, int64_t &xo) {
         int r, cx;
         if constexpr (DIR == 0 && TX > 1) {
             cx = i / (TN + 6);
@@ -385,51 +386,89 @@ void sweep_kernel(SweepArgs A)
             r = i / TX;
             cx = i % TX;
         }
-        const int li = r * TX + cx;
-        const int64_t gi = g0 - 3 + r;
-        int64_t xo;                               // offset of the lane's line from base
+        li = r * TX + cx;
+        gi = g0 - 3 + r;
         if constexpr (DIR != 0) xo = x0 + cx < nx ? cx : nx - 1 - x0;
         else xo = (row0 + cx < nrows ? cx : nrows - 1 - row0) * nx;
-        if constexpr (EULER) {
-            double uc[M];
-            if (A.bc == WT_SIDES && (gi < 0 || gi >= nd)) {
-                int64_t jt;
-                if constexpr (DIR == 0) {
-                    const int64_t row = row0 + xo / nx;
-                    jt = NDIM == 3 ? row % ny : row;
+    };
+    if constexpr (EULER) {
+        // The first and middle sweeps of a stage load every point a thread stages before
+        // converting any, so a thread with two points waits for HBM once, not once per
+        // point (the block's barrier waits for its slowest wave).  The stage-finishing
+        // sweeps keep the loop: unrolled, the 2D one needs 98 VGPRs and loses its fifth
+        // wave per SIMD.
+        constexpr bool STAGE_LOADS_FIRST = MODE == MODE_FIRST || MODE == MODE_MID;
+        constexpr int NIT = (NC + kThreads - 1) / kThreads;
+        double ucs[NIT][M];
+        int lis[NIT] = {};
+        auto load_point = [&](int i, int it) {
+            {
+                int64_t gi, xo;
+                tile_point(i, lis[it], gi, xo);
+                double *uc = ucs[it];
+                if (A.bc == WT_SIDES && (gi < 0 || gi >= nd)) {
+                    int64_t jt;
+                    if constexpr (DIR == 0) {
+                        const int64_t row = row0 + xo / nx;
+                        jt = NDIM == 3 ? row % ny : row;
+                    } else {
+                        jt = NDIM == 3 && DIR == 1 ? tline : x0 + xo;
+                    }
+                    side_point<NDIM, DIR, M>(A, st, gi, nd, base + xo, sstride, jt, uc);
                 } else {
-                    jt = NDIM == 3 && DIR == 1 ? tline : x0 + xo;
+                    const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) uc[c] = A.uin[c * ncell + idx];
+                    if (reflected(gi, nd, A.bc)) uc[1 + DIR] = -uc[1 + DIR];
                 }
-                side_point<NDIM, DIR, M>(A, st, gi, nd, base + xo, sstride, jt, uc);
-            } else {
-                const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
-#pragma unroll
-                for (int c = 0; c < M; ++c) uc[c] = A.uin[c * ncell + idx];
-                if (reflected(gi, nd, A.bc)) uc[1 + DIR] = -uc[1 + DIR];
             }
-            double vel[NDIM], p, H;
-            const bool ok = euler_cell<NDIM, FAST>(uc, A.gamma, vel, p, H);
-            if (!ok) {
-                bool fin = true;
+        };
+        auto convert_point = [&](int it) {
+            {
+                const int li = lis[it];
+                const double *uc = ucs[it];
+                double vel[NDIM], p, H;
+                const bool ok = euler_cell<NDIM, FAST>(uc, A.gamma, vel, p, H);
+                if (!ok) {
+                    bool fin = true;
 #pragma unroll
-                for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
-                err |= fin ? kErrNonphysical : kErrNonfinite;
+                    for (int c = 0; c < M; ++c) fin = fin && __builtin_isfinite(uc[c]);
+                    err |= fin ? kErrNonphysical : kErrNonfinite;
+                }
+#pragma unroll
+                for (int c = 0; c < M; ++c) s_u[c][li] = uc[c];
+                if constexpr (PRESS) {
+                    s_p[li] = p;
+                } else {
+                    double fn[M];
+                    euler_normal_flux<NDIM, DIR>(uc, vel, p, fn);
+#pragma unroll
+                    for (int c = 0; c < M; ++c) s_f[c][li] = fn[c];
+                }
+#pragma unroll
+                for (int k = 0; k < NDIM; ++k) s_v[k][li] = vel[k];
+                s_sr[li] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
+                s_H[li] = H;
             }
+        };
+        if constexpr (STAGE_LOADS_FIRST) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) s_u[c][li] = uc[c];
-            if constexpr (PRESS) {
-                s_p[li] = p;
-            } else {
-                double fn[M];
-                euler_normal_flux<NDIM, DIR>(uc, vel, p, fn);
+            for (int it = 0; it < NIT; ++it)
+                if (threadIdx.x + it * kThreads < NC) load_point(threadIdx.x + it * kThreads, it);
 #pragma unroll
-                for (int c = 0; c < M; ++c) s_f[c][li] = fn[c];
-            }
-#pragma unroll
-            for (int k = 0; k < NDIM; ++k) s_v[k][li] = vel[k];
-            s_sr[li] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
-            s_H[li] = H;
+            for (int it = 0; it < NIT; ++it)
+                if (threadIdx.x + it * kThreads < NC) convert_point(it);
         } else {
+            for (int i = threadIdx.x; i < NC; i += kThreads) {
+                load_point(i, 0);
+                convert_point(0);
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < NC; i += kThreads) {
+            int li;
+            int64_t gi, xo;
+            tile_point(i, li, gi, xo);
             const int64_t idx = base + map_index(gi, nd, A.bc) * sstride + xo;
             const double x = A.uin[idx];
             double f;

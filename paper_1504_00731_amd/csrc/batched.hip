@@ -1063,12 +1063,25 @@ void flat1_pass_kernel(Flat1Args A)
     }
     int err = 0;
     __builtin_amdgcn_s_setprio(2);      // staging at a raised issue priority (as the grid sweeps)
-    for (int i = t; i < NC; i += kThreads) {
-        const int64_t g = map_index(g0 - 3 + i, n, bc);
-        double uc[3];
+    // both points a thread stages (NC > kThreads) loaded before either is converted, so
+    // the block's barrier waits for one HBM latency, not two
+    constexpr int NIT = (NC + kThreads - 1) / kThreads;
+    double ucs[NIT][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) uc[c] = A.uin[c * A.total + off + g];
-        if (reflected(g0 - 3 + i, n, bc)) uc[1] = -uc[1];
+    for (int it = 0; it < NIT; ++it) {
+        const int i = t + it * kThreads;
+        if (i < NC) {
+            const int64_t g = map_index(g0 - 3 + i, n, bc);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ucs[it][c] = A.uin[c * A.total + off + g];
+            if (reflected(g0 - 3 + i, n, bc)) ucs[it][1] = -ucs[it][1];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int i = t + it * kThreads;
+        if (i >= NC) continue;
+        const double *uc = ucs[it];
         double vel[1], p, H;
         if (!euler_cell<1, FAST>(uc, A.gamma, vel, p, H)) {
             const bool fin = __builtin_isfinite(uc[0]) && __builtin_isfinite(uc[1]) && __builtin_isfinite(uc[2]);

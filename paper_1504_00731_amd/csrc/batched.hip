@@ -834,7 +834,7 @@ void flat2_packed_kernel(Flat2Args A)
     }
     // stage the lines' stretches: entry row * TX + lane
     __builtin_amdgcn_s_setprio(2);      // staging at a raised issue priority (as the grid sweeps)
-    for (int e = t; e < nrows * TX; e += kThreads) {
+    auto load_entry = [&](int e, double (&uc)[M]) {
         const int row = e / TX, lane = e % TX;
         int line, g;
         pack_point(q0, row, W, &line, &g);
@@ -842,10 +842,11 @@ void flat2_packed_kernel(Flat2Args A)
         int64_t l = (int64_t)line * TX + lane;
         if (l >= nlanes) l = nlanes - 1;               // lanes past the last row/column repeat it
         const int64_t idx = P.off + (DIR == 0 ? l * P.nx + gm : gm * P.nx + l);
-        double uc[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) uc[c] = A.uin[c * A.total + idx];
         if (reflected(g, nd, bc)) uc[1 + DIR] = -uc[1 + DIR];
+    };
+    auto convert_entry = [&](int e, const double (&uc)[M]) {
         double vel[2], p, H;
         if (!euler_cell<2, FAST>(uc, A.gamma, vel, p, H)) {
             bool fin = true;
@@ -867,6 +868,25 @@ void flat2_packed_kernel(Flat2Args A)
         s_v[1][e] = vel[1];
         s_sr[e] = FAST ? sqrt_fast(uc[0]) : sqrt_rn(uc[0]);
         s_H[e] = H;
+    };
+    if constexpr (DIR == 0) {
+        // the x pass loads both entries a thread stages before converting either (one
+        // HBM latency before the barrier instead of two); the y pass, whose registers
+        // are tighter, keeps the loop
+        constexpr int NIT = (NC + kThreads - 1) / kThreads;
+        double ucs[NIT][M];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it)
+            if (t + it * kThreads < nrows * TX) load_entry(t + it * kThreads, ucs[it]);
+#pragma unroll
+        for (int it = 0; it < NIT; ++it)
+            if (t + it * kThreads < nrows * TX) convert_entry(t + it * kThreads, ucs[it]);
+    } else {
+        for (int e = t; e < nrows * TX; e += kThreads) {
+            double uc[M];
+            load_entry(e, uc);
+            convert_entry(e, uc);
+        }
     }
     __builtin_amdgcn_s_setprio(0);
     __syncthreads();
